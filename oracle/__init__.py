@@ -1,0 +1,286 @@
+"""Plain FP64 CPU oracle of the frozen Gaussian approximation (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` use this package.  It shares no code with the HIP path: the
+arithmetic lives in ``fga_oracle.c`` (direct double-precision loops) and in
+the few numpy steps below (branch combination, thresholding, beam set-up),
+each following the paper's three-step algorithm (Algorithm section):
+
+1. decomposition: FBI transform of f0 and f1 (psi eq. and its rewriting as a
+   windowed Fourier transform, Initial wavefield decomposition section),
+   branch data u_{+-,0} = (f0 +- i eps/(c(q)|p|) f1)/2, and thresholding;
+2. propagation: the characteristic equations for H = +-c(Q)|P|, the dynamic
+   ray tracing equations for dzQ, dzP and the amplitude equation, integrated
+   by classical RK4 (Numerical test section);
+3. reconstruction: the frozen-Gaussian sum (recons eq.).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "fga_oracle.c")
+LIB = os.path.join(HERE, "_fga_oracle.so")
+NSTATE = 23
+
+_lib = None
+
+
+def build() -> str:
+    """Compile the C oracle with gcc (OpenMP, -O2, no fast-math)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+           "-o", LIB + ".tmp", SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        I32, I64, D = ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        G = [P, I32, I32, D, D, D, D]
+        L.or_velocity.argtypes = G + [D, D, P]
+        L.or_velocity_points.argtypes = G + [I64, P, P, P]
+        L.or_fbi.argtypes = [P, I32, I32, D, D, D, D, I32, I32, I32, I32, I32,
+                             I32, I32, I32, D, D, P]
+        L.or_propagate.argtypes = G + [I64, P, P, D, I32]
+        L.or_rhs.argtypes = G + [D, P, P]
+        L.or_reconstruct.argtypes = [I32, I32, D, D, D, D, D, D, I64, P, P, P, P]
+        L.or_reconstruct_points.argtypes = [I32, I32, D, D, D, D, D, D, I64, P,
+                                            P, I64, P, P, P]
+        L.or_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _grid_args(c, grid):
+    return [_p(c), grid.n1, grid.n2, grid.o1, grid.o2, grid.d1, grid.d2]
+
+
+def threads() -> int:
+    return int(lib().or_max_threads())
+
+
+# ------------------------------------------------------------ velocity
+
+def velocity(c: np.ndarray, grid, x1, x2) -> np.ndarray:
+    """Cubic B-spline interpolant of c and its derivatives up to third order
+    at the points (x1, x2): columns c, c1, c2, c11, c12, c22, c111, c112,
+    c122, c222."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    x1 = np.ascontiguousarray(np.atleast_1d(x1), dtype=np.float64)
+    x2 = np.ascontiguousarray(np.atleast_1d(x2), dtype=np.float64)
+    out = np.empty((x1.size, 10))
+    lib().or_velocity_points(*_grid_args(c, grid), x1.size, _p(x1), _p(x2), _p(out))
+    return out
+
+
+# ------------------------------------------------------ step 1: decompose
+
+def pmesh(n: int, dp: float) -> np.ndarray:
+    """Staggered symmetric p-mesh: p_l = (l - (n-1)/2) dp."""
+    return (np.arange(n) - 0.5 * (n - 1)) * dp
+
+
+def qnodes(params):
+    k1 = params.qb1 + params.qs1 * np.arange(params.nq1)
+    k2 = params.qb2 + params.qs2 * np.arange(params.nq2)
+    return k1, k2
+
+
+def fbi(f: np.ndarray, grid, params) -> np.ndarray:
+    """psi(q, p) of the FBI transform as complex [nq2][nq1][np2][np1]."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    pr = params
+    out = np.empty((pr.nq2, pr.nq1, pr.np2, pr.np1, 2))
+    lib().or_fbi(_p(f), grid.n1, grid.n2, grid.d1, grid.d2, pr.eps, pr.tau_fbi,
+                 pr.qb1, pr.qb2, pr.qs1, pr.qs2, pr.nq1, pr.nq2, pr.np1, pr.np2,
+                 pr.dp1, pr.dp2, _p(out))
+    return out[..., 0] + 1j * out[..., 1]
+
+
+@dataclasses.dataclass
+class Beams:
+    """Thresholded beams in the order (shot, branch + then -, q flat, p flat)."""
+    shot: np.ndarray      # int32 [nb]
+    sigma: np.ndarray     # int8  [nb]  (+1 / -1)
+    cand: np.ndarray      # int64 [nb]  ((shot*2 + (sigma<0))*Nq + qflat)*Np + pflat
+    psi: np.ndarray       # complex [nb]  psi_{+-}(q, p)
+    coef: np.ndarray      # [nb][2]  w psi / (2 pi eps)^3
+    state: np.ndarray     # [nb][23]
+    offsets: np.ndarray   # int64 [nshots+1]
+
+    @property
+    def n(self) -> int:
+        return self.shot.size
+
+    def subset(self, idx) -> "Beams":
+        idx = np.asarray(idx)
+        return Beams(self.shot[idx], self.sigma[idx], self.cand[idx],
+                     self.psi[idx], np.ascontiguousarray(self.coef[idx]),
+                     np.ascontiguousarray(self.state[idx]),
+                     np.array([0, idx.size], dtype=np.int64))
+
+
+def branches(psi0, psi1, c, grid, params):
+    """psi_{+-} = (psi0 +- i eps / (c(q)|p|) psi1) / 2  (u_{+-,0} in the psi eq.)."""
+    k1, k2 = qnodes(params)
+    q1 = grid.o1 + grid.d1 * k1
+    q2 = grid.o2 + grid.d2 * k2
+    Q1, Q2 = np.meshgrid(q1, q2)                       # [nq2][nq1]
+    cq = velocity(c, grid, Q1.ravel(), Q2.ravel())[:, 0].reshape(Q1.shape)
+    p1 = pmesh(params.np1, params.dp1)
+    p2 = pmesh(params.np2, params.dp2)
+    pabs = np.sqrt(p1[None, :] ** 2 + p2[:, None] ** 2)  # [np2][np1]
+    if psi1 is None:
+        return 0.5 * psi0, 0.5 * psi0
+    ratio = 1j * params.eps / (cq[:, :, None, None] * pabs[None, None, :, :])
+    return 0.5 * (psi0 + ratio * psi1), 0.5 * (psi0 - ratio * psi1)
+
+
+def decompose(f0: np.ndarray, f1: Optional[np.ndarray], c, grid, params,
+              psi_cache=None) -> Beams:
+    """Step 1 for every shot: FBI, branch split, threshold, initial state.
+
+    Thresholding keeps (sigma, q, p) with |psi_sigma| >= tau * M, M the
+    largest |psi| over both branches of the shot, and |psi| > 0.
+    """
+    pr = params
+    k1, k2 = qnodes(pr)
+    p1m = pmesh(pr.np1, pr.dp1)
+    p2m = pmesh(pr.np2, pr.dp2)
+    nq = pr.nq1 * pr.nq2
+    npp = pr.np1 * pr.np2
+    w = (pr.qs1 * grid.d1) * (pr.qs2 * grid.d2) * pr.dp1 * pr.dp2
+    norm = w / (2 * math.pi * pr.eps) ** 3          # (2 pi eps)^{-3d/2}, d = 2
+    parts = []
+    offsets = [0]
+    for s in range(f0.shape[0]):
+        if psi_cache is not None and s in psi_cache:
+            psi0, psi1 = psi_cache[s]
+        else:
+            psi0 = fbi(f0[s], grid, pr)
+            psi1 = None if f1 is None else fbi(f1[s], grid, pr)
+        pp, pm = branches(psi0, psi1, c, grid, pr)
+        mags = np.stack([np.abs(pp).ravel(), np.abs(pm).ravel()])   # [2][nq*np]
+        M = mags.max()
+        keep = (mags >= pr.tau * M) & (mags > 0)
+        vals = np.stack([pp.ravel(), pm.ravel()])
+        sidx, flat = np.nonzero(keep)           # row-major: branch +, then -
+        qf, pf = flat // npp, flat % npp
+        j2, j1 = qf // pr.nq1, qf % pr.nq1
+        l2, l1 = pf // pr.np1, pf % pr.np1
+        nb = flat.size
+        st = np.zeros((nb, NSTATE))
+        st[:, 0] = grid.o1 + grid.d1 * k1[j1]
+        st[:, 1] = grid.o2 + grid.d2 * k2[j2]
+        st[:, 2] = p1m[l1]
+        st[:, 3] = p2m[l2]
+        # A = dzQ(0) = I, B = dzP(0) = -i I (dz = dq - i dp applied to Q = q, P = p)
+        st[:, 5] = 1.0
+        st[:, 11] = 1.0
+        st[:, 14] = -1.0
+        st[:, 20] = -1.0
+        st[:, 21] = 2.0      # a(0) = 2^{d/2}
+        psi = vals[sidx, flat]
+        coef = np.stack([psi.real * norm, psi.imag * norm], axis=1)
+        cand = ((s * 2 + sidx) * nq + qf) * npp + pf
+        parts.append((np.full(nb, s, np.int32), np.where(sidx == 0, 1, -1).astype(np.int8),
+                      cand.astype(np.int64), psi, coef, st))
+        offsets.append(offsets[-1] + nb)
+    cat = [np.concatenate([p[i] for p in parts]) for i in range(6)]
+    return Beams(cat[0], cat[1], cat[2], cat[3], np.ascontiguousarray(cat[4]),
+                 np.ascontiguousarray(cat[5]), np.array(offsets, dtype=np.int64))
+
+
+# ----------------------------------------------------- step 2: propagate
+
+def propagate(beams: Beams, c, grid, dt: float, nsteps: int) -> None:
+    """Classical RK4 of the ray, dynamic ray tracing and amplitude equations,
+    in place on beams.state."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    sig = np.ascontiguousarray(beams.sigma, dtype=np.int8)
+    assert beams.state.flags.c_contiguous and beams.state.dtype == np.float64
+    lib().or_propagate(*_grid_args(c, grid), beams.n, _p(sig), _p(beams.state),
+                       dt, nsteps)
+
+
+def rhs(y, sigma: float, c, grid) -> np.ndarray:
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    dy = np.empty(NSTATE)
+    lib().or_rhs(*_grid_args(c, grid), float(sigma), _p(y), _p(dy))
+    return dy
+
+
+# -------------------------------------------------- step 3: reconstruct
+
+def reconstruct(beams: Beams, grid, params, shot: Optional[int] = None,
+                imag: bool = False):
+    """u(x) on the whole grid from the beams of one shot (recons eq.)."""
+    sl = slice(None)
+    if shot is not None:
+        sl = slice(int(beams.offsets[shot]), int(beams.offsets[shot + 1]))
+    coef = np.ascontiguousarray(beams.coef[sl])
+    st = np.ascontiguousarray(beams.state[sl])
+    ure = np.empty(grid.shape)
+    uim = np.empty(grid.shape) if imag else None
+    lib().or_reconstruct(grid.n1, grid.n2, grid.o1, grid.o2, grid.d1, grid.d2,
+                         params.eps, params.tau_win, coef.shape[0], _p(coef),
+                         _p(st), _p(ure), _p(uim))
+    return (ure, uim) if imag else ure
+
+
+def reconstruct_points(beams: Beams, grid, params, nodes, shot: Optional[int] = None,
+                       imag: bool = False):
+    """The reconstruction sum at a list of flat node indices (i2*n1 + i1)."""
+    sl = slice(None)
+    if shot is not None:
+        sl = slice(int(beams.offsets[shot]), int(beams.offsets[shot + 1]))
+    coef = np.ascontiguousarray(beams.coef[sl])
+    st = np.ascontiguousarray(beams.state[sl])
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    ore = np.empty(nodes.size)
+    oim = np.empty(nodes.size) if imag else None
+    lib().or_reconstruct_points(grid.n1, grid.n2, grid.o1, grid.o2, grid.d1,
+                                grid.d2, params.eps, params.tau_win,
+                                coef.shape[0], _p(coef), _p(st), nodes.size,
+                                _p(nodes), _p(ore), _p(oim))
+    return (ore, oim) if imag else ore
+
+
+def trace(beams: Beams, c, grid, params, receivers, rec_every: int,
+          nrec: int) -> np.ndarray:
+    """Receiver traces [nshots][nrec][len(receivers)]: u at the receiver nodes
+    at t_k = k * rec_every * dt, k = 1..nrec (beams are advanced in place)."""
+    ns = beams.offsets.size - 1
+    out = np.empty((ns, nrec, len(receivers)))
+    for k in range(nrec):
+        propagate(beams, c, grid, params.dt, rec_every)
+        for s in range(ns):
+            out[s, k] = reconstruct_points(beams, grid, params, receivers, shot=s)
+    return out
+
+
+def forward(f0, f1, c, grid, params, imag=False):
+    """The whole three-step algorithm: u(T) for every shot."""
+    b = decompose(f0, f1, c, grid, params)
+    propagate(b, c, grid, params.dt, params.nsteps)
+    us = [reconstruct(b, grid, params, shot=s, imag=imag) for s in range(f0.shape[0])]
+    return b, us
