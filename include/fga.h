@@ -1,0 +1,159 @@
+/*
+ * fga.h -- C ABI of the MI355X (gfx950) frozen Gaussian approximation path.
+ *
+ * The library computes the paper's three-step algorithm (Yang, Lu and Fomel,
+ * "Seismic modeling using the frozen Gaussian approximation", Algorithm
+ * section) for the 2-D acoustic wave equation u_tt = c(x)^2 Lap u:
+ *
+ *   fga_decompose    step 1: FBI transform of f0 (and f1) on a (q,p) mesh
+ *                    (psi eq. and the local fast FBI of the Initial wavefield
+ *                    decomposition section), branch data u_{+-,0}, relative
+ *                    thresholding, initial beam state;
+ *   fga_propagate    step 2: RK4 of the ray equations (characline eq.) for
+ *                    H = +-c(Q)|P| (hamiltonian eq.), the dynamic ray tracing
+ *                    equations (dzQ, dzP eqs.) and the amplitude equation
+ *                    (a_formu eq.);
+ *   fga_reconstruct  step 3: the frozen-Gaussian sum (recons eq.) on the grid;
+ *   fga_trace        step 3 at receiver nodes at every rec_every-th step.
+ *
+ * Conventions shared by every entry point
+ *   - All pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
+ *     tensors) owned by the caller.  The library owns the context and its
+ *     workspaces only.
+ *   - All work is enqueued on the context's stream and is asynchronous; no
+ *     entry point synchronises except fga_sync_status and fga_copy_offsets.
+ *   - Grid arrays are C-ordered [n2][n1] float64 on nodes x_i = o + i*d
+ *     (axis 1 horizontal and fastest, axis 2 depth).
+ *   - Errors in arguments return immediately with FGA_EINVAL and leave the
+ *     stream untouched.  Errors found on the device (capacity overflow,
+ *     non-finite values, c <= 0) set a sticky status word that
+ *     fga_sync_status reads.  fga_last_error() describes the last failure.
+ */
+#ifndef FGA_H
+#define FGA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fga_ctx fga_ctx;
+
+typedef enum {
+    FGA_OK = 0,
+    FGA_EINVAL = -1,     /* invalid argument (checked on the host)          */
+    FGA_ENOMEM = -2,     /* device allocation of a workspace failed         */
+    FGA_ECAPACITY = -3,  /* more beams kept than the beam buffer holds      */
+    FGA_EHIP = -4,       /* a HIP runtime call failed                       */
+    FGA_ENUMERIC = -5,   /* NaN/Inf in an input or a beam state, or c <= 0  */
+    FGA_ESTATE = -6      /* call out of order (e.g. no velocity set)        */
+} fga_status;
+
+typedef enum {
+    FGA_FP64 = 0,   /* every stage in double precision                       */
+    FGA_MIXED = 1   /* FP32 FBI and splat (phase reduced mod 2 pi in FP64),
+                       FP64 ray/amplitude integration                        */
+} fga_precision;
+
+/* Node-centred grid: x1 = o1 + i1*d1 (i1 < n1), x2 = o2 + i2*d2 (i2 < n2). */
+typedef struct {
+    int32_t n1, n2;
+    double o1, o2, d1, d2;
+} fga_grid;
+
+/* Numerical parameters (lengths in the grid's units).
+ *   eps        the high-frequency parameter (rescaled wavelength)
+ *   q-mesh     grid nodes (qb1 + j1*qs1, qb2 + j2*qs2), j1 < nq1, j2 < nq2
+ *   p-mesh     p_l = (l - (np-1)/2) * dp per axis; np1, np2 even, so p = 0
+ *              is never a node
+ *   tau        keep (branch, q, p) with |psi| >= tau * max|psi| (per shot,
+ *              over both branches) and |psi| > 0
+ *   tau_fbi    the FBI box B_eps has half-width ceil(sqrt(2 eps ln(1/tau_fbi))/d)
+ *   tau_win    each Gaussian is summed over the box of half-width
+ *              ceil(sqrt(2 eps ln(1/tau_win))/d) around the node nearest Q
+ *   dt         RK4 time step                                                */
+typedef struct {
+    double eps;
+    int32_t qb1, qb2, qs1, qs2, nq1, nq2;
+    int32_t np1, np2;
+    double dp1, dp2;
+    double tau, tau_fbi, tau_win;
+    double dt;
+} fga_params;
+
+/* Beam storage: structure of arrays in one float64 buffer
+ * f[FGA_NFIELD][capacity] (field-major), caller-allocated on the device.
+ *   field 0..3   q1, q2, p1, p2          the (q,p) mesh node of the beam
+ *   field 4..5   C = w psi / (2 pi eps)^3 (re, im), w = qs1 d1 qs2 d2 dp1 dp2
+ *   field 6..28  state: Q1, Q2, P1, P2, S, A = dzQ (2x2 complex, row-major,
+ *                re/im interleaved), B = dzP (same), a (re, im)
+ * id[capacity] (int64) is the candidate index
+ *   ((shot*2 + (branch == -1)) * nq1*nq2 + j2*nq1 + j1) * np1*np2 + l2*np1 + l1,
+ * from which shot, branch, q and p follow.  Beams are stored in increasing
+ * id.  offsets[nshots+1] (int64, device) delimit the beams of each shot. */
+#define FGA_NSTATE 23
+#define FGA_NFIELD 29
+#define FGA_F_STATE 6
+
+typedef struct {
+    int64_t capacity;
+    double *f;
+    int64_t *id;
+    int64_t *offsets;
+} fga_beams;
+
+/* Create a context for one grid, one parameter set and one precision.
+ * max_shots bounds nshots of later calls (workspaces are sized for it).
+ * stream is a hipStream_t (NULL = the default stream).                     */
+fga_status fga_create(fga_ctx **ctx, const fga_grid *grid, const fga_params *params,
+                      int32_t precision, int32_t max_shots, void *stream);
+fga_status fga_destroy(fga_ctx *ctx);
+fga_status fga_set_stream(fga_ctx *ctx, void *stream);
+
+/* Copy the velocity c[n2][n1] (device, float64, c > 0) into the context.
+ * c(x) between nodes is the uniform cubic B-spline with these samples as
+ * coefficients, indices clamped to the grid.                               */
+fga_status fga_set_velocity(fga_ctx *ctx, const double *c_dev);
+
+/* Step 1 for nshots shots: f0_dev, f1_dev are [nshots][n2][n1] (f1_dev may
+ * be NULL for f1 = 0).  Writes beams->f, beams->id and beams->offsets.
+ * If more than beams->capacity beams are kept, the first capacity beams (in
+ * id order) are written, offsets are clipped, and the status word reports
+ * FGA_ECAPACITY with the number needed.                                    */
+fga_status fga_decompose(fga_ctx *ctx, int32_t nshots, const double *f0_dev,
+                         const double *f1_dev, fga_beams *beams);
+
+/* Step 2: advance every beam by nsteps RK4 steps of size params.dt.        */
+fga_status fga_propagate(fga_ctx *ctx, fga_beams *beams, int32_t nshots, int32_t nsteps);
+
+/* Step 3: u_dev[nshots][n2][n1] = Re sum over each shot's beams.  u_dev is
+ * overwritten.                                                             */
+fga_status fga_reconstruct(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
+                           double *u_dev);
+
+/* Receiver traces: nrec_t times, advance rec_every steps then evaluate the
+ * sum at the nrec nodes rec_dev[] (flat i2*n1 + i1, int32, device).
+ * traces_dev[nshots][nrec_t][nrec].  The beams end at t = nrec_t*rec_every*dt.
+ * If ckpt_dev is not NULL it receives the beam states before every segment:
+ * ckpt_dev[k][FGA_NSTATE][capacity], k < nrec_t.                           */
+fga_status fga_trace(fga_ctx *ctx, fga_beams *beams, int32_t nshots,
+                     const int32_t *rec_dev, int32_t nrec, int32_t rec_every,
+                     int32_t nrec_t, double *traces_dev, double *ckpt_dev);
+
+/* Synchronise the stream, read the sticky device status word and clear it.
+ * *needed (may be NULL) receives the beam count a capacity overflow needed. */
+fga_status fga_sync_status(fga_ctx *ctx, int64_t *needed);
+
+/* Synchronous copy of beams->offsets[0..nshots] to host memory.            */
+fga_status fga_copy_offsets(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
+                            int64_t *offsets_host);
+
+/* Human-readable description of the last error on this context (or of the
+ * last fga_create failure when ctx is NULL).                               */
+const char *fga_last_error(const fga_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FGA_H */

@@ -1,0 +1,253 @@
+"""MI355X (gfx950) frozen Gaussian approximation: Python binding of libfga.so.
+
+The binding only marshals arguments: every step of the path runs in the HIP
+kernels of ``libfga.so``.  PyTorch supplies device memory and the stream.
+The module-level functions carry the names of the C entry points declared in
+``include/fga.h``; :class:`FGA` is a convenience wrapper around them.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfga.so")
+
+FGA_OK, FGA_EINVAL, FGA_ENOMEM, FGA_ECAPACITY, FGA_EHIP, FGA_ENUMERIC, FGA_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6)
+FGA_FP64, FGA_MIXED = 0, 1
+FGA_NSTATE, FGA_NFIELD, FGA_F_STATE = 23, 29, 6
+
+STATUS_NAMES = {0: "FGA_OK", -1: "FGA_EINVAL", -2: "FGA_ENOMEM", -3: "FGA_ECAPACITY",
+                -4: "FGA_EHIP", -5: "FGA_ENUMERIC", -6: "FGA_ESTATE"}
+
+
+class FGAError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class fga_grid(ctypes.Structure):
+    _fields_ = [("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("o1", ctypes.c_double),
+                ("o2", ctypes.c_double), ("d1", ctypes.c_double), ("d2", ctypes.c_double)]
+
+
+class fga_params(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("qb1", ctypes.c_int32), ("qb2", ctypes.c_int32),
+                ("qs1", ctypes.c_int32), ("qs2", ctypes.c_int32), ("nq1", ctypes.c_int32),
+                ("nq2", ctypes.c_int32), ("np1", ctypes.c_int32), ("np2", ctypes.c_int32),
+                ("dp1", ctypes.c_double), ("dp2", ctypes.c_double), ("tau", ctypes.c_double),
+                ("tau_fbi", ctypes.c_double), ("tau_win", ctypes.c_double),
+                ("dt", ctypes.c_double)]
+
+
+class fga_beams(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int64), ("f", ctypes.c_void_p), ("id", ctypes.c_void_p),
+                ("offsets", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libfga.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1304_3542_amd/build.py "
+                          "(or __graft_entry__.build()); there is no fallback path")
+    L = ctypes.CDLL(path)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    C = ctypes.c_void_p   # fga_ctx*
+    sig = {
+        "fga_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(fga_grid),
+                       ctypes.POINTER(fga_params), I32, I32, P],
+        "fga_destroy": [C],
+        "fga_set_stream": [C, P],
+        "fga_set_velocity": [C, P],
+        "fga_decompose": [C, I32, P, P, ctypes.POINTER(fga_beams)],
+        "fga_propagate": [C, ctypes.POINTER(fga_beams), I32, I32],
+        "fga_reconstruct": [C, ctypes.POINTER(fga_beams), I32, P],
+        "fga_trace": [C, ctypes.POINTER(fga_beams), I32, P, I32, I32, I32, P, P],
+        "fga_sync_status": [C, ctypes.POINTER(ctypes.c_int64)],
+        "fga_copy_offsets": [C, ctypes.POINTER(fga_beams), I32, P],
+        "fga_last_error": [C],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name == "fga_last_error" else ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(ctx, status: int):
+    if status != FGA_OK:
+        msg = load().fga_last_error(ctx).decode()
+        raise FGAError(status, msg)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_handle(stream=None) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+# ------------------------------------------------ names of the C entry points
+
+def fga_create(grid, params, precision: int = FGA_FP64, max_shots: int = 1, stream=None):
+    g = fga_grid(grid.n1, grid.n2, grid.o1, grid.o2, grid.d1, grid.d2)
+    p = fga_params(params.eps, params.qb1, params.qb2, params.qs1, params.qs2, params.nq1,
+                   params.nq2, params.np1, params.np2, params.dp1, params.dp2, params.tau,
+                   params.tau_fbi, params.tau_win, params.dt)
+    ctx = ctypes.c_void_p()
+    st = load().fga_create(ctypes.byref(ctx), ctypes.byref(g), ctypes.byref(p), int(precision),
+                           int(max_shots), _stream_handle(stream))
+    _check(None, st)
+    return ctx
+
+
+def fga_destroy(ctx):
+    _check(ctx, load().fga_destroy(ctx))
+
+
+def fga_set_stream(ctx, stream=None):
+    _check(ctx, load().fga_set_stream(ctx, _stream_handle(stream)))
+
+
+def fga_set_velocity(ctx, c):
+    _require(c, "c", "float64")
+    _check(ctx, load().fga_set_velocity(ctx, _ptr(c)))
+
+
+def fga_decompose(ctx, nshots: int, f0, f1, beams: "Beams"):
+    _require(f0, "f0", "float64")
+    if f1 is not None:
+        _require(f1, "f1", "float64")
+    _check(ctx, load().fga_decompose(ctx, int(nshots), _ptr(f0), _ptr(f1), beams.c_struct()))
+
+
+def fga_propagate(ctx, beams: "Beams", nshots: int, nsteps: int):
+    _check(ctx, load().fga_propagate(ctx, beams.c_struct(), int(nshots), int(nsteps)))
+
+
+def fga_reconstruct(ctx, beams: "Beams", nshots: int, u):
+    _require(u, "u", "float64")
+    _check(ctx, load().fga_reconstruct(ctx, beams.c_struct(), int(nshots), _ptr(u)))
+
+
+def fga_trace(ctx, beams: "Beams", nshots: int, rec, rec_every: int, nrec_t: int, traces,
+              ckpt=None):
+    _require(rec, "rec", "int32")
+    _require(traces, "traces", "float64")
+    _check(ctx, load().fga_trace(ctx, beams.c_struct(), int(nshots), _ptr(rec), rec.numel(),
+                                 int(rec_every), int(nrec_t), _ptr(traces), _ptr(ckpt)))
+
+
+def fga_sync_status(ctx):
+    """Returns (status, needed_capacity) without raising."""
+    needed = ctypes.c_int64(0)
+    st = load().fga_sync_status(ctx, ctypes.byref(needed))
+    return st, needed.value
+
+
+def fga_copy_offsets(ctx, beams: "Beams", nshots: int):
+    import numpy as np
+    out = np.zeros(nshots + 1, dtype=np.int64)
+    _check(ctx, load().fga_copy_offsets(ctx, beams.c_struct(), int(nshots),
+                                        out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def fga_last_error(ctx) -> str:
+    return load().fga_last_error(ctx).decode()
+
+
+def _require(t, name, dtype):
+    import torch
+    want = getattr(torch, dtype)
+    if not t.is_cuda or t.dtype != want or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous CUDA tensor of {dtype}")
+
+
+# ------------------------------------------------------------ convenience
+
+class Beams:
+    """Device beam buffers: f[FGA_NFIELD][capacity] float64, id[capacity]
+    int64, offsets[max_shots+1] int64."""
+
+    def __init__(self, capacity: int, max_shots: int = 1, device="cuda"):
+        import torch
+        self.capacity = int(capacity)
+        self.f = torch.zeros((FGA_NFIELD, self.capacity), dtype=torch.float64, device=device)
+        self.id = torch.zeros(self.capacity, dtype=torch.int64, device=device)
+        self.offsets = torch.zeros(max_shots + 1, dtype=torch.int64, device=device)
+        self._c = fga_beams(self.capacity, self.f.data_ptr(), self.id.data_ptr(),
+                            self.offsets.data_ptr())
+
+    def c_struct(self):
+        return ctypes.byref(self._c)
+
+    @property
+    def state(self):
+        return self.f[FGA_F_STATE:]
+
+
+class FGA:
+    """One grid, one parameter set and one precision on the current device."""
+
+    def __init__(self, grid, params, precision: str = "fp64", max_shots: int = 1, stream=None):
+        self.grid = grid
+        self.params = params
+        self.precision = precision
+        self.max_shots = max_shots
+        self.ctx = fga_create(grid, params, FGA_FP64 if precision == "fp64" else FGA_MIXED,
+                              max_shots, stream)
+
+    def close(self):
+        if self.ctx is not None:
+            fga_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_velocity(self, c):
+        fga_set_velocity(self.ctx, c)
+
+    def decompose(self, f0, f1, beams: Beams):
+        fga_decompose(self.ctx, f0.shape[0], f0, f1, beams)
+
+    def propagate(self, beams: Beams, nshots: int, nsteps: int):
+        fga_propagate(self.ctx, beams, nshots, nsteps)
+
+    def reconstruct(self, beams: Beams, nshots: int, u=None):
+        import torch
+        if u is None:
+            u = torch.empty((nshots, self.grid.n2, self.grid.n1), dtype=torch.float64,
+                            device=beams.f.device)
+        fga_reconstruct(self.ctx, beams, nshots, u)
+        return u
+
+    def trace(self, beams: Beams, nshots: int, rec, rec_every: int, nrec_t: int, ckpt=None):
+        import torch
+        tr = torch.empty((nshots, nrec_t, rec.numel()), dtype=torch.float64,
+                         device=beams.f.device)
+        fga_trace(self.ctx, beams, nshots, rec, rec_every, nrec_t, tr, ckpt)
+        return tr
+
+    def status(self):
+        return fga_sync_status(self.ctx)
+
+    def offsets(self, beams: Beams, nshots: int):
+        return fga_copy_offsets(self.ctx, beams, nshots)

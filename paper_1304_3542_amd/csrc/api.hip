@@ -1,0 +1,271 @@
+// C ABI entry points: argument validation, context and workspace management.
+// The stage kernels live in fbi.hip, propagate.hip and reconstruct.hip.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "fga_internal.h"
+
+static char g_create_err[512] = "";
+
+fga_status fga_fail(fga_ctx *ctx, fga_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(ctx ? ctx->err : g_create_err, 512, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+fga_status fga_hip_check(fga_ctx *ctx, hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return FGA_OK;
+    return fga_fail(ctx, e == hipErrorOutOfMemory ? FGA_ENOMEM : FGA_EHIP, "%s: %s", what,
+                    hipGetErrorString(e));
+}
+
+fga_status fga_ensure(fga_ctx *ctx, void **buf, size_t *have, size_t need, const char *what)
+{
+    if (*have >= need && *buf) return FGA_OK;
+    if (*buf) {
+        // the old buffer may still be read by queued work
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return fga_hip_check(ctx, e, "hipStreamSynchronize");
+        (void)hipFree(*buf);
+        *buf = nullptr;
+        *have = 0;
+    }
+    hipError_t e = hipMalloc(buf, need);
+    if (e != hipSuccess) {
+        *buf = nullptr;
+        return fga_fail(ctx, FGA_ENOMEM, "hipMalloc(%zu bytes) for %s failed: %s", need, what,
+                        hipGetErrorString(e));
+    }
+    *have = need;
+    return FGA_OK;
+}
+
+static fga_status check_params(fga_ctx *ctx, const fga_grid *g, const fga_params *p)
+{
+    if (g->n1 < 4 || g->n2 < 4 || g->n1 > (1 << 15) || g->n2 > (1 << 15))
+        return fga_fail(ctx, FGA_EINVAL, "grid size %d x %d outside [4, 32768]", g->n1, g->n2);
+    if (!(g->d1 > 0) || !(g->d2 > 0) || !isfinite(g->o1) || !isfinite(g->o2))
+        return fga_fail(ctx, FGA_EINVAL, "grid spacing must be positive and origin finite");
+    if (!(p->eps > 0) || !isfinite(p->eps))
+        return fga_fail(ctx, FGA_EINVAL, "eps must be positive");
+    if (p->nq1 < 1 || p->nq2 < 1 || p->qs1 < 1 || p->qs2 < 1)
+        return fga_fail(ctx, FGA_EINVAL, "q-mesh sizes and strides must be >= 1");
+    if (p->qb1 < 0 || p->qb2 < 0 || p->qb1 + (int64_t)(p->nq1 - 1) * p->qs1 >= g->n1 ||
+        p->qb2 + (int64_t)(p->nq2 - 1) * p->qs2 >= g->n2)
+        return fga_fail(ctx, FGA_EINVAL, "q-mesh leaves the grid");
+    if (p->np1 < 2 || p->np2 < 2 || (p->np1 & 1) || (p->np2 & 1) || p->np1 > 4096 ||
+        p->np2 > 4096)
+        return fga_fail(ctx, FGA_EINVAL, "p-mesh sizes must be even, in [2, 4096]");
+    if (!(p->dp1 > 0) || !(p->dp2 > 0))
+        return fga_fail(ctx, FGA_EINVAL, "p-mesh spacing must be positive");
+    if (!(p->tau >= 0 && p->tau <= 1))
+        return fga_fail(ctx, FGA_EINVAL, "tau must lie in [0, 1]");
+    if (!(p->tau_fbi > 0 && p->tau_fbi < 1) || !(p->tau_win > 0 && p->tau_win < 1))
+        return fga_fail(ctx, FGA_EINVAL, "tau_fbi and tau_win must lie in (0, 1)");
+    if (!(p->dt > 0) || !isfinite(p->dt)) return fga_fail(ctx, FGA_EINVAL, "dt must be positive");
+    int R1 = fga_halfwidth(p->eps, p->tau_fbi, g->d1);
+    int R2 = fga_halfwidth(p->eps, p->tau_fbi, g->d2);
+    if (R1 > 8192 || R2 > 8192)
+        return fga_fail(ctx, FGA_EINVAL, "FBI box of %d x %d cells is too large", 2 * R1 + 1,
+                        2 * R2 + 1);
+    return FGA_OK;
+}
+
+extern "C" fga_status fga_create(fga_ctx **out, const fga_grid *g, const fga_params *p,
+                                 int32_t precision, int32_t max_shots, void *stream)
+{
+    if (!out || !g || !p) return fga_fail(nullptr, FGA_EINVAL, "null argument to fga_create");
+    *out = nullptr;
+    if (precision != FGA_FP64 && precision != FGA_MIXED)
+        return fga_fail(nullptr, FGA_EINVAL, "unknown precision %d", precision);
+    if (max_shots < 1 || max_shots > 65535)
+        return fga_fail(nullptr, FGA_EINVAL, "max_shots must lie in [1, 65535]");
+    fga_status st = check_params(nullptr, g, p);
+    if (st != FGA_OK) return st;
+
+    fga_ctx *ctx = (fga_ctx *)calloc(1, sizeof(fga_ctx));
+    if (!ctx) return fga_fail(nullptr, FGA_ENOMEM, "host allocation failed");
+    ctx->g = *g;
+    ctx->p = *p;
+    ctx->prec = precision;
+    ctx->max_shots = max_shots;
+    ctx->stream = (hipStream_t)stream;
+    ctx->R1 = fga_halfwidth(p->eps, p->tau_fbi, g->d1);
+    ctx->R2 = fga_halfwidth(p->eps, p->tau_fbi, g->d2);
+    ctx->W1 = 2 * ctx->R1 + 1;
+    ctx->W2 = 2 * ctx->R2 + 1;
+    ctx->Rw1 = fga_halfwidth(p->eps, p->tau_win, g->d1);
+    ctx->Rw2 = fga_halfwidth(p->eps, p->tau_win, g->d2);
+    double w = (p->qs1 * g->d1) * (p->qs2 * g->d2) * p->dp1 * p->dp2;
+    double tpe = 2.0 * M_PI * p->eps;
+    ctx->norm = w / (tpe * tpe * tpe);
+
+    hipError_t e = hipGetDevice(&ctx->dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, ctx->dev);
+    if (e == hipSuccess) e = hipMalloc((void **)&ctx->c, sizeof(double) * g->n1 * g->n2);
+    if (e == hipSuccess) e = hipMalloc((void **)&ctx->status, 2 * sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&ctx->cq, sizeof(double) * p->nq1 * p->nq2);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&ctx->maxbits, sizeof(unsigned long long) * max_shots);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->status, 0, 2 * sizeof(int64_t), ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        fga_fail(nullptr, FGA_EHIP, "fga_create: %s", hipGetErrorString(e));
+        fga_destroy(ctx);
+        return FGA_EHIP;
+    }
+    *out = ctx;
+    return FGA_OK;
+}
+
+extern "C" fga_status fga_destroy(fga_ctx *ctx)
+{
+    if (!ctx) return FGA_OK;
+    (void)hipStreamSynchronize(ctx->stream);
+    void *bufs[] = {ctx->c, ctx->status, ctx->cq, ctx->maxbits, ctx->E1t, ctx->E2,
+                    ctx->T, ctx->Psi, ctx->blk, ctx->partial};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    free(ctx);
+    return FGA_OK;
+}
+
+extern "C" fga_status fga_set_stream(fga_ctx *ctx, void *stream)
+{
+    if (!ctx) return FGA_EINVAL;
+    ctx->stream = (hipStream_t)stream;
+    return FGA_OK;
+}
+
+__global__ void k_check_velocity(const double *c, int64_t n, int64_t *status)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double v = c[i];
+        if (!(v > 0.0) || !isfinite(v)) atomicOr((unsigned long long *)status, FGA_STATUS_NUMERIC);
+    }
+}
+
+extern "C" fga_status fga_set_velocity(fga_ctx *ctx, const double *c_dev)
+{
+    if (!ctx || !c_dev) return ctx ? fga_fail(ctx, FGA_EINVAL, "null velocity") : FGA_EINVAL;
+    size_t n = (size_t)ctx->g.n1 * ctx->g.n2;
+    FGA_HIP(ctx, hipMemcpyAsync(ctx->c, c_dev, n * sizeof(double), hipMemcpyDeviceToDevice,
+                                ctx->stream));
+    hipLaunchKernelGGL(k_check_velocity, dim3(256), dim3(256), 0, ctx->stream, ctx->c,
+                       (int64_t)n, ctx->status);
+    FGA_HIP(ctx, hipGetLastError());
+    ctx->have_c = true;
+    return FGA_OK;
+}
+
+static fga_status check_beams(fga_ctx *ctx, const fga_beams *b)
+{
+    if (!b || !b->f || !b->id || !b->offsets || b->capacity < 1)
+        return fga_fail(ctx, FGA_EINVAL, "beam buffers must be non-null with capacity >= 1");
+    return FGA_OK;
+}
+
+extern "C" fga_status fga_decompose(fga_ctx *ctx, int32_t nshots, const double *f0,
+                                    const double *f1, fga_beams *beams)
+{
+    if (!ctx) return FGA_EINVAL;
+    if (nshots < 1 || nshots > ctx->max_shots)
+        return fga_fail(ctx, FGA_EINVAL, "nshots %d outside [1, %d]", nshots, ctx->max_shots);
+    if (!f0) return fga_fail(ctx, FGA_EINVAL, "f0 is null");
+    fga_status st = check_beams(ctx, beams);
+    if (st != FGA_OK) return st;
+    if (!ctx->have_c) return fga_fail(ctx, FGA_ESTATE, "fga_set_velocity was not called");
+    return fga_launch_decompose(ctx, nshots, f0, f1, beams);
+}
+
+extern "C" fga_status fga_propagate(fga_ctx *ctx, fga_beams *beams, int32_t nshots,
+                                    int32_t nsteps)
+{
+    if (!ctx) return FGA_EINVAL;
+    fga_status st = check_beams(ctx, beams);
+    if (st != FGA_OK) return st;
+    if (nshots < 1 || nshots > ctx->max_shots)
+        return fga_fail(ctx, FGA_EINVAL, "nshots %d outside [1, %d]", nshots, ctx->max_shots);
+    if (nsteps < 0) return fga_fail(ctx, FGA_EINVAL, "nsteps must be >= 0");
+    if (!ctx->have_c) return fga_fail(ctx, FGA_ESTATE, "fga_set_velocity was not called");
+    if (nsteps == 0) return FGA_OK;
+    return fga_launch_propagate(ctx, beams, nshots, nsteps, nullptr);
+}
+
+extern "C" fga_status fga_reconstruct(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
+                                      double *u)
+{
+    if (!ctx) return FGA_EINVAL;
+    fga_status st = check_beams(ctx, beams);
+    if (st != FGA_OK) return st;
+    if (nshots < 1 || nshots > ctx->max_shots)
+        return fga_fail(ctx, FGA_EINVAL, "nshots %d outside [1, %d]", nshots, ctx->max_shots);
+    if (!u) return fga_fail(ctx, FGA_EINVAL, "u is null");
+    return fga_launch_reconstruct(ctx, beams, nshots, u);
+}
+
+extern "C" fga_status fga_trace(fga_ctx *ctx, fga_beams *beams, int32_t nshots,
+                                const int32_t *rec, int32_t nrec, int32_t rec_every,
+                                int32_t nrec_t, double *traces, double *ckpt)
+{
+    if (!ctx) return FGA_EINVAL;
+    fga_status st = check_beams(ctx, beams);
+    if (st != FGA_OK) return st;
+    if (nshots < 1 || nshots > ctx->max_shots)
+        return fga_fail(ctx, FGA_EINVAL, "nshots %d outside [1, %d]", nshots, ctx->max_shots);
+    if (!rec || nrec < 1 || rec_every < 1 || nrec_t < 1 || !traces)
+        return fga_fail(ctx, FGA_EINVAL, "bad receiver arguments");
+    if (!ctx->have_c) return fga_fail(ctx, FGA_ESTATE, "fga_set_velocity was not called");
+    for (int k = 0; k < nrec_t; ++k) {
+        double *ck = ckpt ? ckpt + (size_t)k * FGA_NSTATE * beams->capacity : nullptr;
+        st = fga_launch_propagate(ctx, beams, nshots, rec_every, ck);
+        if (st != FGA_OK) return st;
+        st = fga_launch_trace_points(ctx, beams, nshots, rec, nrec, traces + (size_t)k * nrec,
+                                     (int64_t)nrec_t * nrec);
+        if (st != FGA_OK) return st;
+    }
+    return FGA_OK;
+}
+
+extern "C" fga_status fga_sync_status(fga_ctx *ctx, int64_t *needed)
+{
+    if (!ctx) return FGA_EINVAL;
+    int64_t h[2] = {0, 0};
+    FGA_HIP(ctx, hipMemcpyAsync(h, ctx->status, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    FGA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    FGA_HIP(ctx, hipMemsetAsync(ctx->status, 0, 2 * sizeof(int64_t), ctx->stream));
+    FGA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (needed) *needed = h[1];
+    if (h[0] & FGA_STATUS_NUMERIC)
+        return fga_fail(ctx, FGA_ENUMERIC, "non-finite value or c <= 0 met on the device");
+    if (h[0] & FGA_STATUS_CAPACITY)
+        return fga_fail(ctx, FGA_ECAPACITY, "beam capacity exceeded: %lld beams needed",
+                        (long long)h[1]);
+    return FGA_OK;
+}
+
+extern "C" fga_status fga_copy_offsets(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
+                                       int64_t *host)
+{
+    if (!ctx) return FGA_EINVAL;
+    fga_status st = check_beams(ctx, beams);
+    if (st != FGA_OK) return st;
+    if (!host || nshots < 1) return fga_fail(ctx, FGA_EINVAL, "bad arguments");
+    FGA_HIP(ctx, hipMemcpyAsync(host, beams->offsets, sizeof(int64_t) * (nshots + 1),
+                                hipMemcpyDeviceToHost, ctx->stream));
+    FGA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return FGA_OK;
+}
+
+extern "C" const char *fga_last_error(const fga_ctx *ctx)
+{
+    return ctx ? ctx->err : g_create_err;
+}

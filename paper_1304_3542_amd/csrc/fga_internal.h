@@ -1,0 +1,147 @@
+// Internal declarations of the gfx950 FGA library: the context, launch
+// helpers, and the device-side cubic B-spline velocity interpolant.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fga.h"
+
+#define FGA_STATUS_CAPACITY 1
+#define FGA_STATUS_NUMERIC 2
+
+struct fga_ctx {
+    fga_grid g;
+    fga_params p;
+    int prec;
+    int max_shots;
+    hipStream_t stream;
+    int dev;
+    int num_cu;
+
+    // FBI box and reconstruction window half-widths (cells)
+    int R1, R2, W1, W2;
+    int Rw1, Rw2;
+    double norm;           // w / (2 pi eps)^3
+
+    double *c;             // velocity samples [n2][n1]
+    bool have_c;
+
+    // FBI workspaces
+    void *E1t;             // [W1][np1] complex (pass-1 kernel table, m-major)
+    void *E2;              // [np2][W2] complex (pass-2 kernel table)
+    void *T;               // [nshots*nfj][n2][nq1*np1] complex
+    void *Psi;             // [nshots*nfj][nq2][np2][nq1*np1] complex
+    size_t T_bytes, Psi_bytes;
+    double *cq;            // c(q) [nq2][nq1]
+    unsigned long long *maxbits;   // per-shot max |psi| (double bits)
+    int64_t *blk;          // per-block counts / offsets of the compaction
+    size_t blk_elems;
+
+    // reconstruction workspace: per-split partial sums
+    double *partial;
+    size_t partial_bytes;
+
+    // sticky device status: [0] flags, [1] needed capacity
+    int64_t *status;
+
+    char err[512];
+};
+
+fga_status fga_fail(fga_ctx *ctx, fga_status st, const char *fmt, ...);
+fga_status fga_hip_check(fga_ctx *ctx, hipError_t e, const char *what);
+fga_status fga_ensure(fga_ctx *ctx, void **buf, size_t *have, size_t need, const char *what);
+
+#define FGA_HIP(ctx, call)                                                       \
+    do {                                                                         \
+        hipError_t e_ = (call);                                                  \
+        if (e_ != hipSuccess) return fga_hip_check((ctx), e_, #call);            \
+    } while (0)
+
+// Stage launchers (defined in the stage sources)
+fga_status fga_launch_decompose(fga_ctx *ctx, int nshots, const double *f0,
+                                const double *f1, fga_beams *beams);
+fga_status fga_launch_propagate(fga_ctx *ctx, fga_beams *beams, int nshots, int nsteps,
+                                double *ckpt);
+fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nshots,
+                                  double *u);
+fga_status fga_launch_trace_points(fga_ctx *ctx, const fga_beams *beams, int nshots,
+                                   const int32_t *rec, int nrec, double *out,
+                                   int64_t out_stride_shot);
+
+static inline int fga_halfwidth(double eps, double tau, double d)
+{
+    return (int)ceil(sqrt(2.0 * eps * log(1.0 / tau)) / d);
+}
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+
+struct VelGrid {
+    const double *c;
+    int n1, n2;
+    double o1, o2, inv_d1, inv_d2;
+};
+
+// Cubic B-spline weights of the four knots floor(t)-1 .. floor(t)+2 and their
+// first and second derivatives in t, for fractional part f in [0, 1).
+__device__ __forceinline__ void bspline_w(double f, double w[4], double dw[4], double ddw[4])
+{
+    double g = 1.0 - f;
+    double f2 = f * f, g2 = g * g;
+    w[0] = g2 * g * (1.0 / 6.0);
+    w[1] = (2.0 / 3.0) - f2 + 0.5 * f2 * f;
+    w[2] = (2.0 / 3.0) - g2 + 0.5 * g2 * g;
+    w[3] = f2 * f * (1.0 / 6.0);
+    dw[0] = -0.5 * g2;
+    dw[1] = -2.0 * f + 1.5 * f2;
+    dw[2] = 2.0 * g - 1.5 * g2;
+    dw[3] = 0.5 * f2;
+    ddw[0] = g;
+    ddw[1] = -2.0 + 3.0 * f;
+    ddw[2] = -2.0 + 3.0 * g;
+    ddw[3] = f;
+}
+
+// c, grad c and the Hessian (c11, c12, c22) of the clamped cubic B-spline.
+__device__ __forceinline__ void vel_eval(const VelGrid &V, double x1, double x2, double &c,
+                                         double &c1, double &c2, double &c11, double &c12,
+                                         double &c22)
+{
+    double t1 = (x1 - V.o1) * V.inv_d1;
+    double t2 = (x2 - V.o2) * V.inv_d2;
+    double fl1 = floor(t1), fl2 = floor(t2);
+    double f1 = t1 - fl1, f2 = t2 - fl2;
+    // clamp the knot index so that far-away points stay representable
+    int i1 = (int)fmin(fmax(fl1, -4.0), (double)V.n1 + 4.0);
+    int i2 = (int)fmin(fmax(fl2, -4.0), (double)V.n2 + 4.0);
+    double wx[4], dwx[4], ddwx[4], wz[4], dwz[4], ddwz[4];
+    bspline_w(f1, wx, dwx, ddwx);
+    bspline_w(f2, wz, dwz, ddwz);
+    int k1[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) k1[k] = min(max(i1 - 1 + k, 0), V.n1 - 1);
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
+#pragma unroll
+    for (int kz = 0; kz < 4; ++kz) {
+        int r = min(max(i2 - 1 + kz, 0), V.n2 - 1);
+        const double *row = V.c + (size_t)r * V.n1;
+        double v0 = row[k1[0]], v1 = row[k1[1]], v2 = row[k1[2]], v3 = row[k1[3]];
+        double a0 = wx[0] * v0 + wx[1] * v1 + wx[2] * v2 + wx[3] * v3;
+        double a1 = dwx[0] * v0 + dwx[1] * v1 + dwx[2] * v2 + dwx[3] * v3;
+        double a2 = ddwx[0] * v0 + ddwx[1] * v1 + ddwx[2] * v2 + ddwx[3] * v3;
+        s0 += wz[kz] * a0;
+        s1 += wz[kz] * a1;
+        s2 += dwz[kz] * a0;
+        s3 += wz[kz] * a2;
+        s4 += dwz[kz] * a1;
+        s5 += ddwz[kz] * a0;
+    }
+    c = s0;
+    c1 = s1 * V.inv_d1;
+    c2 = s2 * V.inv_d2;
+    c11 = s3 * V.inv_d1 * V.inv_d1;
+    c12 = s4 * V.inv_d1 * V.inv_d2;
+    c22 = s5 * V.inv_d2 * V.inv_d2;
+}

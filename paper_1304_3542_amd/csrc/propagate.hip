@@ -1,0 +1,192 @@
+// Step 2 of the FGA algorithm on gfx950: classical RK4 of the ray equations
+// (characline eq.) for H = sigma c(Q)|P| (hamiltonian eq.), of the dynamic
+// ray tracing equations for A = dzQ, B = dzP (dzQ, dzP eqs.), of the action
+// S and of the amplitude a (a_formu eq.).
+//
+// One thread owns one beam for all steps: the 23-double state and the RK4
+// accumulators stay in VGPRs, so HBM sees one read and one write of the
+// state per launch.  c and its derivatives come from the cubic B-spline of
+// the velocity samples (16 taps per evaluation), read through the L2 (the
+// velocity grid is a few MB and stays cache resident).  FP64 throughout:
+// gfx950 runs FP64 FMA at the FP32 rate, and the phase P.(x-Q)/eps needs Q
+// and P to ~1e-14.
+#include "fga_internal.h"
+
+struct Cd {
+    double r, i;
+};
+
+__device__ __forceinline__ Cd cmul(Cd a, Cd b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ Cd cadd(Cd a, Cd b) { return {a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ Cd csub(Cd a, Cd b) { return {a.r - b.r, a.i - b.i}; }
+__device__ __forceinline__ Cd cscale(Cd a, double s) { return {a.r * s, a.i * s}; }
+
+// State layout (23 doubles): Q1 Q2 P1 P2 S | A11 A12 A21 A22 (re,im) |
+// B11 B12 B21 B22 (re,im) | a (re,im)
+struct St {
+    double Q1, Q2, P1, P2, S;
+    Cd A[2][2], B[2][2];
+    Cd a;
+};
+
+__device__ __forceinline__ void axpy(St &o, const St &y, double h, const St &k)
+{
+    o.Q1 = fma(h, k.Q1, y.Q1);
+    o.Q2 = fma(h, k.Q2, y.Q2);
+    o.P1 = fma(h, k.P1, y.P1);
+    o.P2 = fma(h, k.P2, y.P2);
+    o.S = fma(h, k.S, y.S);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            o.A[j][l].r = fma(h, k.A[j][l].r, y.A[j][l].r);
+            o.A[j][l].i = fma(h, k.A[j][l].i, y.A[j][l].i);
+            o.B[j][l].r = fma(h, k.B[j][l].r, y.B[j][l].r);
+            o.B[j][l].i = fma(h, k.B[j][l].i, y.B[j][l].i);
+        }
+    o.a.r = fma(h, k.a.r, y.a.r);
+    o.a.i = fma(h, k.a.i, y.a.i);
+}
+
+// Right-hand side.  With n = |P|, u = P/n, g = grad c, K = Hess c:
+//   H_P = s c u, H_Q = s n g, H_PP = s (c/n)(I - u u^T), H_QQ = s n K,
+//   H_QP = s g u^T, H_PQ = s u g^T, so the dynamic ray tracing equations
+//   become rank-one updates:
+//   dA_j = s[(A_j.g - (c/n) B_j.u) u + (c/n) B_j]
+//   dB_j = -s[n K A_j + (B_j.u) g]
+//   da   = a [ (H_P.H_Q)/H + tr(Z^{-1} dZ)/2 ],  (H_P.H_Q)/H = s u.g,
+//   tr(Z^{-1} dZ) = (Z22 dZ11 - Z12 dZ21 - Z21 dZ12 + Z11 dZ22) / det Z.
+__device__ __forceinline__ void rhs(const VelGrid &V, double s, const St &y, St &k)
+{
+    double c, g1, g2, K11, K12, K22;
+    vel_eval(V, y.Q1, y.Q2, c, g1, g2, K11, K12, K22);
+    double n = sqrt(y.P1 * y.P1 + y.P2 * y.P2);
+    double inv_n = 1.0 / n;
+    double u1 = y.P1 * inv_n, u2 = y.P2 * inv_n;
+    double sc = s * c;
+    double HP1 = sc * u1, HP2 = sc * u2;
+    k.Q1 = HP1;
+    k.Q2 = HP2;
+    k.P1 = -s * n * g1;
+    k.P2 = -s * n * g2;
+    k.S = y.P1 * HP1 + y.P2 * HP2 - sc * n;
+    double con = c * inv_n;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        Cd Ag = cadd(cscale(y.A[j][0], g1), cscale(y.A[j][1], g2));
+        Cd Bu = cadd(cscale(y.B[j][0], u1), cscale(y.B[j][1], u2));
+        Cd m = csub(Ag, cscale(Bu, con));
+        k.A[j][0] = cscale(cadd(cscale(m, u1), cscale(y.B[j][0], con)), s);
+        k.A[j][1] = cscale(cadd(cscale(m, u2), cscale(y.B[j][1], con)), s);
+        // (A_j K)_k = sum_l A[j][l] K[l][k]
+        Cd AK0 = cadd(cscale(y.A[j][0], K11), cscale(y.A[j][1], K12));
+        Cd AK1 = cadd(cscale(y.A[j][0], K12), cscale(y.A[j][1], K22));
+        k.B[j][0] = cscale(cadd(cscale(AK0, n), cscale(Bu, g1)), -s);
+        k.B[j][1] = cscale(cadd(cscale(AK1, n), cscale(Bu, g2)), -s);
+    }
+    Cd Z[2][2], dZ[2][2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            Z[j][l] = {y.A[j][l].r - y.B[j][l].i, y.A[j][l].i + y.B[j][l].r};
+            dZ[j][l] = {k.A[j][l].r - k.B[j][l].i, k.A[j][l].i + k.B[j][l].r};
+        }
+    Cd det = csub(cmul(Z[0][0], Z[1][1]), cmul(Z[0][1], Z[1][0]));
+    Cd num = csub(cadd(cmul(Z[1][1], dZ[0][0]), cmul(Z[0][0], dZ[1][1])),
+                  cadd(cmul(Z[0][1], dZ[1][0]), cmul(Z[1][0], dZ[0][1])));
+    double id2 = 1.0 / (det.r * det.r + det.i * det.i);
+    Cd tr = cscale(cmul(num, Cd{det.r, -det.i}), id2);
+    Cd fac = {s * (u1 * g1 + u2 * g2) + 0.5 * tr.r, 0.5 * tr.i};
+    k.a = cmul(y.a, fac);
+}
+
+__device__ __forceinline__ void load_state(const double *f, int64_t cap, int64_t b, St &y)
+{
+    const double *p = f + (size_t)FGA_F_STATE * cap + b;
+    y.Q1 = p[0 * cap];
+    y.Q2 = p[1 * cap];
+    y.P1 = p[2 * cap];
+    y.P2 = p[3 * cap];
+    y.S = p[4 * cap];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            y.A[j][l].r = p[(5 + 2 * (2 * j + l)) * cap];
+            y.A[j][l].i = p[(6 + 2 * (2 * j + l)) * cap];
+            y.B[j][l].r = p[(13 + 2 * (2 * j + l)) * cap];
+            y.B[j][l].i = p[(14 + 2 * (2 * j + l)) * cap];
+        }
+    y.a.r = p[21 * cap];
+    y.a.i = p[22 * cap];
+}
+
+__device__ __forceinline__ void store_state(double *p, int64_t cap, const St &y)
+{
+    p[0 * cap] = y.Q1;
+    p[1 * cap] = y.Q2;
+    p[2 * cap] = y.P1;
+    p[3 * cap] = y.P2;
+    p[4 * cap] = y.S;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            p[(5 + 2 * (2 * j + l)) * cap] = y.A[j][l].r;
+            p[(6 + 2 * (2 * j + l)) * cap] = y.A[j][l].i;
+            p[(13 + 2 * (2 * j + l)) * cap] = y.B[j][l].r;
+            p[(14 + 2 * (2 * j + l)) * cap] = y.B[j][l].i;
+        }
+    p[21 * cap] = y.a.r;
+    p[22 * cap] = y.a.i;
+}
+
+__global__ void __launch_bounds__(256)
+k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
+      const int64_t *__restrict__ offsets, int nshots, int64_t cap, int64_t NqNp, double dt,
+      int nsteps, double *__restrict__ ckpt, int64_t *status)
+{
+    int64_t nb = offsets[nshots];
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        St y;
+        load_state(f, cap, b, y);
+        if (ckpt) store_state(ckpt + b, cap, y);
+        double s = ((id[b] / NqNp) & 1) ? -1.0 : 1.0;
+        double h2 = 0.5 * dt, h6 = dt / 6.0, h3 = dt / 3.0;
+        for (int it = 0; it < nsteps; ++it) {
+            St k, t, acc;
+            rhs(V, s, y, k);
+            axpy(acc, y, h6, k);
+            axpy(t, y, h2, k);
+            rhs(V, s, t, k);
+            axpy(acc, acc, h3, k);
+            axpy(t, y, h2, k);
+            rhs(V, s, t, k);
+            axpy(acc, acc, h3, k);
+            axpy(t, y, dt, k);
+            rhs(V, s, t, k);
+            axpy(y, acc, h6, k);
+        }
+        if (!isfinite(y.Q1) || !isfinite(y.Q2) || !isfinite(y.a.r) || !isfinite(y.a.i))
+            atomicOr((unsigned long long *)status, FGA_STATUS_NUMERIC);
+        store_state(f + (size_t)FGA_F_STATE * cap + b, cap, y);
+    }
+}
+
+fga_status fga_launch_propagate(fga_ctx *ctx, fga_beams *beams, int nshots, int nsteps,
+                                double *ckpt)
+{
+    const fga_grid &g = ctx->g;
+    VelGrid V{ctx->c, g.n1, g.n2, g.o1, g.o2, 1.0 / g.d1, 1.0 / g.d2};
+    int64_t NqNp = (int64_t)ctx->p.nq1 * ctx->p.nq2 * ctx->p.np1 * ctx->p.np2;
+    // persistent grid: the beam count lives on the device
+    int blocks = ctx->num_cu * 8;
+    hipLaunchKernelGGL(k_rk4, dim3(blocks), dim3(256), 0, ctx->stream, V, beams->f, beams->id,
+                       beams->offsets, nshots, beams->capacity, NqNp, ctx->p.dt, nsteps, ckpt,
+                       ctx->status);
+    FGA_HIP(ctx, hipGetLastError());
+    return FGA_OK;
+}

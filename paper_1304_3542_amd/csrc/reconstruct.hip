@@ -1,0 +1,362 @@
+// Step 3 of the FGA algorithm on gfx950: the frozen-Gaussian sum (recons eq.)
+//   u(x) = Re sum_b C_b a_b e^{i S_b/eps} e^{i P_b.(x-Q_b)/eps - |x-Q_b|^2/(2 eps)}
+// over the nodes of each beam's truncation box.  The Gaussian and the plane
+// wave both factor over the two axes, so inside an output tile
+//   term_b(x1, x2) = U_b(x1) V_b(x2),
+//   U_b(x1) = C_b a_b e^{i(S_b + P1 r1)/eps - r1^2/(2 eps)},  r1 = x1 - Q1,
+//   V_b(x2) = e^{i P2 r2/eps - r2^2/(2 eps)},                r2 = x2 - Q2,
+// with U (V) set to zero outside the beam's box, and Re(U V) = Ur Vr - Ui Vi.
+// A workgroup owns a 64 x 64 tile and one slice of a shot's beam list: it
+// keeps the beams whose box meets the tile (order preserved), evaluates the
+// 128 factors of each into LDS and accumulates the rank-one updates in
+// registers.  Slices write private partial tiles that a second kernel adds
+// in slice order, so the result is deterministic.
+//
+// FP64 path: factors and sums in double.  Mixed path: the phase is formed
+// and reduced mod 2 pi in double, then sin/cos/exp and the sums run in FP32,
+// and every 256 beams the FP32 partial sums are folded into FP64 ones.
+#include <math.h>
+
+#include "fga_internal.h"
+
+#define SP_T 64          // tile edge (nodes)
+#define SP_KC 16         // beams per factor batch
+#define SP_CHUNK 256     // beams scanned per pass (= block size)
+
+template <typename R>
+struct Fac {
+    R re, im;
+};
+
+struct BeamBox {
+    int lo1, hi1, lo2, hi2;
+};
+
+__device__ __forceinline__ BeamBox beam_box(double Q1, double Q2, double o1, double o2,
+                                            double d1, double d2, int Rw1, int Rw2, int n1,
+                                            int n2)
+{
+    // nearest node by floor(t + 1/2); far-away centres are clamped before the
+    // integer conversion (their boxes miss the grid either way)
+    double t1 = fmin(fmax(floor((Q1 - o1) / d1 + 0.5), -1e8), 1e8);
+    double t2 = fmin(fmax(floor((Q2 - o2) / d2 + 0.5), -1e8), 1e8);
+    int c1 = (int)t1, c2 = (int)t2;
+    BeamBox b;
+    b.lo1 = max(c1 - Rw1, 0);
+    b.hi1 = min(c1 + Rw1, n1 - 1);
+    b.lo2 = max(c2 - Rw2, 0);
+    b.hi2 = min(c2 + Rw2, n2 - 1);
+    return b;
+}
+
+struct SplatArgs {
+    const double *f;
+    const int64_t *offsets;
+    int64_t cap;
+    int n1, n2;
+    double o1, o2, d1, d2;
+    double eps, inv_eps, half_inv_eps;
+    int Rw1, Rw2;
+    int nsplit, ntile1;
+    double *partial;   // [nshots][nsplit][n2][n1]
+};
+
+// factor e^{i theta + G} times coef (complex, double) in precision R
+template <typename R>
+__device__ __forceinline__ Fac<R> factor(double theta, double G, double cr, double ci);
+
+template <>
+__device__ __forceinline__ Fac<double> factor<double>(double theta, double G, double cr, double ci)
+{
+    double s, c;
+    sincos(theta, &s, &c);
+    double e = exp(G);
+    double wr = e * c, wi = e * s;
+    return {cr * wr - ci * wi, cr * wi + ci * wr};
+}
+
+template <>
+__device__ __forceinline__ Fac<float> factor<float>(double theta, double G, double cr, double ci)
+{
+    // reduce the phase to [-pi, pi] in double before the FP32 sincos
+    const double inv2pi = 0.15915494309189535, twopi = 6.283185307179586;
+    double red = fma(-twopi, rint(theta * inv2pi), theta);
+    float s, c;
+    sincosf((float)red, &s, &c);
+    float e = expf((float)G);
+    float wr = e * c, wi = e * s;
+    float fr = (float)cr, fi = (float)ci;
+    return {fr * wr - fi * wi, fr * wi + fi * wr};
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_splat(SplatArgs A)
+{
+    __shared__ int lst[SP_CHUNK];
+    __shared__ int wcnt[4];
+    __shared__ Fac<R> U[SP_KC][SP_T];
+    __shared__ Fac<R> Vf[SP_KC][SP_T];
+
+    const int t = threadIdx.x;
+    const int tx = t & 15, tz = t >> 4;
+    const int tile = blockIdx.x;
+    const int X0 = (tile % A.ntile1) * SP_T, Z0 = (tile / A.ntile1) * SP_T;
+    const int split = blockIdx.y, s = blockIdx.z;
+    const int64_t b0 = A.offsets[s], b1 = A.offsets[s + 1];
+    const int64_t nbs = b1 - b0;
+    const int64_t lo = b0 + nbs * split / A.nsplit, hi = b0 + nbs * (split + 1) / A.nsplit;
+    const int64_t cap = A.cap;
+    const double *F = A.f;
+
+    double acc[4][4];
+    R acc_r[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc[i][j] = 0.0;
+            acc_r[i][j] = (R)0;
+        }
+
+    for (int64_t base = lo; base < hi; base += SP_CHUNK) {
+        // 1. keep the beams of this chunk whose box meets the tile
+        int64_t b = base + t;
+        int hit = 0;
+        if (b < hi) {
+            double Q1 = F[(FGA_F_STATE + 0) * cap + b], Q2 = F[(FGA_F_STATE + 1) * cap + b];
+            BeamBox bx = beam_box(Q1, Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
+            hit = (bx.lo1 <= min(bx.hi1, X0 + SP_T - 1) && max(bx.lo1, X0) <= bx.hi1 &&
+                   bx.lo2 <= min(bx.hi2, Z0 + SP_T - 1) && max(bx.lo2, Z0) <= bx.hi2)
+                      ? 1
+                      : 0;
+        }
+        unsigned long long m = __ballot(hit);
+        int lane = t & 63, wv = t >> 6;
+        int before = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) wcnt[wv] = __popcll(m);
+        __syncthreads();
+        int wb = 0, nlist = 0;
+        for (int w = 0; w < 4; ++w) {
+            wb += (w < wv) ? wcnt[w] : 0;
+            nlist += wcnt[w];
+        }
+        if (hit) lst[wb + before] = t;
+        __syncthreads();
+
+        // 2. factor batches and rank-one accumulation
+        for (int k0 = 0; k0 < nlist; k0 += SP_KC) {
+            {
+                int k = t >> 4, sub = t & 15;
+                if (k0 + k < nlist) {
+                    int64_t bb = base + lst[k0 + k];
+                    const double *p = F + bb;
+                    double Q1 = p[(FGA_F_STATE + 0) * cap], Q2 = p[(FGA_F_STATE + 1) * cap];
+                    double P1 = p[(FGA_F_STATE + 2) * cap], P2 = p[(FGA_F_STATE + 3) * cap];
+                    double S = p[(FGA_F_STATE + 4) * cap];
+                    double ar = p[(FGA_F_STATE + 21) * cap], ai = p[(FGA_F_STATE + 22) * cap];
+                    double Cr = p[4 * cap], Ci = p[5 * cap];
+                    double car = Cr * ar - Ci * ai, cai = Cr * ai + Ci * ar;
+                    BeamBox bx = beam_box(Q1, Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
+#pragma unroll
+                    for (int mm = 0; mm < 4; ++mm) {
+                        int xi = sub + 16 * mm;
+                        int i1 = X0 + xi;
+                        Fac<R> v{(R)0, (R)0};
+                        if (i1 >= bx.lo1 && i1 <= bx.hi1) {
+                            double r1 = (A.o1 + i1 * A.d1) - Q1;
+                            v = factor<R>((S + P1 * r1) * A.inv_eps, -r1 * r1 * A.half_inv_eps,
+                                          car, cai);
+                        }
+                        U[k][xi] = v;
+                        int i2 = Z0 + xi;
+                        Fac<R> w{(R)0, (R)0};
+                        if (i2 >= bx.lo2 && i2 <= bx.hi2) {
+                            double r2 = (A.o2 + i2 * A.d2) - Q2;
+                            w = factor<R>(P2 * r2 * A.inv_eps, -r2 * r2 * A.half_inv_eps, 1.0, 0.0);
+                        }
+                        Vf[k][xi] = w;
+                    }
+                } else {
+#pragma unroll
+                    for (int mm = 0; mm < 4; ++mm) {
+                        U[k][sub + 16 * mm] = {(R)0, (R)0};
+                        Vf[k][sub + 16 * mm] = {(R)0, (R)0};
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int k = 0; k < SP_KC; ++k) {
+                Fac<R> u[4], v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) u[i] = U[k][tx + 16 * i];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j] = Vf[k][tz + 16 * j];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc_r[i][j] = fma(u[i].re, v[j].re, fma(-u[i].im, v[j].im, acc_r[i][j]));
+            }
+            __syncthreads();
+        }
+        // fold the working-precision sums into double once per chunk
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                acc[i][j] += (double)acc_r[i][j];
+                acc_r[i][j] = (R)0;
+            }
+    }
+
+    double *out = A.partial + ((size_t)s * A.nsplit + split) * A.n2 * (size_t)A.n1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        int i2 = Z0 + tz + 16 * j;
+        if (i2 >= A.n2) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int i1 = X0 + tx + 16 * i;
+            if (i1 < A.n1) out[(size_t)i2 * A.n1 + i1] = acc[i][j];
+        }
+    }
+}
+
+__global__ void k_splat_reduce(const double *__restrict__ partial, double *__restrict__ u,
+                               int nsplit, int64_t npts, int nshots)
+{
+    int64_t total = npts * nshots;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t s = i / npts, x = i - s * npts;
+        const double *p = partial + (size_t)s * nsplit * npts + x;
+        double v = 0.0;
+        for (int k = 0; k < nsplit; ++k) v += p[(size_t)k * npts];
+        u[i] = v;
+    }
+}
+
+fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nshots, double *u)
+{
+    const fga_grid &g = ctx->g;
+    int nt1 = (g.n1 + SP_T - 1) / SP_T, nt2 = (g.n2 + SP_T - 1) / SP_T;
+    int tiles = nt1 * nt2;
+    int want = (4 * ctx->num_cu + tiles * nshots - 1) / (tiles * nshots);
+    int nsplit = want < 1 ? 1 : (want > 64 ? 64 : want);
+    size_t npts = (size_t)g.n1 * g.n2;
+    fga_status rc = fga_ensure(ctx, (void **)&ctx->partial, &ctx->partial_bytes,
+                               (size_t)nshots * nsplit * npts * sizeof(double), "splat partials");
+    if (rc != FGA_OK) return rc;
+    SplatArgs A;
+    A.f = beams->f;
+    A.offsets = beams->offsets;
+    A.cap = beams->capacity;
+    A.n1 = g.n1;
+    A.n2 = g.n2;
+    A.o1 = g.o1;
+    A.o2 = g.o2;
+    A.d1 = g.d1;
+    A.d2 = g.d2;
+    A.eps = ctx->p.eps;
+    A.inv_eps = 1.0 / ctx->p.eps;
+    A.half_inv_eps = 0.5 / ctx->p.eps;
+    A.Rw1 = ctx->Rw1;
+    A.Rw2 = ctx->Rw2;
+    A.nsplit = nsplit;
+    A.ntile1 = nt1;
+    A.partial = ctx->partial;
+    dim3 grid(tiles, nsplit, nshots);
+    if (ctx->prec == FGA_FP64)
+        hipLaunchKernelGGL(k_splat<double>, grid, dim3(256), 0, ctx->stream, A);
+    else
+        hipLaunchKernelGGL(k_splat<float>, grid, dim3(256), 0, ctx->stream, A);
+    hipLaunchKernelGGL(k_splat_reduce, dim3(1024), dim3(256), 0, ctx->stream, ctx->partial, u,
+                       nsplit, (int64_t)npts, nshots);
+    FGA_HIP(ctx, hipGetLastError());
+    return FGA_OK;
+}
+
+// ------------------------------------------------------------------ traces
+// u at receiver nodes, one thread per (shot, receiver), beams staged in LDS.
+#define TR_BLOCK 256
+
+__global__ void __launch_bounds__(TR_BLOCK)
+k_trace_points(SplatArgs A, const int32_t *__restrict__ rec, int nrec, double *out,
+               int64_t stride_shot)
+{
+    __shared__ double sb[7][TR_BLOCK];
+    int s = blockIdx.y;
+    int r = blockIdx.x * TR_BLOCK + threadIdx.x;
+    int i1 = 0, i2 = 0;
+    if (r < nrec) {
+        int node = rec[r];
+        i1 = node % A.n1;
+        i2 = node / A.n1;
+    }
+    double x1 = A.o1 + i1 * A.d1, x2 = A.o2 + i2 * A.d2;
+    const int64_t b0 = A.offsets[s], b1 = A.offsets[s + 1];
+    const int64_t cap = A.cap;
+    double acc = 0.0;
+    for (int64_t base = b0; base < b1; base += TR_BLOCK) {
+        int64_t b = base + threadIdx.x;
+        if (b < b1) {
+            const double *p = A.f + b;
+            double ar = p[(FGA_F_STATE + 21) * cap], ai = p[(FGA_F_STATE + 22) * cap];
+            double Cr = p[4 * cap], Ci = p[5 * cap];
+            sb[0][threadIdx.x] = p[(FGA_F_STATE + 0) * cap];
+            sb[1][threadIdx.x] = p[(FGA_F_STATE + 1) * cap];
+            sb[2][threadIdx.x] = p[(FGA_F_STATE + 2) * cap];
+            sb[3][threadIdx.x] = p[(FGA_F_STATE + 3) * cap];
+            sb[4][threadIdx.x] = p[(FGA_F_STATE + 4) * cap];
+            sb[5][threadIdx.x] = Cr * ar - Ci * ai;
+            sb[6][threadIdx.x] = Cr * ai + Ci * ar;
+        }
+        __syncthreads();
+        int nb = (int)min((int64_t)TR_BLOCK, b1 - base);
+        if (r < nrec) {
+            for (int k = 0; k < nb; ++k) {
+                double Q1 = sb[0][k], Q2 = sb[1][k];
+                BeamBox bx = beam_box(Q1, Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
+                if (i1 < bx.lo1 || i1 > bx.hi1 || i2 < bx.lo2 || i2 > bx.hi2) continue;
+                double r1 = x1 - Q1, r2 = x2 - Q2;
+                double th = (sb[4][k] + sb[2][k] * r1 + sb[3][k] * r2) * A.inv_eps;
+                double G = -(r1 * r1 + r2 * r2) * A.half_inv_eps;
+                double sn, cs;
+                sincos(th, &sn, &cs);
+                double e = exp(G);
+                acc += e * (sb[5][k] * cs - sb[6][k] * sn);
+            }
+        }
+        __syncthreads();
+    }
+    if (r < nrec) out[(size_t)s * stride_shot + r] = acc;
+}
+
+fga_status fga_launch_trace_points(fga_ctx *ctx, const fga_beams *beams, int nshots,
+                                   const int32_t *rec, int nrec, double *out,
+                                   int64_t stride_shot)
+{
+    const fga_grid &g = ctx->g;
+    SplatArgs A{};
+    A.f = beams->f;
+    A.offsets = beams->offsets;
+    A.cap = beams->capacity;
+    A.n1 = g.n1;
+    A.n2 = g.n2;
+    A.o1 = g.o1;
+    A.o2 = g.o2;
+    A.d1 = g.d1;
+    A.d2 = g.d2;
+    A.eps = ctx->p.eps;
+    A.inv_eps = 1.0 / ctx->p.eps;
+    A.half_inv_eps = 0.5 / ctx->p.eps;
+    A.Rw1 = ctx->Rw1;
+    A.Rw2 = ctx->Rw2;
+    dim3 grid((nrec + TR_BLOCK - 1) / TR_BLOCK, nshots);
+    hipLaunchKernelGGL(k_trace_points, grid, dim3(TR_BLOCK), 0, ctx->stream, A, rec, nrec, out,
+                       stride_shot);
+    FGA_HIP(ctx, hipGetLastError());
+    return FGA_OK;
+}

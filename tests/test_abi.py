@@ -1,0 +1,85 @@
+"""The C-ABI library: it loads, exports every entry point that include/fga.h
+declares, and rejects invalid arguments on the host before any device work
+(these calls need no GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import fga_inputs as fi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fga.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fga_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for n in ("fga_create", "fga_destroy", "fga_set_velocity", "fga_decompose",
+              "fga_propagate", "fga_reconstruct", "fga_trace", "fga_sync_status",
+              "fga_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1304_3542_amd as fga
+    lib = fga.load()
+    for n in _declared():
+        assert hasattr(lib, n), n
+
+
+def _structs(grid, params):
+    import paper_1304_3542_amd as fga
+    g = fga.fga_grid(grid.n1, grid.n2, grid.o1, grid.o2, grid.d1, grid.d2)
+    p = fga.fga_params(params.eps, params.qb1, params.qb2, params.qs1, params.qs2, params.nq1,
+                       params.nq2, params.np1, params.np2, params.dp1, params.dp2, params.tau,
+                       params.tau_fbi, params.tau_win, params.dt)
+    return g, p
+
+
+@pytest.mark.parametrize("bad", [
+    dict(np1=7), dict(np2=0), dict(eps=0.0), dict(eps=float("nan")), dict(nq1=0),
+    dict(qs2=0), dict(qb1=-1), dict(nq1=1000), dict(tau=1.5), dict(tau_fbi=0.0),
+    dict(tau_win=1.0), dict(dt=-1e-3), dict(dp1=0.0),
+])
+def test_create_rejects_bad_params(bad):
+    import paper_1304_3542_amd as fga
+    W = fi.workload("wavepacket")
+    g, p = _structs(W.grid, W.params.replace(**bad))
+    lib = fga.load()
+    ctx = ctypes.c_void_p()
+    st = lib.fga_create(ctypes.byref(ctx), ctypes.byref(g), ctypes.byref(p), 0, 1, None)
+    assert st == fga.FGA_EINVAL
+    assert not ctx.value
+    assert lib.fga_last_error(None)
+
+
+def test_create_rejects_bad_grid_precision_and_shots():
+    import paper_1304_3542_amd as fga
+    W = fi.workload("wavepacket")
+    lib = fga.load()
+    ctx = ctypes.c_void_p()
+    for grid, prec, shots in ((fi.Grid(2, 128, 0, 0, 1, 1), 0, 1),
+                              (fi.Grid(128, 128, 0, 0, -1.0, 1), 0, 1),
+                              (W.grid, 7, 1), (W.grid, 0, 0)):
+        g, p = _structs(grid, W.params)
+        st = lib.fga_create(ctypes.byref(ctx), ctypes.byref(g), ctypes.byref(p), prec, shots,
+                            None)
+        assert st == fga.FGA_EINVAL
+    assert lib.fga_create(None, None, None, 0, 1, None) == fga.FGA_EINVAL
+
+
+def test_null_context_calls_fail_cleanly():
+    import paper_1304_3542_amd as fga
+    lib = fga.load()
+    assert lib.fga_destroy(None) == fga.FGA_OK
+    assert lib.fga_set_velocity(None, None) == fga.FGA_EINVAL
+    assert lib.fga_decompose(None, 1, None, None, None) == fga.FGA_EINVAL
+    assert lib.fga_propagate(None, None, 1, 1) == fga.FGA_EINVAL
+    assert lib.fga_reconstruct(None, None, 1, None) == fga.FGA_EINVAL
+    assert lib.fga_sync_status(None, None) == fga.FGA_EINVAL

@@ -1,0 +1,140 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle on the
+same seeded inputs.  FP64 path: rel-L2 <= 1e-10; mixed path: <= 1e-5."""
+import numpy as np
+import pytest
+
+import fga_inputs as fi
+import oracle
+from gpu_helpers import gpu_run, mixed_params, pairwise_state_err, rel_l2, small_case
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def small():
+    g, p, c, f0, f1 = small_case()
+    b = oracle.decompose(f0, f1, c, g, p)
+    b0 = oracle.Beams(b.shot, b.sigma, b.cand, b.psi, b.coef.copy(), b.state.copy(), b.offsets)
+    oracle.propagate(b, c, g, p.dt, p.nsteps)
+    u = oracle.reconstruct(b, g, p, shot=0)
+    return dict(g=g, p=p, c=c, f0=f0, f1=f1, b0=b0, b=b, u=u)
+
+
+def test_decompose_fp64_matches_oracle(small):
+    g, p = small["g"], small["p"]
+    r = gpu_run(g, p, small["c"], small["f0"], small["f1"], "fp64", nsteps=0, want_u=False)
+    assert r["status"] == 0
+    b0 = small["b0"]
+    np.testing.assert_array_equal(r["offsets"], b0.offsets)
+    np.testing.assert_array_equal(r["id0"], b0.cand)
+    coef = r["f0"][4] + 1j * r["f0"][5]
+    ref = b0.coef[:, 0] + 1j * b0.coef[:, 1]
+    assert np.abs(coef - ref).max() <= FP64_TOL * np.abs(ref).max()
+    np.testing.assert_allclose(r["f0"][0:4].T, b0.state[:, 0:4], rtol=0, atol=1e-14)
+    np.testing.assert_array_equal(r["f0"][6:].T, b0.state)
+
+
+def test_propagate_and_reconstruct_fp64_match_oracle(small):
+    g, p = small["g"], small["p"]
+    r = gpu_run(g, p, small["c"], small["f0"], small["f1"], "fp64")
+    assert r["status"] == 0 and r["status_end"][0] == 0
+    np.testing.assert_array_equal(r["id0"], small["b"].cand)
+    assert pairwise_state_err(r["fT"][6:].T, small["b"].state) <= FP64_TOL
+    assert rel_l2(r["u"][0], small["u"]) <= FP64_TOL
+
+
+def test_mixed_path_within_1e5(small):
+    g, p = small["g"], small["p"]
+    r = gpu_run(g, mixed_params(p), small["c"], small["f0"], small["f1"], "mixed")
+    assert r["status"] == 0
+    assert rel_l2(r["u"][0], small["u"]) <= MIXED_TOL
+
+
+def test_multishot_offsets_and_fields():
+    g, p, c, f0, _ = small_case(seed=22, nshots=3, with_f1=False)
+    p = p.replace(nsteps=20)
+    b = oracle.decompose(f0, None, c, g, p)
+    oracle.propagate(b, c, g, p.dt, p.nsteps)
+    r = gpu_run(g, p, c, f0, None, "fp64")
+    assert r["status"] == 0
+    np.testing.assert_array_equal(r["offsets"], b.offsets)
+    np.testing.assert_array_equal(r["id0"], b.cand)
+    for s in range(3):
+        u = oracle.reconstruct(b, g, p, shot=s)
+        assert rel_l2(r["u"][s], u) <= FP64_TOL
+
+
+def test_zero_input_gives_no_beams():
+    g, p, c, f0, f1 = small_case()
+    r = gpu_run(g, p, c, np.zeros_like(f0), None, "fp64", nsteps=3)
+    assert r["status"] == 0
+    assert r["offsets"].tolist() == [0, 0]
+    assert np.all(r["u"] == 0.0)
+
+
+def test_capacity_overflow_reports_needed_count(small):
+    import paper_1304_3542_amd as fga
+    g, p = small["g"], small["p"]
+    nb = int(small["b0"].offsets[-1])
+    r = gpu_run(g, p, small["c"], small["f0"], small["f1"], "fp64", capacity=nb // 3,
+                nsteps=2)
+    assert r["status"] == fga.FGA_ECAPACITY
+    assert r["needed"] == nb
+    assert r["offsets"][-1] == nb // 3
+    np.testing.assert_array_equal(r["id0"], small["b0"].cand[: nb // 3])
+
+
+def test_tau_one_keeps_the_maximum(small):
+    g, p = small["g"], small["p"].replace(tau=1.0)
+    b = oracle.decompose(small["f0"], small["f1"], small["c"], g, p)
+    r = gpu_run(g, p, small["c"], small["f0"], small["f1"], "fp64", nsteps=0, want_u=False)
+    assert 1 <= r["offsets"][-1] <= 2
+    np.testing.assert_array_equal(r["id0"], b.cand)
+
+
+def test_bad_velocity_sets_numeric_status():
+    import torch
+    import paper_1304_3542_amd as fga
+    g, p, c, f0, f1 = small_case()
+    c = c.copy()
+    c[10, 10] = -1.0
+    ctx = fga.FGA(g, p, "fp64")
+    ctx.set_velocity(torch.from_numpy(c).cuda())
+    st, _ = ctx.status()
+    assert st == fga.FGA_ENUMERIC
+    st, _ = ctx.status()          # the status word is cleared by the read
+    assert st == fga.FGA_OK
+
+
+def test_invalid_arguments_rejected_on_host():
+    import torch
+    import paper_1304_3542_amd as fga
+    g, p, c, f0, f1 = small_case()
+    with pytest.raises(fga.FGAError) as e:
+        fga.FGA(g, p.replace(np1=11), "fp64")
+    assert e.value.status == fga.FGA_EINVAL
+    ctx = fga.FGA(g, p, "fp64")
+    beams = fga.Beams(16, 1)
+    with pytest.raises(fga.FGAError) as e:     # no velocity yet
+        ctx.decompose(torch.zeros((1,) + g.shape, dtype=torch.float64, device="cuda"), None,
+                      beams)
+    assert e.value.status == fga.FGA_ESTATE
+
+
+def test_trace_matches_oracle():
+    import torch
+    import paper_1304_3542_amd as fga
+    g, p, c, f0, _ = small_case(seed=23, nshots=2, with_f1=False)
+    rec = np.arange(0, g.n1 * 3, 2, dtype=np.int32)        # rows 0..2, every other node
+    b = oracle.decompose(f0, None, c, g, p)
+    tr_or = oracle.trace(b, c, g, p, rec, rec_every=5, nrec=4)
+    ctx = fga.FGA(g, p, "fp64", max_shots=2)
+    ctx.set_velocity(torch.from_numpy(c).cuda())
+    beams = fga.Beams(int(b.offsets[-1]) + 10, 2)
+    ctx.decompose(torch.from_numpy(f0).cuda(), None, beams)
+    tr = ctx.trace(beams, 2, torch.from_numpy(rec).cuda(), 5, 4).cpu().numpy()
+    assert ctx.status()[0] == 0
+    assert rel_l2(tr, tr_or) <= FP64_TOL
