@@ -141,7 +141,7 @@ def cpu_baseline(W, nbeams, budget_s):
     psi = oracle.fbi(W.f0[0], g, qs)
     t_fbi = (time.perf_counter() - t) / 2 * nq
     # beams: the largest |psi| of the sampled q nodes, both branches
-    nsb = 256
+    nsb = 1024
     order = np.argsort(-np.abs(psi.ravel()))[:nsb // 2]
     j2, j1, l2, l1 = np.unravel_index(order, psi.shape)
     k1, k2 = oracle.qnodes(qs)

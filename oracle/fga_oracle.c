@@ -282,7 +282,7 @@ void or_propagate(const double *c, int n1, int n2, double o1, double o2,
                   double *state, double dt, int nsteps)
 {
     vel_t v = {c, n1, n2, o1, o2, d1, d2};
-#pragma omp parallel for schedule(dynamic, 64)
+#pragma omp parallel for schedule(dynamic, 4)
     for (int64_t b = 0; b < nb; ++b) {
         double *y = state + (size_t)b * NSTATE;
         double s = (double)sigma[b];

@@ -110,6 +110,9 @@ extern "C" fga_status fga_create(fga_ctx **out, const fga_grid *g, const fga_par
     hipError_t e = hipGetDevice(&ctx->dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, ctx->dev);
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->c, sizeof(double) * g->n1 * g->n2);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&ctx->cpad, sizeof(double) * (g->n1 + 2 * FGA_VPAD) *
+                                               (g->n2 + 2 * FGA_VPAD));
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->status, 2 * sizeof(int64_t));
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->cq, sizeof(double) * p->nq1 * p->nq2);
     if (e == hipSuccess)
@@ -129,7 +132,7 @@ extern "C" fga_status fga_destroy(fga_ctx *ctx)
 {
     if (!ctx) return FGA_OK;
     (void)hipStreamSynchronize(ctx->stream);
-    void *bufs[] = {ctx->c, ctx->status, ctx->cq, ctx->maxbits, ctx->E1t, ctx->E2,
+    void *bufs[] = {ctx->c, ctx->cpad, ctx->status, ctx->cq, ctx->maxbits, ctx->E1t, ctx->E2,
                     ctx->T, ctx->Psi, ctx->blk, ctx->partial};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -144,12 +147,19 @@ extern "C" fga_status fga_set_stream(fga_ctx *ctx, void *stream)
     return FGA_OK;
 }
 
-__global__ void k_check_velocity(const double *c, int64_t n, int64_t *status)
+// Checks c > 0 and finite, and writes the padded copy (edge values
+// replicated into the halo, i.e. clamped indices).
+__global__ void k_pad_velocity(const double *c, int n1, int n2, double *cpad, int64_t *status)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        double v = c[i];
+    int ld = n1 + 2 * FGA_VPAD, rows = n2 + 2 * FGA_VPAD;
+    int64_t n = (int64_t)ld * rows;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int r = (int)(i / ld), q = (int)(i % ld);
+        int i2 = min(max(r - FGA_VPAD, 0), n2 - 1), i1 = min(max(q - FGA_VPAD, 0), n1 - 1);
+        double v = c[(size_t)i2 * n1 + i1];
         if (!(v > 0.0) || !isfinite(v)) atomicOr((unsigned long long *)status, FGA_STATUS_NUMERIC);
+        cpad[i] = v;
     }
 }
 
@@ -159,8 +169,8 @@ extern "C" fga_status fga_set_velocity(fga_ctx *ctx, const double *c_dev)
     size_t n = (size_t)ctx->g.n1 * ctx->g.n2;
     FGA_HIP(ctx, hipMemcpyAsync(ctx->c, c_dev, n * sizeof(double), hipMemcpyDeviceToDevice,
                                 ctx->stream));
-    hipLaunchKernelGGL(k_check_velocity, dim3(256), dim3(256), 0, ctx->stream, ctx->c,
-                       (int64_t)n, ctx->status);
+    hipLaunchKernelGGL(k_pad_velocity, dim3(256), dim3(256), 0, ctx->stream, ctx->c,
+                       ctx->g.n1, ctx->g.n2, ctx->cpad, ctx->status);
     FGA_HIP(ctx, hipGetLastError());
     ctx->have_c = true;
     return FGA_OK;

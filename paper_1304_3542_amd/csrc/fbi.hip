@@ -52,14 +52,12 @@ __global__ void k_tables(cplx<R> *E1t, cplx<R> *E2, int R1, int R2, int np1, int
     }
 }
 
-__global__ void k_cq(const double *c, int n1, int n2, double o1, double o2, double d1,
-                     double d2, int qb1, int qb2, int qs1, int qs2, int nq1, int nq2,
-                     double *cq)
+__global__ void k_cq(VelGrid V, double o1, double o2, double d1, double d2, int qb1, int qb2,
+                     int qs1, int qs2, int nq1, int nq2, double *cq)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nq1 * nq2) return;
     int j1 = i % nq1, j2 = i / nq1;
-    VelGrid V{c, n1, n2, o1, o2, 1.0 / d1, 1.0 / d2};
     double x1 = o1 + (qb1 + j1 * qs1) * d1, x2 = o2 + (qb2 + j2 * qs2) * d2;
     double cv, c1, c2, c11, c12, c22;
     vel_eval(V, x1, x2, cv, c1, c2, c11, c12, c22);
@@ -465,7 +463,7 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
         FGA_HIP(ctx, hipGetLastError());
     }
     int nq = p.nq1 * p.nq2;
-    hipLaunchKernelGGL(k_cq, dim3((nq + 255) / 256), dim3(256), 0, st, ctx->c, g.n1, g.n2, g.o1,
+    hipLaunchKernelGGL(k_cq, dim3((nq + 255) / 256), dim3(256), 0, st, fga_velgrid(ctx), g.o1,
                        g.o2, g.d1, g.d2, p.qb1, p.qb2, p.qs1, p.qs2, p.nq1, p.nq2, ctx->cq);
     hipLaunchKernelGGL(k_fbi_pass1<R>, dim3(g.n2, S), dim3(256), 0, st, f0, f1, nfj,
                        (const cplx<R> *)ctx->E1t, (cplx<R> *)ctx->T, g.n1, g.n2, ctx->R1, p.qb1,

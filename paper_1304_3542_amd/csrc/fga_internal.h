@@ -25,6 +25,7 @@ struct fga_ctx {
     double norm;           // w / (2 pi eps)^3
 
     double *c;             // velocity samples [n2][n1]
+    double *cpad;          // the same with a replicated halo of FGA_VPAD cells
     bool have_c;
 
     // FBI workspaces
@@ -78,9 +79,15 @@ static inline int fga_halfwidth(double eps, double tau, double d)
 // Device helpers
 // ---------------------------------------------------------------------------
 
+// The velocity samples are stored with a halo of FGA_VPAD replicated edge
+// values on every side, so the four B-spline knots of any point whose knot
+// index is first clamped to [-4, n + 4] are in range without per-tap
+// clamping, and taps of one row are consecutive doubles.
+#define FGA_VPAD 6
+
 struct VelGrid {
-    const double *c;
-    int n1, n2;
+    const double *c;   // padded samples, row length ld, origin at [FGA_VPAD][FGA_VPAD]
+    int n1, n2, ld;
     double o1, o2, inv_d1, inv_d2;
 };
 
@@ -113,21 +120,19 @@ __device__ __forceinline__ void vel_eval(const VelGrid &V, double x1, double x2,
     double t2 = (x2 - V.o2) * V.inv_d2;
     double fl1 = floor(t1), fl2 = floor(t2);
     double f1 = t1 - fl1, f2 = t2 - fl2;
-    // clamp the knot index so that far-away points stay representable
-    int i1 = (int)fmin(fmax(fl1, -4.0), (double)V.n1 + 4.0);
-    int i2 = (int)fmin(fmax(fl2, -4.0), (double)V.n2 + 4.0);
+    // four or more cells outside the grid every knot reads the edge value, so
+    // clamping the knot index to [-4, n + 3] keeps the taps inside the halo
+    int i1 = (int)fmin(fmax(fl1, -4.0), (double)V.n1 + 3.0);
+    int i2 = (int)fmin(fmax(fl2, -4.0), (double)V.n2 + 3.0);
     double wx[4], dwx[4], ddwx[4], wz[4], dwz[4], ddwz[4];
     bspline_w(f1, wx, dwx, ddwx);
     bspline_w(f2, wz, dwz, ddwz);
-    int k1[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) k1[k] = min(max(i1 - 1 + k, 0), V.n1 - 1);
+    const double *base = V.c + (size_t)(i2 - 1 + FGA_VPAD) * V.ld + (i1 - 1 + FGA_VPAD);
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
 #pragma unroll
     for (int kz = 0; kz < 4; ++kz) {
-        int r = min(max(i2 - 1 + kz, 0), V.n2 - 1);
-        const double *row = V.c + (size_t)r * V.n1;
-        double v0 = row[k1[0]], v1 = row[k1[1]], v2 = row[k1[2]], v3 = row[k1[3]];
+        const double *row = base + kz * V.ld;
+        double v0 = row[0], v1 = row[1], v2 = row[2], v3 = row[3];
         double a0 = wx[0] * v0 + wx[1] * v1 + wx[2] * v2 + wx[3] * v3;
         double a1 = dwx[0] * v0 + dwx[1] * v1 + dwx[2] * v2 + dwx[3] * v3;
         double a2 = ddwx[0] * v0 + ddwx[1] * v1 + ddwx[2] * v2 + ddwx[3] * v3;
@@ -144,4 +149,18 @@ __device__ __forceinline__ void vel_eval(const VelGrid &V, double x1, double x2,
     c11 = s3 * V.inv_d1 * V.inv_d1;
     c12 = s4 * V.inv_d1 * V.inv_d2;
     c22 = s5 * V.inv_d2 * V.inv_d2;
+}
+
+static inline VelGrid fga_velgrid(const fga_ctx *ctx)
+{
+    VelGrid V;
+    V.c = ctx->cpad;
+    V.n1 = ctx->g.n1;
+    V.n2 = ctx->g.n2;
+    V.ld = ctx->g.n1 + 2 * FGA_VPAD;
+    V.o1 = ctx->g.o1;
+    V.o2 = ctx->g.o2;
+    V.inv_d1 = 1.0 / ctx->g.d1;
+    V.inv_d2 = 1.0 / ctx->g.d2;
+    return V;
 }

@@ -49,6 +49,16 @@ __device__ __forceinline__ void axpy(St &o, const St &y, double h, const St &k)
     o.a.i = fma(h, k.a.i, y.a.i);
 }
 
+// Reciprocal and inverse square root: hardware estimate refined by Newton
+// steps to full double precision.
+__device__ __forceinline__ double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
 // Right-hand side.  With n = |P|, u = P/n, g = grad c, K = Hess c:
 //   H_P = s c u, H_Q = s n g, H_PP = s (c/n)(I - u u^T), H_QQ = s n K,
 //   H_QP = s g u^T, H_PQ = s u g^T, so the dynamic ray tracing equations
@@ -61,8 +71,9 @@ __device__ __forceinline__ void rhs(const VelGrid &V, double s, const St &y, St 
 {
     double c, g1, g2, K11, K12, K22;
     vel_eval(V, y.Q1, y.Q2, c, g1, g2, K11, K12, K22);
-    double n = sqrt(y.P1 * y.P1 + y.P2 * y.P2);
-    double inv_n = 1.0 / n;
+    double n2 = y.P1 * y.P1 + y.P2 * y.P2;
+    double n = sqrt(n2);
+    double inv_n = rcp64(n);
     double u1 = y.P1 * inv_n, u2 = y.P2 * inv_n;
     double sc = s * c;
     double HP1 = sc * u1, HP2 = sc * u2;
@@ -96,7 +107,7 @@ __device__ __forceinline__ void rhs(const VelGrid &V, double s, const St &y, St 
     Cd det = csub(cmul(Z[0][0], Z[1][1]), cmul(Z[0][1], Z[1][0]));
     Cd num = csub(cadd(cmul(Z[1][1], dZ[0][0]), cmul(Z[0][0], dZ[1][1])),
                   cadd(cmul(Z[0][1], dZ[1][0]), cmul(Z[1][0], dZ[0][1])));
-    double id2 = 1.0 / (det.r * det.r + det.i * det.i);
+    double id2 = rcp64(det.r * det.r + det.i * det.i);
     Cd tr = cscale(cmul(num, Cd{det.r, -det.i}), id2);
     Cd fac = {s * (u1 * g1 + u2 * g2) + 0.5 * tr.r, 0.5 * tr.i};
     k.a = cmul(y.a, fac);
@@ -143,32 +154,115 @@ __device__ __forceinline__ void store_state(double *p, int64_t cap, const St &y)
     p[22 * cap] = y.a.i;
 }
 
-__global__ void __launch_bounds__(256)
+#define RK_BLOCK 256
+
+// One RK4 stage fused with its use: k = f(t), acc += wacc k, and unless this
+// is the last stage t = y + hnext k.  Each slope component is consumed as
+// soon as it is produced, so only y, acc and t stay live across the stage.
+// The amplitude needs Z = A + iB of the stage input and dZ = k_A + i k_B:
+// det Z is formed first, row 0 of Z is kept aside before row 0 of t is
+// overwritten, and the adjugate trace is accumulated row by row.
+template <bool LAST>
+__device__ __forceinline__ void stage(const VelGrid &V, double s, St &t, St &acc, const St &y,
+                                      double wacc, double hnext)
+{
+    double c, g1, g2, K11, K12, K22;
+    vel_eval(V, t.Q1, t.Q2, c, g1, g2, K11, K12, K22);
+    double n = sqrt(t.P1 * t.P1 + t.P2 * t.P2);
+    double inv_n = rcp64(n);
+    double u1 = t.P1 * inv_n, u2 = t.P2 * inv_n;
+    double sc = s * c;
+    double con = c * inv_n;
+    double ug = s * (u1 * g1 + u2 * g2);   // (H_P . H_Q) / H
+    {
+        double kQ1 = sc * u1, kQ2 = sc * u2;
+        double kP1 = -s * n * g1, kP2 = -s * n * g2;
+        double kS = t.P1 * kQ1 + t.P2 * kQ2 - sc * n;
+        acc.Q1 = fma(wacc, kQ1, acc.Q1);
+        acc.Q2 = fma(wacc, kQ2, acc.Q2);
+        acc.P1 = fma(wacc, kP1, acc.P1);
+        acc.P2 = fma(wacc, kP2, acc.P2);
+        acc.S = fma(wacc, kS, acc.S);
+        if (!LAST) {
+            t.Q1 = fma(hnext, kQ1, y.Q1);
+            t.Q2 = fma(hnext, kQ2, y.Q2);
+            t.P1 = fma(hnext, kP1, y.P1);
+            t.P2 = fma(hnext, kP2, y.P2);
+            t.S = fma(hnext, kS, y.S);
+        }
+    }
+    Cd Z0[2] = {{t.A[0][0].r - t.B[0][0].i, t.A[0][0].i + t.B[0][0].r},
+                {t.A[0][1].r - t.B[0][1].i, t.A[0][1].i + t.B[0][1].r}};
+    Cd Z1[2] = {{t.A[1][0].r - t.B[1][0].i, t.A[1][0].i + t.B[1][0].r},
+                {t.A[1][1].r - t.B[1][1].i, t.A[1][1].i + t.B[1][1].r}};
+    Cd det = csub(cmul(Z0[0], Z1[1]), cmul(Z0[1], Z1[0]));
+    Cd num = {0.0, 0.0};
+    // sign-folded coefficients of the rank-one updates
+    double su1 = s * u1, su2 = s * u2, scon = s * con;
+    double nK11 = -s * n * K11, nK12 = -s * n * K12, nK22 = -s * n * K22;
+    double mg1 = -s * g1, mg2 = -s * g2;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        Cd Ag = {fma(t.A[j][0].r, g1, t.A[j][1].r * g2), fma(t.A[j][0].i, g1, t.A[j][1].i * g2)};
+        Cd Bu = {fma(t.B[j][0].r, u1, t.B[j][1].r * u2), fma(t.B[j][0].i, u1, t.B[j][1].i * u2)};
+        Cd m = {fma(-con, Bu.r, Ag.r), fma(-con, Bu.i, Ag.i)};
+        Cd kA0 = {fma(m.r, su1, scon * t.B[j][0].r), fma(m.i, su1, scon * t.B[j][0].i)};
+        Cd kA1 = {fma(m.r, su2, scon * t.B[j][1].r), fma(m.i, su2, scon * t.B[j][1].i)};
+        Cd kB0 = {fma(t.A[j][0].r, nK11, fma(t.A[j][1].r, nK12, Bu.r * mg1)),
+                  fma(t.A[j][0].i, nK11, fma(t.A[j][1].i, nK12, Bu.i * mg1))};
+        Cd kB1 = {fma(t.A[j][0].r, nK12, fma(t.A[j][1].r, nK22, Bu.r * mg2)),
+                  fma(t.A[j][0].i, nK12, fma(t.A[j][1].i, nK22, Bu.i * mg2))};
+        Cd dZ0 = {kA0.r - kB0.i, kA0.i + kB0.r};
+        Cd dZ1 = {kA1.r - kB1.i, kA1.i + kB1.r};
+        // adjugate trace: row 0 pairs with (Z22, -Z21), row 1 with (-Z12, Z11)
+        if (j == 0)
+            num = cadd(num, csub(cmul(Z1[1], dZ0), cmul(Z1[0], dZ1)));
+        else
+            num = cadd(num, csub(cmul(Z0[0], dZ1), cmul(Z0[1], dZ0)));
+        acc.A[j][0] = {fma(wacc, kA0.r, acc.A[j][0].r), fma(wacc, kA0.i, acc.A[j][0].i)};
+        acc.A[j][1] = {fma(wacc, kA1.r, acc.A[j][1].r), fma(wacc, kA1.i, acc.A[j][1].i)};
+        acc.B[j][0] = {fma(wacc, kB0.r, acc.B[j][0].r), fma(wacc, kB0.i, acc.B[j][0].i)};
+        acc.B[j][1] = {fma(wacc, kB1.r, acc.B[j][1].r), fma(wacc, kB1.i, acc.B[j][1].i)};
+        if (!LAST) {
+            t.A[j][0] = {fma(hnext, kA0.r, y.A[j][0].r), fma(hnext, kA0.i, y.A[j][0].i)};
+            t.A[j][1] = {fma(hnext, kA1.r, y.A[j][1].r), fma(hnext, kA1.i, y.A[j][1].i)};
+            t.B[j][0] = {fma(hnext, kB0.r, y.B[j][0].r), fma(hnext, kB0.i, y.B[j][0].i)};
+            t.B[j][1] = {fma(hnext, kB1.r, y.B[j][1].r), fma(hnext, kB1.i, y.B[j][1].i)};
+        }
+    }
+    double id2 = rcp64(det.r * det.r + det.i * det.i);
+    Cd tr = cscale(cmul(num, Cd{det.r, -det.i}), id2);
+    Cd ka = cmul(t.a, Cd{ug + 0.5 * tr.r, 0.5 * tr.i});
+    acc.a = {fma(wacc, ka.r, acc.a.r), fma(wacc, ka.i, acc.a.i)};
+    if (!LAST) t.a = {fma(hnext, ka.r, y.a.r), fma(hnext, ka.i, y.a.i)};
+}
+
+// One workgroup thread per beam; the state at the start of the step lives
+// in LDS (it is read three times per step), the RK4 accumulator, the stage
+// input and the slope live in VGPRs.
+__global__ void __launch_bounds__(RK_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
       const int64_t *__restrict__ offsets, int nshots, int64_t cap, int64_t NqNp, double dt,
       int nsteps, double *__restrict__ ckpt, int64_t *status)
 {
+    const int tid = threadIdx.x;
     int64_t nb = offsets[nshots];
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
-         b += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t b0 = (int64_t)blockIdx.x * RK_BLOCK; b0 < nb;
+         b0 += (int64_t)gridDim.x * RK_BLOCK) {
+        int64_t b = b0 + tid;
+        if (b >= nb) continue;
         St y;
         load_state(f, cap, b, y);
         if (ckpt) store_state(ckpt + b, cap, y);
         double s = ((id[b] / NqNp) & 1) ? -1.0 : 1.0;
         double h2 = 0.5 * dt, h6 = dt / 6.0, h3 = dt / 3.0;
         for (int it = 0; it < nsteps; ++it) {
-            St k, t, acc;
-            rhs(V, s, y, k);
-            axpy(acc, y, h6, k);
-            axpy(t, y, h2, k);
-            rhs(V, s, t, k);
-            axpy(acc, acc, h3, k);
-            axpy(t, y, h2, k);
-            rhs(V, s, t, k);
-            axpy(acc, acc, h3, k);
-            axpy(t, y, dt, k);
-            rhs(V, s, t, k);
-            axpy(y, acc, h6, k);
+            St t = y, acc = y;
+            stage<false>(V, s, t, acc, y, h6, h2);
+            stage<false>(V, s, t, acc, y, h3, h2);
+            stage<false>(V, s, t, acc, y, h3, dt);
+            stage<true>(V, s, t, acc, y, h6, 0.0);
+            y = acc;
         }
         if (!isfinite(y.Q1) || !isfinite(y.Q2) || !isfinite(y.a.r) || !isfinite(y.a.i))
             atomicOr((unsigned long long *)status, FGA_STATUS_NUMERIC);
@@ -179,8 +273,7 @@ k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
 fga_status fga_launch_propagate(fga_ctx *ctx, fga_beams *beams, int nshots, int nsteps,
                                 double *ckpt)
 {
-    const fga_grid &g = ctx->g;
-    VelGrid V{ctx->c, g.n1, g.n2, g.o1, g.o2, 1.0 / g.d1, 1.0 / g.d2};
+    VelGrid V = fga_velgrid(ctx);
     int64_t NqNp = (int64_t)ctx->p.nq1 * ctx->p.nq2 * ctx->p.np1 * ctx->p.np2;
     // persistent grid: the beam count lives on the device
     int blocks = ctx->num_cu * 8;
