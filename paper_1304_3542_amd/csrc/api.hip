@@ -133,7 +133,7 @@ extern "C" fga_status fga_destroy(fga_ctx *ctx)
     if (!ctx) return FGA_OK;
     (void)hipStreamSynchronize(ctx->stream);
     void *bufs[] = {ctx->c, ctx->cpad, ctx->status, ctx->cq, ctx->maxbits, ctx->E1t, ctx->E2,
-                    ctx->T, ctx->Psi, ctx->blk, ctx->partial};
+                    ctx->T, ctx->Psi, ctx->blk, ctx->partial, ctx->srec, ctx->sbox};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     free(ctx);

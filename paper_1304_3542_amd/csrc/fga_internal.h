@@ -39,9 +39,11 @@ struct fga_ctx {
     int64_t *blk;          // per-block counts / offsets of the compaction
     size_t blk_elems;
 
-    // reconstruction workspace: per-split partial sums
+    // reconstruction workspaces: per-split partial sums, per-beam records
     double *partial;
     size_t partial_bytes;
+    void *srec, *sbox;
+    size_t srec_bytes, sbox_bytes;
 
     // sticky device status: [0] flags, [1] needed capacity
     int64_t *status;

@@ -224,6 +224,227 @@ k_splat(SplatArgs A)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Mixed-precision splat on the matrix cores.
+//
+// One wavefront owns a 64 x 64 output tile and one slice of a shot's beams.
+// Per beam, lane l evaluates V at x2 = Z0 + l and U at x1 = X0 + l (phase in
+// FP64 revolutions reduced to [-1/2, 1/2], then the hardware FP32 sin, cos
+// and exp2), so every factor is computed once and never leaves registers.
+// Re(U V) = Vr Ur + Vi (-Ui) is a K = 2 product per beam:
+//   A (32 x 2, rows = x2):  A[i][0] = Vr(i), A[i][1] = Vi(i)
+//   B (2 x 32, cols = x1):  B[0][j] = Ur(j), B[1][j] = -Ui(j)
+// With v_mfma_f32_32x32x2f32 lane l holds A[l % 32][l / 32] and
+// B[l / 32][l % 32]; the halves of the wave swap their factors once
+// (xor 32) to build the two 32-row and two 32-column fragments.  Four MFMAs
+// per beam cover the tile; the FP32 accumulators are folded into FP64 ones
+// after every 64 candidate beams.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// Per-beam record of the mixed splat, formed once per reconstruction:
+// phases in revolutions as affine functions of the node coordinate,
+//   theta1(x1) = (S + P1 (x1 - Q1)) / (2 pi eps) = A1 + B1 x1,
+//   theta2(x2) = P2 (x2 - Q2) / (2 pi eps)       = A2 + B2 x2,
+// the Gaussian centre, C a in FP32 and the truncation box.  64 bytes, read
+// with one scalar load per beam.
+struct __align__(64) SplatRec {
+    double A1, B1, A2, B2, Q1, Q2;
+    float car, cai;
+    short lo1, hi1, lo2, hi2;
+};
+
+__global__ void __launch_bounds__(256)
+k_splat_prep(SplatArgs A, int nshots, SplatRec *__restrict__ rec, short4 *__restrict__ box)
+{
+    const int64_t nb = A.offsets[nshots];
+    const int64_t cap = A.cap;
+    const double inv2pe = A.inv_eps * 0.15915494309189535;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        const double *p = A.f + b;
+        double Q1 = p[(FGA_F_STATE + 0) * cap], Q2 = p[(FGA_F_STATE + 1) * cap];
+        double P1 = p[(FGA_F_STATE + 2) * cap], P2 = p[(FGA_F_STATE + 3) * cap];
+        double S = p[(FGA_F_STATE + 4) * cap];
+        double ar = p[(FGA_F_STATE + 21) * cap], ai = p[(FGA_F_STATE + 22) * cap];
+        double Cr = p[4 * cap], Ci = p[5 * cap];
+        BeamBox bx = beam_box(Q1, Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
+        SplatRec r;
+        r.B1 = P1 * inv2pe;
+        r.A1 = (S - P1 * Q1) * inv2pe;
+        r.B2 = P2 * inv2pe;
+        r.A2 = -P2 * Q2 * inv2pe;
+        r.Q1 = Q1;
+        r.Q2 = Q2;
+        r.car = (float)(Cr * ar - Ci * ai);
+        r.cai = (float)(Cr * ai + Ci * ar);
+        // empty boxes stay empty after narrowing (lo > hi)
+        r.lo1 = (short)min(bx.lo1, A.n1);
+        r.hi1 = (short)max(bx.hi1, -1);
+        r.lo2 = (short)min(bx.lo2, A.n2);
+        r.hi2 = (short)max(bx.hi2, -1);
+        rec[b] = r;
+        box[b] = make_short4(r.lo1, r.hi1, r.lo2, r.hi2);
+    }
+}
+
+struct Frags {
+    float a0, a1, b0, b1;
+};
+
+// Factors of one beam at this lane's x1 and x2 and the MFMA fragments:
+// v_permlane32_swap(x, y) exchanges the upper half of x with the lower half
+// of y, which turns (Vr, Vi) into the fragments of the two 32-row blocks and
+// (Ur, -Ui) into those of the two 32-column blocks.
+__device__ __forceinline__ Frags beam_frags(const SplatRec &r, int i1, int i2, double x1,
+                                            double x2, float hl2e)
+{
+    float ur = 0.f, nui = 0.f, vr = 0.f, vi = 0.f;
+    if (i1 >= r.lo1 && i1 <= r.hi1) {
+        double t = fma(r.B1, x1, r.A1);
+        float th = (float)(t - rint(t));
+        float rf = (float)(x1 - r.Q1);
+        float e = __builtin_amdgcn_exp2f(-rf * rf * hl2e);
+        float sn = __builtin_amdgcn_sinf(th), cs = __builtin_amdgcn_cosf(th);
+        ur = e * (r.car * cs - r.cai * sn);
+        nui = -e * (r.car * sn + r.cai * cs);
+    }
+    if (i2 >= r.lo2 && i2 <= r.hi2) {
+        double t = fma(r.B2, x2, r.A2);
+        float th = (float)(t - rint(t));
+        float rf = (float)(x2 - r.Q2);
+        float e = __builtin_amdgcn_exp2f(-rf * rf * hl2e);
+        vr = e * __builtin_amdgcn_cosf(th);
+        vi = e * __builtin_amdgcn_sinf(th);
+    }
+    auto va = __builtin_amdgcn_permlane32_swap(__float_as_uint(vr), __float_as_uint(vi), false,
+                                               false);
+    auto ub = __builtin_amdgcn_permlane32_swap(__float_as_uint(ur), __float_as_uint(nui), false,
+                                               false);
+    return {__uint_as_float(va[0]), __uint_as_float(va[1]), __uint_as_float(ub[0]),
+            __uint_as_float(ub[1])};
+}
+
+// rank-one update of the 64 x 64 tile; 32 x 32 blocks that the beam's box
+// misses are skipped (the test is uniform across the wavefront)
+__device__ __forceinline__ void tile_update(const Frags &fr, const SplatRec &r, int X0, int Z0,
+                                            floatx16 &acc00, floatx16 &acc01, floatx16 &acc10,
+                                            floatx16 &acc11)
+{
+    // the record is the same in every lane: make the box scalar so that the
+    // block tests are scalar branches
+    const int lo1 = __builtin_amdgcn_readfirstlane(r.lo1), hi1 = __builtin_amdgcn_readfirstlane(r.hi1);
+    const int lo2 = __builtin_amdgcn_readfirstlane(r.lo2), hi2 = __builtin_amdgcn_readfirstlane(r.hi2);
+    const bool c0 = lo1 <= X0 + 31 && hi1 >= X0, c1 = lo1 <= X0 + 63 && hi1 >= X0 + 32;
+    const bool w0 = lo2 <= Z0 + 31 && hi2 >= Z0, w1 = lo2 <= Z0 + 63 && hi2 >= Z0 + 32;
+    if (w0 && c0) acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(fr.a0, fr.b0, acc00, 0, 0, 0);
+    if (w0 && c1) acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(fr.a0, fr.b1, acc01, 0, 0, 0);
+    if (w1 && c0) acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(fr.a1, fr.b0, acc10, 0, 0, 0);
+    if (w1 && c1) acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(fr.a1, fr.b1, acc11, 0, 0, 0);
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_splat_mfma(SplatArgs A, int nunits, const SplatRec *__restrict__ rec,
+             const short4 *__restrict__ box)
+{
+    const int lane = threadIdx.x & 63;
+    const int unit = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (unit >= nunits) return;   // whole wavefronts leave; no workgroup barrier below
+    const int ntiles = A.ntile1 * ((A.n2 + SP_T - 1) / SP_T);
+    const int tile = unit % ntiles;
+    const int split = (unit / ntiles) % A.nsplit;
+    const int s = unit / (ntiles * A.nsplit);
+    const int X0 = (tile % A.ntile1) * SP_T, Z0 = (tile / A.ntile1) * SP_T;
+    const int64_t b0 = A.offsets[s], b1 = A.offsets[s + 1];
+    const int64_t nbs = b1 - b0;
+    const int64_t lo = b0 + nbs * split / A.nsplit, hi = b0 + nbs * (split + 1) / A.nsplit;
+    const float hl2e = (float)A.half_inv_eps * 1.4426950408889634f;
+    const int i1 = X0 + lane, i2 = Z0 + lane;
+    const double x1 = A.o1 + i1 * A.d1, x2 = A.o2 + i2 * A.d2;
+
+    floatx16 acc00, acc01, acc10, acc11;
+    double acc64[4][16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        acc00[r] = acc01[r] = acc10[r] = acc11[r] = 0.f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc64[q][r] = 0.0;
+    }
+
+    // the records of the beams of one chunk that meet the tile, compacted in
+    // beam order; wavefront-private, read back with uniform addresses
+    __shared__ SplatRec stage_rec[4][64];
+    SplatRec *st = stage_rec[threadIdx.x >> 6];
+
+    const short4 nobox = make_short4(1, 0, 1, 0);
+    short4 bx_next = lo + lane < hi ? box[lo + lane] : nobox;
+    int chunks = 0;
+    for (int64_t base = lo; base < hi; base += 64) {
+        const int64_t b = base + lane;
+        const short4 bx = bx_next;
+        // prefetch the boxes of the next chunk
+        bx_next = base + 64 + lane < hi ? box[base + 64 + lane] : nobox;
+        const bool hit = bx.x <= min((int)bx.y, X0 + SP_T - 1) && max((int)bx.x, X0) <= bx.y &&
+                         bx.z <= min((int)bx.w, Z0 + SP_T - 1) && max((int)bx.z, Z0) <= bx.w;
+        const unsigned long long mask = __ballot(hit);
+        if (!mask) continue;
+        const int nhit = __popcll(mask);
+        if (hit) {
+            const float4 *src = reinterpret_cast<const float4 *>(rec + b);
+            float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
+            float4 *dst = reinterpret_cast<float4 *>(st + __popcll(mask & ((1ull << lane) - 1ull)));
+            dst[0] = q0;
+            dst[1] = q1;
+            dst[2] = q2;
+            dst[3] = q3;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // software pipeline: the next record is read and its factors formed
+        // while the matrix cores work on the current beam
+        SplatRec r = st[0];
+        Frags fr = beam_frags(r, i1, i2, x1, x2, hl2e);
+        for (int k = 1; k < nhit; ++k) {
+            SplatRec rn = st[k];
+            tile_update(fr, r, X0, Z0, acc00, acc01, acc10, acc11);
+            r = rn;
+            fr = beam_frags(r, i1, i2, x1, x2, hl2e);
+        }
+        tile_update(fr, r, X0, Z0, acc00, acc01, acc10, acc11);
+        __builtin_amdgcn_wave_barrier();
+        // fold the FP32 sums (at most 256 beams) into FP64
+        if (++chunks == 4 || base + 64 >= hi) {
+            chunks = 0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                acc64[0][k] += (double)acc00[k];
+                acc64[1][k] += (double)acc01[k];
+                acc64[2][k] += (double)acc10[k];
+                acc64[3][k] += (double)acc11[k];
+                acc00[k] = acc01[k] = acc10[k] = acc11[k] = 0.f;
+            }
+        }
+    }
+    // sums of chunks after the last fold
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        acc64[0][k] += (double)acc00[k];
+        acc64[1][k] += (double)acc01[k];
+        acc64[2][k] += (double)acc10[k];
+        acc64[3][k] += (double)acc11[k];
+    }
+
+    // D[i][j] of a 32 x 32 block: j = lane % 32, i = 8 (r / 4) + 4 (lane / 32) + r % 4;
+    // block (a, c) covers rows x2 = Z0 + 32 a + i and columns x1 = X0 + 32 c + j
+    double *out = A.partial + ((size_t)s * A.nsplit + split) * A.n2 * (size_t)A.n1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            int row = Z0 + 32 * (q >> 1) + 8 * (k >> 2) + 4 * (lane >> 5) + (k & 3);
+            int col = X0 + 32 * (q & 1) + (lane & 31);
+            if (row < A.n2 && col < A.n1) out[(size_t)row * A.n1 + col] = acc64[q][k];
+        }
+}
+
 __global__ void k_splat_reduce(const double *__restrict__ partial, double *__restrict__ u,
                                int nsplit, int64_t npts, int nshots)
 {
@@ -243,8 +464,14 @@ fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nsho
     const fga_grid &g = ctx->g;
     int nt1 = (g.n1 + SP_T - 1) / SP_T, nt2 = (g.n2 + SP_T - 1) / SP_T;
     int tiles = nt1 * nt2;
-    int want = (4 * ctx->num_cu + tiles * nshots - 1) / (tiles * nshots);
-    int nsplit = want < 1 ? 1 : (want > 64 ? 64 : want);
+    bool mfma = ctx->prec == FGA_MIXED;
+    // enough work units to fill every SIMD twice (mixed: one wavefront per
+    // unit; FP64: one workgroup of four wavefronts per unit)
+    // mixed: about 32 wavefronts per CU, so that the dispatcher evens out
+    // tiles of very different load; FP64: 4 workgroups per CU
+    int want_units = mfma ? 32 * ctx->num_cu : 4 * ctx->num_cu;
+    int want = (want_units + tiles * nshots - 1) / (tiles * nshots);
+    int nsplit = want < 1 ? 1 : (want > 256 ? 256 : want);
     size_t npts = (size_t)g.n1 * g.n2;
     fga_status rc = fga_ensure(ctx, (void **)&ctx->partial, &ctx->partial_bytes,
                                (size_t)nshots * nsplit * npts * sizeof(double), "splat partials");
@@ -267,11 +494,22 @@ fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nsho
     A.nsplit = nsplit;
     A.ntile1 = nt1;
     A.partial = ctx->partial;
-    dim3 grid(tiles, nsplit, nshots);
-    if (ctx->prec == FGA_FP64)
-        hipLaunchKernelGGL(k_splat<double>, grid, dim3(256), 0, ctx->stream, A);
-    else
-        hipLaunchKernelGGL(k_splat<float>, grid, dim3(256), 0, ctx->stream, A);
+    if (mfma) {
+        rc = fga_ensure(ctx, &ctx->srec, &ctx->srec_bytes,
+                        (size_t)beams->capacity * sizeof(SplatRec), "splat records");
+        if (rc != FGA_OK) return rc;
+        rc = fga_ensure(ctx, &ctx->sbox, &ctx->sbox_bytes,
+                        (size_t)beams->capacity * sizeof(short4), "splat boxes");
+        if (rc != FGA_OK) return rc;
+        hipLaunchKernelGGL(k_splat_prep, dim3(2 * ctx->num_cu), dim3(256), 0, ctx->stream, A,
+                           nshots, (SplatRec *)ctx->srec, (short4 *)ctx->sbox);
+        int nunits = tiles * nsplit * nshots;
+        hipLaunchKernelGGL(k_splat_mfma, dim3((nunits + 3) / 4), dim3(256), 0, ctx->stream, A,
+                           nunits, (const SplatRec *)ctx->srec, (const short4 *)ctx->sbox);
+    } else {
+        hipLaunchKernelGGL(k_splat<double>, dim3(tiles, nsplit, nshots), dim3(256), 0,
+                           ctx->stream, A);
+    }
     hipLaunchKernelGGL(k_splat_reduce, dim3(1024), dim3(256), 0, ctx->stream, ctx->partial, u,
                        nsplit, (int64_t)npts, nshots);
     FGA_HIP(ctx, hipGetLastError());
