@@ -14,7 +14,10 @@
  *                    equations (dzQ, dzP eqs.) and the amplitude equation
  *                    (a_formu eq.);
  *   fga_reconstruct  step 3: the frozen-Gaussian sum (recons eq.) on the grid;
- *   fga_trace        step 3 at receiver nodes at every rec_every-th step.
+ *   fga_trace        step 3 at receiver nodes at every rec_every-th step;
+ *   fga_trace_adjoint, fga_decompose_adjoint
+ *                    the gradient of a receiver misfit with respect to the
+ *                    velocity samples and the initial wavefield.
  *
  * Conventions shared by every entry point
  *   - All pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
@@ -140,6 +143,36 @@ fga_status fga_reconstruct(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
 fga_status fga_trace(fga_ctx *ctx, fga_beams *beams, int32_t nshots,
                      const int32_t *rec_dev, int32_t nrec, int32_t rec_every,
                      int32_t nrec_t, double *traces_dev, double *ckpt_dev);
+
+/* Adjoint of fga_trace: the gradient of J = 1/2 sum (traces - data)^2
+ * through the RK4 integration of the ray, dynamic ray tracing and amplitude
+ * equations and the receiver sums, with the beam set and every truncation
+ * box held fixed (the exact gradient of the discrete forward).
+ *   beams      the beams of the forward call (their coefficients C and ids
+ *              are read; the states are not)
+ *   rec, nrec, rec_every, nrec_t   as in the forward fga_trace call
+ *   ckpt_dev   the checkpoints that fga_trace wrote ([nrec_t][23][capacity])
+ *   gtr_dev    dJ/dtraces [nshots][nrec_t][nrec] (e.g. traces - data)
+ *   dc_dev     [n2][n1]: dJ/dc is ADDED (caller zeroes it first); the sum
+ *              uses device atomics, so its rounding order is not fixed
+ *   gcoef_dev  [2][capacity]: dJ/d(Re C, Im C) per beam, overwritten
+ * Scratch of rec_every * 23 doubles per beam capacity is held by the
+ * context.                                                                 */
+fga_status fga_trace_adjoint(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
+                             const int32_t *rec_dev, int32_t nrec, int32_t rec_every,
+                             int32_t nrec_t, const double *ckpt_dev, const double *gtr_dev,
+                             double *dc_dev, double *gcoef_dev);
+
+/* Adjoint of fga_decompose for the beams it kept (the threshold set is held
+ * fixed): from dJ/dC (gcoef_dev, [2][capacity]) to dJ/df0 (df0_dev
+ * [nshots][n2][n1], overwritten) through C = w psi_{+-}/(2 pi eps)^3,
+ * u_{+-,0} (psi eq.) and the transposed windowed DFTs.  When the forward
+ * call had f1 != NULL, df1_dev receives dJ/df1 and dJ/dc through c(q) is
+ * ADDED to dc_dev (both then required).  Uses the FBI output of the most
+ * recent fga_decompose on this context, which must have produced beams.    */
+fga_status fga_decompose_adjoint(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
+                                 const double *gcoef_dev, double *df0_dev, double *df1_dev,
+                                 double *dc_dev);
 
 /* Synchronise the stream, read the sticky device status word and clear it.
  * *needed (may be NULL) receives the beam count a capacity overflow needed. */

@@ -72,6 +72,8 @@ def load(path: str = LIB_PATH):
         "fga_propagate": [C, ctypes.POINTER(fga_beams), I32, I32],
         "fga_reconstruct": [C, ctypes.POINTER(fga_beams), I32, P],
         "fga_trace": [C, ctypes.POINTER(fga_beams), I32, P, I32, I32, I32, P, P],
+        "fga_trace_adjoint": [C, ctypes.POINTER(fga_beams), I32, P, I32, I32, I32, P, P, P, P],
+        "fga_decompose_adjoint": [C, ctypes.POINTER(fga_beams), I32, P, P, P, P],
         "fga_sync_status": [C, ctypes.POINTER(ctypes.c_int64)],
         "fga_copy_offsets": [C, ctypes.POINTER(fga_beams), I32, P],
         "fga_last_error": [C],
@@ -149,6 +151,23 @@ def fga_trace(ctx, beams: "Beams", nshots: int, rec, rec_every: int, nrec_t: int
     _require(traces, "traces", "float64")
     _check(ctx, load().fga_trace(ctx, beams.c_struct(), int(nshots), _ptr(rec), rec.numel(),
                                  int(rec_every), int(nrec_t), _ptr(traces), _ptr(ckpt)))
+
+
+def fga_trace_adjoint(ctx, beams: "Beams", nshots: int, rec, rec_every: int, nrec_t: int,
+                      ckpt, gtr, dc, gcoef):
+    _require(rec, "rec", "int32")
+    for t, n in ((ckpt, "ckpt"), (gtr, "gtr"), (dc, "dc"), (gcoef, "gcoef")):
+        _require(t, n, "float64")
+    _check(ctx, load().fga_trace_adjoint(ctx, beams.c_struct(), int(nshots), _ptr(rec),
+                                         rec.numel(), int(rec_every), int(nrec_t), _ptr(ckpt),
+                                         _ptr(gtr), _ptr(dc), _ptr(gcoef)))
+
+
+def fga_decompose_adjoint(ctx, beams: "Beams", nshots: int, gcoef, df0, df1=None, dc=None):
+    for t, n in ((gcoef, "gcoef"), (df0, "df0")):
+        _require(t, n, "float64")
+    _check(ctx, load().fga_decompose_adjoint(ctx, beams.c_struct(), int(nshots), _ptr(gcoef),
+                                             _ptr(df0), _ptr(df1), _ptr(dc)))
 
 
 def fga_sync_status(ctx):
@@ -245,6 +264,20 @@ class FGA:
                          device=beams.f.device)
         fga_trace(self.ctx, beams, nshots, rec, rec_every, nrec_t, tr, ckpt)
         return tr
+
+    def trace_adjoint(self, beams: Beams, nshots: int, rec, rec_every: int, nrec_t: int, ckpt,
+                      gtr, dc):
+        import torch
+        gcoef = torch.empty((2, beams.capacity), dtype=torch.float64, device=beams.f.device)
+        fga_trace_adjoint(self.ctx, beams, nshots, rec, rec_every, nrec_t, ckpt, gtr, dc, gcoef)
+        return gcoef
+
+    def decompose_adjoint(self, beams: Beams, nshots: int, gcoef, df1=None, dc=None):
+        import torch
+        df0 = torch.empty((nshots, self.grid.n2, self.grid.n1), dtype=torch.float64,
+                          device=beams.f.device)
+        fga_decompose_adjoint(self.ctx, beams, nshots, gcoef, df0, df1, dc)
+        return df0
 
     def status(self):
         return fga_sync_status(self.ctx)

@@ -1,0 +1,621 @@
+// Adjoint of the receiver-trace forward on gfx950: the exact gradient of the
+// discrete forward (decompose -> RK4 -> traces) of
+//   J = 1/2 sum (traces - data)^2
+// with respect to the velocity samples and the initial wavefield, with the
+// thresholded beam set and every truncation box held fixed.
+//
+//  * k_trace_adjoint: one thread per beam walks the record segments
+//    backwards.  Each segment is recomputed from the checkpoint written by
+//    the forward (its step states go to a per-beam scratch), the trace
+//    cotangent at the record is added to the state cotangent lambda, and
+//    lambda is pulled back through every RK4 step with the hand-written
+//    vector-Jacobian product of the right-hand side.  dJ/dc reaches the
+//    velocity samples through the B-spline tap weights (FP64 atomics);
+//    dJ/dC per beam is returned for the decomposition adjoint.
+//  * fga_decompose_adjoint: dJ/dpsi_{+-} = w/(2 pi eps)^3 dJ/dC, pulled back
+//    through u_{+-,0} to dJ/dpsi_0 (and dJ/dpsi_1, dJ/dc(q) when f1 was
+//    given), then through the two windowed DFT passes in transpose.
+#include <math.h>
+
+#include "rk4.h"
+
+__device__ __forceinline__ Cd cconj(Cd a) { return {a.r, -a.i}; }
+// a * conj(b)
+__device__ __forceinline__ Cd cmulc(Cd a, Cd b) { return {a.r * b.r + a.i * b.i, a.i * b.r - a.r * b.i}; }
+// Re(conj(a) b)
+__device__ __forceinline__ double cdotr(Cd a, Cd b) { return a.r * b.r + a.i * b.i; }
+// -i z
+__device__ __forceinline__ Cd cmuli_neg(Cd z) { return {z.i, -z.r}; }
+
+__device__ __forceinline__ void st_zero(St &z)
+{
+    z.Q1 = z.Q2 = z.P1 = z.P2 = z.S = 0.0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int l = 0; l < 2; ++l) z.A[j][l] = z.B[j][l] = Cd{0.0, 0.0};
+    z.a = Cd{0.0, 0.0};
+}
+
+// o = x + h y
+__device__ __forceinline__ St st_axpy(const St &x, double h, const St &y)
+{
+    St o;
+    axpy(o, x, h, y);
+    return o;
+}
+
+// Velocity with third derivatives, and the per-axis tap factors
+// (w, dw/d, ddw/d^2) for the scatter of dJ/d(c, grad c, Hess c) to samples.
+struct Vel3 {
+    double c, g1, g2, K11, K12, K22, T111, T112, T122, T222;
+    double ax[3][4], az[3][4];
+    int i1, i2;
+};
+
+__device__ __forceinline__ void vel_eval3(const VelGrid &V, double x1, double x2, Vel3 &o)
+{
+    double t1 = (x1 - V.o1) * V.inv_d1, t2 = (x2 - V.o2) * V.inv_d2;
+    double fl1 = floor(t1), fl2 = floor(t2);
+    double f1 = t1 - fl1, f2 = t2 - fl2;
+    o.i1 = (int)fmin(fmax(fl1, -4.0), (double)V.n1 + 3.0);
+    o.i2 = (int)fmin(fmax(fl2, -4.0), (double)V.n2 + 3.0);
+    double wx[4], dwx[4], ddwx[4], wz[4], dwz[4], ddwz[4];
+    bspline_w(f1, wx, dwx, ddwx);
+    bspline_w(f2, wz, dwz, ddwz);
+    const double dddw[4] = {-1.0, 3.0, -3.0, 1.0};
+    const double *base = V.c + (size_t)(o.i2 - 1 + FGA_VPAD) * V.ld + (o.i1 - 1 + FGA_VPAD);
+    double s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int kz = 0; kz < 4; ++kz) {
+        const double *row = base + kz * V.ld;
+        double v0 = row[0], v1 = row[1], v2 = row[2], v3 = row[3];
+        double a0 = wx[0] * v0 + wx[1] * v1 + wx[2] * v2 + wx[3] * v3;
+        double a1 = dwx[0] * v0 + dwx[1] * v1 + dwx[2] * v2 + dwx[3] * v3;
+        double a2 = ddwx[0] * v0 + ddwx[1] * v1 + ddwx[2] * v2 + ddwx[3] * v3;
+        double a3 = dddw[0] * v0 + dddw[1] * v1 + dddw[2] * v2 + dddw[3] * v3;
+        s[0] += wz[kz] * a0;
+        s[1] += wz[kz] * a1;
+        s[2] += dwz[kz] * a0;
+        s[3] += wz[kz] * a2;
+        s[4] += dwz[kz] * a1;
+        s[5] += ddwz[kz] * a0;
+        s[6] += wz[kz] * a3;
+        s[7] += dwz[kz] * a2;
+        s[8] += ddwz[kz] * a1;
+        s[9] += dddw[kz] * a0;
+    }
+    const double i1d = V.inv_d1, i2d = V.inv_d2;
+    o.c = s[0];
+    o.g1 = s[1] * i1d;
+    o.g2 = s[2] * i2d;
+    o.K11 = s[3] * i1d * i1d;
+    o.K12 = s[4] * i1d * i2d;
+    o.K22 = s[5] * i2d * i2d;
+    o.T111 = s[6] * i1d * i1d * i1d;
+    o.T112 = s[7] * i1d * i1d * i2d;
+    o.T122 = s[8] * i1d * i2d * i2d;
+    o.T222 = s[9] * i2d * i2d * i2d;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        o.ax[0][k] = wx[k];
+        o.ax[1][k] = dwx[k] * i1d;
+        o.ax[2][k] = ddwx[k] * i1d * i1d;
+        o.az[0][k] = wz[k];
+        o.az[1][k] = dwz[k] * i2d;
+        o.az[2][k] = ddwz[k] * i2d * i2d;
+    }
+}
+
+// dc[clamped taps] += d(c, g1, g2, K11, K12, K22)/d(samples)^T vb
+__device__ __forceinline__ void scatter_dc(const Vel3 &v, const double vb[6], double *dc, int n1,
+                                           int n2)
+{
+#pragma unroll
+    for (int kz = 0; kz < 4; ++kz) {
+        double px0 = vb[0] * v.az[0][kz] + vb[2] * v.az[1][kz] + vb[5] * v.az[2][kz];
+        double px1 = vb[1] * v.az[0][kz] + vb[4] * v.az[1][kz];
+        double px2 = vb[3] * v.az[0][kz];
+        int r = min(max(v.i2 - 1 + kz, 0), n2 - 1);
+#pragma unroll
+        for (int kx = 0; kx < 4; ++kx) {
+            int q = min(max(v.i1 - 1 + kx, 0), n1 - 1);
+            double val = px0 * v.ax[0][kx] + px1 * v.ax[1][kx] + px2 * v.ax[2][kx];
+            atomicAdd(&dc[(size_t)r * n1 + q], val);
+        }
+    }
+}
+
+// xb += (df/dx)^T kb, dc += (df/dc)^T kb, for k = f(x) the right-hand side
+// of rk4.h.  The action slope is identically zero as a function of the
+// state (H is homogeneous of degree one in P), so it carries no cotangent.
+__device__ void rhs_vjp(const VelGrid &V, double s, const St &x, const St &kb, St &xb, double *dc,
+                        int n1, int n2)
+{
+    // ---- forward quantities
+    Vel3 v;
+    vel_eval3(V, x.Q1, x.Q2, v);
+    const double c = v.c, g[2] = {v.g1, v.g2};
+    const double K[2][2] = {{v.K11, v.K12}, {v.K12, v.K22}};
+    const double n = sqrt(x.P1 * x.P1 + x.P2 * x.P2);
+    const double inv_n = rcp64(n);
+    const double u[2] = {x.P1 * inv_n, x.P2 * inv_n};
+    const double con = c * inv_n;
+    Cd Ag[2], Bu[2], m[2], AK[2][2], kA[2][2], kB[2][2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        Ag[j] = cadd(cscale(x.A[j][0], g[0]), cscale(x.A[j][1], g[1]));
+        Bu[j] = cadd(cscale(x.B[j][0], u[0]), cscale(x.B[j][1], u[1]));
+        m[j] = csub(Ag[j], cscale(Bu[j], con));
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            AK[j][k] = cadd(cscale(x.A[j][0], K[0][k]), cscale(x.A[j][1], K[1][k]));
+            kA[j][k] = cscale(cadd(cscale(m[j], u[k]), cscale(x.B[j][k], con)), s);
+            kB[j][k] = cscale(cadd(cscale(AK[j][k], n), cscale(Bu[j], g[k])), -s);
+        }
+    }
+    Cd Z[2][2], dZ[2][2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            Z[j][k] = {x.A[j][k].r - x.B[j][k].i, x.A[j][k].i + x.B[j][k].r};
+            dZ[j][k] = {kA[j][k].r - kB[j][k].i, kA[j][k].i + kB[j][k].r};
+        }
+    const Cd det = csub(cmul(Z[0][0], Z[1][1]), cmul(Z[0][1], Z[1][0]));
+    const Cd num = csub(cadd(cmul(Z[1][1], dZ[0][0]), cmul(Z[0][0], dZ[1][1])),
+                        cadd(cmul(Z[0][1], dZ[1][0]), cmul(Z[1][0], dZ[0][1])));
+    const double id2 = rcp64(det.r * det.r + det.i * det.i);
+    const Cd inv_det = cscale(cconj(det), id2);
+    const Cd tr = cmul(num, inv_det);
+    const double ug = u[0] * g[0] + u[1] * g[1];
+    const Cd h = {s * ug + 0.5 * tr.r, 0.5 * tr.i};
+
+    // ---- reverse
+    // ka = a h
+    xb.a = cadd(xb.a, cmulc(kb.a, h));
+    const Cd hb = cmulc(kb.a, x.a);
+    const double ugb = s * hb.r;
+    const Cd trb = cscale(hb, 0.5);
+    // tr = num / det
+    const Cd numb = cmulc(trb, inv_det);                 // trb / conj(det)
+    const Cd detb = cscale(cmulc(trb, cmul(tr, inv_det)), -1.0);   // -trb conj(tr/det)
+    Cd dZb[2][2], Zb[2][2];
+    dZb[0][0] = cmulc(numb, Z[1][1]);
+    dZb[1][1] = cmulc(numb, Z[0][0]);
+    dZb[1][0] = cscale(cmulc(numb, Z[0][1]), -1.0);
+    dZb[0][1] = cscale(cmulc(numb, Z[1][0]), -1.0);
+    Zb[1][1] = cadd(cmulc(numb, dZ[0][0]), cmulc(detb, Z[0][0]));
+    Zb[0][0] = cadd(cmulc(numb, dZ[1][1]), cmulc(detb, Z[1][1]));
+    Zb[0][1] = cscale(cadd(cmulc(numb, dZ[1][0]), cmulc(detb, Z[1][0])), -1.0);
+    Zb[1][0] = cscale(cadd(cmulc(numb, dZ[0][1]), cmulc(detb, Z[0][1])), -1.0);
+
+    double ub[2] = {ugb * g[0], ugb * g[1]};
+    double gbv[2] = {ugb * u[0], ugb * u[1]};
+    double nb = 0.0, conb = 0.0, cb = 0.0, K11b = 0.0, K12b = 0.0, K22b = 0.0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        Cd kAb[2], kBb[2], Ab[2], Bb[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            // Z = A + iB and dZ = kA + i kB
+            Ab[k] = Zb[j][k];
+            Bb[k] = cmuli_neg(Zb[j][k]);
+            kAb[k] = cadd(kb.A[j][k], dZb[j][k]);
+            kBb[k] = cadd(kb.B[j][k], cmuli_neg(dZb[j][k]));
+        }
+        // kB[j][k] = -s (n AK_j[k] + Bu_j g_k)
+        Cd AKb[2];
+        Cd Bub = {0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            AKb[k] = cscale(kBb[k], -s * n);
+            nb += -s * cdotr(AK[j][k], kBb[k]);
+            Bub = cadd(Bub, cscale(kBb[k], -s * g[k]));
+            gbv[k] += -s * cdotr(Bu[j], kBb[k]);
+        }
+        // AK_j[k] = sum_l A[j][l] K[l][k]
+#pragma unroll
+        for (int l = 0; l < 2; ++l)
+            Ab[l] = cadd(Ab[l], cadd(cscale(AKb[0], K[l][0]), cscale(AKb[1], K[l][1])));
+        K11b += cdotr(x.A[j][0], AKb[0]);
+        K12b += cdotr(x.A[j][0], AKb[1]) + cdotr(x.A[j][1], AKb[0]);
+        K22b += cdotr(x.A[j][1], AKb[1]);
+        // kA[j][k] = s (m_j u_k + con B[j][k])
+        Cd mb = {0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            mb = cadd(mb, cscale(kAb[k], s * u[k]));
+            ub[k] += s * cdotr(m[j], kAb[k]);
+            conb += s * cdotr(x.B[j][k], kAb[k]);
+            Bb[k] = cadd(Bb[k], cscale(kAb[k], s * con));
+        }
+        // m_j = Ag_j - con Bu_j
+        const Cd Agb = mb;
+        conb += -cdotr(Bu[j], mb);
+        Bub = cadd(Bub, cscale(mb, -con));
+        // Bu_j = sum_l B[j][l] u_l ; Ag_j = sum_l A[j][l] g_l
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            Bb[l] = cadd(Bb[l], cscale(Bub, u[l]));
+            ub[l] += cdotr(x.B[j][l], Bub);
+            Ab[l] = cadd(Ab[l], cscale(Agb, g[l]));
+            gbv[l] += cdotr(x.A[j][l], Agb);
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            xb.A[j][k] = cadd(xb.A[j][k], Ab[k]);
+            xb.B[j][k] = cadd(xb.B[j][k], Bb[k]);
+        }
+    }
+    // con = c / n
+    cb += conb * inv_n;
+    nb += -conb * c * inv_n * inv_n;
+    // kP = -s n g
+    nb += -s * (g[0] * kb.P1 + g[1] * kb.P2);
+    gbv[0] += -s * n * kb.P1;
+    gbv[1] += -s * n * kb.P2;
+    // kQ = s c u
+    cb += s * (u[0] * kb.Q1 + u[1] * kb.Q2);
+    ub[0] += s * c * kb.Q1;
+    ub[1] += s * c * kb.Q2;
+    // u = P / n, n = |P|
+    nb += -(ub[0] * u[0] + ub[1] * u[1]) * inv_n;
+    xb.P1 += ub[0] * inv_n + nb * u[0];
+    xb.P2 += ub[1] * inv_n + nb * u[1];
+    // (c, g, K) = B-spline(Q; samples)
+    xb.Q1 += cb * v.g1 + gbv[0] * v.K11 + gbv[1] * v.K12 + K11b * v.T111 + K12b * v.T112 +
+             K22b * v.T122;
+    xb.Q2 += cb * v.g2 + gbv[0] * v.K12 + gbv[1] * v.K22 + K11b * v.T112 + K12b * v.T122 +
+             K22b * v.T222;
+    const double vb[6] = {cb, gbv[0], gbv[1], K11b, K12b, K22b};
+    scatter_dc(v, vb, dc, n1, n2);
+}
+
+__device__ __forceinline__ St st_scale(double h, const St &x)
+{
+    St z;
+    st_zero(z);
+    return st_axpy(z, h, x);
+}
+
+// lambda <- (d y_{n+1} / d y_n)^T lambda for one classical RK4 step from y:
+// the stage inputs y2, y3, y4 are recomputed, then the four stages are
+// pulled back in reverse order (kbar_i = b_i dt lambda + a_{i+1,i} dt ybar_{i+1}).
+__device__ void step_vjp(const VelGrid &V, double s, const St &y, St &lam, double dt, double *dc,
+                         int n1, int n2)
+{
+    St k;
+    rhs(V, s, y, k);
+    const St y2 = st_axpy(y, 0.5 * dt, k);
+    rhs(V, s, y2, k);
+    const St y3 = st_axpy(y, 0.5 * dt, k);
+    rhs(V, s, y3, k);
+    const St y4 = st_axpy(y, dt, k);
+    St yb = lam, xb;
+    st_zero(xb);
+    rhs_vjp(V, s, y4, st_scale(dt / 6.0, lam), xb, dc, n1, n2);
+    yb = st_axpy(yb, 1.0, xb);
+    St kbar = st_axpy(st_scale(dt / 3.0, lam), dt, xb);
+    st_zero(xb);
+    rhs_vjp(V, s, y3, kbar, xb, dc, n1, n2);
+    yb = st_axpy(yb, 1.0, xb);
+    kbar = st_axpy(st_scale(dt / 3.0, lam), 0.5 * dt, xb);
+    st_zero(xb);
+    rhs_vjp(V, s, y2, kbar, xb, dc, n1, n2);
+    yb = st_axpy(yb, 1.0, xb);
+    kbar = st_axpy(st_scale(dt / 6.0, lam), 0.5 * dt, xb);
+    st_zero(xb);
+    rhs_vjp(V, s, y, kbar, xb, dc, n1, n2);
+    lam = st_axpy(yb, 1.0, xb);
+}
+
+struct TraceAdjArgs {
+    VelGrid V;
+    const double *f;          // beams (coefficients)
+    const int64_t *id;
+    const int64_t *offsets;
+    int nshots;
+    int64_t cap, NqNp;
+    const int32_t *rec;
+    int nrec, rec_every, nrec_t;
+    const double *ckpt;       // [nrec_t][NSTATE][cap]
+    const double *gtr;        // [nshots][nrec_t][nrec]
+    double *scratch;          // [rec_every][NSTATE][cap]
+    double *dc;               // [n2][n1]
+    double *gcoef;            // [2][cap]
+    int n1, n2;
+    double o1, o2, d1, d2, eps, dt;
+    int Rw1, Rw2;
+};
+
+__global__ void __launch_bounds__(128)
+k_trace_adjoint(TraceAdjArgs A)
+{
+    const int64_t nb = A.offsets[A.nshots];
+    const int64_t cap = A.cap;
+    const double inv_eps = 1.0 / A.eps;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t idb = A.id[b];
+        const double s = ((idb / A.NqNp) & 1) ? -1.0 : 1.0;
+        const int shot = (int)(idb / (2 * A.NqNp));
+        const Cd C = {A.f[4 * cap + b], A.f[5 * cap + b]};
+        St lam;
+        st_zero(lam);
+        Cd gC = {0.0, 0.0};
+        for (int k = A.nrec_t - 1; k >= 0; --k) {
+            // recompute the segment from its checkpoint
+            St y;
+            load_state_raw(A.ckpt + (size_t)k * FGA_NSTATE * cap, cap, b, y);
+            for (int j = 0; j < A.rec_every; ++j) {
+                store_state(A.scratch + (size_t)j * FGA_NSTATE * cap + b, cap, y);
+                St t = y, acc = y;
+                stage<false>(A.V, s, t, acc, y, A.dt / 6.0, 0.5 * A.dt);
+                stage<false>(A.V, s, t, acc, y, A.dt / 3.0, 0.5 * A.dt);
+                stage<false>(A.V, s, t, acc, y, A.dt / 3.0, A.dt);
+                stage<true>(A.V, s, t, acc, y, A.dt / 6.0, 0.0);
+                y = acc;
+            }
+            // cotangent of the traces of record k (boxes held fixed)
+            const double *R = A.gtr + ((size_t)shot * A.nrec_t + k) * A.nrec;
+            BeamBox bx = beam_box(y.Q1, y.Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
+            for (int r = 0; r < A.nrec; ++r) {
+                int node = A.rec[r];
+                int i1 = node % A.n1, i2 = node / A.n1;
+                if (i1 < bx.lo1 || i1 > bx.hi1 || i2 < bx.lo2 || i2 > bx.hi2) continue;
+                double r1 = (A.o1 + i1 * A.d1) - y.Q1, r2 = (A.o2 + i2 * A.d2) - y.Q2;
+                double th = (y.S + y.P1 * r1 + y.P2 * r2) * inv_eps;
+                double G = -(r1 * r1 + r2 * r2) * 0.5 * inv_eps;
+                double sn, cs;
+                sincos(th, &sn, &cs);
+                double e = exp(G);
+                Cd ew = {e * cs, e * sn};          // e^{i theta + G}
+                Cd w = cmul(y.a, ew);              // a e^{...}
+                Cd E = cmul(C, w);                 // the term whose real part is traced
+                double Rv = R[r];
+                gC = cadd(gC, cscale(cconj(w), Rv));
+                lam.a = cadd(lam.a, cscale(cconj(cmul(C, ew)), Rv));
+                lam.S += Rv * (-E.i) * inv_eps;
+                lam.P1 += Rv * (-E.i) * r1 * inv_eps;
+                lam.P2 += Rv * (-E.i) * r2 * inv_eps;
+                lam.Q1 += Rv * (E.i * y.P1 + E.r * r1) * inv_eps;
+                lam.Q2 += Rv * (E.i * y.P2 + E.r * r2) * inv_eps;
+            }
+            // pull lambda back through the segment
+            for (int j = A.rec_every - 1; j >= 0; --j) {
+                St yj;
+                load_state_raw(A.scratch + (size_t)j * FGA_NSTATE * cap, cap, b, yj);
+                step_vjp(A.V, s, yj, lam, A.dt, A.dc, A.n1, A.n2);
+            }
+        }
+        A.gcoef[b] = gC.r;
+        A.gcoef[cap + b] = gC.i;
+    }
+}
+
+fga_status fga_launch_trace_adjoint(fga_ctx *ctx, const fga_beams *beams, int nshots,
+                                    const int32_t *rec, int nrec, int rec_every, int nrec_t,
+                                    const double *ckpt, const double *gtr, double *dc,
+                                    double *gcoef)
+{
+    size_t need = (size_t)rec_every * FGA_NSTATE * beams->capacity * sizeof(double);
+    fga_status rc = fga_ensure(ctx, &ctx->adj_scratch, &ctx->adj_scratch_bytes, need,
+                               "adjoint segment scratch");
+    if (rc != FGA_OK) return rc;
+    TraceAdjArgs A;
+    A.V = fga_velgrid(ctx);
+    A.f = beams->f;
+    A.id = beams->id;
+    A.offsets = beams->offsets;
+    A.nshots = nshots;
+    A.cap = beams->capacity;
+    A.NqNp = (int64_t)ctx->p.nq1 * ctx->p.nq2 * ctx->p.np1 * ctx->p.np2;
+    A.rec = rec;
+    A.nrec = nrec;
+    A.rec_every = rec_every;
+    A.nrec_t = nrec_t;
+    A.ckpt = ckpt;
+    A.gtr = gtr;
+    A.scratch = (double *)ctx->adj_scratch;
+    A.dc = dc;
+    A.gcoef = gcoef;
+    A.n1 = ctx->g.n1;
+    A.n2 = ctx->g.n2;
+    A.o1 = ctx->g.o1;
+    A.o2 = ctx->g.o2;
+    A.d1 = ctx->g.d1;
+    A.d2 = ctx->g.d2;
+    A.eps = ctx->p.eps;
+    A.dt = ctx->p.dt;
+    A.Rw1 = ctx->Rw1;
+    A.Rw2 = ctx->Rw2;
+    hipLaunchKernelGGL(k_trace_adjoint, dim3(ctx->num_cu * 4), dim3(128), 0, ctx->stream, A);
+    FGA_HIP(ctx, hipGetLastError());
+    return FGA_OK;
+}
+
+// ------------------------------------------------------- decomposition adjoint
+
+template <typename R>
+struct cplxR {
+    R re, im;
+};
+
+__global__ void k_fill_zero(double *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// dJ/dpsi_0 (and dJ/dpsi_1, dJ/dc(q)) in the layout of the forward FBI
+// output, from dJ/dC of every beam.  psi_{+-} = (psi0 + sigma i r psi1)/2 with
+// r = eps / (c(q)|p|); the two branches of one (q, p) add to the same slot
+// (two additions to zero commute exactly, so the result is deterministic).
+template <typename R>
+__global__ void k_scatter_psib(const int64_t *__restrict__ id, const int64_t *__restrict__ offsets,
+                               int nshots, const double *__restrict__ gcoef, int64_t cap,
+                               const cplxR<R> *__restrict__ Psi, const double *__restrict__ cq,
+                               int nq1, int nq2, int np1, int np2, int nfj, double dp1,
+                               double dp2, double eps, double norm, double *psib, double *cqb)
+{
+    const int64_t nb = offsets[nshots];
+    const int64_t Nq = (int64_t)nq1 * nq2, Np = (int64_t)np1 * np2, NqNp = Nq * Np;
+    const size_t NC = (size_t)nq1 * np1;
+    const size_t plane = (size_t)nq2 * np2 * NC;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        int64_t cid = id[b];
+        int s = (int)(cid / (2 * NqNp));
+        int64_t cl = cid - (int64_t)s * 2 * NqNp;
+        int sb = (int)(cl / NqNp);
+        int64_t rem = cl - sb * NqNp;
+        int64_t qf = rem / Np, pf = rem - qf * Np;
+        int j2 = (int)(qf / nq1), j1 = (int)(qf - (int64_t)j2 * nq1);
+        int l2 = (int)(pf / np1), l1 = (int)(pf - (int64_t)l2 * np1);
+        size_t off = ((size_t)j2 * np2 + l2) * NC + (size_t)j1 * np1 + l1;
+        // dJ/dpsi_{+-} = norm dJ/dC
+        double pr = norm * gcoef[b], pi = norm * gcoef[cap + b];
+        double *p0 = psib + 2 * ((size_t)(s * nfj) * plane + off);
+        atomicAdd(p0, 0.5 * pr);
+        atomicAdd(p0 + 1, 0.5 * pi);
+        if (nfj == 2) {
+            double sg = sb == 0 ? 1.0 : -1.0;
+            double pp1 = (l1 - 0.5 * (np1 - 1)) * dp1, pp2 = (l2 - 0.5 * (np2 - 1)) * dp2;
+            double cqv = cq[qf];
+            double r = eps / (cqv * sqrt(pp1 * pp1 + pp2 * pp2));
+            // d psi / d psi1 = sigma i r / 2  ->  psi1b += conj(.) psib = -sigma i r/2 psib
+            double *p1 = psib + 2 * ((size_t)(s * nfj + 1) * plane + off);
+            atomicAdd(p1, 0.5 * sg * r * pi);
+            atomicAdd(p1 + 1, -0.5 * sg * r * pr);
+            // d psi / d r = sigma i psi1 / 2 ; d r / d c(q) = -r / c(q)
+            cplxR<R> v = Psi[(size_t)(s * nfj + 1) * plane + off];
+            double wr = -0.5 * sg * (double)v.im, wi = 0.5 * sg * (double)v.re;
+            double rb = wr * pr + wi * pi;
+            atomicAdd(&cqb[qf], rb * (-r / cqv));
+        }
+    }
+}
+
+// dc += dJ/dc(q) pulled through the B-spline at every q node
+__global__ void k_cq_adjoint(VelGrid V, const double *cqb, double o1, double o2, double d1,
+                             double d2, int qb1, int qb2, int qs1, int qs2, int nq1, int nq2,
+                             double *dc)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq1 * nq2) return;
+    int j1 = i % nq1, j2 = i / nq1;
+    double x1 = o1 + (qb1 + j1 * qs1) * d1, x2 = o2 + (qb2 + j2 * qs2) * d2;
+    Vel3 v;
+    vel_eval3(V, x1, x2, v);
+    double vb[6] = {cqb[i], 0, 0, 0, 0, 0};
+    scatter_dc(v, vb, dc, V.n1, V.n2);
+}
+
+// Transposed pass 2: Tb[sf][i2][c] = d2 sum_{j2, l2} conj(E2[l2][i2 - k2(j2)]) psib[sf][j2][l2][c]
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_fbi_pass2_t(const double *__restrict__ psib, const cplxR<R> *__restrict__ E2, double *Tb,
+              int n2, int R2, int qb2, int qs2, int nq2, int np2, int NC, double d2)
+{
+    const int W2 = 2 * R2 + 1;
+    const int i2 = blockIdx.y, sf = blockIdx.z;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= NC) return;
+    double ar = 0.0, ai = 0.0;
+    for (int j2 = 0; j2 < nq2; ++j2) {
+        const int m = i2 - (qb2 + j2 * qs2);   // window offset of node i2 from q node j2
+        if (m < -R2 || m > R2) continue;
+        const double *pb = psib + 2 * (((size_t)sf * nq2 + j2) * np2 * (size_t)NC + c);
+        for (int l2 = 0; l2 < np2; ++l2) {
+            cplxR<R> e = E2[(size_t)l2 * W2 + m + R2];
+            double er = (double)e.re, ei = (double)e.im;
+            double br = pb[2 * (size_t)l2 * NC], bi = pb[2 * (size_t)l2 * NC + 1];
+            // conj(e) * b
+            ar += er * br + ei * bi;
+            ai += er * bi - ei * br;
+        }
+    }
+    double *out = Tb + 2 * (((size_t)sf * n2 + i2) * NC + c);
+    out[0] = ar * d2;
+    out[1] = ai * d2;
+}
+
+// Transposed pass 1: fb[sf][i2][i1] = d1 Re sum_{j1, l1} conj(E1t[i1 - k1(j1)][l1]) Tb[sf][i2][j1 np1 + l1]
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_fbi_pass1_t(const double *__restrict__ Tb, const cplxR<R> *__restrict__ E1t, double *f0b,
+              double *f1b, int nfj, int n1, int n2, int R1, int qb1, int qs1, int nq1, int np1,
+              double d1)
+{
+    const int i1 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i2 = blockIdx.y, sf = blockIdx.z;
+    if (i1 >= n1) return;
+    const int NC = nq1 * np1;
+    const double *tb = Tb + 2 * (((size_t)sf * n2 + i2) * NC);
+    double acc = 0.0;
+    for (int j1 = 0; j1 < nq1; ++j1) {
+        const int m = i1 - (qb1 + j1 * qs1);   // window offset of node i1 from q node j1
+        if (m < -R1 || m > R1) continue;
+        const cplxR<R> *e = E1t + (size_t)(m + R1) * np1;
+        const double *t = tb + 2 * (size_t)j1 * np1;
+        for (int l1 = 0; l1 < np1; ++l1) {
+            // Re(conj(e) t)
+            acc += (double)e[l1].re * t[2 * l1] + (double)e[l1].im * t[2 * l1 + 1];
+        }
+    }
+    int s = sf / nfj, fj = sf % nfj;
+    double *out = fj == 0 ? f0b : f1b;
+    if (out) out[((size_t)s * n2 + i2) * n1 + i1] = acc * d1;
+}
+
+template <typename R>
+static fga_status decompose_adjoint_impl(fga_ctx *ctx, const fga_beams *beams, int nshots,
+                                         const double *gcoef, double *df0, double *df1,
+                                         double *dc)
+{
+    const fga_grid &g = ctx->g;
+    const fga_params &p = ctx->p;
+    hipStream_t st = ctx->stream;
+    const int nfj = ctx->last_nfj;
+    const int S = nshots * nfj;
+    const size_t NC = (size_t)p.nq1 * p.np1;
+    const size_t psib_elems = (size_t)S * p.nq2 * p.np2 * NC * 2;
+    const size_t tb_elems = (size_t)S * g.n2 * NC * 2;
+    fga_status rc = fga_ensure(ctx, &ctx->adj_psib, &ctx->adj_psib_bytes,
+                               (psib_elems + tb_elems + (size_t)p.nq1 * p.nq2) * sizeof(double),
+                               "decomposition adjoint workspace");
+    if (rc != FGA_OK) return rc;
+    double *psib = (double *)ctx->adj_psib;
+    double *Tb = psib + psib_elems;
+    double *cqb = Tb + tb_elems;
+    hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, st, psib,
+                       (int64_t)(psib_elems + tb_elems + (size_t)p.nq1 * p.nq2));
+    hipLaunchKernelGGL(k_scatter_psib<R>, dim3(ctx->num_cu * 4), dim3(256), 0, st, beams->id,
+                       beams->offsets, nshots, gcoef, beams->capacity,
+                       (const cplxR<R> *)ctx->Psi, ctx->cq, p.nq1, p.nq2, p.np1, p.np2, nfj,
+                       p.dp1, p.dp2, p.eps, ctx->norm, psib, cqb);
+    hipLaunchKernelGGL(k_fbi_pass2_t<R>, dim3((unsigned)((NC + 255) / 256), g.n2, S), dim3(256),
+                       0, st, psib, (const cplxR<R> *)ctx->E2, Tb, g.n2, ctx->R2, p.qb2, p.qs2,
+                       p.nq2, p.np2, (int)NC, g.d2);
+    hipLaunchKernelGGL(k_fbi_pass1_t<R>, dim3((g.n1 + 255) / 256, g.n2, S), dim3(256), 0, st, Tb,
+                       (const cplxR<R> *)ctx->E1t, df0, df1, nfj, g.n1, g.n2, ctx->R1, p.qb1,
+                       p.qs1, p.nq1, p.np1, g.d1);
+    if (nfj == 2 && dc) {
+        int nq = p.nq1 * p.nq2;
+        hipLaunchKernelGGL(k_cq_adjoint, dim3((nq + 255) / 256), dim3(256), 0, st,
+                           fga_velgrid(ctx), cqb, g.o1, g.o2, g.d1, g.d2, p.qb1, p.qb2, p.qs1,
+                           p.qs2, p.nq1, p.nq2, dc);
+    }
+    FGA_HIP(ctx, hipGetLastError());
+    return FGA_OK;
+}
+
+fga_status fga_launch_decompose_adjoint(fga_ctx *ctx, const fga_beams *beams, int nshots,
+                                        const double *gcoef, double *df0, double *df1, double *dc)
+{
+    if (ctx->prec == FGA_FP64)
+        return decompose_adjoint_impl<double>(ctx, beams, nshots, gcoef, df0, df1, dc);
+    return decompose_adjoint_impl<float>(ctx, beams, nshots, gcoef, df0, df1, dc);
+}

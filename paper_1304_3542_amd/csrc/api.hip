@@ -133,7 +133,8 @@ extern "C" fga_status fga_destroy(fga_ctx *ctx)
     if (!ctx) return FGA_OK;
     (void)hipStreamSynchronize(ctx->stream);
     void *bufs[] = {ctx->c, ctx->cpad, ctx->status, ctx->cq, ctx->maxbits, ctx->E1t, ctx->E2,
-                    ctx->T, ctx->Psi, ctx->blk, ctx->partial, ctx->srec, ctx->sbox};
+                    ctx->T, ctx->Psi, ctx->blk, ctx->partial, ctx->srec, ctx->sbox,
+                    ctx->adj_scratch, ctx->adj_psib};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     free(ctx);
@@ -243,6 +244,43 @@ extern "C" fga_status fga_trace(fga_ctx *ctx, fga_beams *beams, int32_t nshots,
         if (st != FGA_OK) return st;
     }
     return FGA_OK;
+}
+
+extern "C" fga_status fga_trace_adjoint(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
+                                        const int32_t *rec, int32_t nrec, int32_t rec_every,
+                                        int32_t nrec_t, const double *ckpt, const double *gtr,
+                                        double *dc, double *gcoef)
+{
+    if (!ctx) return FGA_EINVAL;
+    fga_status st = check_beams(ctx, beams);
+    if (st != FGA_OK) return st;
+    if (nshots < 1 || nshots > ctx->max_shots)
+        return fga_fail(ctx, FGA_EINVAL, "nshots %d outside [1, %d]", nshots, ctx->max_shots);
+    if (!rec || nrec < 1 || rec_every < 1 || nrec_t < 1 || !ckpt || !gtr || !dc || !gcoef)
+        return fga_fail(ctx, FGA_EINVAL, "bad trace-adjoint arguments");
+    if (!ctx->have_c) return fga_fail(ctx, FGA_ESTATE, "fga_set_velocity was not called");
+    return fga_launch_trace_adjoint(ctx, beams, nshots, rec, nrec, rec_every, nrec_t, ckpt, gtr,
+                                    dc, gcoef);
+}
+
+extern "C" fga_status fga_decompose_adjoint(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
+                                            const double *gcoef, double *df0, double *df1,
+                                            double *dc)
+{
+    if (!ctx) return FGA_EINVAL;
+    fga_status st = check_beams(ctx, beams);
+    if (st != FGA_OK) return st;
+    if (nshots < 1 || nshots > ctx->max_shots)
+        return fga_fail(ctx, FGA_EINVAL, "nshots %d outside [1, %d]", nshots, ctx->max_shots);
+    if (!gcoef || !df0) return fga_fail(ctx, FGA_EINVAL, "gcoef and df0 must be non-null");
+    if (!ctx->Psi || ctx->last_nfj < 1)
+        return fga_fail(ctx, FGA_ESTATE, "fga_decompose has not run on this context");
+    if (nshots != ctx->last_nshots)
+        return fga_fail(ctx, FGA_EINVAL, "nshots %d differs from the last fga_decompose (%d)",
+                        nshots, ctx->last_nshots);
+    if (ctx->last_nfj == 2 && (!df1 || !dc))
+        return fga_fail(ctx, FGA_EINVAL, "the decomposition used f1: df1 and dc are required");
+    return fga_launch_decompose_adjoint(ctx, beams, nshots, gcoef, df0, df1, dc);
 }
 
 extern "C" fga_status fga_sync_status(fga_ctx *ctx, int64_t *needed)

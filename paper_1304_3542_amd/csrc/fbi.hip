@@ -415,6 +415,8 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
     hipStream_t st = ctx->stream;
     int nfj = f1 ? 2 : 1;
     int S = nshots * nfj;
+    ctx->last_nfj = nfj;
+    ctx->last_nshots = nshots;
     if ((int64_t)S * p.nq2 > 65535 || S > 65535)
         return fga_fail(ctx, FGA_EINVAL, "nshots * (1 + (f1 != NULL)) * nq2 = %lld exceeds 65535",
                         (long long)S * p.nq2);

@@ -45,6 +45,11 @@ struct fga_ctx {
     void *srec, *sbox;
     size_t srec_bytes, sbox_bytes;
 
+    // adjoint workspaces and the branch count of the last decomposition
+    void *adj_scratch, *adj_psib;
+    size_t adj_scratch_bytes, adj_psib_bytes;
+    int last_nfj, last_nshots;
+
     // sticky device status: [0] flags, [1] needed capacity
     int64_t *status;
 
@@ -71,6 +76,14 @@ fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nsho
 fga_status fga_launch_trace_points(fga_ctx *ctx, const fga_beams *beams, int nshots,
                                    const int32_t *rec, int nrec, double *out,
                                    int64_t out_stride_shot);
+
+fga_status fga_launch_trace_adjoint(fga_ctx *ctx, const fga_beams *beams, int nshots,
+                                    const int32_t *rec, int nrec, int rec_every, int nrec_t,
+                                    const double *ckpt, const double *gtr, double *dc,
+                                    double *gcoef);
+fga_status fga_launch_decompose_adjoint(fga_ctx *ctx, const fga_beams *beams, int nshots,
+                                        const double *gcoef, double *df0, double *df1,
+                                        double *dc);
 
 static inline int fga_halfwidth(double eps, double tau, double d)
 {
@@ -151,6 +164,29 @@ __device__ __forceinline__ void vel_eval(const VelGrid &V, double x1, double x2,
     c11 = s3 * V.inv_d1 * V.inv_d1;
     c12 = s4 * V.inv_d1 * V.inv_d2;
     c22 = s5 * V.inv_d2 * V.inv_d2;
+}
+
+// Truncation box of a Gaussian centred at Q: the nodes within Rw cells of the
+// node nearest Q (floor(t + 1/2)), clipped to the grid.
+struct BeamBox {
+    int lo1, hi1, lo2, hi2;
+};
+
+__device__ __forceinline__ BeamBox beam_box(double Q1, double Q2, double o1, double o2,
+                                            double d1, double d2, int Rw1, int Rw2, int n1,
+                                            int n2)
+{
+    // nearest node by floor(t + 1/2); far-away centres are clamped before the
+    // integer conversion (their boxes miss the grid either way)
+    double t1 = fmin(fmax(floor((Q1 - o1) / d1 + 0.5), -1e8), 1e8);
+    double t2 = fmin(fmax(floor((Q2 - o2) / d2 + 0.5), -1e8), 1e8);
+    int c1 = (int)t1, c2 = (int)t2;
+    BeamBox b;
+    b.lo1 = max(c1 - Rw1, 0);
+    b.hi1 = min(c1 + Rw1, n1 - 1);
+    b.lo2 = max(c2 - Rw2, 0);
+    b.hi2 = min(c2 + Rw2, n2 - 1);
+    return b;
 }
 
 static inline VelGrid fga_velgrid(const fga_ctx *ctx)

@@ -28,27 +28,6 @@ struct Fac {
     R re, im;
 };
 
-struct BeamBox {
-    int lo1, hi1, lo2, hi2;
-};
-
-__device__ __forceinline__ BeamBox beam_box(double Q1, double Q2, double o1, double o2,
-                                            double d1, double d2, int Rw1, int Rw2, int n1,
-                                            int n2)
-{
-    // nearest node by floor(t + 1/2); far-away centres are clamped before the
-    // integer conversion (their boxes miss the grid either way)
-    double t1 = fmin(fmax(floor((Q1 - o1) / d1 + 0.5), -1e8), 1e8);
-    double t2 = fmin(fmax(floor((Q2 - o2) / d2 + 0.5), -1e8), 1e8);
-    int c1 = (int)t1, c2 = (int)t2;
-    BeamBox b;
-    b.lo1 = max(c1 - Rw1, 0);
-    b.hi1 = min(c1 + Rw1, n1 - 1);
-    b.lo2 = max(c2 - Rw2, 0);
-    b.hi2 = min(c2 + Rw2, n2 - 1);
-    return b;
-}
-
 struct SplatArgs {
     const double *f;
     const int64_t *offsets;

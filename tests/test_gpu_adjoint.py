@@ -1,0 +1,68 @@
+"""Parity of the hand-written adjoint (fga_trace_adjoint +
+fga_decompose_adjoint, through the C ABI) with the gradient oracle
+(reverse-mode autodiff of a plain forward), on the same seeded inputs."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.adjoint as oadj
+from test_oracle_adjoint import adjoint_case, c_oracle_traces
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_gradient(g, p, c, f0, f1, rec, every, nrec, data, precision="fp64"):
+    import torch
+    import paper_1304_3542_amd as fga
+    ns = f0.shape[0]
+    ctx = fga.FGA(g, p, precision, max_shots=ns)
+    ctx.set_velocity(torch.from_numpy(c).cuda())
+    cand = 2 * p.nq1 * p.nq2 * p.np1 * p.np2 * ns
+    beams = fga.Beams(cand, ns)
+    f1t = None if f1 is None else torch.from_numpy(f1).cuda()
+    ctx.decompose(torch.from_numpy(f0).cuda(), f1t, beams)
+    rec_t = torch.from_numpy(rec).cuda()
+    ckpt = torch.empty((nrec, fga.FGA_NSTATE, beams.capacity), dtype=torch.float64, device="cuda")
+    tr = ctx.trace(beams, ns, rec_t, every, nrec, ckpt)
+    gtr = tr - torch.from_numpy(data).cuda()
+    dc = torch.zeros_like(ctx_c := torch.from_numpy(c).cuda())
+    gcoef = ctx.trace_adjoint(beams, ns, rec_t, every, nrec, ckpt, gtr.contiguous(), dc)
+    df1 = None if f1 is None else torch.empty_like(f1t)
+    df0 = ctx.decompose_adjoint(beams, ns, gcoef, df1, dc if f1 is not None else None)
+    st = ctx.status()
+    nb = int(ctx.offsets(beams, ns)[-1])
+    return dict(status=st, ids=beams.id[:nb].cpu().numpy(), tr=tr.cpu().numpy(),
+                dc=dc.cpu().numpy(), df0=df0.cpu().numpy(),
+                df1=None if df1 is None else df1.cpu().numpy())
+
+
+def rel_max(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("with_f1", [False, True])
+def test_adjoint_fp64_matches_gradient_oracle(with_f1):
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(with_f1)
+    b = oracle.decompose(f0, f1, c, g, p)
+    data = 0.5 * c_oracle_traces(c * 1.02, f0, f1, g, p, b.cand, rec, every, nrec)
+    J, dc, df0, df1, tr = oadj.gradient(c, f0, f1, g, p, b.cand, rec, every, nrec, data)
+    r = gpu_gradient(g, p, c, f0, f1, rec, every, nrec, data)
+    assert r["status"][0] == 0
+    np.testing.assert_array_equal(r["ids"], b.cand)
+    assert rel_max(r["tr"], tr) <= 1e-10
+    assert rel_max(r["dc"], dc) <= 1e-10, rel_max(r["dc"], dc)
+    assert rel_max(r["df0"], df0) <= 1e-10, rel_max(r["df0"], df0)
+    if with_f1:
+        assert rel_max(r["df1"], df1) <= 1e-10
+
+
+def test_adjoint_mixed_within_1e5():
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(False)
+    b = oracle.decompose(f0, f1, c, g, p)
+    data = 0.5 * c_oracle_traces(c * 1.02, f0, f1, g, p, b.cand, rec, every, nrec)
+    J, dc, df0, df1, tr = oadj.gradient(c, f0, f1, g, p, b.cand, rec, every, nrec, data)
+    r = gpu_gradient(g, p.replace(tau_fbi=1e-8, tau_win=1e-8), c, f0, f1, rec, every, nrec,
+                     data, "mixed")
+    assert r["status"][0] == 0
+    assert np.linalg.norm(r["dc"] - dc) / np.linalg.norm(dc) <= 1e-5
+    assert np.linalg.norm(r["df0"] - df0) / np.linalg.norm(df0) <= 1e-5

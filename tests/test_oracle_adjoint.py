@@ -1,0 +1,123 @@
+"""Pins of the gradient oracle (oracle/adjoint.py, torch autograd of a plain
+forward): its forward equals the C oracle's receiver traces, and its
+gradient equals central finite differences of the C oracle's misfit with
+the beam set held fixed."""
+import math
+
+import numpy as np
+import pytest
+
+import fga_inputs as fi
+import oracle
+import oracle.adjoint as oadj
+
+
+def adjoint_case(with_f1=False, seed=41):
+    g = fi.Grid(40, 32, 0.0, 0.0, 1 / 32, 1 / 32)
+    eps = 1 / 200
+    c = fi.smooth_layered_velocity(g, seed=seed, smooth_cells=3.0)
+    r = fi.rng(seed)
+    ns = 2
+    f0 = np.stack([fi.wavepacket_source(g, (r.uniform(0.45, 0.8), 0.35), 0.06,
+                                        (r.uniform(-0.4, 0.4), 0.9), eps) for _ in range(ns)])
+    f1 = None
+    if with_f1:
+        f1 = np.stack([0.7 * fi.wavepacket_source(g, (0.6, 0.4), 0.05, (0.8, 0.3), eps)
+                       for _ in range(ns)])
+    p = fi.Params(eps, 3, 4, 4, 4, 9, 6, 8, 8, 0.35, 0.35, 1e-3, 1e-16, 1e-16, 1e-3, 15)
+    rec = np.arange(2 * g.n1, 3 * g.n1, dtype=np.int32)          # row i2 = 2
+    return g, p, c, f0, f1, rec, 5, 3
+
+
+def c_oracle_traces(c, f0, f1, g, p, cand, rec, rec_every, nrec, c_for_branches=None):
+    """C-oracle traces of the beams `cand` (frozen set) for the given c and f0."""
+    ns = f0.shape[0]
+    cb = c if c_for_branches is None else c_for_branches
+    nq, npp = p.nq1 * p.nq2, p.np1 * p.np2
+    coef, states, sig, offs = [], [], [], [0]
+    k1, k2 = oracle.qnodes(p)
+    pm1, pm2 = oracle.pmesh(p.np1, p.dp1), oracle.pmesh(p.np2, p.dp2)
+    w = (p.qs1 * g.d1) * (p.qs2 * g.d2) * p.dp1 * p.dp2
+    norm = w / (2 * math.pi * p.eps) ** 3
+    for s in range(ns):
+        psi0 = oracle.fbi(f0[s], g, p)
+        psi1 = None if f1 is None else oracle.fbi(f1[s], g, p)
+        pp, pm = oracle.branches(psi0, psi1, cb, g, p)
+        vals = np.stack([pp.ravel(), pm.ravel()])
+        mine = cand[(cand // (2 * nq * npp)) == s] - s * 2 * nq * npp
+        sb, flat = mine // (nq * npp), mine % (nq * npp)
+        psi = vals[sb, flat]
+        qf, pf = flat // npp, flat % npp
+        st = np.zeros((mine.size, oracle.NSTATE))
+        st[:, 0] = g.o1 + g.d1 * k1[qf % p.nq1]
+        st[:, 1] = g.o2 + g.d2 * k2[qf // p.nq1]
+        st[:, 2] = pm1[pf % p.np1]
+        st[:, 3] = pm2[pf // p.np1]
+        st[:, 5] = st[:, 11] = 1.0
+        st[:, 14] = st[:, 20] = -1.0
+        st[:, 21] = 2.0
+        coef.append(np.stack([psi.real, psi.imag], 1) * norm)
+        states.append(st)
+        sig.append(np.where(sb == 0, 1, -1).astype(np.int8))
+        offs.append(offs[-1] + mine.size)
+    b = oracle.Beams(np.zeros(offs[-1], np.int32), np.concatenate(sig), cand.copy(),
+                     np.zeros(offs[-1], complex), np.ascontiguousarray(np.concatenate(coef)),
+                     np.ascontiguousarray(np.concatenate(states)), np.array(offs, np.int64))
+    return oracle.trace(b, c, g, p, rec, rec_every, nrec)
+
+
+@pytest.mark.parametrize("with_f1", [False, True])
+def test_torch_forward_matches_c_oracle(with_f1):
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(with_f1)
+    b = oracle.decompose(f0, f1, c, g, p)
+    assert 50 < b.n < 8000
+    tr_c = oracle.trace(b, c, g, p, rec, every, nrec)
+    import torch
+    tr_t = oadj.traces(torch.tensor(c), torch.tensor(f0),
+                       None if f1 is None else torch.tensor(f1), g, p, b.cand, rec, every,
+                       nrec, f0.shape[0]).numpy()
+    assert np.abs(tr_c).max() > 1e-3
+    np.testing.assert_allclose(tr_t, tr_c, rtol=0, atol=1e-12 * np.abs(tr_c).max())
+
+
+@pytest.mark.parametrize("with_f1", [False, True])
+def test_gradient_matches_finite_differences(with_f1):
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(with_f1)
+    b = oracle.decompose(f0, f1, c, g, p)
+    cand = b.cand
+    data = 0.5 * c_oracle_traces(c * 1.02, f0, f1, g, p, cand, rec, every, nrec)
+    J, dc, df0, df1, tr = oadj.gradient(c, f0, f1, g, p, cand, rec, every, nrec, data)
+
+    def Jc(cc, ff0, ff1):
+        t = c_oracle_traces(cc, ff0, ff1, g, p, cand, rec, every, nrec)
+        return 0.5 * ((t - data) ** 2).sum()
+
+    assert abs(Jc(c, f0, f1) - J) <= 1e-12 * abs(J)
+    # the cells and nodes with the largest gradients, plus a few seeded ones
+    r = fi.rng(5)
+    cells = list(np.argsort(-np.abs(dc).ravel())[:4]) + list(r.choice(c.size, 2, replace=False))
+    for idx in cells:
+        i2, i1 = np.unravel_index(idx, c.shape)
+        h = 1e-6 * c[i2, i1]
+        cp, cm = c.copy(), c.copy()
+        cp[i2, i1] += h
+        cm[i2, i1] -= h
+        fd = (Jc(cp, f0, f1) - Jc(cm, f0, f1)) / (2 * h)
+        assert abs(fd - dc[i2, i1]) <= 1e-6 * np.abs(dc).max(), (idx, fd, dc[i2, i1])
+    nodes = list(np.argsort(-np.abs(df0).ravel())[:3])
+    for idx in nodes:
+        s, i2, i1 = np.unravel_index(idx, df0.shape)
+        h = 1e-6
+        fp, fm = f0.copy(), f0.copy()
+        fp[s, i2, i1] += h
+        fm[s, i2, i1] -= h
+        fd = (Jc(c, fp, f1) - Jc(c, fm, f1)) / (2 * h)
+        assert abs(fd - df0[s, i2, i1]) <= 1e-6 * np.abs(df0).max(), (idx, fd, df0[s, i2, i1])
+    if with_f1:
+        idx = int(np.argmax(np.abs(df1).ravel()))
+        s, i2, i1 = np.unravel_index(idx, df1.shape)
+        fp, fm = f1.copy(), f1.copy()
+        fp[s, i2, i1] += 1e-6
+        fm[s, i2, i1] -= 1e-6
+        fd = (Jc(c, f0, fp) - Jc(c, f0, fm)) / 2e-6
+        assert abs(fd - df1[s, i2, i1]) <= 1e-6 * np.abs(df1).max()
