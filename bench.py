@@ -30,14 +30,38 @@ import fga_inputs as fi  # noqa: E402
 
 PEAK = {"hbm": 8.0e12, "fp64": 78.6e12, "fp32": 157.3e12}
 
-# FP64 operations of one RK4 step of one beam (4 right-hand sides + the RK4
-# combinations), counted from the formulas the kernel implements: B-spline
-# weights (2 x 26), 16 taps x 6 products (96 FMA = 192), scalings 8, |P| and
-# u (sqrt ~ 1 + div ~ 1 + 3), H derivatives 8, dS 4, dzQ update 2 x (2 x 8 +
-# 2 x 12) = 80, dzP update 2 x (2 x 8 + 2 x 8) = 64, Z/dZ 16, det 8, adjugate
-# trace 32, 1/|det|^2 and the quotient 12, da 12: ~493 per evaluation; RK4
-# combinations 4 x 2 x 23 FMA = 368 per step.
-RK4_FLOP_PER_BEAM_STEP = 4 * 493 + 368
+# FP64 operations (an FMA counts two) of one RK4 step of one beam, counted
+# from the formulas the kernel evaluates per stage: cubic B-spline weights
+# and 16-tap sums of c, grad c, Hess c (~196), |P| and u (~15), the
+# Hamiltonian derivatives and Q/P/S slopes (~30), Z, det Z and the
+# sign-folded coefficients (~36), the rank-one dzQ/dzP updates with the
+# adjugate trace and the accumulator/stage updates of both rows (~200),
+# 1/|det Z|^2, tr(Z^-1 dZ) and the amplitude slope and updates (~37):
+# ~521 per stage, four stages less the last stage's unused input update.
+RK4_FLOP_PER_BEAM_STEP = 2030
+PROFILE_JSON = os.path.join(ROOT, "profiles", "point512_hbm_counters.json")
+KERNEL_SOURCES = {
+    "k_rk4": ["paper_1304_3542_amd/csrc/propagate.hip", "paper_1304_3542_amd/csrc/rk4.h",
+              "paper_1304_3542_amd/csrc/fga_internal.h"],
+    "k_splat_mfma": ["paper_1304_3542_amd/csrc/reconstruct.hip",
+                     "paper_1304_3542_amd/csrc/fga_internal.h"],
+}
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE counter
+    summary, or None if the kernel's sources changed since it was taken."""
+    import hashlib
+    if not os.path.exists(PROFILE_JSON) or kernel not in KERNEL_SOURCES:
+        return None
+    z = json.load(open(PROFILE_JSON))
+    h = hashlib.sha256()
+    for fn in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(ROOT, fn), "rb").read())
+    if z.get("source_sha", {}).get(kernel) != h.hexdigest()[:16]:
+        return None
+    k = z["kernels"].get(kernel)
+    return None if k is None else k["hbm_bytes_scaled"]
 
 
 def parse():
@@ -51,6 +75,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="rough budget of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=3,
+                    help="timed iterations of the adjoint workload (0 skips it)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (HBM counter calibration)")
     return ap.parse_args()
@@ -114,6 +140,73 @@ def time_path(path, steps, warmup):
     wall = (time.perf_counter() - t0) / steps
     st = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in evs])
     return wall * 1e3, st.mean(axis=0)
+
+
+def time_splat_kernel(path, reps=3):
+    """Duration of the reconstruction on its stream (HIP events): the
+    record pre-pass, the MFMA splat and the split reduction together."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ts = []
+    for _ in range(reps):
+        ev[0].record()
+        path.ctx.reconstruct(path.beams, path.W.nshots, path.u)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ts.append(ev[0].elapsed_time(ev[1]))
+    return float(np.median(ts))
+
+
+def adjoint_iteration(steps):
+    """ms per iteration of forward + adjoint on the 256 x 256, 8-shot receiver
+    workload (FP64): decompose, trace with checkpoints, trace adjoint,
+    decomposition adjoint."""
+    import torch
+    import paper_1304_3542_amd as fga
+    W = fi.workload("adjoint256", "fp64")
+    g, p = W.grid, W.params
+    ns = W.nshots
+    nrec_t = p.nsteps // W.rec_every
+    ctx = fga.FGA(g, p, "fp64", max_shots=ns)
+    c = torch.from_numpy(W.c).cuda()
+    ctx.set_velocity(c)
+    f0 = torch.from_numpy(np.ascontiguousarray(W.f0)).cuda()
+    cap = 2 * p.nq1 * p.nq2 * p.np1 * p.np2 * ns
+    beams = fga.Beams(cap, ns)
+    ctx.decompose(f0, None, beams)
+    nb = int(ctx.offsets(beams, ns)[-1])
+    beams = fga.Beams(nb + 1024, ns)
+    rec = torch.from_numpy(W.receivers).cuda()
+    ckpt = torch.empty((nrec_t, fga.FGA_NSTATE, beams.capacity), dtype=torch.float64,
+                       device="cuda")
+    # data: traces of the perturbed model through the same path
+    ctx.set_velocity(torch.from_numpy(W.c_true).cuda())
+    ctx.decompose(f0, None, beams)
+    data = ctx.trace(beams, ns, rec, W.rec_every, nrec_t)
+    ctx.set_velocity(c)
+    dc = torch.zeros_like(c)
+
+    def it():
+        ctx.decompose(f0, None, beams)
+        tr = ctx.trace(beams, ns, rec, W.rec_every, nrec_t, ckpt)
+        dc.zero_()
+        gcoef = ctx.trace_adjoint(beams, ns, rec, W.rec_every, nrec_t, ckpt,
+                                  (tr - data).contiguous(), dc)
+        return ctx.decompose_adjoint(beams, ns, gcoef)
+
+    it()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(steps):
+        it()
+    ev[1].record()
+    torch.cuda.synchronize()
+    st, _ = ctx.status()
+    return {"ms_per_iter": ev[0].elapsed_time(ev[1]) / steps, "nbeams": nb, "nshots": ns,
+            "status": st, "workload": "adjoint256: 256x256 on [0,2]x[0,1], eps=1/128, 8 surface "
+            "shots, 256 receivers on the top row every 10 steps, T=0.25 s, FP64 gradient "
+            "w.r.t. c and f0"}
 
 
 def box_pairs(f, nb, W, tau_win):
@@ -221,27 +314,30 @@ def main():
         }
 
     pairs = box_pairs(f_host, nb, W, W.params.tau_win)
+    splat_ms = time_splat_kernel(mixed)
     npts = W.grid.n1 * W.grid.n2 * W.nshots
     stages = {"decompose": stage_ms[0], "propagate": stage_ms[1], "reconstruct": stage_ms[2]}
     dom = max(stages, key=stages.get)
-    if dom == "propagate":
-        fl = RK4_FLOP_PER_BEAM_STEP * W.params.nsteps * nb
-        achieved = fl / (stage_ms[1] * 1e-3)
-        roof = {"kernel": "k_rk4", "bound": "alu", "achieved": achieved / 1e12,
-                "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK["fp64"], "traffic": None}
-    elif dom == "reconstruct":
-        fl = 4.0 * pairs
-        achieved = fl / (stage_ms[2] * 1e-3)
-        roof = {"kernel": "k_splat_mfma", "bound": "mfma", "achieved": achieved / 1e12,
-                "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK["fp32"], "traffic": None}
-    else:
-        roof = {"kernel": "decompose", "bound": "alu", "achieved": None, "peak": None,
-                "unit": "TFLOP/s", "frac": None, "traffic": None}
+    rk_fl = RK4_FLOP_PER_BEAM_STEP * W.params.nsteps * nb
+    rk_ach = rk_fl / (stage_ms[1] * 1e-3)
+    sp_fl = 4.0 * pairs
+    sp_ach = sp_fl / (splat_ms * 1e-3)
+    kernels = {
+        "k_rk4": {"bound": "alu", "achieved": rk_ach / 1e12, "peak": PEAK["fp64"] / 1e12,
+                  "unit": "TFLOP/s", "frac": rk_ach / PEAK["fp64"], "ms": stage_ms[1],
+                  "flop_per_launch": rk_fl, "traffic": profiled_traffic("k_rk4")},
+        "k_splat_mfma": {"bound": "mfma", "achieved": sp_ach / 1e12,
+                         "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
+                         "frac": sp_ach / PEAK["fp32"], "ms": splat_ms,
+                         "flop_per_launch": sp_fl, "traffic": profiled_traffic("k_splat_mfma")},
+    }
+    roof = dict(kernels["k_rk4" if dom != "reconstruct" else "k_splat_mfma"])
+    roof["kernel"] = "k_rk4" if dom != "reconstruct" else "k_splat_mfma"
+    for key in ("ms", "flop_per_launch"):
+        roof.pop(key)
 
     out = {
-        "metric": "beams/s end-to-end (FBI+trace+sum) at rel-L2<=1e-5 vs FP64",
+        "metric": "beams/s end-to-end (FBI+trace+sum) at rel-L2<=1e-5 vs FP64; adjoint ms/iter",
         "value": nb / (ms_step * 1e-3),
         "unit": "beams/s",
         "n_gpus": 1,
@@ -267,7 +363,10 @@ def main():
                      "stages_ms": dict(zip(stages, stage64.tolist())),
                      "speedup_mixed_over_fp64": ms64 / ms_step},
         "roofline": roof,
+        "kernels": kernels,
     }
+    if args.adjoint_steps > 0:
+        out["adjoint"] = adjoint_iteration(args.adjoint_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Wd, nb, args.cpu_seconds)
     print(json.dumps(out), flush=True)

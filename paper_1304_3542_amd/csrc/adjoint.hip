@@ -107,30 +107,63 @@ __device__ __forceinline__ void vel_eval3(const VelGrid &V, double x1, double x2
     }
 }
 
-// dc[clamped taps] += d(c, g1, g2, K11, K12, K22)/d(samples)^T vb
-__device__ __forceinline__ void scatter_dc(const Vel3 &v, const double vb[6], double *dc, int n1,
-                                           int n2)
+// Per-thread accumulator of dJ/d(samples) over the 4 x 4 knots of one cell:
+// contributions are summed in place while the ray stays in the cell and the
+// sums go to the grid with atomics only when the cell changes.
+struct DcAcc {
+    double v[16];
+    int i1, i2;   // knot base of the held sums (i1 = INT_MIN: empty)
+};
+
+__device__ __forceinline__ void dcacc_init(DcAcc &a)
 {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) a.v[k] = 0.0;
+    a.i1 = -2147483647 - 1;
+    a.i2 = 0;
+}
+
+__device__ __forceinline__ void dcacc_flush(DcAcc &a, double *dc, int n1, int n2)
+{
+    if (a.i1 == -2147483647 - 1) return;
+#pragma unroll
+    for (int kz = 0; kz < 4; ++kz) {
+        int r = min(max(a.i2 - 1 + kz, 0), n2 - 1);
+#pragma unroll
+        for (int kx = 0; kx < 4; ++kx) {
+            int q = min(max(a.i1 - 1 + kx, 0), n1 - 1);
+            if (a.v[4 * kz + kx] != 0.0) atomicAdd(&dc[(size_t)r * n1 + q], a.v[4 * kz + kx]);
+            a.v[4 * kz + kx] = 0.0;
+        }
+    }
+    a.i1 = -2147483647 - 1;
+}
+
+// acc += d(c, g1, g2, K11, K12, K22)/d(samples)^T vb at the knots of v
+__device__ __forceinline__ void scatter_dc(const Vel3 &v, const double vb[6], DcAcc &acc,
+                                           double *dc, int n1, int n2)
+{
+    if (v.i1 != acc.i1 || v.i2 != acc.i2) {
+        dcacc_flush(acc, dc, n1, n2);
+        acc.i1 = v.i1;
+        acc.i2 = v.i2;
+    }
 #pragma unroll
     for (int kz = 0; kz < 4; ++kz) {
         double px0 = vb[0] * v.az[0][kz] + vb[2] * v.az[1][kz] + vb[5] * v.az[2][kz];
         double px1 = vb[1] * v.az[0][kz] + vb[4] * v.az[1][kz];
         double px2 = vb[3] * v.az[0][kz];
-        int r = min(max(v.i2 - 1 + kz, 0), n2 - 1);
 #pragma unroll
-        for (int kx = 0; kx < 4; ++kx) {
-            int q = min(max(v.i1 - 1 + kx, 0), n1 - 1);
-            double val = px0 * v.ax[0][kx] + px1 * v.ax[1][kx] + px2 * v.ax[2][kx];
-            atomicAdd(&dc[(size_t)r * n1 + q], val);
-        }
+        for (int kx = 0; kx < 4; ++kx)
+            acc.v[4 * kz + kx] += px0 * v.ax[0][kx] + px1 * v.ax[1][kx] + px2 * v.ax[2][kx];
     }
 }
 
 // xb += (df/dx)^T kb, dc += (df/dc)^T kb, for k = f(x) the right-hand side
 // of rk4.h.  The action slope is identically zero as a function of the
 // state (H is homogeneous of degree one in P), so it carries no cotangent.
-__device__ void rhs_vjp(const VelGrid &V, double s, const St &x, const St &kb, St &xb, double *dc,
-                        int n1, int n2)
+__device__ void rhs_vjp(const VelGrid &V, double s, const St &x, const St &kb, St &xb, DcAcc &dacc,
+                        double *dc, int n1, int n2)
 {
     // ---- forward quantities
     Vel3 v;
@@ -269,7 +302,7 @@ __device__ void rhs_vjp(const VelGrid &V, double s, const St &x, const St &kb, S
     xb.Q2 += cb * v.g2 + gbv[0] * v.K12 + gbv[1] * v.K22 + K11b * v.T112 + K12b * v.T122 +
              K22b * v.T222;
     const double vb[6] = {cb, gbv[0], gbv[1], K11b, K12b, K22b};
-    scatter_dc(v, vb, dc, n1, n2);
+    scatter_dc(v, vb, dacc, dc, n1, n2);
 }
 
 __device__ __forceinline__ St st_scale(double h, const St &x)
@@ -282,8 +315,8 @@ __device__ __forceinline__ St st_scale(double h, const St &x)
 // lambda <- (d y_{n+1} / d y_n)^T lambda for one classical RK4 step from y:
 // the stage inputs y2, y3, y4 are recomputed, then the four stages are
 // pulled back in reverse order (kbar_i = b_i dt lambda + a_{i+1,i} dt ybar_{i+1}).
-__device__ void step_vjp(const VelGrid &V, double s, const St &y, St &lam, double dt, double *dc,
-                         int n1, int n2)
+__device__ void step_vjp(const VelGrid &V, double s, const St &y, St &lam, double dt, DcAcc &dacc,
+                         double *dc, int n1, int n2)
 {
     St k;
     rhs(V, s, y, k);
@@ -294,19 +327,19 @@ __device__ void step_vjp(const VelGrid &V, double s, const St &y, St &lam, doubl
     const St y4 = st_axpy(y, dt, k);
     St yb = lam, xb;
     st_zero(xb);
-    rhs_vjp(V, s, y4, st_scale(dt / 6.0, lam), xb, dc, n1, n2);
+    rhs_vjp(V, s, y4, st_scale(dt / 6.0, lam), xb, dacc, dc, n1, n2);
     yb = st_axpy(yb, 1.0, xb);
     St kbar = st_axpy(st_scale(dt / 3.0, lam), dt, xb);
     st_zero(xb);
-    rhs_vjp(V, s, y3, kbar, xb, dc, n1, n2);
+    rhs_vjp(V, s, y3, kbar, xb, dacc, dc, n1, n2);
     yb = st_axpy(yb, 1.0, xb);
     kbar = st_axpy(st_scale(dt / 3.0, lam), 0.5 * dt, xb);
     st_zero(xb);
-    rhs_vjp(V, s, y2, kbar, xb, dc, n1, n2);
+    rhs_vjp(V, s, y2, kbar, xb, dacc, dc, n1, n2);
     yb = st_axpy(yb, 1.0, xb);
     kbar = st_axpy(st_scale(dt / 6.0, lam), 0.5 * dt, xb);
     st_zero(xb);
-    rhs_vjp(V, s, y, kbar, xb, dc, n1, n2);
+    rhs_vjp(V, s, y, kbar, xb, dacc, dc, n1, n2);
     lam = st_axpy(yb, 1.0, xb);
 }
 
@@ -344,6 +377,8 @@ k_trace_adjoint(TraceAdjArgs A)
         St lam;
         st_zero(lam);
         Cd gC = {0.0, 0.0};
+        DcAcc dacc;
+        dcacc_init(dacc);
         for (int k = A.nrec_t - 1; k >= 0; --k) {
             // recompute the segment from its checkpoint
             St y;
@@ -386,9 +421,10 @@ k_trace_adjoint(TraceAdjArgs A)
             for (int j = A.rec_every - 1; j >= 0; --j) {
                 St yj;
                 load_state_raw(A.scratch + (size_t)j * FGA_NSTATE * cap, cap, b, yj);
-                step_vjp(A.V, s, yj, lam, A.dt, A.dc, A.n1, A.n2);
+                step_vjp(A.V, s, yj, lam, A.dt, dacc, A.dc, A.n1, A.n2);
             }
         }
+        dcacc_flush(dacc, A.dc, A.n1, A.n2);
         A.gcoef[b] = gC.r;
         A.gcoef[cap + b] = gC.i;
     }
@@ -510,7 +546,10 @@ __global__ void k_cq_adjoint(VelGrid V, const double *cqb, double o1, double o2,
     Vel3 v;
     vel_eval3(V, x1, x2, v);
     double vb[6] = {cqb[i], 0, 0, 0, 0, 0};
-    scatter_dc(v, vb, dc, V.n1, V.n2);
+    DcAcc dacc;
+    dcacc_init(dacc);
+    scatter_dc(v, vb, dacc, dc, V.n1, V.n2);
+    dcacc_flush(dacc, dc, V.n1, V.n2);
 }
 
 // Transposed pass 2: Tb[sf][i2][c] = d2 sum_{j2, l2} conj(E2[l2][i2 - k2(j2)]) psib[sf][j2][l2][c]

@@ -134,7 +134,7 @@ extern "C" fga_status fga_destroy(fga_ctx *ctx)
     (void)hipStreamSynchronize(ctx->stream);
     void *bufs[] = {ctx->c, ctx->cpad, ctx->status, ctx->cq, ctx->maxbits, ctx->E1t, ctx->E2,
                     ctx->T, ctx->Psi, ctx->blk, ctx->partial, ctx->srec, ctx->sbox,
-                    ctx->adj_scratch, ctx->adj_psib};
+                    ctx->adj_scratch, ctx->adj_psib, ctx->trace_part};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     free(ctx);

@@ -44,6 +44,8 @@ struct fga_ctx {
     size_t partial_bytes;
     void *srec, *sbox;
     size_t srec_bytes, sbox_bytes;
+    void *trace_part;      // per-split partial receiver sums
+    size_t trace_part_bytes;
 
     // adjoint workspaces and the branch count of the last decomposition
     void *adj_scratch, *adj_psib;

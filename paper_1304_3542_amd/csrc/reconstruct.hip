@@ -496,29 +496,32 @@ fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nsho
 }
 
 // ------------------------------------------------------------------ traces
-// u at receiver nodes, one thread per (shot, receiver), beams staged in LDS.
+// u at receiver nodes.  Workgroup (split, shot, receiver block): one thread
+// per receiver, one slice of the shot's beams staged through LDS; the slices
+// write partial sums that a second kernel adds in slice order.
 #define TR_BLOCK 256
 
 __global__ void __launch_bounds__(TR_BLOCK)
-k_trace_points(SplatArgs A, const int32_t *__restrict__ rec, int nrec, double *out,
-               int64_t stride_shot)
+k_trace_points(SplatArgs A, const int32_t *__restrict__ rec, int nrec, double *partial)
 {
     __shared__ double sb[7][TR_BLOCK];
-    int s = blockIdx.y;
-    int r = blockIdx.x * TR_BLOCK + threadIdx.x;
+    const int split = blockIdx.x, s = blockIdx.y;
+    const int r = blockIdx.z * TR_BLOCK + threadIdx.x;
     int i1 = 0, i2 = 0;
     if (r < nrec) {
         int node = rec[r];
         i1 = node % A.n1;
         i2 = node / A.n1;
     }
-    double x1 = A.o1 + i1 * A.d1, x2 = A.o2 + i2 * A.d2;
+    const double x1 = A.o1 + i1 * A.d1, x2 = A.o2 + i2 * A.d2;
     const int64_t b0 = A.offsets[s], b1 = A.offsets[s + 1];
+    const int64_t nbs = b1 - b0;
+    const int64_t lo = b0 + nbs * split / A.nsplit, hi = b0 + nbs * (split + 1) / A.nsplit;
     const int64_t cap = A.cap;
     double acc = 0.0;
-    for (int64_t base = b0; base < b1; base += TR_BLOCK) {
+    for (int64_t base = lo; base < hi; base += TR_BLOCK) {
         int64_t b = base + threadIdx.x;
-        if (b < b1) {
+        if (b < hi) {
             const double *p = A.f + b;
             double ar = p[(FGA_F_STATE + 21) * cap], ai = p[(FGA_F_STATE + 22) * cap];
             double Cr = p[4 * cap], Ci = p[5 * cap];
@@ -531,7 +534,7 @@ k_trace_points(SplatArgs A, const int32_t *__restrict__ rec, int nrec, double *o
             sb[6][threadIdx.x] = Cr * ai + Ci * ar;
         }
         __syncthreads();
-        int nb = (int)min((int64_t)TR_BLOCK, b1 - base);
+        int nb = (int)min((int64_t)TR_BLOCK, hi - base);
         if (r < nrec) {
             for (int k = 0; k < nb; ++k) {
                 double Q1 = sb[0][k], Q2 = sb[1][k];
@@ -548,7 +551,19 @@ k_trace_points(SplatArgs A, const int32_t *__restrict__ rec, int nrec, double *o
         }
         __syncthreads();
     }
-    if (r < nrec) out[(size_t)s * stride_shot + r] = acc;
+    if (r < nrec) partial[((size_t)s * A.nsplit + split) * nrec + r] = acc;
+}
+
+__global__ void k_trace_reduce(const double *__restrict__ partial, int nsplit, int nrec,
+                               int nshots, double *out, int64_t stride_shot)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrec * nshots) return;
+    int s = i / nrec, r = i % nrec;
+    const double *p = partial + (size_t)s * nsplit * nrec + r;
+    double v = 0.0;
+    for (int k = 0; k < nsplit; ++k) v += p[(size_t)k * nrec];
+    out[(size_t)s * stride_shot + r] = v;
 }
 
 fga_status fga_launch_trace_points(fga_ctx *ctx, const fga_beams *beams, int nshots,
@@ -556,6 +571,13 @@ fga_status fga_launch_trace_points(fga_ctx *ctx, const fga_beams *beams, int nsh
                                    int64_t stride_shot)
 {
     const fga_grid &g = ctx->g;
+    const int rblocks = (nrec + TR_BLOCK - 1) / TR_BLOCK;
+    int want = (4 * ctx->num_cu + nshots * rblocks - 1) / (nshots * rblocks);
+    int nsplit = want < 1 ? 1 : (want > 256 ? 256 : want);
+    fga_status rc = fga_ensure(ctx, &ctx->trace_part, &ctx->trace_part_bytes,
+                               (size_t)nshots * nsplit * nrec * sizeof(double),
+                               "trace partial sums");
+    if (rc != FGA_OK) return rc;
     SplatArgs A{};
     A.f = beams->f;
     A.offsets = beams->offsets;
@@ -571,8 +593,11 @@ fga_status fga_launch_trace_points(fga_ctx *ctx, const fga_beams *beams, int nsh
     A.half_inv_eps = 0.5 / ctx->p.eps;
     A.Rw1 = ctx->Rw1;
     A.Rw2 = ctx->Rw2;
-    dim3 grid((nrec + TR_BLOCK - 1) / TR_BLOCK, nshots);
-    hipLaunchKernelGGL(k_trace_points, grid, dim3(TR_BLOCK), 0, ctx->stream, A, rec, nrec, out,
+    A.nsplit = nsplit;
+    hipLaunchKernelGGL(k_trace_points, dim3(nsplit, nshots, rblocks), dim3(TR_BLOCK), 0,
+                       ctx->stream, A, rec, nrec, (double *)ctx->trace_part);
+    hipLaunchKernelGGL(k_trace_reduce, dim3((nrec * nshots + 255) / 256), dim3(256), 0,
+                       ctx->stream, (const double *)ctx->trace_part, nsplit, nrec, nshots, out,
                        stride_shot);
     FGA_HIP(ctx, hipGetLastError());
     return FGA_OK;

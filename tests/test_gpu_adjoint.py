@@ -66,3 +66,58 @@ def test_adjoint_mixed_within_1e5():
     assert r["status"][0] == 0
     assert np.linalg.norm(r["dc"] - dc) / np.linalg.norm(dc) <= 1e-5
     assert np.linalg.norm(r["df0"] - df0) / np.linalg.norm(df0) <= 1e-5
+
+
+def test_adjoint_full_size_matches_finite_differences():
+    """adjoint256 at full size (8 shots, 256 receivers, 25 records, 250
+    steps): dJ/dc from the adjoint equals central differences of the FP64
+    GPU forward with the beam set held fixed, at 32 seeded cells (and the
+    4 cells of largest gradient)."""
+    import torch
+    import fga_inputs as fi
+    import paper_1304_3542_amd as fga
+    W = fi.workload("adjoint256", "fp64")
+    g, p = W.grid, W.params
+    ns = W.nshots
+    nrec_t = p.nsteps // W.rec_every
+    ctx = fga.FGA(g, p, "fp64", max_shots=ns)
+    c = torch.from_numpy(W.c).cuda()
+    ctx.set_velocity(c)
+    f0 = torch.from_numpy(np.ascontiguousarray(W.f0)).cuda()
+    beams = fga.Beams(2 * p.nq1 * p.nq2 * p.np1 * p.np2 * ns, ns)
+    ctx.decompose(f0, None, beams)
+    nb = int(ctx.offsets(beams, ns)[-1])
+    assert ctx.status()[0] == 0 and nb > 10000
+    f_init = beams.f.clone()
+    rec = torch.from_numpy(W.receivers).cuda()
+    ctx.set_velocity(torch.from_numpy(W.c_true).cuda())
+    data = ctx.trace(beams, ns, rec, W.rec_every, nrec_t)
+
+    def J(cgrid):
+        beams.f.copy_(f_init)
+        ctx.set_velocity(cgrid)
+        tr = ctx.trace(beams, ns, rec, W.rec_every, nrec_t)
+        return 0.5 * float(((tr - data) ** 2).sum())
+
+    beams.f.copy_(f_init)
+    ctx.set_velocity(c)
+    ckpt = torch.empty((nrec_t, fga.FGA_NSTATE, beams.capacity), dtype=torch.float64,
+                       device="cuda")
+    tr = ctx.trace(beams, ns, rec, W.rec_every, nrec_t, ckpt)
+    dc = torch.zeros_like(c)
+    ctx.trace_adjoint(beams, ns, rec, W.rec_every, nrec_t, ckpt, (tr - data).contiguous(), dc)
+    assert ctx.status()[0] == 0
+    dcn = dc.cpu().numpy()
+    scale = np.abs(dcn).max()
+    assert scale > 0
+    r = fi.rng(32)
+    cells = list(r.choice(c.numel(), 32, replace=False)) + list(np.argsort(-np.abs(dcn).ravel())[:4])
+    cn = W.c.copy()
+    for idx in cells:
+        i2, i1 = np.unravel_index(idx, cn.shape)
+        h = 1e-6 * cn[i2, i1]
+        cp, cm = cn.copy(), cn.copy()
+        cp[i2, i1] += h
+        cm[i2, i1] -= h
+        fd = (J(torch.from_numpy(cp).cuda()) - J(torch.from_numpy(cm).cuda())) / (2 * h)
+        assert abs(fd - dcn[i2, i1]) <= 1e-6 * scale, (idx, fd, dcn[i2, i1], scale)
