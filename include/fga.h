@@ -174,6 +174,30 @@ fga_status fga_decompose_adjoint(fga_ctx *ctx, const fga_beams *beams, int32_t n
                                  const double *gcoef_dev, double *df0_dev, double *df1_dev,
                                  double *dc_dev);
 
+/* Batched forward under a HIP graph (many shots with uneven beam counts in
+ * one set of launches: every kernel reads the per-shot beam ranges from the
+ * device offsets, so nothing is read back on the host).  fga_graph_capture
+ * runs decompose -> propagate(nsteps) -> reconstruct once on the context's
+ * stream (sizing every workspace), then records the same sequence into a
+ * graph on a context-owned capture stream and instantiates it; the stream
+ * must not be capturing already.  fga_graph_launch replays it on the
+ * context's stream with the pointers given at capture (update the inputs in
+ * place between replays).  A later capture replaces the graph.             */
+fga_status fga_graph_capture(fga_ctx *ctx, int32_t nshots, const double *f0_dev,
+                             const double *f1_dev, fga_beams *beams, int32_t nsteps,
+                             double *u_dev);
+fga_status fga_graph_launch(fga_ctx *ctx);
+
+/* Splat autotuner: times fga_reconstruct of these (already propagated)
+ * beams for a ladder of work splits (wavefronts per CU for the mixed MFMA
+ * splat, workgroups per CU for the FP64 splat), keeps the fastest for this
+ * context and appends it to the JSON-lines cache cache_path (may be NULL),
+ * keyed by grid size, window, precision, shot count and CU count; a cached
+ * key is reused without timing.  u_dev is overwritten.  *chosen (may be
+ * NULL) receives the choice.  Synchronises the stream.                     */
+fga_status fga_autotune(fga_ctx *ctx, const fga_beams *beams, int32_t nshots, double *u_dev,
+                        const char *cache_path, int32_t *chosen);
+
 /* Synchronise the stream, read the sticky device status word and clear it.
  * *needed (may be NULL) receives the beam count a capacity overflow needed. */
 fga_status fga_sync_status(fga_ctx *ctx, int64_t *needed);

@@ -74,6 +74,10 @@ def load(path: str = LIB_PATH):
         "fga_trace": [C, ctypes.POINTER(fga_beams), I32, P, I32, I32, I32, P, P],
         "fga_trace_adjoint": [C, ctypes.POINTER(fga_beams), I32, P, I32, I32, I32, P, P, P, P],
         "fga_decompose_adjoint": [C, ctypes.POINTER(fga_beams), I32, P, P, P, P],
+        "fga_graph_capture": [C, I32, P, P, ctypes.POINTER(fga_beams), I32, P],
+        "fga_graph_launch": [C],
+        "fga_autotune": [C, ctypes.POINTER(fga_beams), I32, P, ctypes.c_char_p,
+                         ctypes.POINTER(ctypes.c_int32)],
         "fga_sync_status": [C, ctypes.POINTER(ctypes.c_int64)],
         "fga_copy_offsets": [C, ctypes.POINTER(fga_beams), I32, P],
         "fga_last_error": [C],
@@ -168,6 +172,26 @@ def fga_decompose_adjoint(ctx, beams: "Beams", nshots: int, gcoef, df0, df1=None
         _require(t, n, "float64")
     _check(ctx, load().fga_decompose_adjoint(ctx, beams.c_struct(), int(nshots), _ptr(gcoef),
                                              _ptr(df0), _ptr(df1), _ptr(dc)))
+
+
+def fga_graph_capture(ctx, nshots: int, f0, f1, beams: "Beams", nsteps: int, u):
+    _require(f0, "f0", "float64")
+    _require(u, "u", "float64")
+    _check(ctx, load().fga_graph_capture(ctx, int(nshots), _ptr(f0), _ptr(f1), beams.c_struct(),
+                                         int(nsteps), _ptr(u)))
+
+
+def fga_graph_launch(ctx):
+    _check(ctx, load().fga_graph_launch(ctx))
+
+
+def fga_autotune(ctx, beams: "Beams", nshots: int, u, cache_path: Optional[str] = None) -> int:
+    _require(u, "u", "float64")
+    chosen = ctypes.c_int32(0)
+    _check(ctx, load().fga_autotune(ctx, beams.c_struct(), int(nshots), _ptr(u),
+                                    None if cache_path is None else cache_path.encode(),
+                                    ctypes.byref(chosen)))
+    return chosen.value
 
 
 def fga_sync_status(ctx):
@@ -278,6 +302,15 @@ class FGA:
                           device=beams.f.device)
         fga_decompose_adjoint(self.ctx, beams, nshots, gcoef, df0, df1, dc)
         return df0
+
+    def graph_capture(self, f0, f1, beams: Beams, nsteps: int, u):
+        fga_graph_capture(self.ctx, f0.shape[0], f0, f1, beams, nsteps, u)
+
+    def graph_launch(self):
+        fga_graph_launch(self.ctx)
+
+    def autotune(self, beams: Beams, nshots: int, u, cache_path: Optional[str] = None) -> int:
+        return fga_autotune(self.ctx, beams, nshots, u, cache_path)
 
     def status(self):
         return fga_sync_status(self.ctx)

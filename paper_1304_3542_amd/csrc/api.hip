@@ -29,6 +29,8 @@ fga_status fga_hip_check(fga_ctx *ctx, hipError_t e, const char *what)
 fga_status fga_ensure(fga_ctx *ctx, void **buf, size_t *have, size_t need, const char *what)
 {
     if (*have >= need && *buf) return FGA_OK;
+    if (ctx->capturing)
+        return fga_fail(ctx, FGA_ESTATE, "%s would need an allocation during graph capture", what);
     if (*buf) {
         // the old buffer may still be read by queued work
         hipError_t e = hipStreamSynchronize(ctx->stream);
@@ -132,6 +134,9 @@ extern "C" fga_status fga_destroy(fga_ctx *ctx)
 {
     if (!ctx) return FGA_OK;
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     void *bufs[] = {ctx->c, ctx->cpad, ctx->status, ctx->cq, ctx->maxbits, ctx->E1t, ctx->E2,
                     ctx->T, ctx->Psi, ctx->blk, ctx->partial, ctx->srec, ctx->sbox,
                     ctx->adj_scratch, ctx->adj_psib, ctx->trace_part};
@@ -281,6 +286,147 @@ extern "C" fga_status fga_decompose_adjoint(fga_ctx *ctx, const fga_beams *beams
     if (ctx->last_nfj == 2 && (!df1 || !dc))
         return fga_fail(ctx, FGA_EINVAL, "the decomposition used f1: df1 and dc are required");
     return fga_launch_decompose_adjoint(ctx, beams, nshots, gcoef, df0, df1, dc);
+}
+
+// One forward pass (decompose, propagate, reconstruct) of nshots shots.
+static fga_status forward_pass(fga_ctx *ctx, int nshots, const double *f0, const double *f1,
+                               fga_beams *beams, int nsteps, double *u)
+{
+    fga_status st = fga_launch_decompose(ctx, nshots, f0, f1, beams);
+    if (st == FGA_OK && nsteps > 0) st = fga_launch_propagate(ctx, beams, nshots, nsteps, nullptr);
+    if (st == FGA_OK) st = fga_launch_reconstruct(ctx, beams, nshots, u);
+    return st;
+}
+
+extern "C" fga_status fga_graph_capture(fga_ctx *ctx, int32_t nshots, const double *f0,
+                                        const double *f1, fga_beams *beams, int32_t nsteps,
+                                        double *u)
+{
+    if (!ctx) return FGA_EINVAL;
+    fga_status st = check_beams(ctx, beams);
+    if (st != FGA_OK) return st;
+    if (nshots < 1 || nshots > ctx->max_shots || !f0 || !u || nsteps < 0)
+        return fga_fail(ctx, FGA_EINVAL, "bad graph-capture arguments");
+    if (!ctx->have_c) return fga_fail(ctx, FGA_ESTATE, "fga_set_velocity was not called");
+    // one eager pass on the context's stream sizes every workspace
+    st = forward_pass(ctx, nshots, f0, f1, beams, nsteps, u);
+    if (st != FGA_OK) return st;
+    FGA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->graph_exec) {
+        FGA_HIP(ctx, hipGraphExecDestroy(ctx->graph_exec));
+        ctx->graph_exec = nullptr;
+    }
+    if (ctx->graph) {
+        FGA_HIP(ctx, hipGraphDestroy(ctx->graph));
+        ctx->graph = nullptr;
+    }
+    if (!ctx->cap_stream) FGA_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = ctx->stream;
+    ctx->stream = ctx->cap_stream;
+    ctx->capturing = true;
+    hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = forward_pass(ctx, nshots, f0, f1, beams, nsteps, u);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (st == FGA_OK && e2 != hipSuccess) st = fga_hip_check(ctx, e2, "hipStreamEndCapture");
+        if (st == FGA_OK) {
+            ctx->graph = g;
+            hipError_t e3 = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+            if (e3 != hipSuccess) st = fga_hip_check(ctx, e3, "hipGraphInstantiate");
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+    } else {
+        st = fga_hip_check(ctx, e, "hipStreamBeginCapture");
+    }
+    ctx->capturing = false;
+    ctx->stream = user;
+    return st;
+}
+
+extern "C" fga_status fga_graph_launch(fga_ctx *ctx)
+{
+    if (!ctx) return FGA_EINVAL;
+    if (!ctx->graph_exec) return fga_fail(ctx, FGA_ESTATE, "no captured graph");
+    FGA_HIP(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
+    return FGA_OK;
+}
+
+// Times the reconstruction for a ladder of work splits on the given beams
+// (which must be propagated already), keeps the fastest, and records it in
+// a JSON-lines cache keyed by grid, window, precision and shot count.
+extern "C" fga_status fga_autotune(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
+                                   double *u, const char *cache_path, int32_t *chosen)
+{
+    if (!ctx) return FGA_EINVAL;
+    fga_status st = check_beams(ctx, beams);
+    if (st != FGA_OK) return st;
+    if (nshots < 1 || nshots > ctx->max_shots || !u)
+        return fga_fail(ctx, FGA_EINVAL, "bad autotune arguments");
+    char key[256];
+    snprintf(key, sizeof key, "%dx%d|Rw%dx%d|prec%d|shots%d|cu%d", ctx->g.n1, ctx->g.n2,
+             ctx->Rw1, ctx->Rw2, ctx->prec, nshots, ctx->num_cu);
+    if (cache_path) {
+        FILE *fp = fopen(cache_path, "r");
+        if (fp) {
+            char line[512], k[256];
+            int v;
+            int found = 0;
+            while (fgets(line, sizeof line, fp))
+                if (sscanf(line, "{\"key\": \"%255[^\"]\", \"splat_units_per_cu\": %d}", k, &v) == 2 &&
+                    strcmp(k, key) == 0) {
+                    ctx->splat_units_per_cu = v;
+                    found = 1;
+                }
+            fclose(fp);
+            if (found) {
+                if (chosen) *chosen = ctx->splat_units_per_cu;
+                return FGA_OK;
+            }
+        }
+    }
+    const int mixed[] = {4, 8, 16, 32, 64, 128};
+    const int fp64[] = {1, 2, 4, 8, 16};
+    const int *cand = ctx->prec == FGA_MIXED ? mixed : fp64;
+    int ncand = ctx->prec == FGA_MIXED ? 6 : 5;
+    hipEvent_t e0, e1;
+    FGA_HIP(ctx, hipEventCreate(&e0));
+    FGA_HIP(ctx, hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_v = 0;
+    for (int i = 0; i < ncand && st == FGA_OK; ++i) {
+        ctx->splat_units_per_cu = cand[i];
+        st = fga_launch_reconstruct(ctx, beams, nshots, u);   // sizes the workspace
+        if (st != FGA_OK) break;
+        float tot = 0.f;
+        for (int r = 0; r < 3 && st == FGA_OK; ++r) {
+            (void)hipEventRecord(e0, ctx->stream);
+            st = fga_launch_reconstruct(ctx, beams, nshots, u);
+            (void)hipEventRecord(e1, ctx->stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            tot += ms;
+        }
+        if (tot < best) {
+            best = tot;
+            best_v = cand[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != FGA_OK) return st;
+    ctx->splat_units_per_cu = best_v;
+    if (chosen) *chosen = best_v;
+    if (cache_path) {
+        FILE *fp = fopen(cache_path, "a");
+        if (fp) {
+            fprintf(fp, "{\"key\": \"%s\", \"splat_units_per_cu\": %d}\n", key, best_v);
+            fclose(fp);
+        }
+    }
+    return FGA_OK;
 }
 
 extern "C" fga_status fga_sync_status(fga_ctx *ctx, int64_t *needed)

@@ -55,6 +55,16 @@ struct fga_ctx {
     // sticky device status: [0] flags, [1] needed capacity
     int64_t *status;
 
+    // splat work split: target wavefronts (mixed) or workgroups (FP64) per
+    // CU; 0 = built-in default, set by fga_autotune
+    int splat_units_per_cu;
+
+    // graph capture / replay of the whole forward
+    bool capturing;
+    hipStream_t cap_stream;
+    hipGraph_t graph;
+    hipGraphExec_t graph_exec;
+
     char err[512];
 };
 

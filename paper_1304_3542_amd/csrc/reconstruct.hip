@@ -448,7 +448,8 @@ fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nsho
     // unit; FP64: one workgroup of four wavefronts per unit)
     // mixed: about 32 wavefronts per CU, so that the dispatcher evens out
     // tiles of very different load; FP64: 4 workgroups per CU
-    int want_units = mfma ? 32 * ctx->num_cu : 4 * ctx->num_cu;
+    int per_cu = ctx->splat_units_per_cu > 0 ? ctx->splat_units_per_cu : (mfma ? 32 : 4);
+    int want_units = per_cu * ctx->num_cu;
     int want = (want_units + tiles * nshots - 1) / (tiles * nshots);
     int nsplit = want < 1 ? 1 : (want > 256 ? 256 : want);
     size_t npts = (size_t)g.n1 * g.n2;
