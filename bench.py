@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="rough budget of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=3,
+                    help="timed graph replays of the 64-shot batch (0 skips it)")
     ap.add_argument("--adjoint-steps", type=int, default=3,
                     help="timed iterations of the adjoint workload (0 skips it)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -207,6 +209,49 @@ def adjoint_iteration(steps):
             "status": st, "workload": "adjoint256: 256x256 on [0,2]x[0,1], eps=1/128, 8 surface "
             "shots, 256 receivers on the top row every 10 steps, T=0.25 s, FP64 gradient "
             "w.r.t. c and f0"}
+
+
+def batched_shots(steps):
+    """64 surface shots with uneven beam counts (shots512, mixed precision)
+    as one graph: capture decompose -> propagate -> reconstruct once, then
+    time replays; the splat split is chosen by the autotuner."""
+    import torch
+    import paper_1304_3542_amd as fga
+    W = fi.workload("shots512", "mixed")
+    ns = W.nshots
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = fga.FGA(W.grid, W.params, "mixed", max_shots=ns)
+        ctx.set_velocity(torch.from_numpy(W.c).cuda())
+        f0 = torch.from_numpy(np.ascontiguousarray(W.f0)).cuda()
+        beams = fga.Beams(4_000_000, ns)
+        ctx.decompose(f0, None, beams)
+        st, need = ctx.status()
+        if st == fga.FGA_ECAPACITY:
+            beams = fga.Beams(int(need * 1.05) + 1024, ns)
+            ctx.decompose(f0, None, beams)
+        off = ctx.offsets(beams, ns)
+        counts = np.diff(off)
+        u = torch.empty((ns, W.grid.n2, W.grid.n1), dtype=torch.float64, device="cuda")
+        ctx.propagate(beams, ns, W.params.nsteps)
+        chosen = ctx.autotune(beams, ns, u)
+        ctx.graph_capture(f0, None, beams, W.params.nsteps, u)
+        ctx.graph_launch()
+        stream.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(steps):
+            ctx.graph_launch()
+        ev[1].record(stream)
+        stream.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / steps
+        st, _ = ctx.status()
+    nb = int(off[-1])
+    return {"workload": "shots512: 64 surface shots on the 512x512 model, random width "
+            "1-4 cells and wavenumber 0.5-2, q 20x10, p 56x56, tau=1e-4, mixed, one graph",
+            "nshots": ns, "nbeams": nb, "beams_per_shot_min": int(counts.min()),
+            "beams_per_shot_max": int(counts.max()), "ms_per_replay": ms,
+            "beams_per_s": nb / (ms * 1e-3), "splat_units_per_cu": chosen, "status": st}
 
 
 def box_pairs(f, nb, W, tau_win):
@@ -367,6 +412,8 @@ def main():
     }
     if args.adjoint_steps > 0:
         out["adjoint"] = adjoint_iteration(args.adjoint_steps)
+    if args.batch_steps > 0:
+        out["batched"] = batched_shots(args.batch_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Wd, nb, args.cpu_seconds)
     print(json.dumps(out), flush=True)

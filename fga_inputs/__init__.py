@@ -256,7 +256,7 @@ def workload(name: str, precision: str = "fp64", nshots: Optional[int] = None) -
         eps = 1 / 1024
         c = smooth_layered_velocity(grid, seed=5)
         f0 = gaussian_source(grid, (1.0, 0.5), 2 * grid.d1)
-        p = Params(eps, 10, 0, 14, 14, 147, 74, 400, 400, 0.0141, 0.0141,
+        p = Params(eps, 3, 0, 14, 14, 147, 74, 400, 400, 0.0141, 0.0141,
                    1e-6, tw, tw, 1e-3, 250)
         return Workload(name, grid, p, c, f0[None], None)
     raise KeyError(name)

@@ -83,3 +83,21 @@ def test_null_context_calls_fail_cleanly():
     assert lib.fga_propagate(None, None, 1, 1) == fga.FGA_EINVAL
     assert lib.fga_reconstruct(None, None, 1, None) == fga.FGA_EINVAL
     assert lib.fga_sync_status(None, None) == fga.FGA_EINVAL
+
+
+@pytest.mark.parametrize("name", fi.WORKLOADS)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_every_workload_passes_host_validation(name, precision):
+    """The named workloads are valid for fga_create (argument checks run on
+    the host before any device call, so without a GPU the call ends at the
+    device query, never with FGA_EINVAL)."""
+    import paper_1304_3542_amd as fga
+    W = fi.workload(name, precision)
+    g, p = _structs(W.grid, W.params)
+    lib = fga.load()
+    ctx = ctypes.c_void_p()
+    st = lib.fga_create(ctypes.byref(ctx), ctypes.byref(g), ctypes.byref(p),
+                        0 if precision == "fp64" else 1, max(W.nshots, 1), None)
+    assert st != fga.FGA_EINVAL, lib.fga_last_error(None)
+    if st == fga.FGA_OK:
+        lib.fga_destroy(ctx)

@@ -138,3 +138,67 @@ def test_trace_matches_oracle():
     tr = ctx.trace(beams, 2, torch.from_numpy(rec).cuda(), 5, 4).cpu().numpy()
     assert ctx.status()[0] == 0
     assert rel_l2(tr, tr_or) <= FP64_TOL
+
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", f"{name}_fp64.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated (tests/golden/make_golden.py)")
+    return np.load(path)
+
+
+def _full_run(W, precision, capacity):
+    import torch
+    import paper_1304_3542_amd as fga
+    ctx = fga.FGA(W.grid, W.params, precision)
+    ctx.set_velocity(torch.from_numpy(W.c).cuda())
+    beams = fga.Beams(capacity, 1)
+    f1 = None if W.f1 is None else torch.from_numpy(np.ascontiguousarray(W.f1)).cuda()
+    ctx.decompose(torch.from_numpy(np.ascontiguousarray(W.f0)).cuda(), f1, beams)
+    assert ctx.status()[0] == 0
+    nb = int(ctx.offsets(beams, 1)[-1])
+    ids = beams.id[:nb].cpu().numpy()
+    coef = beams.f[4:6, :nb].cpu().numpy().T
+    ctx.propagate(beams, 1, W.params.nsteps)
+    u = ctx.reconstruct(beams, 1)[0].cpu().numpy()
+    state = beams.f[6:, :nb].cpu().numpy().T
+    assert ctx.status()[0] == 0
+    return nb, ids, coef, state, u
+
+
+@pytest.mark.parametrize("name", ["point512", "wavepacket"])
+def test_full_size_fp64_against_stored_oracle_values(name):
+    """Full-size workloads (1.2e6 / 1.37e6 beams): beam count, a seeded
+    sample of beams (id, coefficient, state at T) and u(T) at stored nodes
+    against the oracle (values written by tests/golden/make_golden.py)."""
+    z = _golden(name)
+    W = fi.workload(name, "fp64")
+    nb, ids, coef, state, u = _full_run(W, "fp64", int(z["nbeams"]) + 4096)
+    assert nb == int(z["nbeams"])
+    pick = z["pick"]
+    np.testing.assert_array_equal(ids[pick], z["ids"])
+    assert np.abs(coef[pick] - z["coef"]).max() <= FP64_TOL * np.abs(z["coef"]).max()
+    assert pairwise_state_err(state[pick], z["stateT"]) <= FP64_TOL
+    assert rel_l2(u.ravel()[z["nodes"]], z["u"]) <= FP64_TOL
+
+
+def test_full_size_mixed_against_stored_oracle_values():
+    z = _golden("point512")
+    W = fi.workload("point512", "mixed")
+    nb, ids, coef, state, u = _full_run(W, "mixed", int(z["nbeams"]) + 4096)
+    assert abs(nb - int(z["nbeams"])) <= 1e-3 * int(z["nbeams"])
+    assert rel_l2(u.ravel()[z["nodes"]], z["u"]) <= MIXED_TOL
+
+
+def test_wavepacket_against_exact_solution():
+    """Physics check of the whole GPU path (parity unpinned: the O(eps)
+    constant of the asymptotics is not printed in the paper): the FP64 GPU
+    result at T = 0.25 s against the exact spectral solution in c = 1."""
+    import oracle.spectral as spectral
+    W = fi.workload("wavepacket", "fp64")
+    nb, ids, coef, state, u = _full_run(W, "fp64", 1_500_000)
+    ue = spectral.solve(W.f0[0], W.f1[0], W.grid, 1.0, W.params.dt * W.params.nsteps)
+    rel = rel_l2(u, ue)
+    print(f"wavepacket: GPU FGA vs exact rel-L2 = {rel:.3e} ({nb} beams)", flush=True)
+    assert rel < 0.02
