@@ -139,7 +139,7 @@ extern "C" fga_status fga_destroy(fga_ctx *ctx)
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     void *bufs[] = {ctx->c, ctx->cpad, ctx->status, ctx->cq, ctx->maxbits, ctx->E1t, ctx->E2,
                     ctx->T, ctx->Psi, ctx->blk, ctx->partial, ctx->srec, ctx->sbox,
-                    ctx->adj_scratch, ctx->adj_psib, ctx->trace_part};
+                    ctx->adj_scratch, ctx->adj_psib, ctx->trace_part, ctx->bin};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     free(ctx);

@@ -1,0 +1,444 @@
+// Beam -> tile binning and the binned mixed-precision splat.
+//
+// Every beam's truncation box covers a rectangle of 64 x 64 output tiles.
+// The beams are binned into one list per (shot, tile), each list in
+// ascending beam order, without sorting:
+//   1. k_bin_count       one wavefront per chunk of 1024 beams counts, in LDS,
+//                        the beams of the chunk that meet every tile;
+//   2. k_bin_scan_tiles  per tile, an exclusive scan over the chunks (each
+//                        chunk's offset inside the tile's list);
+//      k_bin_scan_items  a scan over the tiles (list starts) and the split of
+//                        every list into work items of equal length (the last
+//                        item of a list shorter);
+//   3. k_bin_fill        each chunk again, 64 beams at a time: for each tile of
+//                        the lanes' union rectangle a ballot ranks the lanes,
+//                        so the lists come out in beam order.
+// The splat runs one wavefront per work item (the grid is sized for the
+// largest possible item count; wavefronts past the device count leave at
+// once); every item writes a private partial tile, and the partial tiles of
+// one tile are added in item order.  All counts stay on the device
+// (graph-capturable), and the result does not depend on scheduling.
+#include "splat.h"
+
+#define BIN_WCH 1024             // beams per wavefront chunk
+#define BIN_ITEM_MIN 256         // hits per work item, at least
+#define BIN_MAX_TILES 8192       // (shot, tile) pairs per call (LDS counters)
+#define BIN_SCAN_GROUPS 16       // chunk groups per tile in the chunk scan
+
+struct BinItem {
+    int64_t start;   // first entry in the list array
+    int32_t len;     // entries
+    int32_t tile;    // shot * ntiles + tile
+};
+
+struct BinArgs {
+    const int64_t *id;
+    const int64_t *offsets;
+    const short4 *box;
+    int nshots;
+    int64_t per_shot;     // candidates per shot (2 Nq Np)
+    int ntile1, ntiles;   // tiles per row, tiles per shot
+    int ntiles_total;
+    int32_t *wcnt;        // [chunk][ntiles_total]: counts, then offsets
+    int64_t *tile_start;  // [ntiles_total + 1]: counts, then list starts
+    int32_t *tile_item;   // [ntiles_total + 1]: first item of each tile
+    BinItem *items;       // [max_items]
+    int64_t *meta;        // [0] hits, [1] items, [2] item length
+    int32_t *list;        // beam indices
+    int items_target;     // the item length is about hits / items_target
+};
+
+__device__ __forceinline__ int bin_nchunks(const BinArgs &B)
+{
+    const int64_t nb = B.offsets[B.nshots];
+    return (int)((nb + BIN_WCH - 1) / BIN_WCH);
+}
+
+__device__ __forceinline__ bool box_tiles(const short4 bx, int &t1lo, int &t1hi, int &t2lo,
+                                          int &t2hi)
+{
+    if (bx.x > bx.y || bx.z > bx.w) return false;
+    t1lo = bx.x / SP_T;
+    t1hi = bx.y / SP_T;
+    t2lo = bx.z / SP_T;
+    t2hi = bx.w / SP_T;
+    return true;
+}
+
+__global__ void __launch_bounds__(64)
+k_bin_count(BinArgs B)
+{
+    extern __shared__ int cnt[];
+    const int lane = threadIdx.x;
+    const int64_t nb = B.offsets[B.nshots];
+    const int nused = bin_nchunks(B);
+    for (int chunk = blockIdx.x; chunk < nused; chunk += gridDim.x) {
+        for (int t = lane; t < B.ntiles_total; t += 64) cnt[t] = 0;
+        __syncthreads();
+        for (int r = 0; r < BIN_WCH / 64; ++r) {
+            const int64_t b = (int64_t)chunk * BIN_WCH + r * 64 + lane;
+            int t1lo, t1hi, t2lo, t2hi;
+            if (b < nb && box_tiles(B.box[b], t1lo, t1hi, t2lo, t2hi)) {
+                const int s = (int)(B.id[b] / B.per_shot);
+                for (int t2 = t2lo; t2 <= t2hi; ++t2)
+                    for (int t1 = t1lo; t1 <= t1hi; ++t1)
+                        atomicAdd(&cnt[s * B.ntiles + t2 * B.ntile1 + t1], 1);
+            }
+        }
+        __syncthreads();
+        int32_t *out = B.wcnt + (size_t)chunk * B.ntiles_total;
+        for (int t = lane; t < B.ntiles_total; t += 64) out[t] = cnt[t];
+        __syncthreads();
+    }
+}
+
+// Exclusive scan over the chunks for 64 tiles per workgroup: thread
+// (group g, lane l) owns tile 64 blockIdx.x + l and a contiguous range of
+// chunks; the wavefront reads 64 consecutive counts per chunk.
+__global__ void __launch_bounds__(64 * BIN_SCAN_GROUPS)
+k_bin_scan_tiles(BinArgs B)
+{
+    __shared__ int64_t gsum[BIN_SCAN_GROUPS][64];
+    const int l = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int t = blockIdx.x * 64 + l;
+    const bool ok = t < B.ntiles_total;
+    const int nused = bin_nchunks(B);
+    const int per = (nused + BIN_SCAN_GROUPS - 1) / BIN_SCAN_GROUPS;
+    const int c0 = min(grp * per, nused), c1 = min(c0 + per, nused);
+    int32_t *col = B.wcnt + t;
+    const size_t ld = (size_t)B.ntiles_total;
+    int64_t sum = 0;
+    if (ok) {
+        for (int c = c0; c < c1; c += 8) {
+            int32_t v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = c + k < c1 ? col[(size_t)(c + k) * ld] : 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sum += v[k];
+        }
+    }
+    gsum[grp][l] = sum;
+    __syncthreads();
+    int64_t run = 0;
+    for (int k = 0; k < grp; ++k) run += gsum[k][l];
+    if (ok) {
+        for (int c = c0; c < c1; c += 8) {
+            int32_t v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = c + k < c1 ? col[(size_t)(c + k) * ld] : 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (c + k < c1) col[(size_t)(c + k) * ld] = (int32_t)run;
+                run += v[k];
+            }
+        }
+        if (grp == BIN_SCAN_GROUPS - 1) B.tile_start[t] = run;   // the tile's count
+    }
+}
+
+// block-wide exclusive scan of v over 1024 threads; returns the total
+__device__ int64_t block_scan_1024(int64_t &v, int64_t *sh)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        int64_t x = t >= o ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += x;
+        __syncthreads();
+    }
+    const int64_t total = sh[1023];
+    v = sh[t] - v;
+    __syncthreads();
+    return total;
+}
+
+#define BIN_PER_THREAD (BIN_MAX_TILES / 1024)
+
+__global__ void __launch_bounds__(1024)
+k_bin_scan_items(BinArgs B)
+{
+    __shared__ int64_t sh[1024];
+    const int t = threadIdx.x;
+    const int T = B.ntiles_total;
+    const int lo = t * BIN_PER_THREAD;
+    int64_t cnt[BIN_PER_THREAD];
+    int64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < BIN_PER_THREAD; ++k) {
+        cnt[k] = lo + k < T ? B.tile_start[lo + k] : 0;
+        sum += cnt[k];
+    }
+    int64_t off = sum;
+    const int64_t H = block_scan_1024(off, sh);
+    int64_t L = (H + B.items_target - 1) / B.items_target;
+    L = L < BIN_ITEM_MIN ? BIN_ITEM_MIN : (L + 63) / 64 * 64;
+    int64_t nit = 0;
+#pragma unroll
+    for (int k = 0; k < BIN_PER_THREAD; ++k) nit += (cnt[k] + L - 1) / L;
+    int64_t ioff = nit;
+    const int64_t NI = block_scan_1024(ioff, sh);
+    if (t == 0) {
+        B.meta[0] = H;
+        B.meta[1] = NI;
+        B.meta[2] = L;
+        B.tile_start[T] = H;
+        B.tile_item[T] = (int32_t)NI;
+    }
+#pragma unroll
+    for (int k = 0; k < BIN_PER_THREAD; ++k) {
+        if (lo + k >= T) break;
+        B.tile_start[lo + k] = off;
+        B.tile_item[lo + k] = (int32_t)ioff;
+        for (int64_t e = 0; e < cnt[k]; e += L, ++ioff) {
+            BinItem it;
+            it.start = off + e;
+            it.len = (int32_t)(cnt[k] - e < L ? cnt[k] - e : L);
+            it.tile = lo + k;
+            B.items[ioff] = it;
+        }
+        off += cnt[k];
+    }
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+__global__ void __launch_bounds__(64)
+k_bin_fill(BinArgs B)
+{
+    extern __shared__ int run[];
+    const int lane = threadIdx.x;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int64_t nb = B.offsets[B.nshots];
+    const int nused = bin_nchunks(B);
+    for (int chunk = blockIdx.x; chunk < nused; chunk += gridDim.x) {
+        for (int t = lane; t < B.ntiles_total; t += 64) run[t] = 0;
+        __syncthreads();
+        const int32_t *woff = B.wcnt + (size_t)chunk * B.ntiles_total;
+        for (int r = 0; r < BIN_WCH / 64; ++r) {
+            const int64_t b = (int64_t)chunk * BIN_WCH + r * 64 + lane;
+            int t1lo = 0, t1hi = -1, t2lo = 0, t2hi = -1, s = -1;
+            if (b < nb && box_tiles(B.box[b], t1lo, t1hi, t2lo, t2hi))
+                s = (int)(B.id[b] / B.per_shot);
+            const int smin = wave_min(s < 0 ? 0x7fffffff : s), smax = wave_max(s);
+            for (int ss = smin; ss <= smax; ++ss) {
+                const bool mine = s == ss;
+                if (!__ballot(mine)) continue;
+                const int u1lo = wave_min(mine ? t1lo : 0x7fffffff);
+                const int u1hi = wave_max(mine ? t1hi : -1);
+                const int u2lo = wave_min(mine ? t2lo : 0x7fffffff);
+                const int u2hi = wave_max(mine ? t2hi : -1);
+                for (int t2 = u2lo; t2 <= u2hi; ++t2)
+                    for (int t1 = u1lo; t1 <= u1hi; ++t1) {
+                        const bool hit =
+                            mine && t1 >= t1lo && t1 <= t1hi && t2 >= t2lo && t2 <= t2hi;
+                        const unsigned long long m = __ballot(hit);
+                        if (!m) continue;
+                        const int tt = ss * B.ntiles + t2 * B.ntile1 + t1;
+                        const int base = run[tt];
+                        if (hit)
+                            B.list[B.tile_start[tt] + woff[tt] + base + __popcll(m & below)] =
+                                (int32_t)b;
+                        __builtin_amdgcn_wave_barrier();
+                        if (lane == 0) run[tt] = base + __popcll(m);
+                        __builtin_amdgcn_wave_barrier();
+                    }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_splat_binned(SplatArgs A, BinArgs B, const SplatRec *__restrict__ rec)
+{
+    // records of the current 64 list entries; wavefront-private, read back
+    // with uniform addresses
+    __shared__ SplatRec stage_rec[4][64];
+    SplatRec *st = stage_rec[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63;
+    const int it = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const float hl2e = (float)A.half_inv_eps * 1.4426950408889634f;
+    // whole wavefronts leave; no workgroup barrier below
+    if (it < (int)B.meta[1]) {
+        const BinItem item = B.items[it];
+        const int t = item.tile % B.ntiles;
+        const int X0 = (t % A.ntile1) * SP_T, Z0 = (t / A.ntile1) * SP_T;
+        const int i1 = X0 + lane, i2 = Z0 + lane;
+        const double x1 = A.o1 + i1 * A.d1, x2 = A.o2 + i2 * A.d2;
+        floatx16 acc00, acc01, acc10, acc11;
+        double acc64[4][16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            acc00[r] = acc01[r] = acc10[r] = acc11[r] = 0.f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc64[q][r] = 0.0;
+        }
+        const int32_t *lst = B.list + item.start;
+        int32_t b_next = lane < item.len ? lst[lane] : 0;
+        int chunks = 0;
+        for (int k0 = 0; k0 < item.len; k0 += 64) {
+            const int nk = min(64, item.len - k0);
+            const int32_t b = b_next;
+            if (k0 + 64 + lane < item.len) b_next = lst[k0 + 64 + lane];
+            if (lane < nk) {
+                const float4 *src = reinterpret_cast<const float4 *>(rec + b);
+                float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
+                float4 *dst = reinterpret_cast<float4 *>(st + lane);
+                dst[0] = q0;
+                dst[1] = q1;
+                dst[2] = q2;
+                dst[3] = q3;
+            }
+            __builtin_amdgcn_wave_barrier();
+            // software pipeline: the next record is read and its factors
+            // formed while the matrix cores work on the current beam
+            SplatRec r = st[0];
+            Frags fr = beam_frags(r, i1, i2, x1, x2, hl2e);
+            for (int k = 1; k < nk; ++k) {
+                SplatRec rn = st[k];
+                tile_update(fr, r, X0, Z0, acc00, acc01, acc10, acc11);
+                r = rn;
+                fr = beam_frags(r, i1, i2, x1, x2, hl2e);
+            }
+            tile_update(fr, r, X0, Z0, acc00, acc01, acc10, acc11);
+            __builtin_amdgcn_wave_barrier();
+            // fold the FP32 sums (256 beams at most) into FP64
+            if (++chunks == 4) {
+                chunks = 0;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    acc64[0][k] += (double)acc00[k];
+                    acc64[1][k] += (double)acc01[k];
+                    acc64[2][k] += (double)acc10[k];
+                    acc64[3][k] += (double)acc11[k];
+                    acc00[k] = acc01[k] = acc10[k] = acc11[k] = 0.f;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            acc64[0][k] += (double)acc00[k];
+            acc64[1][k] += (double)acc01[k];
+            acc64[2][k] += (double)acc10[k];
+            acc64[3][k] += (double)acc11[k];
+        }
+        // D[i][j] of a 32 x 32 block: j = lane % 32, i = 8 (r / 4) + 4 (lane / 32) + r % 4;
+        // block (a, c) covers tile rows 32 a + i and tile columns 32 c + j
+        double *out = A.partial + (size_t)it * SP_T * SP_T;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int row = 32 * (q >> 1) + 8 * (k >> 2) + 4 * (lane >> 5) + (k & 3);
+                const int col = 32 * (q & 1) + (lane & 31);
+                out[row * SP_T + col] = acc64[q][k];
+            }
+    }
+}
+
+// u[s][i2][i1] = the sum of the partial tiles of its tile, in item order
+__global__ void k_splat_reduce_binned(SplatArgs A, BinArgs B, double *__restrict__ u)
+{
+    const int64_t npts = (int64_t)A.n1 * A.n2;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npts * B.nshots;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int s = (int)(i / npts);
+        const int64_t x = i - s * npts;
+        const int i2 = (int)(x / A.n1), i1 = (int)(x - (int64_t)i2 * A.n1);
+        const int tt = s * B.ntiles + (i2 / SP_T) * A.ntile1 + i1 / SP_T;
+        const int local = (i2 % SP_T) * SP_T + (i1 % SP_T);
+        const int a = B.tile_item[tt], e = B.tile_item[tt + 1];
+        double v = 0.0;
+        for (int it = a; it < e; ++it) v += A.partial[(size_t)it * SP_T * SP_T + local];
+        u[i] = v;
+    }
+}
+
+bool fga_splat_binned_fits(const fga_ctx *ctx, int nshots)
+{
+    const int64_t nt1 = (ctx->g.n1 + SP_T - 1) / SP_T, nt2 = (ctx->g.n2 + SP_T - 1) / SP_T;
+    return nt1 * nt2 * nshots <= BIN_MAX_TILES;
+}
+
+// Launches the binned splat of the records and boxes k_splat_prep wrote.
+fga_status fga_launch_splat_binned(fga_ctx *ctx, const fga_beams *beams, int nshots, double *u,
+                                   SplatArgs A, const void *rec, const void *box)
+{
+    const fga_grid &g = ctx->g;
+    const int nt1 = (g.n1 + SP_T - 1) / SP_T, nt2 = (g.n2 + SP_T - 1) / SP_T;
+    const int ntiles = nt1 * nt2;
+    const int T = ntiles * nshots;
+    if (T > BIN_MAX_TILES)
+        return fga_fail(ctx, FGA_EINVAL, "binned splat: %d tiles exceed %d", T, BIN_MAX_TILES);
+    const int64_t cap = beams->capacity;
+    const int64_t nchunks = (cap + BIN_WCH - 1) / BIN_WCH;
+    // tiles one box can meet along each axis (a box is 2 Rw + 1 nodes wide)
+    const int64_t tp1 = std::min<int64_t>(nt1, 2 * ctx->Rw1 / SP_T + 2);
+    const int64_t tp2 = std::min<int64_t>(nt2, 2 * ctx->Rw2 / SP_T + 2);
+    // one wavefront per item: about units wavefronts per CU, set by the
+    // autotuner.  The sum over tiles of ceil(count / L) is at most
+    // hits / L + tiles, and hits / L <= items_target.
+    const int units = ctx->splat_units_per_cu > 0 ? ctx->splat_units_per_cu : 32;
+    const int items_target = units * ctx->num_cu;
+    const int max_items = items_target + T;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    const size_t o_wcnt = take((size_t)nchunks * T * sizeof(int32_t));
+    const size_t o_ts = take((size_t)(T + 1) * sizeof(int64_t));
+    const size_t o_ti = take((size_t)(T + 1) * sizeof(int32_t));
+    const size_t o_items = take((size_t)max_items * sizeof(BinItem));
+    const size_t o_meta = take(4 * sizeof(int64_t));
+    const size_t o_list = take((size_t)cap * tp1 * tp2 * sizeof(int32_t));
+    fga_status rc = fga_ensure(ctx, &ctx->bin, &ctx->bin_bytes, off, "binning workspace");
+    if (rc != FGA_OK) return rc;
+    rc = fga_ensure(ctx, (void **)&ctx->partial, &ctx->partial_bytes,
+                    (size_t)max_items * SP_T * SP_T * sizeof(double), "splat partials");
+    if (rc != FGA_OK) return rc;
+    char *w = (char *)ctx->bin;
+    BinArgs B;
+    B.id = beams->id;
+    B.offsets = beams->offsets;
+    B.box = (const short4 *)box;
+    B.nshots = nshots;
+    B.per_shot = 2LL * ctx->p.nq1 * ctx->p.nq2 * ctx->p.np1 * ctx->p.np2;
+    B.ntile1 = nt1;
+    B.ntiles = ntiles;
+    B.ntiles_total = T;
+    B.wcnt = (int32_t *)(w + o_wcnt);
+    B.tile_start = (int64_t *)(w + o_ts);
+    B.tile_item = (int32_t *)(w + o_ti);
+    B.items = (BinItem *)(w + o_items);
+    B.meta = (int64_t *)(w + o_meta);
+    B.list = (int32_t *)(w + o_list);
+    B.items_target = items_target;
+    A.partial = ctx->partial;
+    A.ntile1 = nt1;
+    const size_t lds = (size_t)T * sizeof(int);
+    const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>(nchunks, 16 * ctx->num_cu));
+    hipLaunchKernelGGL(k_bin_count, dim3(cgrid), dim3(64), lds, ctx->stream, B);
+    hipLaunchKernelGGL(k_bin_scan_tiles, dim3((T + 63) / 64), dim3(64 * BIN_SCAN_GROUPS), 0,
+                       ctx->stream, B);
+    hipLaunchKernelGGL(k_bin_scan_items, dim3(1), dim3(1024), 0, ctx->stream, B);
+    hipLaunchKernelGGL(k_bin_fill, dim3(cgrid), dim3(64), lds, ctx->stream, B);
+    hipLaunchKernelGGL(k_splat_binned, dim3((max_items + 3) / 4), dim3(256), 0, ctx->stream, A,
+                       B, (const SplatRec *)rec);
+    hipLaunchKernelGGL(k_splat_reduce_binned, dim3(1024), dim3(256), 0, ctx->stream, A, B, u);
+    FGA_HIP(ctx, hipGetLastError());
+    return FGA_OK;
+}

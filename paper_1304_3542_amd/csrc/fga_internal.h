@@ -46,6 +46,8 @@ struct fga_ctx {
     size_t srec_bytes, sbox_bytes;
     void *trace_part;      // per-split partial receiver sums
     size_t trace_part_bytes;
+    void *bin;             // beam -> tile binning of the mixed splat
+    size_t bin_bytes;
 
     // adjoint workspaces and the branch count of the last decomposition
     void *adj_scratch, *adj_psib;

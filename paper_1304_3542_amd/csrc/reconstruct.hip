@@ -17,27 +17,11 @@
 // and every 256 beams the FP32 partial sums are folded into FP64 ones.
 #include <math.h>
 
-#include "fga_internal.h"
-
-#define SP_T 64          // tile edge (nodes)
-#define SP_KC 16         // beams per factor batch
-#define SP_CHUNK 256     // beams scanned per pass (= block size)
+#include "splat.h"
 
 template <typename R>
 struct Fac {
     R re, im;
-};
-
-struct SplatArgs {
-    const double *f;
-    const int64_t *offsets;
-    int64_t cap;
-    int n1, n2;
-    double o1, o2, d1, d2;
-    double eps, inv_eps, half_inv_eps;
-    int Rw1, Rw2;
-    int nsplit, ntile1;
-    double *partial;   // [nshots][nsplit][n2][n1]
 };
 
 // factor e^{i theta + G} times coef (complex, double) in precision R
@@ -203,35 +187,6 @@ k_splat(SplatArgs A)
     }
 }
 
-// ---------------------------------------------------------------------------
-// Mixed-precision splat on the matrix cores.
-//
-// One wavefront owns a 64 x 64 output tile and one slice of a shot's beams.
-// Per beam, lane l evaluates V at x2 = Z0 + l and U at x1 = X0 + l (phase in
-// FP64 revolutions reduced to [-1/2, 1/2], then the hardware FP32 sin, cos
-// and exp2), so every factor is computed once and never leaves registers.
-// Re(U V) = Vr Ur + Vi (-Ui) is a K = 2 product per beam:
-//   A (32 x 2, rows = x2):  A[i][0] = Vr(i), A[i][1] = Vi(i)
-//   B (2 x 32, cols = x1):  B[0][j] = Ur(j), B[1][j] = -Ui(j)
-// With v_mfma_f32_32x32x2f32 lane l holds A[l % 32][l / 32] and
-// B[l / 32][l % 32]; the halves of the wave swap their factors once
-// (xor 32) to build the two 32-row and two 32-column fragments.  Four MFMAs
-// per beam cover the tile; the FP32 accumulators are folded into FP64 ones
-// after every 64 candidate beams.
-typedef float floatx16 __attribute__((ext_vector_type(16)));
-
-// Per-beam record of the mixed splat, formed once per reconstruction:
-// phases in revolutions as affine functions of the node coordinate,
-//   theta1(x1) = (S + P1 (x1 - Q1)) / (2 pi eps) = A1 + B1 x1,
-//   theta2(x2) = P2 (x2 - Q2) / (2 pi eps)       = A2 + B2 x2,
-// the Gaussian centre, C a in FP32 and the truncation box.  64 bytes, read
-// with one scalar load per beam.
-struct __align__(64) SplatRec {
-    double A1, B1, A2, B2, Q1, Q2;
-    float car, cai;
-    short lo1, hi1, lo2, hi2;
-};
-
 __global__ void __launch_bounds__(256)
 k_splat_prep(SplatArgs A, int nshots, SplatRec *__restrict__ rec, short4 *__restrict__ box)
 {
@@ -264,61 +219,6 @@ k_splat_prep(SplatArgs A, int nshots, SplatRec *__restrict__ rec, short4 *__rest
         rec[b] = r;
         box[b] = make_short4(r.lo1, r.hi1, r.lo2, r.hi2);
     }
-}
-
-struct Frags {
-    float a0, a1, b0, b1;
-};
-
-// Factors of one beam at this lane's x1 and x2 and the MFMA fragments:
-// v_permlane32_swap(x, y) exchanges the upper half of x with the lower half
-// of y, which turns (Vr, Vi) into the fragments of the two 32-row blocks and
-// (Ur, -Ui) into those of the two 32-column blocks.
-__device__ __forceinline__ Frags beam_frags(const SplatRec &r, int i1, int i2, double x1,
-                                            double x2, float hl2e)
-{
-    float ur = 0.f, nui = 0.f, vr = 0.f, vi = 0.f;
-    if (i1 >= r.lo1 && i1 <= r.hi1) {
-        double t = fma(r.B1, x1, r.A1);
-        float th = (float)(t - rint(t));
-        float rf = (float)(x1 - r.Q1);
-        float e = __builtin_amdgcn_exp2f(-rf * rf * hl2e);
-        float sn = __builtin_amdgcn_sinf(th), cs = __builtin_amdgcn_cosf(th);
-        ur = e * (r.car * cs - r.cai * sn);
-        nui = -e * (r.car * sn + r.cai * cs);
-    }
-    if (i2 >= r.lo2 && i2 <= r.hi2) {
-        double t = fma(r.B2, x2, r.A2);
-        float th = (float)(t - rint(t));
-        float rf = (float)(x2 - r.Q2);
-        float e = __builtin_amdgcn_exp2f(-rf * rf * hl2e);
-        vr = e * __builtin_amdgcn_cosf(th);
-        vi = e * __builtin_amdgcn_sinf(th);
-    }
-    auto va = __builtin_amdgcn_permlane32_swap(__float_as_uint(vr), __float_as_uint(vi), false,
-                                               false);
-    auto ub = __builtin_amdgcn_permlane32_swap(__float_as_uint(ur), __float_as_uint(nui), false,
-                                               false);
-    return {__uint_as_float(va[0]), __uint_as_float(va[1]), __uint_as_float(ub[0]),
-            __uint_as_float(ub[1])};
-}
-
-// rank-one update of the 64 x 64 tile; 32 x 32 blocks that the beam's box
-// misses are skipped (the test is uniform across the wavefront)
-__device__ __forceinline__ void tile_update(const Frags &fr, const SplatRec &r, int X0, int Z0,
-                                            floatx16 &acc00, floatx16 &acc01, floatx16 &acc10,
-                                            floatx16 &acc11)
-{
-    // the record is the same in every lane: make the box scalar so that the
-    // block tests are scalar branches
-    const int lo1 = __builtin_amdgcn_readfirstlane(r.lo1), hi1 = __builtin_amdgcn_readfirstlane(r.hi1);
-    const int lo2 = __builtin_amdgcn_readfirstlane(r.lo2), hi2 = __builtin_amdgcn_readfirstlane(r.hi2);
-    const bool c0 = lo1 <= X0 + 31 && hi1 >= X0, c1 = lo1 <= X0 + 63 && hi1 >= X0 + 32;
-    const bool w0 = lo2 <= Z0 + 31 && hi2 >= Z0, w1 = lo2 <= Z0 + 63 && hi2 >= Z0 + 32;
-    if (w0 && c0) acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(fr.a0, fr.b0, acc00, 0, 0, 0);
-    if (w0 && c1) acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(fr.a0, fr.b1, acc01, 0, 0, 0);
-    if (w1 && c0) acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(fr.a1, fr.b0, acc10, 0, 0, 0);
-    if (w1 && c1) acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(fr.a1, fr.b1, acc11, 0, 0, 0);
 }
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
@@ -438,25 +338,17 @@ __global__ void k_splat_reduce(const double *__restrict__ partial, double *__res
     }
 }
 
+bool fga_splat_binned_fits(const fga_ctx *ctx, int nshots);
+fga_status fga_launch_splat_binned(fga_ctx *ctx, const fga_beams *beams, int nshots, double *u,
+                                   SplatArgs A, const void *rec, const void *box);
+
 fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nshots, double *u)
 {
     const fga_grid &g = ctx->g;
     int nt1 = (g.n1 + SP_T - 1) / SP_T, nt2 = (g.n2 + SP_T - 1) / SP_T;
     int tiles = nt1 * nt2;
     bool mfma = ctx->prec == FGA_MIXED;
-    // enough work units to fill every SIMD twice (mixed: one wavefront per
-    // unit; FP64: one workgroup of four wavefronts per unit)
-    // mixed: about 32 wavefronts per CU, so that the dispatcher evens out
-    // tiles of very different load; FP64: 4 workgroups per CU
-    int per_cu = ctx->splat_units_per_cu > 0 ? ctx->splat_units_per_cu : (mfma ? 32 : 4);
-    int want_units = per_cu * ctx->num_cu;
-    int want = (want_units + tiles * nshots - 1) / (tiles * nshots);
-    int nsplit = want < 1 ? 1 : (want > 256 ? 256 : want);
-    size_t npts = (size_t)g.n1 * g.n2;
-    fga_status rc = fga_ensure(ctx, (void **)&ctx->partial, &ctx->partial_bytes,
-                               (size_t)nshots * nsplit * npts * sizeof(double), "splat partials");
-    if (rc != FGA_OK) return rc;
-    SplatArgs A;
+    SplatArgs A{};
     A.f = beams->f;
     A.offsets = beams->offsets;
     A.cap = beams->capacity;
@@ -471,9 +363,8 @@ fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nsho
     A.half_inv_eps = 0.5 / ctx->p.eps;
     A.Rw1 = ctx->Rw1;
     A.Rw2 = ctx->Rw2;
-    A.nsplit = nsplit;
     A.ntile1 = nt1;
-    A.partial = ctx->partial;
+    fga_status rc;
     if (mfma) {
         rc = fga_ensure(ctx, &ctx->srec, &ctx->srec_bytes,
                         (size_t)beams->capacity * sizeof(SplatRec), "splat records");
@@ -483,6 +374,26 @@ fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nsho
         if (rc != FGA_OK) return rc;
         hipLaunchKernelGGL(k_splat_prep, dim3(2 * ctx->num_cu), dim3(256), 0, ctx->stream, A,
                            nshots, (SplatRec *)ctx->srec, (short4 *)ctx->sbox);
+        // beams binned per tile and split into equal work items, unless the
+        // tile count exceeds the binning's LDS counters
+        if (fga_splat_binned_fits(ctx, nshots))
+            return fga_launch_splat_binned(ctx, beams, nshots, u, A, ctx->srec, ctx->sbox);
+    }
+    // every tile scans a slice of its shot's beams: enough slices for about
+    // per_cu work units per CU (mixed: one wavefront per unit, so that the
+    // dispatcher evens out tiles of very different load; FP64: one workgroup
+    // of four wavefronts per unit)
+    int per_cu = ctx->splat_units_per_cu > 0 ? ctx->splat_units_per_cu : (mfma ? 32 : 4);
+    int want_units = per_cu * ctx->num_cu;
+    int want = (want_units + tiles * nshots - 1) / (tiles * nshots);
+    int nsplit = want < 1 ? 1 : (want > 256 ? 256 : want);
+    A.nsplit = nsplit;
+    size_t npts = (size_t)g.n1 * g.n2;
+    rc = fga_ensure(ctx, (void **)&ctx->partial, &ctx->partial_bytes,
+                    (size_t)nshots * nsplit * npts * sizeof(double), "splat partials");
+    if (rc != FGA_OK) return rc;
+    A.partial = ctx->partial;
+    if (mfma) {
         int nunits = tiles * nsplit * nshots;
         hipLaunchKernelGGL(k_splat_mfma, dim3((nunits + 3) / 4), dim3(256), 0, ctx->stream, A,
                            nunits, (const SplatRec *)ctx->srec, (const short4 *)ctx->sbox);
