@@ -140,31 +140,52 @@ __device__ __forceinline__ void bspline_w(double f, double w[4], double dw[4], d
     ddw[3] = f;
 }
 
-// c, grad c and the Hessian (c11, c12, c22) of the clamped cubic B-spline.
-__device__ __forceinline__ void vel_eval(const VelGrid &V, double x1, double x2, double &c,
-                                         double &c1, double &c2, double &c11, double &c12,
-                                         double &c22)
+// Knot cell of the B-spline evaluation at (x1, x2): the clamped index of the
+// cell holding the point and the fractional offsets inside it.  Four or more
+// cells outside the grid every knot reads the edge value, so clamping the
+// index to [-4, n + 3] keeps the 4 x 4 taps inside the halo.
+struct VelCell {
+    int i1, i2;
+    double f1, f2;
+};
+
+__device__ __forceinline__ VelCell vel_cell(const VelGrid &V, double x1, double x2)
 {
     double t1 = (x1 - V.o1) * V.inv_d1;
     double t2 = (x2 - V.o2) * V.inv_d2;
     double fl1 = floor(t1), fl2 = floor(t2);
-    double f1 = t1 - fl1, f2 = t2 - fl2;
-    // four or more cells outside the grid every knot reads the edge value, so
-    // clamping the knot index to [-4, n + 3] keeps the taps inside the halo
-    int i1 = (int)fmin(fmax(fl1, -4.0), (double)V.n1 + 3.0);
-    int i2 = (int)fmin(fmax(fl2, -4.0), (double)V.n2 + 3.0);
+    VelCell k;
+    k.f1 = t1 - fl1;
+    k.f2 = t2 - fl2;
+    k.i1 = (int)fmin(fmax(fl1, -4.0), (double)V.n1 + 3.0);
+    k.i2 = (int)fmin(fmax(fl2, -4.0), (double)V.n2 + 3.0);
+    return k;
+}
+
+// first of the 4 x 4 taps (row kz starts kz * V.ld further on)
+__device__ __forceinline__ const double *vel_taps(const VelGrid &V, const VelCell &k)
+{
+    return V.c + (size_t)(k.i2 - 1 + FGA_VPAD) * V.ld + (k.i1 - 1 + FGA_VPAD);
+}
+
+// c, grad c and the Hessian (c11, c12, c22) of the clamped cubic B-spline
+// from the taps of the cell; row(kz, v) fills v[0..3] with tap row kz.
+template <class Rows>
+__device__ __forceinline__ void vel_combine(const VelGrid &V, const VelCell &k, Rows row,
+                                            double &c, double &c1, double &c2, double &c11,
+                                            double &c12, double &c22)
+{
     double wx[4], dwx[4], ddwx[4], wz[4], dwz[4], ddwz[4];
-    bspline_w(f1, wx, dwx, ddwx);
-    bspline_w(f2, wz, dwz, ddwz);
-    const double *base = V.c + (size_t)(i2 - 1 + FGA_VPAD) * V.ld + (i1 - 1 + FGA_VPAD);
+    bspline_w(k.f1, wx, dwx, ddwx);
+    bspline_w(k.f2, wz, dwz, ddwz);
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
 #pragma unroll
     for (int kz = 0; kz < 4; ++kz) {
-        const double *row = base + kz * V.ld;
-        double v0 = row[0], v1 = row[1], v2 = row[2], v3 = row[3];
-        double a0 = wx[0] * v0 + wx[1] * v1 + wx[2] * v2 + wx[3] * v3;
-        double a1 = dwx[0] * v0 + dwx[1] * v1 + dwx[2] * v2 + dwx[3] * v3;
-        double a2 = ddwx[0] * v0 + ddwx[1] * v1 + ddwx[2] * v2 + ddwx[3] * v3;
+        double v[4];
+        row(kz, v);
+        double a0 = wx[0] * v[0] + wx[1] * v[1] + wx[2] * v[2] + wx[3] * v[3];
+        double a1 = dwx[0] * v[0] + dwx[1] * v[1] + dwx[2] * v[2] + dwx[3] * v[3];
+        double a2 = ddwx[0] * v[0] + ddwx[1] * v[1] + ddwx[2] * v[2] + ddwx[3] * v[3];
         s0 += wz[kz] * a0;
         s1 += wz[kz] * a1;
         s2 += dwz[kz] * a0;
@@ -178,6 +199,26 @@ __device__ __forceinline__ void vel_eval(const VelGrid &V, double x1, double x2,
     c11 = s3 * V.inv_d1 * V.inv_d1;
     c12 = s4 * V.inv_d1 * V.inv_d2;
     c22 = s5 * V.inv_d2 * V.inv_d2;
+}
+
+// c, grad c and the Hessian of the clamped cubic B-spline at (x1, x2), taps
+// read from the padded samples.
+__device__ __forceinline__ void vel_eval(const VelGrid &V, double x1, double x2, double &c,
+                                         double &c1, double &c2, double &c11, double &c12,
+                                         double &c22)
+{
+    const VelCell k = vel_cell(V, x1, x2);
+    const double *base = vel_taps(V, k);
+    vel_combine(
+        V, k,
+        [&](int kz, double *v) {
+            const double *r = base + kz * V.ld;
+            v[0] = r[0];
+            v[1] = r[1];
+            v[2] = r[2];
+            v[3] = r[3];
+        },
+        c, c1, c2, c11, c12, c22);
 }
 
 // Truncation box of a Gaussian centred at Q: the nodes within Rw cells of the

@@ -6,24 +6,77 @@
 // One thread owns one beam for all steps: the 23-double state and the RK4
 // accumulators stay in VGPRs, so HBM sees one read and one write of the
 // state per launch.  c and its derivatives come from the cubic B-spline of
-// the velocity samples (16 taps per evaluation), read through the L2 (the
-// velocity grid is a few MB and stays cache resident).  FP64 throughout:
-// gfx950 runs FP64 FMA at the FP32 rate, and the phase P.(x-Q)/eps needs Q
-// and P to ~1e-14.
+// the velocity samples (16 taps per evaluation, through the L2).  The taps
+// of the next evaluation are requested as soon as its position is known
+// (right after the slope of Q), straight into LDS with global_load_lds, so
+// the L2 latency overlaps the rest of the stage without holding VGPRs.
+// FP64 throughout: gfx950 runs FP64 FMA at the FP32 rate, and the phase
+// P.(x-Q)/eps needs Q and P to ~1e-14.
 #include "fga_internal.h"
 
 #include "rk4.h"
 
 #define RK_BLOCK 256
 
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Velocity source of the RK4 stages: prefetch() sends the 16 taps of the
+// knot cell of (x1, x2) from the padded samples to this wavefront's LDS
+// slots, as eight 16-byte transfers per lane; eval() waits for them and
+// combines them.  Slot 2 kz + h holds taps 2h, 2h + 1 of row kz, lane l at
+// entry l.  The wavefront issues no other vector-memory load inside the step
+// loop, so waiting for every outstanding one waits exactly for the taps.
+// (The padded samples, a few MB, stay resident in every XCD's L2; a table of
+// per-cell polynomial coefficients would need fewer operations to evaluate
+// but is 16 times larger and falls out of the L2.)
+struct VelDma {
+    VelGrid V;
+    double2 *buf;   // this wavefront's 8 slots of 64 entries
+    int lane;
+    __device__ __forceinline__ void prefetch(double x1, double x2) const
+    {
+        const double *base = vel_taps(V, vel_cell(V, x1, x2));
+#pragma unroll
+        for (int kz = 0; kz < 4; ++kz) {
+            const double *r = base + kz * V.ld;
+            __builtin_amdgcn_global_load_lds((const void *)r, (lds_void *)(buf + (2 * kz) * 64),
+                                             16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void *)(r + 2),
+                                             (lds_void *)(buf + (2 * kz + 1) * 64), 16, 0, 0);
+        }
+    }
+    __device__ __forceinline__ void eval(double x1, double x2, double &c, double &c1, double &c2,
+                                         double &c11, double &c12, double &c22) const
+    {
+        // the LDS writes of global_load_lds complete with the load counter
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        const VelCell k = vel_cell(V, x1, x2);
+        vel_combine(
+            V, k,
+            [&](int kz, double *v) {
+                const double2 a = buf[(2 * kz) * 64 + lane], b = buf[(2 * kz + 1) * 64 + lane];
+                v[0] = a.x;
+                v[1] = a.y;
+                v[2] = b.x;
+                v[3] = b.y;
+            },
+            c, c1, c2, c11, c12, c22);
+    }
+};
+
 // One thread per beam; the state, the RK4 accumulator and the stage input
-// live in VGPRs (two wavefronts per SIMD).
+// live in VGPRs (two wavefronts per SIMD), the velocity taps in 8 KB of LDS
+// per wavefront.
 __global__ void __launch_bounds__(RK_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
       const int64_t *__restrict__ offsets, int nshots, int64_t cap, int64_t NqNp, double dt,
       int nsteps, double *__restrict__ ckpt, int64_t *status)
 {
+    __shared__ double2 taps[RK_BLOCK / 64][8 * 64];
     const int tid = threadIdx.x;
+    // the wavefront index is uniform: keep the LDS base in a scalar register
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const VelDma vel{V, taps[wave], tid & 63};
     int64_t nb = offsets[nshots];
     for (int64_t b0 = (int64_t)blockIdx.x * RK_BLOCK; b0 < nb;
          b0 += (int64_t)gridDim.x * RK_BLOCK) {
@@ -34,14 +87,18 @@ k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
         if (ckpt) store_state(ckpt + b, cap, y);
         double s = ((id[b] / NqNp) & 1) ? -1.0 : 1.0;
         double h2 = 0.5 * dt, h6 = dt / 6.0, h3 = dt / 3.0;
+        if (nsteps > 0) vel.prefetch(y.Q1, y.Q2);
         for (int it = 0; it < nsteps; ++it) {
             St t = y, acc = y;
-            stage<false>(V, s, t, acc, y, h6, h2);
-            stage<false>(V, s, t, acc, y, h3, h2);
-            stage<false>(V, s, t, acc, y, h3, dt);
-            stage<true>(V, s, t, acc, y, h6, 0.0);
+            rk_stage<false>(vel, s, t, acc, y, h6, h2);
+            rk_stage<false>(vel, s, t, acc, y, h3, h2);
+            rk_stage<false>(vel, s, t, acc, y, h3, dt);
+            rk_stage<true>(vel, s, t, acc, y, h6, 0.0);
             y = acc;
         }
+        // no LDS transfer (the last step requests one more) may outlive the
+        // wavefront's use of the slots
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         if (!isfinite(y.Q1) || !isfinite(y.Q2) || !isfinite(y.a.r) || !isfinite(y.a.i))
             atomicOr((unsigned long long *)status, FGA_STATUS_NUMERIC);
         store_state(f + (size_t)FGA_F_STATE * cap + b, cap, y);

@@ -53,6 +53,16 @@ __device__ __forceinline__ double rcp64(double x)
     return r;
 }
 
+// 1/sqrt(x): hardware estimate refined by two Newton steps
+// r <- r + r (1 - x r^2) / 2.
+__device__ __forceinline__ double rsq64(double x)
+{
+    double r = __builtin_amdgcn_rsq(x);
+    r = fma(0.5 * r, fma(-x * r, r, 1.0), r);
+    r = fma(0.5 * r, fma(-x * r, r, 1.0), r);
+    return r;
+}
+
 // Right-hand side.  With n = |P|, u = P/n, g = grad c, K = Hess c:
 //   H_P = s c u, H_Q = s n g, H_PP = s (c/n)(I - u u^T), H_QQ = s n K,
 //   H_QP = s g u^T, H_PQ = s u g^T, so the dynamic ray tracing equations
@@ -155,20 +165,37 @@ __device__ __forceinline__ void store_state(double *p, int64_t cap, const St &y)
     p[22 * cap] = y.a.i;
 }
 
+// Velocity source of a stage that reads the taps from the padded samples
+// when the stage evaluates c.
+struct VelDirect {
+    VelGrid V;
+    __device__ __forceinline__ void eval(double x1, double x2, double &c, double &c1, double &c2,
+                                         double &c11, double &c12, double &c22) const
+    {
+        vel_eval(V, x1, x2, c, c1, c2, c11, c12, c22);
+    }
+    __device__ __forceinline__ void prefetch(double, double) const {}
+};
+
 // One RK4 stage fused with its use: k = f(t), acc += wacc k, and unless this
 // is the last stage t = y + hnext k.  Each slope component is consumed as
 // soon as it is produced, so only y, acc and t stay live across the stage.
 // The amplitude needs Z = A + iB of the stage input and dZ = k_A + i k_B:
 // det Z is formed first, row 0 of Z is kept aside before row 0 of t is
 // overwritten, and the adjugate trace is accumulated row by row.
-template <bool LAST>
-__device__ __forceinline__ void stage(const VelGrid &V, double s, St &t, St &acc, const St &y,
-                                      double wacc, double hnext)
+// The position of the next evaluation of c (the next stage's, after the last
+// stage the next step's first) is known once the slope of Q is; it goes to
+// vel.prefetch before the rest of the stage is computed.  (The request after
+// the final step is not used; a branch around it would cost more registers.)
+template <bool LAST, class Vel>
+__device__ __forceinline__ void rk_stage(const Vel &vel, double s, St &t, St &acc, const St &y,
+                                         double wacc, double hnext)
 {
     double c, g1, g2, K11, K12, K22;
-    vel_eval(V, t.Q1, t.Q2, c, g1, g2, K11, K12, K22);
-    double n = sqrt(t.P1 * t.P1 + t.P2 * t.P2);
-    double inv_n = rcp64(n);
+    vel.eval(t.Q1, t.Q2, c, g1, g2, K11, K12, K22);
+    const double n2 = fma(t.P1, t.P1, t.P2 * t.P2);
+    const double inv_n = rsq64(n2);
+    const double n = n2 * inv_n;
     double u1 = t.P1 * inv_n, u2 = t.P2 * inv_n;
     double sc = s * c;
     double con = c * inv_n;
@@ -182,9 +209,11 @@ __device__ __forceinline__ void stage(const VelGrid &V, double s, St &t, St &acc
         acc.P1 = fma(wacc, kP1, acc.P1);
         acc.P2 = fma(wacc, kP2, acc.P2);
         acc.S = fma(wacc, kS, acc.S);
+        if (LAST) vel.prefetch(acc.Q1, acc.Q2);
         if (!LAST) {
             t.Q1 = fma(hnext, kQ1, y.Q1);
             t.Q2 = fma(hnext, kQ2, y.Q2);
+            vel.prefetch(t.Q1, t.Q2);
             t.P1 = fma(hnext, kP1, y.P1);
             t.P2 = fma(hnext, kP2, y.P2);
             t.S = fma(hnext, kS, y.S);
@@ -236,3 +265,10 @@ __device__ __forceinline__ void stage(const VelGrid &V, double s, St &t, St &acc
     if (!LAST) t.a = {fma(hnext, ka.r, y.a.r), fma(hnext, ka.i, y.a.i)};
 }
 
+// the stage with the taps read where c is evaluated
+template <bool LAST>
+__device__ __forceinline__ void stage(const VelGrid &V, double s, St &t, St &acc, const St &y,
+                                      double wacc, double hnext)
+{
+    rk_stage<LAST>(VelDirect{V}, s, t, acc, y, wacc, hnext);
+}
