@@ -66,31 +66,85 @@ __global__ void k_cq(VelGrid V, double o1, double o2, double d1, double d2, int 
 
 // ------------------------------------------------------------------ pass 1
 // T[sf][i2][j1*np1 + l1] = d1 * sum_m E1t[m][l1] f_sf[i2][k1(j1) + m]
+// For each q column j1 this is a real x complex GEMM (M = rows i2,
+// N = np1, K = box width): a workgroup computes a 64 x 64 tile of one j1 with
+// the row windows and the table staged through LDS, 16 outputs per thread.
+#define P1_BM 64
+#define P1_BN 64
+#define P1_BK 16
+
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_fbi_pass1(const double *f0, const double *f1, int nfj, const cplx<R> *__restrict__ E1t,
             cplx<R> *__restrict__ T, int n1, int n2, int R1, int qb1, int qs1, int nq1,
             int np1, double d1)
 {
-    int i2 = blockIdx.x;
-    int sf = blockIdx.y;
-    int s = sf / nfj, fj = sf % nfj;
-    const double *row = (fj == 0 ? f0 : f1) + ((size_t)s * n2 + i2) * n1;
-    int NC = nq1 * np1;
-    cplx<R> *out = T + ((size_t)sf * n2 + i2) * NC;
-    for (int cidx = threadIdx.x; cidx < NC; cidx += blockDim.x) {
-        int j1 = cidx / np1, l1 = cidx % np1;
-        int k1 = qb1 + j1 * qs1;
-        int mlo = max(-R1, -k1), mhi = min(R1, n1 - 1 - k1);
-        R ar = 0, ai = 0;
-        for (int m = mlo; m <= mhi; ++m) {
-            R v = (R)row[k1 + m];
-            cplx<R> e = E1t[(size_t)(m + R1) * np1 + l1];
-            ar += e.re * v;
-            ai += e.im * v;
+    __shared__ R As[P1_BK][P1_BM + 1];
+    __shared__ cplx<R> Bs[P1_BK][P1_BN];
+    const int sfj = blockIdx.z;
+    const int sf = sfj / nq1, j1 = sfj % nq1;
+    const int s = sf / nfj, fj = sf % nfj;
+    const double *fs = (fj == 0 ? f0 : f1) + (size_t)s * n2 * n1;
+    const int k1 = qb1 + j1 * qs1;
+    const int mlo = max(-R1, -k1), mhi = min(R1, n1 - 1 - k1);
+    const int K = mhi - mlo + 1;
+    const int l0 = blockIdx.x * P1_BN, r0 = blockIdx.y * P1_BM;
+    const int t = threadIdx.x;
+    const int tn = t % 16, tm = t / 16;
+    R accr[4][4], acci[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) accr[i][j] = acci[i][j] = 0;
+    for (int kk = 0; kk < K; kk += P1_BK) {
+        // row windows: P1_BM rows x P1_BK taps (16 consecutive doubles per row)
+        for (int e = t; e < P1_BM * P1_BK; e += 256) {
+            const int r = e / P1_BK, k = e % P1_BK;
+            const int i2 = r0 + r;
+            R v = 0;
+            if (i2 < n2 && kk + k < K) v = (R)fs[(size_t)i2 * n1 + k1 + mlo + kk + k];
+            As[k][r] = v;
         }
-        out[cidx].re = ar * (R)d1;
-        out[cidx].im = ai * (R)d1;
+        // table: P1_BK taps x P1_BN wavenumbers
+        for (int e = t; e < P1_BK * P1_BN; e += 256) {
+            const int k = e / P1_BN, n = e % P1_BN;
+            const int l = l0 + n;
+            cplx<R> v{0, 0};
+            if (l < np1 && kk + k < K) v = E1t[(size_t)(mlo + kk + k + R1) * np1 + l];
+            Bs[k][n] = v;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < P1_BK; ++k) {
+            R a[4];
+            cplx<R> b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[k][tm + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[k][tn + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    accr[i][j] += b[j].re * a[i];
+                    acci[i][j] += b[j].im * a[i];
+                }
+        }
+        __syncthreads();
+    }
+    const int NC = nq1 * np1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int i2 = r0 + tm + 16 * i;
+        if (i2 >= n2) continue;
+        cplx<R> *out = T + ((size_t)sf * n2 + i2) * NC + (size_t)j1 * np1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int l = l0 + tn + 16 * j;
+            if (l >= np1) continue;
+            out[l].re = accr[i][j] * (R)d1;
+            out[l].im = acci[i][j] * (R)d1;
+        }
     }
 }
 
@@ -268,19 +322,21 @@ __device__ __forceinline__ R threshold_of(const unsigned long long *maxbits, int
     return (R)(tau * M);
 }
 
-// per-block keep counts, blocks in candidate order
+// Per-block keep counts, blocks in candidate order.  A block covers
+// CMP_TILE consecutive candidates in CMP_ITEMS rounds of CMP_BLOCK; in every
+// round consecutive threads read consecutive candidates.
 template <typename R>
 __global__ void __launch_bounds__(CMP_BLOCK)
 k_count(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGeom G,
         const unsigned long long *maxbits, double tau, int64_t *blk, int nblk)
 {
     __shared__ int red[CMP_BLOCK / 64];
-    int s = blockIdx.y;
-    R thr = threshold_of<R>(maxbits, s, tau);
-    int64_t base = (int64_t)blockIdx.x * CMP_TILE + (int64_t)threadIdx.x * CMP_ITEMS;
+    const int s = blockIdx.y;
+    const R thr = threshold_of<R>(maxbits, s, tau);
+    const int64_t base = (int64_t)blockIdx.x * CMP_TILE + threadIdx.x;
     int cnt = 0;
     for (int i = 0; i < CMP_ITEMS; ++i) {
-        int64_t cl = base + i;
+        const int64_t cl = base + (int64_t)i * CMP_BLOCK;
         if (cl >= G.per_shot) break;
         R re, im;
         cand_psi(Psi, cq, G, s, cl, re, im);
@@ -334,6 +390,9 @@ k_scan_blocks(int64_t *blk, int64_t n, int nblk, int nshots, int64_t *offsets,
     }
 }
 
+// Compaction in candidate order: per round, a wave ballot ranks the kept
+// candidates inside each wavefront and the wavefront totals (LDS) order the
+// wavefronts, so kept beams of one round land at consecutive positions.
 template <typename R>
 __global__ void __launch_bounds__(CMP_BLOCK)
 k_scatter(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGeom G,
@@ -342,49 +401,42 @@ k_scatter(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGe
           int qs1, int qs2, double norm)
 {
     __shared__ int wsum[CMP_BLOCK / 64];
-    int s = blockIdx.y;
-    R thr = threshold_of<R>(maxbits, s, tau);
-    int64_t base = (int64_t)blockIdx.x * CMP_TILE + (int64_t)threadIdx.x * CMP_ITEMS;
-    unsigned mask = 0;
-    int cnt = 0;
-    for (int i = 0; i < CMP_ITEMS; ++i) {
-        int64_t cl = base + i;
-        if (cl >= G.per_shot) break;
-        R re, im;
-        cand_psi(Psi, cq, G, s, cl, re, im);
-        if (keep_cand(cabs_r(re, im), thr)) {
-            mask |= 1u << i;
-            ++cnt;
-        }
-    }
-    // block-wide exclusive prefix of cnt (wave64 scan + wave totals)
-    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int incl = cnt;
-    for (int o = 1; o < 64; o <<= 1) {
-        int v = __shfl_up(incl, o);
-        if (lane >= o) incl += v;
-    }
-    if (lane == 63) wsum[wv] = incl;
-    __syncthreads();
-    int wbase = 0;
-    for (int w = 0; w < wv; ++w) wbase += wsum[w];
-    int64_t pos = blk[(size_t)s * nblk + blockIdx.x] + wbase + incl - cnt;
+    const int s = blockIdx.y;
+    const R thr = threshold_of<R>(maxbits, s, tau);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
     const int64_t cap = B.capacity;
     const int64_t NqNp = G.Nq * G.Np;
-    for (int i = 0; i < CMP_ITEMS && mask; ++i) {
-        if (!(mask & (1u << i))) continue;
-        mask &= ~(1u << i);
-        int64_t cl = base + i;
-        if (pos < cap) {
-            R re, im;
+    int64_t run = blk[(size_t)s * nblk + blockIdx.x];
+    for (int i = 0; i < CMP_ITEMS; ++i) {
+        const int64_t cl = (int64_t)blockIdx.x * CMP_TILE + (int64_t)i * CMP_BLOCK + threadIdx.x;
+        R re = 0, im = 0;
+        bool keep = false;
+        if (cl < G.per_shot) {
             cand_psi(Psi, cq, G, s, cl, re, im);
-            int sb = (int)(cl / NqNp);
-            int64_t rem = cl - sb * NqNp;
-            int64_t qf = rem / G.Np, pf = rem - qf * G.Np;
-            int j2 = (int)(qf / G.nq1), j1 = (int)(qf - (int64_t)j2 * G.nq1);
-            int l2 = (int)(pf / G.np1), l1 = (int)(pf - (int64_t)l2 * G.np1);
-            double q1 = o1 + (qb1 + j1 * qs1) * d1, q2 = o2 + (qb2 + j2 * qs2) * d2;
-            double p1 = (l1 - 0.5 * (G.np1 - 1)) * G.dp1, p2 = (l2 - 0.5 * (G.np2 - 1)) * G.dp2;
+            keep = keep_cand(cabs_r(re, im), thr);
+        }
+        const unsigned long long m = __ballot(keep);
+        if (lane == 0) wsum[wv] = __popcll(m);
+        __syncthreads();
+        int wbase = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < CMP_BLOCK / 64; ++w) {
+            wbase += w < wv ? wsum[w] : 0;
+            tot += wsum[w];
+        }
+        __syncthreads();
+        const int64_t pos = run + wbase + __popcll(m & below);
+        run += tot;
+        if (keep && pos < cap) {
+            const int sb = (int)(cl / NqNp);
+            const int64_t rem = cl - sb * NqNp;
+            const int64_t qf = rem / G.Np, pf = rem - qf * G.Np;
+            const int j2 = (int)(qf / G.nq1), j1 = (int)(qf - (int64_t)j2 * G.nq1);
+            const int l2 = (int)(pf / G.np1), l1 = (int)(pf - (int64_t)l2 * G.np1);
+            const double q1 = o1 + (qb1 + j1 * qs1) * d1, q2 = o2 + (qb2 + j2 * qs2) * d2;
+            const double p1 = (l1 - 0.5 * (G.np1 - 1)) * G.dp1;
+            const double p2 = (l2 - 0.5 * (G.np2 - 1)) * G.dp2;
             double *f = B.f;
             f[0 * cap + pos] = q1;
             f[1 * cap + pos] = q2;
@@ -392,15 +444,14 @@ k_scatter(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGe
             f[3 * cap + pos] = p2;
             f[4 * cap + pos] = norm * (double)re;
             f[5 * cap + pos] = norm * (double)im;
-            double init[FGA_NSTATE] = {q1, q2, p1, p2, 0.0,
-                                       1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0,    // A = I
-                                       0.0, -1.0, 0.0, 0.0, 0.0, 0.0, 0.0, -1.0,  // B = -i I
-                                       2.0, 0.0};                                 // a = 2
+            const double init[FGA_NSTATE] = {q1, q2, p1, p2, 0.0,
+                                             1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0,    // A = I
+                                             0.0, -1.0, 0.0, 0.0, 0.0, 0.0, 0.0, -1.0,  // B = -i I
+                                             2.0, 0.0};                                 // a = 2
 #pragma unroll
             for (int k = 0; k < FGA_NSTATE; ++k) f[(size_t)(FGA_F_STATE + k) * cap + pos] = init[k];
             B.id[pos] = (int64_t)s * G.per_shot + cl;
         }
-        ++pos;
     }
 }
 
@@ -417,9 +468,10 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
     int S = nshots * nfj;
     ctx->last_nfj = nfj;
     ctx->last_nshots = nshots;
-    if ((int64_t)S * p.nq2 > 65535 || S > 65535)
-        return fga_fail(ctx, FGA_EINVAL, "nshots * (1 + (f1 != NULL)) * nq2 = %lld exceeds 65535",
-                        (long long)S * p.nq2);
+    if ((int64_t)S * std::max(p.nq1, p.nq2) > 65535)
+        return fga_fail(ctx, FGA_EINVAL,
+                        "nshots * (1 + (f1 != NULL)) * max(nq1, nq2) = %lld exceeds 65535",
+                        (long long)S * std::max(p.nq1, p.nq2));
     size_t NC = (size_t)p.nq1 * p.np1;
     size_t e1 = (size_t)ctx->W1 * p.np1, e2 = (size_t)ctx->W2 * p.np2;
 
@@ -467,7 +519,8 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
     int nq = p.nq1 * p.nq2;
     hipLaunchKernelGGL(k_cq, dim3((nq + 255) / 256), dim3(256), 0, st, fga_velgrid(ctx), g.o1,
                        g.o2, g.d1, g.d2, p.qb1, p.qb2, p.qs1, p.qs2, p.nq1, p.nq2, ctx->cq);
-    hipLaunchKernelGGL(k_fbi_pass1<R>, dim3(g.n2, S), dim3(256), 0, st, f0, f1, nfj,
+    dim3 g1((p.np1 + P1_BN - 1) / P1_BN, (g.n2 + P1_BM - 1) / P1_BM, S * p.nq1);
+    hipLaunchKernelGGL(k_fbi_pass1<R>, g1, dim3(256), 0, st, f0, f1, nfj,
                        (const cplx<R> *)ctx->E1t, (cplx<R> *)ctx->T, g.n1, g.n2, ctx->R1, p.qb1,
                        p.qs1, p.nq1, p.np1, g.d1);
     dim3 g2((unsigned)((NC + P2_BN - 1) / P2_BN), (p.np2 + P2_BM - 1) / P2_BM, S * p.nq2);
