@@ -12,6 +12,8 @@
 // the L2 latency overlaps the rest of the stage without holding VGPRs.
 // FP64 throughout: gfx950 runs FP64 FMA at the FP32 rate, and the phase
 // P.(x-Q)/eps needs Q and P to ~1e-14.
+#include <limits.h>
+
 #include "fga_internal.h"
 
 #include "rk4.h"
@@ -24,26 +26,76 @@ typedef __attribute__((address_space(3))) void lds_void;
 // knot cell of (x1, x2) from the padded samples to this wavefront's LDS
 // slots, as eight 16-byte transfers per lane; eval() waits for them and
 // combines them.  Slot 2 kz + h holds taps 2h, 2h + 1 of row kz, lane l at
-// entry l.  The wavefront issues no other vector-memory load inside the step
-// loop, so waiting for every outstanding one waits exactly for the taps.
-// (The padded samples, a few MB, stay resident in every XCD's L2; a table of
-// per-cell polynomial coefficients would need fewer operations to evaluate
-// but is 16 times larger and falls out of the L2.)
+// entry l.  A beam moves a fraction of a cell per stage, so a lane whose cell
+// is the one its slots already hold requests nothing: the L2 -> CU traffic
+// drops several-fold (it, not the FP64 arithmetic, bounds this loop
+// otherwise).  The wavefront issues no other vector-memory load inside the
+// step loop, so waiting for every outstanding one waits exactly for the
+// taps.
+// The eight transfers of one tap request for the lanes in mask: 16 bytes
+// from each of a[0..7] (row kz: a[2 kz] at its first tap, a[2 kz + 1] two
+// taps on) into the slots at LDS address lds, 1 KB apart.  (No instruction
+// offset: on these transfers it would move the LDS destination as well.)
+// Written as one block so that the EXEC change leaves no branch in the
+// compiled loop (a branch there makes the register allocator spill the RK4
+// state); each M0 write is followed by the wait state that an LDS transfer
+// after it requires.  No VGPR receives data.
+__device__ __forceinline__ void tap_dma(const double *const a[8], unsigned lds,
+                                        unsigned long long mask)
+{
+    unsigned long long saved;
+    asm volatile(
+        "s_and_saveexec_b64 %0, %9\n\t"
+        "s_mov_b32 m0, %10\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dwordx4 %1, off\n\t"
+        "s_add_u32 m0, %10, 0x400\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dwordx4 %2, off\n\t"
+        "s_add_u32 m0, %10, 0x800\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dwordx4 %3, off\n\t"
+        "s_add_u32 m0, %10, 0xc00\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dwordx4 %4, off\n\t"
+        "s_add_u32 m0, %10, 0x1000\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dwordx4 %5, off\n\t"
+        "s_add_u32 m0, %10, 0x1400\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dwordx4 %6, off\n\t"
+        "s_add_u32 m0, %10, 0x1800\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dwordx4 %7, off\n\t"
+        "s_add_u32 m0, %10, 0x1c00\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dwordx4 %8, off\n\t"
+        "s_mov_b64 exec, %0"
+        : "=&s"(saved)
+        : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]),
+          "v"(a[7]), "s"(mask), "s"(lds)
+        : "m0", "scc", "memory");
+}
+
 struct VelDma {
     VelGrid V;
     double2 *buf;   // this wavefront's 8 slots of 64 entries
     int lane;
-    __device__ __forceinline__ void prefetch(double x1, double x2) const
+    int cur1, cur2;   // knot cell whose taps the slots hold (none at first)
+    __device__ __forceinline__ void prefetch(double x1, double x2)
     {
-        const double *base = vel_taps(V, vel_cell(V, x1, x2));
+        const VelCell k = vel_cell(V, x1, x2);
+        const bool changed = k.i1 != cur1 || k.i2 != cur2;
+        cur1 = k.i1;
+        cur2 = k.i2;
+        const double *base = vel_taps(V, k);
+        const double *a[8];
 #pragma unroll
         for (int kz = 0; kz < 4; ++kz) {
-            const double *r = base + kz * V.ld;
-            __builtin_amdgcn_global_load_lds((const void *)r, (lds_void *)(buf + (2 * kz) * 64),
-                                             16, 0, 0);
-            __builtin_amdgcn_global_load_lds((const void *)(r + 2),
-                                             (lds_void *)(buf + (2 * kz + 1) * 64), 16, 0, 0);
+            a[2 * kz] = base + kz * V.ld;
+            a[2 * kz + 1] = base + kz * V.ld + 2;
         }
+        tap_dma(a, (unsigned)(size_t)(lds_void *)buf, __ballot(changed));
     }
     __device__ __forceinline__ void eval(double x1, double x2, double &c, double &c1, double &c2,
                                          double &c11, double &c12, double &c22) const
@@ -76,7 +128,7 @@ k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
     const int tid = threadIdx.x;
     // the wavefront index is uniform: keep the LDS base in a scalar register
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const VelDma vel{V, taps[wave], tid & 63};
+    VelDma vel{V, taps[wave], tid & 63, INT_MIN, INT_MIN};
     int64_t nb = offsets[nshots];
     for (int64_t b0 = (int64_t)blockIdx.x * RK_BLOCK; b0 < nb;
          b0 += (int64_t)gridDim.x * RK_BLOCK) {
@@ -87,6 +139,7 @@ k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
         if (ckpt) store_state(ckpt + b, cap, y);
         double s = ((id[b] / NqNp) & 1) ? -1.0 : 1.0;
         double h2 = 0.5 * dt, h6 = dt / 6.0, h3 = dt / 3.0;
+        vel.cur1 = vel.cur2 = INT_MIN;   // new beam: its slots hold nothing yet
         if (nsteps > 0) vel.prefetch(y.Q1, y.Q2);
         for (int it = 0; it < nsteps; ++it) {
             St t = y, acc = y;

@@ -188,7 +188,7 @@ struct VelDirect {
 // vel.prefetch before the rest of the stage is computed.  (The request after
 // the final step is not used; a branch around it would cost more registers.)
 template <bool LAST, class Vel>
-__device__ __forceinline__ void rk_stage(const Vel &vel, double s, St &t, St &acc, const St &y,
+__device__ __forceinline__ void rk_stage(Vel &vel, double s, St &t, St &acc, const St &y,
                                          double wacc, double hnext)
 {
     double c, g1, g2, K11, K12, K22;
@@ -270,5 +270,6 @@ template <bool LAST>
 __device__ __forceinline__ void stage(const VelGrid &V, double s, St &t, St &acc, const St &y,
                                       double wacc, double hnext)
 {
-    rk_stage<LAST>(VelDirect{V}, s, t, acc, y, wacc, hnext);
+    VelDirect vel{V};
+    rk_stage<LAST>(vel, s, t, acc, y, wacc, hnext);
 }
