@@ -115,6 +115,8 @@ extern "C" fga_status fga_create(fga_ctx **out, const fga_grid *g, const fga_par
     if (e == hipSuccess)
         e = hipMalloc((void **)&ctx->cpad, sizeof(double) * (g->n1 + 2 * FGA_VPAD) *
                                                (g->n2 + 2 * FGA_VPAD));
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&ctx->ccoef, sizeof(double) * 16 * fga_vcells(g->n1, g->n2));
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->status, 2 * sizeof(int64_t));
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->cq, sizeof(double) * p->nq1 * p->nq2);
     if (e == hipSuccess)
@@ -137,7 +139,7 @@ extern "C" fga_status fga_destroy(fga_ctx *ctx)
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-    void *bufs[] = {ctx->c, ctx->cpad, ctx->status, ctx->cq, ctx->maxbits, ctx->E1t, ctx->E2,
+    void *bufs[] = {ctx->c, ctx->cpad, ctx->ccoef, ctx->status, ctx->cq, ctx->maxbits, ctx->E1t, ctx->E2,
                     ctx->T, ctx->Psi, ctx->blk, ctx->partial, ctx->srec, ctx->sbox,
                     ctx->adj_scratch, ctx->adj_psib, ctx->trace_part, ctx->bin};
     for (void *b : bufs)
@@ -169,6 +171,41 @@ __global__ void k_pad_velocity(const double *c, int n1, int n2, double *cpad, in
     }
 }
 
+// Bicubic coefficients of every knot cell: with the uniform B-spline basis
+// in powers of the offset f, w_k(f) = sum_a M[k][a] f^a / 6, the cell's
+// polynomial is C[b][a] = sum_{kz,kx} M[kz][b] M[kx][a] v[kz][kx] / 36 over
+// its 4 x 4 taps v (row kz along axis 2).
+__global__ void k_vel_coef(const double *cpad, int n1, int n2, double *coef)
+{
+    const double M[4][4] = {{1, -3, 3, -1}, {4, 0, -6, 3}, {1, 3, 3, -3}, {0, 0, 0, 1}};
+    const int ld = n1 + 2 * FGA_VPAD, nc1 = n1 + 2 * FGA_VCELL_PAD;
+    const int64_t ncell = fga_vcells(n1, n2);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncell;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int i1 = (int)(i % nc1) - FGA_VCELL_PAD, i2 = (int)(i / nc1) - FGA_VCELL_PAD;
+        const double *base = cpad + (size_t)(i2 - 1 + FGA_VPAD) * ld + (i1 - 1 + FGA_VPAD);
+        double T[4][4];   // T[kz][a] = sum_kx v[kz][kx] M[kx][a]
+#pragma unroll
+        for (int kz = 0; kz < 4; ++kz)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                double t = 0.0;
+#pragma unroll
+                for (int kx = 0; kx < 4; ++kx) t += base[kz * ld + kx] * M[kx][a];
+                T[kz][a] = t;
+            }
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                double t = 0.0;
+#pragma unroll
+                for (int kz = 0; kz < 4; ++kz) t += M[kz][b] * T[kz][a];
+                coef[i * 16 + 4 * b + a] = t * (1.0 / 36.0);
+            }
+    }
+}
+
 extern "C" fga_status fga_set_velocity(fga_ctx *ctx, const double *c_dev)
 {
     if (!ctx || !c_dev) return ctx ? fga_fail(ctx, FGA_EINVAL, "null velocity") : FGA_EINVAL;
@@ -177,6 +214,8 @@ extern "C" fga_status fga_set_velocity(fga_ctx *ctx, const double *c_dev)
                                 ctx->stream));
     hipLaunchKernelGGL(k_pad_velocity, dim3(256), dim3(256), 0, ctx->stream, ctx->c,
                        ctx->g.n1, ctx->g.n2, ctx->cpad, ctx->status);
+    hipLaunchKernelGGL(k_vel_coef, dim3(1024), dim3(256), 0, ctx->stream, ctx->cpad, ctx->g.n1,
+                       ctx->g.n2, ctx->ccoef);
     FGA_HIP(ctx, hipGetLastError());
     ctx->have_c = true;
     return FGA_OK;

@@ -26,6 +26,7 @@ struct fga_ctx {
 
     double *c;             // velocity samples [n2][n1]
     double *cpad;          // the same with a replicated halo of FGA_VPAD cells
+    double *ccoef;         // bicubic coefficients of every knot cell (16 per cell)
     bool have_c;
 
     // FBI workspaces
@@ -115,10 +116,19 @@ static inline int fga_halfwidth(double eps, double tau, double d)
 #define FGA_VPAD 6
 
 struct VelGrid {
-    const double *c;   // padded samples, row length ld, origin at [FGA_VPAD][FGA_VPAD]
+    const double *c;      // padded samples, row length ld, origin at [FGA_VPAD][FGA_VPAD]
+    const double *coef;   // per knot cell polynomial coefficients (vel_cell_coef)
     int n1, n2, ld;
     double o1, o2, inv_d1, inv_d2;
 };
+
+// Knot cells i1 in [-4, n1 + 3], i2 in [-4, n2 + 3] (see vel_cell): the
+// coefficient table holds (n1 + 8) (n2 + 8) cells of 16 doubles.
+#define FGA_VCELL_PAD 4
+__host__ __device__ static inline int64_t fga_vcells(int n1, int n2)
+{
+    return (int64_t)(n1 + 2 * FGA_VCELL_PAD) * (n2 + 2 * FGA_VCELL_PAD);
+}
 
 // Cubic B-spline weights of the four knots floor(t)-1 .. floor(t)+2 and their
 // first and second derivatives in t, for fractional part f in [0, 1).
@@ -221,6 +231,45 @@ __device__ __forceinline__ void vel_eval(const VelGrid &V, double x1, double x2,
         c, c1, c2, c11, c12, c22);
 }
 
+// Inside one knot cell the clamped cubic B-spline is the bicubic polynomial
+// c = sum_{a,b} C[b][a] f1^a f2^b of the fractional offsets.  The table holds
+// C[b][a] at entry 4 b + a of the cell's 16 doubles (one 128-byte line).
+__device__ __forceinline__ const double *vel_cell_coef(const VelGrid &V, const VelCell &k)
+{
+    return V.coef + ((int64_t)(k.i2 + FGA_VCELL_PAD) * (V.n1 + 2 * FGA_VCELL_PAD) +
+                     (k.i1 + FGA_VCELL_PAD)) * 16;
+}
+
+// c, grad c and the Hessian from the cell's coefficients C[b][a] by Horner's
+// rule: first in f2 for every power of f1 (value, first and second
+// derivative), then in f1.
+__device__ __forceinline__ void vel_poly(const VelGrid &V, const VelCell &k,
+                                         const double C[4][4], double &c, double &c1, double &c2,
+                                         double &c11, double &c12, double &c22)
+{
+    const double f1 = k.f1, f2 = k.f2;
+    double q[4], q1[4], q2[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        q[a] = fma(fma(fma(C[3][a], f2, C[2][a]), f2, C[1][a]), f2, C[0][a]);
+        const double t3 = 3.0 * C[3][a], t2 = 2.0 * C[2][a];
+        q1[a] = fma(fma(t3, f2, t2), f2, C[1][a]);
+        q2[a] = fma(2.0 * t3, f2, t2);
+    }
+    const double u3 = 3.0 * q[3], u2 = 2.0 * q[2];
+    c = fma(fma(fma(q[3], f1, q[2]), f1, q[1]), f1, q[0]);
+    const double d1 = fma(fma(u3, f1, u2), f1, q[1]);
+    const double d11 = fma(2.0 * u3, f1, u2);
+    const double d2 = fma(fma(fma(q1[3], f1, q1[2]), f1, q1[1]), f1, q1[0]);
+    const double d12 = fma(fma(3.0 * q1[3], f1, 2.0 * q1[2]), f1, q1[1]);
+    const double d22 = fma(fma(fma(q2[3], f1, q2[2]), f1, q2[1]), f1, q2[0]);
+    c1 = d1 * V.inv_d1;
+    c2 = d2 * V.inv_d2;
+    c11 = d11 * (V.inv_d1 * V.inv_d1);
+    c12 = d12 * (V.inv_d1 * V.inv_d2);
+    c22 = d22 * (V.inv_d2 * V.inv_d2);
+}
+
 // Truncation box of a Gaussian centred at Q: the nodes within Rw cells of the
 // node nearest Q (floor(t + 1/2)), clipped to the grid.
 struct BeamBox {
@@ -248,6 +297,7 @@ static inline VelGrid fga_velgrid(const fga_ctx *ctx)
 {
     VelGrid V;
     V.c = ctx->cpad;
+    V.coef = ctx->ccoef;
     V.n1 = ctx->g.n1;
     V.n2 = ctx->g.n2;
     V.ld = ctx->g.n1 + 2 * FGA_VPAD;

@@ -6,10 +6,12 @@
 // One thread owns one beam for all steps: the 23-double state and the RK4
 // accumulators stay in VGPRs, so HBM sees one read and one write of the
 // state per launch.  c and its derivatives come from the cubic B-spline of
-// the velocity samples (16 taps per evaluation, through the L2).  The taps
-// of the next evaluation are requested as soon as its position is known
-// (right after the slope of Q), straight into LDS with global_load_lds, so
-// the L2 latency overlaps the rest of the stage without holding VGPRs.
+// the velocity samples, evaluated as the bicubic polynomial of the knot cell
+// (16 coefficients per cell, formed once per velocity model).  The
+// coefficients of the next evaluation are requested as soon as its position
+// is known (right after the slope of Q), straight into LDS with
+// global_load_lds, so the cache latency overlaps the rest of the stage
+// without holding VGPRs.
 // FP64 throughout: gfx950 runs FP64 FMA at the FP32 rate, and the phase
 // P.(x-Q)/eps needs Q and P to ~1e-14.
 #include <limits.h>
@@ -22,26 +24,15 @@
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-// Velocity source of the RK4 stages: prefetch() sends the 16 taps of the
-// knot cell of (x1, x2) from the padded samples to this wavefront's LDS
-// slots, as eight 16-byte transfers per lane; eval() waits for them and
-// combines them.  Slot 2 kz + h holds taps 2h, 2h + 1 of row kz, lane l at
-// entry l.  A beam moves a fraction of a cell per stage, so a lane whose cell
-// is the one its slots already hold requests nothing: the L2 -> CU traffic
-// drops several-fold (it, not the FP64 arithmetic, bounds this loop
-// otherwise).  The wavefront issues no other vector-memory load inside the
-// step loop, so waiting for every outstanding one waits exactly for the
-// taps.
-// The eight transfers of one tap request for the lanes in mask: 16 bytes
-// from each of a[0..7] (row kz: a[2 kz] at its first tap, a[2 kz + 1] two
-// taps on) into the slots at LDS address lds, 1 KB apart.  (No instruction
-// offset: on these transfers it would move the LDS destination as well.)
-// Written as one block so that the EXEC change leaves no branch in the
-// compiled loop (a branch there makes the register allocator spill the RK4
-// state); each M0 write is followed by the wait state that an LDS transfer
-// after it requires.  No VGPR receives data.
-__device__ __forceinline__ void tap_dma(const double *const a[8], unsigned lds,
-                                        unsigned long long mask)
+// The eight transfers of one request for the lanes in mask: 16 bytes from
+// each of a[0..7] into the slots at LDS address lds, 1 KB apart.  (No
+// instruction offset: on these transfers it would move the LDS destination
+// as well.)  Written as one block so that the EXEC change leaves no branch
+// in the compiled loop (a branch there makes the register allocator spill
+// the RK4 state); each M0 write is followed by the wait state that an LDS
+// transfer after it requires.  No VGPR receives data.
+__device__ __forceinline__ void cell_dma(const double *const a[8], unsigned lds,
+                                         unsigned long long mask)
 {
     unsigned long long saved;
     asm volatile(
@@ -77,25 +68,34 @@ __device__ __forceinline__ void tap_dma(const double *const a[8], unsigned lds,
         : "m0", "scc", "memory");
 }
 
+// Velocity source of the RK4 stages: prefetch() sends the 16 polynomial
+// coefficients of the knot cell of (x1, x2) (one 128-byte line) to this
+// wavefront's LDS slots, as eight 16-byte transfers per lane; eval() waits
+// for them and evaluates the bicubic.  Slot s holds coefficients 2s, 2s + 1,
+// lane l at entry l.  A beam moves a fraction of a cell per stage, so a lane
+// whose cell is the one its slots already hold requests nothing, and the
+// cache -> CU traffic, which bounds this loop otherwise, drops several-fold.
+// (The table is 16 times the velocity grid and does not stay in the L2, but
+// at this request rate one line per request and the shorter evaluation win
+// over the 16 taps of the padded grid.)  The wavefront issues no other
+// vector-memory load inside the step loop, so waiting for every outstanding
+// one waits exactly for these.
 struct VelDma {
     VelGrid V;
     double2 *buf;   // this wavefront's 8 slots of 64 entries
     int lane;
-    int cur1, cur2;   // knot cell whose taps the slots hold (none at first)
+    int cur1, cur2;   // knot cell whose coefficients the slots hold (none at first)
     __device__ __forceinline__ void prefetch(double x1, double x2)
     {
         const VelCell k = vel_cell(V, x1, x2);
         const bool changed = k.i1 != cur1 || k.i2 != cur2;
         cur1 = k.i1;
         cur2 = k.i2;
-        const double *base = vel_taps(V, k);
+        const double *cc = vel_cell_coef(V, k);
         const double *a[8];
 #pragma unroll
-        for (int kz = 0; kz < 4; ++kz) {
-            a[2 * kz] = base + kz * V.ld;
-            a[2 * kz + 1] = base + kz * V.ld + 2;
-        }
-        tap_dma(a, (unsigned)(size_t)(lds_void *)buf, __ballot(changed));
+        for (int sl = 0; sl < 8; ++sl) a[sl] = cc + 2 * sl;
+        cell_dma(a, (unsigned)(size_t)(lds_void *)buf, __ballot(changed));
     }
     __device__ __forceinline__ void eval(double x1, double x2, double &c, double &c1, double &c2,
                                          double &c11, double &c12, double &c22) const
@@ -103,32 +103,30 @@ struct VelDma {
         // the LDS writes of global_load_lds complete with the load counter
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         const VelCell k = vel_cell(V, x1, x2);
-        vel_combine(
-            V, k,
-            [&](int kz, double *v) {
-                const double2 a = buf[(2 * kz) * 64 + lane], b = buf[(2 * kz + 1) * 64 + lane];
-                v[0] = a.x;
-                v[1] = a.y;
-                v[2] = b.x;
-                v[3] = b.y;
-            },
-            c, c1, c2, c11, c12, c22);
+        double C[4][4];
+#pragma unroll
+        for (int sl = 0; sl < 8; ++sl) {
+            const double2 v = buf[sl * 64 + lane];
+            C[sl >> 1][2 * (sl & 1)] = v.x;
+            C[sl >> 1][2 * (sl & 1) + 1] = v.y;
+        }
+        vel_poly(V, k, C, c, c1, c2, c11, c12, c22);
     }
 };
 
 // One thread per beam; the state, the RK4 accumulator and the stage input
-// live in VGPRs (two wavefronts per SIMD), the velocity taps in 8 KB of LDS
-// per wavefront.
+// live in VGPRs (two wavefronts per SIMD), the cell coefficients in 8 KB of
+// LDS per wavefront.
 __global__ void __launch_bounds__(RK_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
       const int64_t *__restrict__ offsets, int nshots, int64_t cap, int64_t NqNp, double dt,
       int nsteps, double *__restrict__ ckpt, int64_t *status)
 {
-    __shared__ double2 taps[RK_BLOCK / 64][8 * 64];
+    __shared__ double2 slots[RK_BLOCK / 64][8 * 64];
     const int tid = threadIdx.x;
     // the wavefront index is uniform: keep the LDS base in a scalar register
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    VelDma vel{V, taps[wave], tid & 63, INT_MIN, INT_MIN};
+    VelDma vel{V, slots[wave], tid & 63, INT_MIN, INT_MIN};
     int64_t nb = offsets[nshots];
     for (int64_t b0 = (int64_t)blockIdx.x * RK_BLOCK; b0 < nb;
          b0 += (int64_t)gridDim.x * RK_BLOCK) {
