@@ -69,7 +69,7 @@ def profiled_traffic(kernel):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="point512")
     ap.add_argument("--fp64-steps", type=int, default=1,
@@ -131,6 +131,8 @@ class Path:
 
 
 def time_path(path, steps, warmup):
+    """Wall ms per step (host clock over all steps), mean per-stage ms and the
+    per-step device times (HIP events from the first stage to the last)."""
     import torch
     for _ in range(warmup):
         path.step()
@@ -143,7 +145,8 @@ def time_path(path, steps, warmup):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     st = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in evs])
-    return wall * 1e3, st.mean(axis=0)
+    per_step = np.array([e[0].elapsed_time(e[3]) for e in evs])
+    return wall * 1e3, st.mean(axis=0), per_step
 
 
 def time_splat_kernel(path, reps=3):
@@ -340,13 +343,13 @@ def main():
 
     mixed = Path(W, "mixed", min(cand, 4_000_000))
     nb = mixed.fit_capacity()
-    ms_step, stage_ms = time_path(mixed, args.steps, args.warmup)
+    ms_step, stage_ms, per_step = time_path(mixed, args.steps, args.warmup)
     u_mixed = mixed.u.cpu().numpy()
     f_host = mixed.beams.f[:, :nb].cpu().numpy()
 
     fp64 = Path(Wd, "fp64", min(cand, 4_000_000))
     nb64 = fp64.fit_capacity()
-    ms64, stage64 = time_path(fp64, args.fp64_steps, 0)
+    ms64, stage64, _ = time_path(fp64, args.fp64_steps, 0)
     u64 = fp64.u.cpu().numpy()
     rel_vs_fp64 = float(np.linalg.norm(u_mixed - u64) / np.linalg.norm(u64))
 
@@ -395,6 +398,10 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_device": {"median": float(np.median(per_step)),
+                               "iqr": float(np.percentile(per_step, 75) -
+                                            np.percentile(per_step, 25)),
+                               "min": float(per_step.min()), "max": float(per_step.max())},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
