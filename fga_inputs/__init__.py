@@ -81,6 +81,7 @@ class Params:
     tau_win: float      # truncation level of the reconstruction window
     dt: float
     nsteps: int
+    top_n: int = 0      # > 0: keep the top_n largest |psi| per branch and shot instead
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)

@@ -154,12 +154,25 @@ def branches(psi0, psi1, c, grid, params):
     return 0.5 * (psi0 + ratio * psi1), 0.5 * (psi0 - ratio * psi1)
 
 
+def select_top_n(mags: np.ndarray, n: int) -> np.ndarray:
+    """Indices of the n largest entries of mags (one branch of one shot), as
+    in the Numerical test section (the N largest amplitudes of psi_+- for
+    each wave branch), in increasing index order.  Equal magnitudes are
+    taken in increasing index order; zero magnitudes are never taken, so
+    fewer than n come back when fewer are nonzero."""
+    order = np.lexsort((np.arange(mags.size), -mags))   # by -|psi|, then index
+    sel = order[:n]
+    return np.sort(sel[mags[sel] > 0])
+
+
 def decompose(f0: np.ndarray, f1: Optional[np.ndarray], c, grid, params,
               psi_cache=None) -> Beams:
-    """Step 1 for every shot: FBI, branch split, threshold, initial state.
+    """Step 1 for every shot: FBI, branch split, selection, initial state.
 
-    Thresholding keeps (sigma, q, p) with |psi_sigma| >= tau * M, M the
-    largest |psi| over both branches of the shot, and |psi| > 0.
+    With params.top_n == 0, thresholding keeps (sigma, q, p) with
+    |psi_sigma| >= tau * M, M the largest |psi| over both branches of the
+    shot, and |psi| > 0; with top_n > 0 each branch keeps its top_n largest
+    |psi_sigma| (select_top_n).
     """
     pr = params
     k1, k2 = qnodes(pr)
@@ -179,8 +192,13 @@ def decompose(f0: np.ndarray, f1: Optional[np.ndarray], c, grid, params,
             psi1 = None if f1 is None else fbi(f1[s], grid, pr)
         pp, pm = branches(psi0, psi1, c, grid, pr)
         mags = np.stack([np.abs(pp).ravel(), np.abs(pm).ravel()])   # [2][nq*np]
-        M = mags.max()
-        keep = (mags >= pr.tau * M) & (mags > 0)
+        if pr.top_n > 0:
+            keep = np.zeros(mags.shape, bool)
+            for br in range(2):
+                keep[br, select_top_n(mags[br], pr.top_n)] = True
+        else:
+            M = mags.max()
+            keep = (mags >= pr.tau * M) & (mags > 0)
         vals = np.stack([pp.ravel(), pm.ravel()])
         sidx, flat = np.nonzero(keep)           # row-major: branch +, then -
         qf, pf = flat // npp, flat % npp

@@ -244,6 +244,72 @@ def test_threshold_set_brute_force():
     np.testing.assert_allclose(b.psi, vals[keep], rtol=0, atol=1e-12 * M)
 
 
+def test_top_n_tie_rule():
+    """The reading of "the N largest amplitudes" on designed input: equal
+    magnitudes are taken in increasing candidate index, zeros never, and the
+    result comes back in index order."""
+    m = np.array([3.0, 1.0, 3.0, 2.0, 3.0, 0.0, 0.0, 2.5])
+    np.testing.assert_array_equal(oracle.select_top_n(m, 1), [0])
+    np.testing.assert_array_equal(oracle.select_top_n(m, 2), [0, 2])
+    np.testing.assert_array_equal(oracle.select_top_n(m, 4), [0, 2, 4, 7])
+    np.testing.assert_array_equal(oracle.select_top_n(m, 5), [0, 2, 3, 4, 7])
+    np.testing.assert_array_equal(oracle.select_top_n(m, 100), [0, 1, 2, 3, 4, 7])
+    np.testing.assert_array_equal(oracle.select_top_n(np.zeros(5), 3), [])
+
+
+def _topn_case(seed=31):
+    n = 24
+    g = fi.Grid(n, n, 0.0, 0.0, 1 / 24, 1 / 24)
+    r = fi.rng(seed)
+    f0 = r.standard_normal(g.shape) * fi.gaussian_source(g, (0.48, 0.53), 0.08)
+    f1 = 0.4 * r.standard_normal(g.shape) * fi.gaussian_source(g, (0.5, 0.5), 0.1)
+    c = 1.0 + 0.5 * r.uniform(size=g.shape)
+    p = fi.Params(1 / 120, 3, 2, 4, 5, 5, 4, 6, 8, 0.12, 0.1, 0.05, 1e-16, 1e-16, 1e-3, 0)
+    return g, p, c, f0, f1
+
+
+def test_top_n_against_brute_force_magnitudes():
+    """Each branch keeps the candidates of its N largest |psi_+-|, with psi
+    from the unwindowed brute-force integral; N = 1 is the branch maximum
+    and the sets are nested in N."""
+    g, p, c, f0, f1 = _topn_case()
+    psi0 = _brute_psi(f0, g, p)
+    psi1 = _brute_psi(f1, g, p)
+    pp, pm = oracle.branches(psi0, psi1, c, g, p)
+    nq, npp = p.nq1 * p.nq2, p.np1 * p.np2
+    prev = None
+    for n in (1, 7, 60, 2 * nq * npp):
+        b = oracle.decompose(f0[None], f1[None], c, g, p.replace(top_n=n))
+        got = set(b.cand.tolist())
+        for br, v in enumerate((pp, pm)):
+            mags = np.abs(v).ravel()
+            mine = sorted(x - br * nq * npp for x in got if br * nq * npp <= x < (br + 1) * nq * npp)
+            assert len(mine) == min(n, int((mags > 0).sum()))
+            # every kept magnitude is >= every dropped one (no ties in this input)
+            drop = np.setdiff1d(np.arange(mags.size), mine)
+            if drop.size and mine:
+                assert mags[mine].min() > mags[drop].max()
+            if n == 1:
+                assert mine == [int(np.argmax(mags))]
+        if prev is not None:
+            assert prev <= got
+        prev = got
+
+
+def test_top_n_equals_threshold_set():
+    """With f1 = 0 both branches carry the same magnitudes, so the relative
+    threshold keeps the same count N in each; top-N with that N keeps the
+    same beams, in the same order."""
+    g, p, c, f0, _ = _topn_case(seed=33)
+    for tau in (0.3, 0.05, 1e-3):
+        bt = oracle.decompose(f0[None], None, c, g, p.replace(tau=tau))
+        npl, nmi = (bt.sigma > 0).sum(), (bt.sigma < 0).sum()
+        assert npl == nmi > 0
+        bn = oracle.decompose(f0[None], None, c, g, p.replace(top_n=int(npl)))
+        np.testing.assert_array_equal(bn.cand, bt.cand)
+        np.testing.assert_array_equal(bn.coef, bt.coef)
+
+
 def test_branch_symmetry():
     """For real f0, f1: psi_+(q, -p) = conj psi_-(q, p) (from u_{+-,0} and a
     symmetric p-mesh), so both branches keep the same number of beams."""
