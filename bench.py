@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=3,
                     help="timed graph replays of the 64-shot batch (0 skips it)")
+    ap.add_argument("--topn-steps", type=int, default=5,
+                    help="timed steps of the N-largest selection workload (0 skips it)")
     ap.add_argument("--adjoint-steps", type=int, default=3,
                     help="timed iterations of the adjoint workload (0 skips it)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -260,6 +262,24 @@ def batched_shots(steps):
             "beams_per_s": nb / (ms * 1e-3), "splat_units_per_cu": chosen, "status": st}
 
 
+def topn_step(steps):
+    """The paper's selection mode: point512 keeping the N = 5650 largest
+    |psi| of each wave branch (mixed precision); ms per decompose ->
+    propagate -> reconstruct step and its stages."""
+    import torch
+    W = fi.workload("topn512", "mixed")
+    path = Path(W, "mixed", 4 * W.params.top_n)
+    nb = path.fit_capacity()
+    ms, stage_ms, per_step = time_path(path, steps, 1)
+    st, _ = path.ctx.status()
+    return {"workload": "topn512: point512 keeping the 5650 largest |psi| per wave branch "
+            "(radix select), mixed", "nbeams": nb, "ms_per_step": ms,
+            "ms_per_step_device_median": float(np.median(per_step)),
+            "beams_per_s": nb / (ms * 1e-3),
+            "stages_ms": dict(zip(("decompose", "propagate", "reconstruct"),
+                                  stage_ms.tolist())), "status": st}
+
+
 def box_pairs(f, nb, W, tau_win):
     """Number of (beam, node) pairs the windowed sum visits."""
     g, p = W.grid, W.params
@@ -427,6 +447,8 @@ def main():
         out["adjoint"] = adjoint_iteration(args.adjoint_steps)
     if args.batch_steps > 0:
         out["batched"] = batched_shots(args.batch_steps)
+    if args.topn_steps > 0:
+        out["topn"] = topn_step(args.topn_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Wd, nb, args.cpu_seconds)
     print(json.dumps(out), flush=True)

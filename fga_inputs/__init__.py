@@ -231,6 +231,11 @@ def workload(name: str, precision: str = "fp64", nshots: Optional[int] = None) -
         p = Params(eps, 2, 8, 13, 26, 40, 20, 112, 112, 0.05, 0.05,
                    1e-6, tw, tw, 1e-3, 250)
         return Workload(name, grid, p, c, f0[None], None)
+    if name == "topn512":
+        # point512 with the N-largest selection of the paper's experiment
+        # (N = 5650 beams per wave branch)
+        W = workload("point512", precision)
+        return Workload(name, W.grid, W.params.replace(top_n=5650), W.c, W.f0, None)
     if name == "shots512":
         grid = Grid(512, 512, 0.0, 0.0, 1 / 256, 1 / 512)
         eps = 1 / 256
@@ -263,4 +268,4 @@ def workload(name: str, precision: str = "fp64", nshots: Optional[int] = None) -
     raise KeyError(name)
 
 
-WORKLOADS = ("wavepacket", "point512", "shots512", "adjoint256", "large2048")
+WORKLOADS = ("wavepacket", "point512", "topn512", "shots512", "adjoint256", "large2048")

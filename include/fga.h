@@ -71,7 +71,15 @@ typedef struct {
  *   p-mesh     p_l = (l - (np-1)/2) * dp per axis; np1, np2 even, so p = 0
  *              is never a node
  *   tau        keep (branch, q, p) with |psi| >= tau * max|psi| (per shot,
- *              over both branches) and |psi| > 0
+ *              over both branches) and |psi| > 0 (thresholding paragraph of
+ *              the Initial wavefield decomposition section); used when
+ *              top_n = 0
+ *   top_n      if > 0: each branch of each shot keeps instead its top_n
+ *              largest |psi| (the N-largest selection of the Numerical test
+ *              section), equal magnitudes in increasing candidate order,
+ *              never |psi| = 0 (so fewer when fewer are nonzero).  The
+ *              magnitudes are compared in the precision of the FBI (FP32 in
+ *              FGA_MIXED)
  *   tau_fbi    the FBI box B_eps has half-width ceil(sqrt(2 eps ln(1/tau_fbi))/d)
  *   tau_win    each Gaussian is summed over the box of half-width
  *              ceil(sqrt(2 eps ln(1/tau_win))/d) around the node nearest Q
@@ -83,6 +91,7 @@ typedef struct {
     double dp1, dp2;
     double tau, tau_fbi, tau_win;
     double dt;
+    int32_t top_n;
 } fga_params;
 
 /* Beam storage: structure of arrays in one float64 buffer

@@ -72,6 +72,7 @@ static fga_status check_params(fga_ctx *ctx, const fga_grid *g, const fga_params
     if (!(p->tau_fbi > 0 && p->tau_fbi < 1) || !(p->tau_win > 0 && p->tau_win < 1))
         return fga_fail(ctx, FGA_EINVAL, "tau_fbi and tau_win must lie in (0, 1)");
     if (!(p->dt > 0) || !isfinite(p->dt)) return fga_fail(ctx, FGA_EINVAL, "dt must be positive");
+    if (p->top_n < 0) return fga_fail(ctx, FGA_EINVAL, "top_n must be >= 0");
     int R1 = fga_halfwidth(p->eps, p->tau_fbi, g->d1);
     int R2 = fga_halfwidth(p->eps, p->tau_fbi, g->d2);
     if (R1 > 8192 || R2 > 8192)

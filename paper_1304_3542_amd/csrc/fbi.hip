@@ -309,46 +309,220 @@ __global__ void k_zero_u64(unsigned long long *p, int n)
 #define CMP_BLOCK 256
 #define CMP_TILE (CMP_ITEMS * CMP_BLOCK)
 
-template <typename R>
-__device__ __forceinline__ bool keep_cand(R mag, R thr)
+// ---------------------------------------------------------------- selection
+// Every (shot, branch) keeps the candidates whose magnitude key is above
+// Sel.key, plus the first Sel.ties of those whose key equals it, in
+// candidate order.  The key is the bit pattern of |psi| (non-negative floats
+// order like their bit patterns); NaN maps to 0, which is never kept.
+struct Sel {
+    unsigned long long key;
+    long long ties;
+    unsigned long long prefix;   // radix select: digits fixed so far
+    long long rem;               // radix select: rank still to place (< 0: done)
+};
+
+__device__ __forceinline__ unsigned long long mag_key(float m)
 {
-    return mag >= thr && mag > (R)0;
+    return isnan(m) ? 0ull : (unsigned long long)__float_as_uint(m);
+}
+__device__ __forceinline__ unsigned long long mag_key(double m)
+{
+    return isnan(m) ? 0ull : (unsigned long long)__double_as_longlong(m);
+}
+
+// Relative threshold: keep |psi| >= tau M and |psi| > 0, M the largest
+// |psi| of the shot over both branches (thresholding paragraph), i.e.
+// key >= key(tau M), and key > 0 when tau M = 0.
+template <typename R>
+__global__ void k_sel_threshold(const unsigned long long *maxbits, double tau, Sel *sel,
+                                int nsb)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsb) return;
+    const double M = __longlong_as_double((long long)maxbits[i >> 1]);
+    const unsigned long long kt = mag_key((R)(tau * M));
+    sel[i].key = kt ? kt - 1 : 0;
+    sel[i].ties = 0;
+}
+
+// N largest per branch (Numerical test section) by radix select on the key,
+// eight bits per pass from the top: per pass a histogram of the next digit
+// over the candidates that match the digits fixed so far, then the digit
+// whose bucket holds the remaining rank.  After the last pass the key of the
+// N-th largest is fixed, and rem of the candidates equal to it are still to
+// take (the first rem in candidate order).  Fewer than N nonzero candidates:
+// all of them are kept.
+#define TOPN_BINS 256
+
+__global__ void k_topn_init(Sel *sel, unsigned long long *hist, int nsb, long long n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nsb * TOPN_BINS;
+         i += gridDim.x * blockDim.x) {
+        hist[i] = 0ull;
+        if (i < nsb) {
+            sel[i].key = 0ull;
+            sel[i].ties = 0;
+            sel[i].prefix = 0ull;
+            sel[i].rem = n;
+        }
+    }
 }
 
 template <typename R>
-__device__ __forceinline__ R threshold_of(const unsigned long long *maxbits, int s, double tau)
+__global__ void __launch_bounds__(256)
+k_topn_hist(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGeom G,
+            const Sel *sel, unsigned long long *hist, int pass, int npass)
 {
-    double M = __longlong_as_double((long long)maxbits[s]);
-    return (R)(tau * M);
+    __shared__ unsigned int h[TOPN_BINS];
+    const int y = blockIdx.y, s = y >> 1, sb = y & 1;
+    const Sel S = sel[y];
+    if (S.rem < 0) return;   // uniform over the workgroup
+    for (int d = threadIdx.x; d < TOPN_BINS; d += blockDim.x) h[d] = 0u;
+    __syncthreads();
+    const int shift = (npass - 1 - pass) * 8;
+    const int64_t NqNp = G.Nq * G.Np;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < NqNp;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        R re, im;
+        cand_psi(Psi, cq, G, s, sb * NqNp + c, re, im);
+        const unsigned long long key = mag_key(cabs_r(re, im));
+        if (key == 0ull) continue;
+        if (pass > 0 && (key >> (shift + 8)) != S.prefix) continue;
+        atomicAdd(&h[(key >> shift) & (TOPN_BINS - 1)], 1u);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < TOPN_BINS; d += blockDim.x)
+        if (h[d]) atomicAdd(&hist[(size_t)y * TOPN_BINS + d], (unsigned long long)h[d]);
 }
 
-// Per-block keep counts, blocks in candidate order.  A block covers
-// CMP_TILE consecutive candidates in CMP_ITEMS rounds of CMP_BLOCK; in every
-// round consecutive threads read consecutive candidates.
+__global__ void k_topn_pick(Sel *sel, unsigned long long *hist, int nsb, int pass, int npass)
+{
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= nsb) return;
+    Sel S = sel[y];
+    unsigned long long *hh = hist + (size_t)y * TOPN_BINS;
+    if (S.rem >= 0) {
+        long long above = 0;
+        int digit = -1;
+        for (int d = TOPN_BINS - 1; d >= 0; --d) {
+            const long long c = (long long)hh[d];
+            if (above + c >= S.rem) {
+                digit = d;
+                break;
+            }
+            above += c;
+        }
+        if (digit < 0) {
+            // fewer nonzero candidates than N (only possible in the first pass)
+            S.key = 0ull;
+            S.ties = 0;
+            S.rem = -1;
+        } else {
+            S.prefix = (S.prefix << 8) | (unsigned long long)digit;
+            S.rem -= above;
+            if (pass == npass - 1) {
+                S.key = S.prefix;
+                S.ties = S.rem;
+                S.rem = -1;
+            }
+        }
+        sel[y] = S;
+    }
+    for (int d = 0; d < TOPN_BINS; ++d) hh[d] = 0ull;
+}
+
+// ---------------------------------------------------------------- compaction
+// Blocks never straddle the two branches of a shot: a shot has 2 nblkb
+// blocks, block bx covers the candidates sb NqNp + (bx - sb nblkb) CMP_TILE
+// + [0, CMP_TILE) of branch sb = bx / nblkb, in CMP_ITEMS rounds of
+// CMP_BLOCK consecutive candidates.
+struct CmpBlock {
+    int s, sb;
+    int64_t first, end;   // candidate range (shot-local index)
+};
+
+__device__ __forceinline__ CmpBlock cmp_block(const CandGeom &G, int nblkb)
+{
+    CmpBlock B;
+    B.s = blockIdx.y;
+    B.sb = blockIdx.x / nblkb;
+    const int64_t NqNp = G.Nq * G.Np;
+    B.first = B.sb * NqNp + (int64_t)(blockIdx.x - B.sb * nblkb) * CMP_TILE;
+    B.end = min(B.first + (int64_t)CMP_TILE, (B.sb + 1) * NqNp);
+    return B;
+}
+
+// per block: kept-above-key count (gt) and equal-key count (eq)
 template <typename R>
 __global__ void __launch_bounds__(CMP_BLOCK)
 k_count(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGeom G,
-        const unsigned long long *maxbits, double tau, int64_t *blk, int nblk)
+        const Sel *sel, int64_t *blk_gt, int64_t *blk_eq, int nblkb)
 {
-    __shared__ int red[CMP_BLOCK / 64];
-    const int s = blockIdx.y;
-    const R thr = threshold_of<R>(maxbits, s, tau);
-    const int64_t base = (int64_t)blockIdx.x * CMP_TILE + threadIdx.x;
-    int cnt = 0;
+    __shared__ int red[2][CMP_BLOCK / 64];
+    const CmpBlock B = cmp_block(G, nblkb);
+    const unsigned long long K = sel[B.s * 2 + B.sb].key;
+    int gt = 0, eq = 0;
     for (int i = 0; i < CMP_ITEMS; ++i) {
-        const int64_t cl = base + (int64_t)i * CMP_BLOCK;
-        if (cl >= G.per_shot) break;
+        const int64_t cl = B.first + (int64_t)i * CMP_BLOCK + threadIdx.x;
+        if (cl >= B.end) break;
         R re, im;
-        cand_psi(Psi, cq, G, s, cl, re, im);
-        cnt += keep_cand(cabs_r(re, im), thr) ? 1 : 0;
+        cand_psi(Psi, cq, G, B.s, cl, re, im);
+        const unsigned long long key = mag_key(cabs_r(re, im));
+        gt += key > K ? 1 : 0;
+        eq += (key == K && key != 0ull) ? 1 : 0;
     }
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
+    for (int o = 32; o > 0; o >>= 1) {
+        gt += __shfl_xor(gt, o);
+        eq += __shfl_xor(eq, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = gt;
+        red[1][threadIdx.x >> 6] = eq;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int tot = 0;
-        for (int w = 0; w < CMP_BLOCK / 64; ++w) tot += red[w];
-        blk[(size_t)s * nblk + blockIdx.x] = tot;
+        int tg = 0, te = 0;
+        for (int w = 0; w < CMP_BLOCK / 64; ++w) {
+            tg += red[0][w];
+            te += red[1][w];
+        }
+        const size_t at = (size_t)B.s * 2 * nblkb + blockIdx.x;
+        blk_gt[at] = tg;
+        blk_eq[at] = te;
+    }
+}
+
+// One workgroup per (shot, branch): exclusive scan of the equal-key counts
+// over the branch's blocks (the tie rank at each block's start, into blk_eq)
+// and the ties each block takes, added to its kept count (blk_gt).
+__global__ void __launch_bounds__(1024)
+k_scan_ties(const Sel *sel, int64_t *blk_gt, int64_t *blk_eq, int nblkb)
+{
+    __shared__ int64_t part[1024];
+    const int y = blockIdx.x;   // shot * 2 + branch
+    const long long ties = sel[y].ties;
+    int64_t *eq = blk_eq + (size_t)y * nblkb;
+    int64_t *gt = blk_gt + (size_t)y * nblkb;
+    const int t = threadIdx.x;
+    const int per = (nblkb + 1023) / 1024;
+    const int lo = min(t * per, nblkb), hi = min(lo + per, nblkb);
+    int64_t sum = 0;
+    for (int i = lo; i < hi; ++i) sum += eq[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int64_t v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - sum;
+    for (int i = lo; i < hi; ++i) {
+        const int64_t e = eq[i];
+        const int64_t take = min(max((int64_t)ties - run, (int64_t)0), e);
+        gt[i] += take;
+        eq[i] = run;
+        run += e;
     }
 }
 
@@ -390,44 +564,59 @@ k_scan_blocks(int64_t *blk, int64_t n, int nblk, int nshots, int64_t *offsets,
     }
 }
 
-// Compaction in candidate order: per round, a wave ballot ranks the kept
-// candidates inside each wavefront and the wavefront totals (LDS) order the
-// wavefronts, so kept beams of one round land at consecutive positions.
+// exclusive prefix over the workgroup of a per-round wave ballot
+__device__ __forceinline__ int block_rank(unsigned long long m, int *wsum, int &total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) wsum[wv] = __popcll(m);
+    __syncthreads();
+    int base = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < CMP_BLOCK / 64; ++w) {
+        base += w < wv ? wsum[w] : 0;
+        total += wsum[w];
+    }
+    __syncthreads();
+    return base + __popcll(m & ((1ull << lane) - 1ull));
+}
+
+// Compaction in candidate order: per round, wave ballots rank the tied and
+// the kept candidates inside each wavefront and the wavefront totals (LDS)
+// order the wavefronts, so kept beams of one round land at consecutive
+// positions and ties are taken in candidate order.
 template <typename R>
 __global__ void __launch_bounds__(CMP_BLOCK)
 k_scatter(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGeom G,
-          const unsigned long long *maxbits, double tau, const int64_t *blk, int nblk,
+          const Sel *sel, const int64_t *blk_pos, const int64_t *blk_tie, int nblkb,
           fga_beams B, double o1, double o2, double d1, double d2, int qb1, int qb2,
           int qs1, int qs2, double norm)
 {
     __shared__ int wsum[CMP_BLOCK / 64];
-    const int s = blockIdx.y;
-    const R thr = threshold_of<R>(maxbits, s, tau);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const unsigned long long below = (1ull << lane) - 1ull;
+    const CmpBlock C = cmp_block(G, nblkb);
+    const int s = C.s;
+    const Sel S = sel[s * 2 + C.sb];
     const int64_t cap = B.capacity;
     const int64_t NqNp = G.Nq * G.Np;
-    int64_t run = blk[(size_t)s * nblk + blockIdx.x];
+    const size_t at = (size_t)s * 2 * nblkb + blockIdx.x;
+    int64_t run = blk_pos[at];
+    int64_t tie_run = blk_tie[at];
     for (int i = 0; i < CMP_ITEMS; ++i) {
-        const int64_t cl = (int64_t)blockIdx.x * CMP_TILE + (int64_t)i * CMP_BLOCK + threadIdx.x;
+        const int64_t cl = C.first + (int64_t)i * CMP_BLOCK + threadIdx.x;
         R re = 0, im = 0;
-        bool keep = false;
-        if (cl < G.per_shot) {
+        unsigned long long key = 0ull;
+        if (cl < C.end) {
             cand_psi(Psi, cq, G, s, cl, re, im);
-            keep = keep_cand(cabs_r(re, im), thr);
+            key = mag_key(cabs_r(re, im));
         }
-        const unsigned long long m = __ballot(keep);
-        if (lane == 0) wsum[wv] = __popcll(m);
-        __syncthreads();
-        int wbase = 0, tot = 0;
-#pragma unroll
-        for (int w = 0; w < CMP_BLOCK / 64; ++w) {
-            wbase += w < wv ? wsum[w] : 0;
-            tot += wsum[w];
-        }
-        __syncthreads();
-        const int64_t pos = run + wbase + __popcll(m & below);
-        run += tot;
+        const bool tie = key == S.key && key != 0ull;
+        int ntie = 0;
+        const int tr = block_rank(__ballot(tie), wsum, ntie);
+        const bool keep = key > S.key || (tie && tie_run + tr < S.ties);
+        tie_run += ntie;
+        int nkeep = 0;
+        const int64_t pos = run + block_rank(__ballot(keep), wsum, nkeep);
+        run += nkeep;
         if (keep && pos < cap) {
             const int sb = (int)(cl / NqNp);
             const int64_t rem = cl - sb * NqNp;
@@ -468,6 +657,8 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
     int S = nshots * nfj;
     ctx->last_nfj = nfj;
     ctx->last_nshots = nshots;
+    if (p.top_n > 0 && 2 * nshots > 65535)
+        return fga_fail(ctx, FGA_EINVAL, "top_n selection takes at most 32767 shots per call");
     if ((int64_t)S * std::max(p.nq1, p.nq2) > 65535)
         return fga_fail(ctx, FGA_EINVAL,
                         "nshots * (1 + (f1 != NULL)) * max(nq1, nq2) = %lld exceeds 65535",
@@ -500,15 +691,24 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
     G.dp1 = p.dp1;
     G.dp2 = p.dp2;
     G.eps = p.eps;
-    int64_t nblk64 = (G.per_shot + CMP_TILE - 1) / CMP_TILE;
-    if (nblk64 > 0x7fffffff) return fga_fail(ctx, FGA_EINVAL, "too many candidates per shot");
-    int nblk = (int)nblk64;
-    size_t blk_bytes = (size_t)nshots * nblk * sizeof(int64_t);
+    const int64_t nblkb64 = (G.Nq * G.Np + CMP_TILE - 1) / CMP_TILE;
+    if (2 * nblkb64 > 0x7fffffff) return fga_fail(ctx, FGA_EINVAL, "too many candidates per shot");
+    const int nblkb = (int)nblkb64, nblk = 2 * nblkb;
+    // compaction counts: kept (then positions) and equal-key counts (then tie
+    // ranks) per block; the selection records and radix histograms
+    const size_t nblk_all = (size_t)nshots * nblk;
+    const int nsb = 2 * nshots;
+    const size_t sel_bytes = (size_t)nsb * sizeof(Sel), hist_bytes = (size_t)nsb * TOPN_BINS * 8;
+    const size_t sel_elems = (sel_bytes + hist_bytes + 7) / 8;
     size_t have_blk = ctx->blk_elems * sizeof(int64_t);
-    if ((rc = fga_ensure(ctx, (void **)&ctx->blk, &have_blk, blk_bytes, "compaction counts")) !=
+    if ((rc = fga_ensure(ctx, (void **)&ctx->blk, &have_blk,
+                         (2 * nblk_all + sel_elems) * sizeof(int64_t), "compaction counts")) !=
         FGA_OK)
         return rc;
     ctx->blk_elems = have_blk / sizeof(int64_t);
+    int64_t *blk_kept = ctx->blk, *blk_eq = ctx->blk + nblk_all;
+    Sel *sel = (Sel *)(ctx->blk + 2 * nblk_all);
+    unsigned long long *hist = (unsigned long long *)((char *)sel + sel_bytes);
 
     if (fresh) {
         hipLaunchKernelGGL(k_tables<R>, dim3(512), dim3(256), 0, st, (cplx<R> *)ctx->E1t,
@@ -527,17 +727,32 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
     hipLaunchKernelGGL(k_fbi_pass2<R>, g2, dim3(256), 0, st, (const cplx<R> *)ctx->T,
                        (const cplx<R> *)ctx->E2, (cplx<R> *)ctx->Psi, g.n2, ctx->R2, p.qb2,
                        p.qs2, p.nq2, p.np2, (int)NC, g.d2);
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, st, ctx->maxbits, nshots);
-    int gmax = (int)std::min<int64_t>((G.per_shot + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_branch_max<R>, dim3(gmax, nshots), dim3(256), 0, st,
-                       (const cplx<R> *)ctx->Psi, ctx->cq, G, ctx->maxbits);
+    if (p.top_n > 0) {
+        const int npass = (int)sizeof(R);   // eight bits of the key per pass
+        hipLaunchKernelGGL(k_topn_init, dim3((nsb * TOPN_BINS + 255) / 256), dim3(256), 0, st,
+                           sel, hist, nsb, (long long)p.top_n);
+        const int gh = (int)std::min<int64_t>((G.Nq * G.Np + 255) / 256, 512);
+        for (int pass = 0; pass < npass; ++pass) {
+            hipLaunchKernelGGL(k_topn_hist<R>, dim3(gh, nsb), dim3(256), 0, st,
+                               (const cplx<R> *)ctx->Psi, ctx->cq, G, sel, hist, pass, npass);
+            hipLaunchKernelGGL(k_topn_pick, dim3((nsb + 63) / 64), dim3(64), 0, st, sel, hist,
+                               nsb, pass, npass);
+        }
+    } else {
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, st, ctx->maxbits, nshots);
+        int gmax = (int)std::min<int64_t>((G.per_shot + 255) / 256, 1024);
+        hipLaunchKernelGGL(k_branch_max<R>, dim3(gmax, nshots), dim3(256), 0, st,
+                           (const cplx<R> *)ctx->Psi, ctx->cq, G, ctx->maxbits);
+        hipLaunchKernelGGL(k_sel_threshold<R>, dim3((nsb + 63) / 64), dim3(64), 0, st,
+                           ctx->maxbits, p.tau, sel, nsb);
+    }
     hipLaunchKernelGGL(k_count<R>, dim3(nblk, nshots), dim3(CMP_BLOCK), 0, st,
-                       (const cplx<R> *)ctx->Psi, ctx->cq, G, ctx->maxbits, p.tau, ctx->blk, nblk);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, ctx->blk,
-                       (int64_t)nshots * nblk, nblk, nshots, beams->offsets, beams->capacity,
-                       ctx->status);
+                       (const cplx<R> *)ctx->Psi, ctx->cq, G, sel, blk_kept, blk_eq, nblkb);
+    hipLaunchKernelGGL(k_scan_ties, dim3(nsb), dim3(1024), 0, st, sel, blk_kept, blk_eq, nblkb);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, blk_kept, (int64_t)nblk_all,
+                       nblk, nshots, beams->offsets, beams->capacity, ctx->status);
     hipLaunchKernelGGL(k_scatter<R>, dim3(nblk, nshots), dim3(CMP_BLOCK), 0, st,
-                       (const cplx<R> *)ctx->Psi, ctx->cq, G, ctx->maxbits, p.tau, ctx->blk, nblk,
+                       (const cplx<R> *)ctx->Psi, ctx->cq, G, sel, blk_kept, blk_eq, nblkb,
                        *beams, g.o1, g.o2, g.d1, g.d2, p.qb1, p.qb2, p.qs1, p.qs2, ctx->norm);
     FGA_HIP(ctx, hipGetLastError());
     return FGA_OK;
