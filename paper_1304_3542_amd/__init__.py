@@ -317,3 +317,62 @@ class FGA:
 
     def offsets(self, beams: Beams, nshots: int):
         return fga_copy_offsets(self.ctx, beams, nshots)
+
+
+def _trace_function():
+    import torch
+
+    class TraceFunction(torch.autograd.Function):
+        """Receiver traces as a differentiable function of the velocity
+        samples c and the initial data f0 (and f1): forward = fga_decompose
+        + fga_trace with checkpoints, backward = fga_trace_adjoint +
+        fga_decompose_adjoint (the library's hand-written adjoint; the beam
+        set and truncation boxes of the forward are held fixed).  The beams
+        and the context must not run another decomposition between the
+        forward and the backward call."""
+
+        @staticmethod
+        def forward(actx, c, f0, f1, fga, beams, rec, rec_every, nrec_t):
+            nshots = f0.shape[0]
+            c = c.detach().contiguous()
+            f0 = f0.detach().contiguous()
+            f1 = None if f1 is None else f1.detach().contiguous()
+            fga.set_velocity(c)
+            fga.decompose(f0, f1, beams)
+            ckpt = torch.empty((nrec_t, FGA_NSTATE, beams.capacity), dtype=torch.float64,
+                               device=beams.f.device)
+            tr = fga.trace(beams, nshots, rec, rec_every, nrec_t, ckpt)
+            actx.fga, actx.beams, actx.rec = fga, beams, rec
+            actx.rec_every, actx.nrec_t, actx.nshots = rec_every, nrec_t, nshots
+            actx.has_f1 = f1 is not None
+            actx.save_for_backward(c, ckpt)
+            return tr
+
+        @staticmethod
+        def backward(actx, gtr):
+            c, ckpt = actx.saved_tensors
+            fga, beams = actx.fga, actx.beams
+            dc = torch.zeros_like(c)
+            gcoef = fga.trace_adjoint(beams, actx.nshots, actx.rec, actx.rec_every, actx.nrec_t,
+                                      ckpt, gtr.contiguous(), dc)
+            df1 = None
+            if actx.has_f1:
+                df1 = torch.empty((actx.nshots,) + tuple(c.shape), dtype=torch.float64,
+                                  device=c.device)
+            df0 = fga.decompose_adjoint(beams, actx.nshots, gcoef, df1,
+                                        dc if actx.has_f1 else None)
+            return dc, df0, df1, None, None, None, None, None
+
+    return TraceFunction
+
+
+_TRACE_FN = None
+
+
+def traces(c, f0, f1, fga: FGA, beams: Beams, rec, rec_every: int, nrec_t: int):
+    """Differentiable receiver traces [nshots][nrec_t][nrec] (torch autograd):
+    gradients with respect to c, f0 and f1 come from the library's adjoint."""
+    global _TRACE_FN
+    if _TRACE_FN is None:
+        _TRACE_FN = _trace_function()
+    return _TRACE_FN.apply(c, f0, f1, fga, beams, rec, rec_every, nrec_t)

@@ -121,3 +121,31 @@ def test_adjoint_full_size_matches_finite_differences():
         cm[i2, i1] -= h
         fd = (J(torch.from_numpy(cp).cuda()) - J(torch.from_numpy(cm).cuda())) / (2 * h)
         assert abs(fd - dcn[i2, i1]) <= 1e-6 * scale, (idx, fd, dcn[i2, i1], scale)
+
+
+@pytest.mark.parametrize("with_f1", [False, True])
+def test_autograd_function_matches_oracle_gradient(with_f1):
+    """The adjoint behind torch.autograd: loss.backward() through
+    paper_1304_3542_amd.traces gives the gradient oracle's dJ/dc, dJ/df0
+    (and dJ/df1)."""
+    import torch
+    import paper_1304_3542_amd as fga
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(with_f1)
+    b = oracle.decompose(f0, f1, c, g, p)
+    data = 0.5 * c_oracle_traces(c * 1.02, f0, f1, g, p, b.cand, rec, every, nrec)
+    J, dc, df0, df1, _ = oadj.gradient(c, f0, f1, g, p, b.cand, rec, every, nrec, data)
+    ns = f0.shape[0]
+    ctx = fga.FGA(g, p, "fp64", max_shots=ns)
+    beams = fga.Beams(2 * p.nq1 * p.nq2 * p.np1 * p.np2 * ns, ns)
+    ct = torch.from_numpy(c).cuda().requires_grad_(True)
+    f0t = torch.from_numpy(f0).cuda().requires_grad_(True)
+    f1t = None if f1 is None else torch.from_numpy(f1).cuda().requires_grad_(True)
+    tr = fga.traces(ct, f0t, f1t, ctx, beams, torch.from_numpy(rec).cuda(), every, nrec)
+    loss = 0.5 * ((tr - torch.from_numpy(data).cuda()) ** 2).sum()
+    loss.backward()
+    assert ctx.status()[0] == 0
+    assert abs(loss.item() - J) <= 1e-10 * abs(J)
+    assert rel_max(ct.grad.cpu().numpy(), dc) <= 1e-10
+    assert rel_max(f0t.grad.cpu().numpy(), df0) <= 1e-10
+    if with_f1:
+        assert rel_max(f1t.grad.cpu().numpy(), df1) <= 1e-10
