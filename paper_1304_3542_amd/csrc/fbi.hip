@@ -12,6 +12,8 @@
 // Pass 2 is a batched complex GEMM (M = np2, N = nq1*np1, K = box height).
 #include <math.h>
 
+#include <type_traits>
+
 #include "fga_internal.h"
 
 template <typename R>
@@ -226,6 +228,112 @@ k_fbi_pass2(const cplx<R> *__restrict__ T, const cplx<R> *__restrict__ E2,
             out[(size_t)l * NC + cc].im = acci[i][j] * (R)d2;
         }
     }
+}
+
+// Pass 2 of the mixed path on the matrix cores.  A complex MAC over k is a
+// K = 2 real product: with v_mfma_f32_32x32x2f32 lane l holds A[l % 32][l / 32]
+// and B[l / 32][l % 32], so
+//   Re Psi:  A = [Re E, -Im E] (rows l2, k = re/im part), B = [Re T ; Im T]
+//   Im Psi:  A = [Im E,  Re E],                            B = [Re T ; Im T]
+// two MFMAs per complex k and 32 x 32 block.  A workgroup of four wavefronts
+// computes a 128 (l2) x 128 (c) tile of one (shot, j2); each wavefront a
+// 64 x 64 quarter (2 x 2 blocks, Re and Im: eight FP32 accumulators).  The
+// table and T are staged through LDS, 16 window rows at a time.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+#define P2M_T 128
+#define P2M_K 16
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_fbi_pass2_mfma(const cplx<float> *__restrict__ T, const cplx<float> *__restrict__ E2,
+                 cplx<float> *__restrict__ Psi, int n2, int R2, int qb2, int qs2, int nq2,
+                 int np2, int NC, double d2)
+{
+    __shared__ float2 Es[P2M_K][P2M_T];   // [k][l2]
+    __shared__ float2 Ts[P2M_K][P2M_T];   // [k][c]
+    const int W2 = 2 * R2 + 1;
+    const int sfj = blockIdx.z;
+    const int sf = sfj / nq2, j2 = sfj % nq2;
+    const int k2 = qb2 + j2 * qs2;
+    const int mlo = max(-R2, -k2), mhi = min(R2, n2 - 1 - k2);
+    const int K = mhi - mlo + 1;
+    const int c0 = blockIdx.x * P2M_T, l0 = blockIdx.y * P2M_T;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    const int wr = wv >> 1, wc = wv & 1;
+    const int i = lane & 31;
+    const bool hi = lane >= 32;
+    const cplx<float> *Tb = T + (size_t)sf * n2 * NC;
+    floatx16 accr[2][2], acci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) accr[a][b][r] = acci[a][b][r] = 0.f;
+    for (int kk = 0; kk < K; kk += P2M_K) {
+        // table: 128 rows x 16 window rows (16 consecutive complex per row)
+        for (int e = t; e < P2M_T * P2M_K; e += 256) {
+            const int r = e / P2M_K, k = e % P2M_K;
+            const int l = l0 + r;
+            float2 v = make_float2(0.f, 0.f);
+            if (l < np2 && kk + k < K) {
+                const cplx<float> x = E2[(size_t)l * W2 + mlo + kk + k + R2];
+                v = make_float2(x.re, x.im);
+            }
+            Es[k][r] = v;
+        }
+        // T: 16 window rows x 128 columns
+        for (int e = t; e < P2M_K * P2M_T; e += 256) {
+            const int k = e / P2M_T, n = e % P2M_T;
+            const int cc = c0 + n;
+            float2 v = make_float2(0.f, 0.f);
+            if (cc < NC && kk + k < K) {
+                const cplx<float> x = Tb[(size_t)(k2 + mlo + kk + k) * NC + cc];
+                v = make_float2(x.re, x.im);
+            }
+            Ts[k][n] = v;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < P2M_K; ++k) {
+            float ar[2], ai[2], b[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const float2 e = Es[k][wr * 64 + a * 32 + i];
+                ar[a] = hi ? -e.y : e.x;
+                ai[a] = hi ? e.x : e.y;
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const float2 x = Ts[k][wc * 64 + c * 32 + i];
+                b[c] = hi ? x.y : x.x;
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    accr[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[a], b[c], accr[a][c], 0, 0, 0);
+                    acci[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[a], b[c], acci[a][c], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    // D[i][j] of a 32 x 32 block: j = lane % 32, i = 8 (r / 4) + 4 (lane / 32) + r % 4
+    cplx<float> *out = Psi + ((size_t)sf * nq2 + j2) * np2 * (size_t)NC;
+    const float s2 = (float)d2;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int l = l0 + wr * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int cc = c0 + wc * 64 + c * 32 + (lane & 31);
+                if (l < np2 && cc < NC) {
+                    out[(size_t)l * NC + cc].re = accr[a][c][r] * s2;
+                    out[(size_t)l * NC + cc].im = acci[a][c][r] * s2;
+                }
+            }
 }
 
 // --------------------------------------------------- branches and threshold
@@ -723,10 +831,17 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
     hipLaunchKernelGGL(k_fbi_pass1<R>, g1, dim3(256), 0, st, f0, f1, nfj,
                        (const cplx<R> *)ctx->E1t, (cplx<R> *)ctx->T, g.n1, g.n2, ctx->R1, p.qb1,
                        p.qs1, p.nq1, p.np1, g.d1);
-    dim3 g2((unsigned)((NC + P2_BN - 1) / P2_BN), (p.np2 + P2_BM - 1) / P2_BM, S * p.nq2);
-    hipLaunchKernelGGL(k_fbi_pass2<R>, g2, dim3(256), 0, st, (const cplx<R> *)ctx->T,
-                       (const cplx<R> *)ctx->E2, (cplx<R> *)ctx->Psi, g.n2, ctx->R2, p.qb2,
-                       p.qs2, p.nq2, p.np2, (int)NC, g.d2);
+    if (std::is_same<R, float>::value) {
+        dim3 g2((unsigned)((NC + P2M_T - 1) / P2M_T), (p.np2 + P2M_T - 1) / P2M_T, S * p.nq2);
+        hipLaunchKernelGGL(k_fbi_pass2_mfma, g2, dim3(256), 0, st, (const cplx<float> *)ctx->T,
+                           (const cplx<float> *)ctx->E2, (cplx<float> *)ctx->Psi, g.n2, ctx->R2,
+                           p.qb2, p.qs2, p.nq2, p.np2, (int)NC, g.d2);
+    } else {
+        dim3 g2((unsigned)((NC + P2_BN - 1) / P2_BN), (p.np2 + P2_BM - 1) / P2_BM, S * p.nq2);
+        hipLaunchKernelGGL(k_fbi_pass2<R>, g2, dim3(256), 0, st, (const cplx<R> *)ctx->T,
+                           (const cplx<R> *)ctx->E2, (cplx<R> *)ctx->Psi, g.n2, ctx->R2, p.qb2,
+                           p.qs2, p.nq2, p.np2, (int)NC, g.d2);
+    }
     if (p.top_n > 0) {
         const int npass = (int)sizeof(R);   // eight bits of the key per pass
         hipLaunchKernelGGL(k_topn_init, dim3((nsb * TOPN_BINS + 255) / 256), dim3(256), 0, st,

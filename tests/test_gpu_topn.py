@@ -101,7 +101,8 @@ def test_topn_full_size_counts_and_order():
     """topn512 (point512 with N = 5650 per branch): the kept beams are 5650 per
     branch, in candidate order, with |C| of every kept beam of a branch at
     least that of the largest dropped one (the dropped maximum taken from
-    the threshold run that keeps a superset)."""
+    the threshold run that keeps a superset; in mixed precision up to the
+    FP32 rounding of the magnitudes)."""
     import torch
     import paper_1304_3542_amd as fga
     for prec in ("fp64", "mixed"):
@@ -130,6 +131,9 @@ def test_topn_full_size_counts_and_order():
         kept = np.isin(rids, ids)
         assert kept.sum() == ids.size
         nqp = p.nq1 * p.nq2 * p.np1 * p.np2
+        # the mixed path orders FP32 magnitudes: near-ties may swap at the
+        # FP32 rounding of |psi| (relative ~1e-7)
+        slack = 0.0 if prec == "fp64" else 1e-6
         for br in range(2):
             inb = (rids // nqp) == br
-            assert rmag[inb & kept].min() >= rmag[inb & ~kept].max()
+            assert rmag[inb & kept].min() >= (1.0 - slack) * rmag[inb & ~kept].max()
