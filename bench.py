@@ -280,6 +280,24 @@ def topn_step(steps):
                                   stage_ms.tolist())), "status": st}
 
 
+def fbi_flops(W, tau_fbi):
+    """Algorithmic flops of the two FBI passes of one decomposition (FMA = 2):
+    pass 1, a real x complex MAC (4 flop) per (shot, row, q column, p1,
+    window column); pass 2, a complex MAC (8 flop) per (shot, q row, p2,
+    q column x p1, window row); windows clipped at the grid edges."""
+    g, p = W.grid, W.params
+    R1 = math.ceil(math.sqrt(2 * p.eps * math.log(1 / tau_fbi)) / g.d1)
+    R2 = math.ceil(math.sqrt(2 * p.eps * math.log(1 / tau_fbi)) / g.d2)
+    k1 = p.qb1 + p.qs1 * np.arange(p.nq1)
+    k2 = p.qb2 + p.qs2 * np.arange(p.nq2)
+    K1 = (np.minimum(R1, g.n1 - 1 - k1) + np.minimum(R1, k1) + 1).sum()
+    K2 = (np.minimum(R2, g.n2 - 1 - k2) + np.minimum(R2, k2) + 1).sum()
+    nsf = W.nshots * (1 if W.f1 is None else 2)
+    pass1 = 4.0 * nsf * g.n2 * p.np1 * K1
+    pass2 = 8.0 * nsf * p.np2 * p.nq1 * p.np1 * K2
+    return pass1, pass2
+
+
 def box_pairs(f, nb, W, tau_win):
     """Number of (beam, node) pairs the windowed sum visits."""
     g, p = W.grid, W.params
@@ -393,7 +411,16 @@ def main():
     rk_ach = rk_fl / (stage_ms[1] * 1e-3)
     sp_fl = 4.0 * pairs
     sp_ach = sp_fl / (splat_ms * 1e-3)
+    f1_fl, f2_fl = fbi_flops(W, W.params.tau_fbi)
+    fb_ach = (f1_fl + f2_fl) / (stage_ms[0] * 1e-3)
     kernels = {
+        # ms is the whole decomposition (both passes, selection, compaction);
+        # the passes alone are in the kernel trace under profiles/
+        "k_fbi_pass2_mfma": {"bound": "mfma", "achieved": fb_ach / 1e12,
+                             "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
+                             "frac": fb_ach / PEAK["fp32"], "ms": stage_ms[0],
+                             "ms_covers": "decompose stage",
+                             "flop_per_launch": f2_fl, "flop_pass1": f1_fl},
         "k_rk4": {"bound": "alu", "achieved": rk_ach / 1e12, "peak": PEAK["fp64"] / 1e12,
                   "unit": "TFLOP/s", "frac": rk_ach / PEAK["fp64"], "ms": stage_ms[1],
                   "flop_per_launch": rk_fl, "traffic": profiled_traffic("k_rk4")},
