@@ -268,7 +268,9 @@ k_splat_binned(SplatArgs A, BinArgs B, const SplatRec *__restrict__ rec)
     __shared__ SplatRec stage_rec[4][64];
     SplatRec *st = stage_rec[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
-    const int it = blockIdx.x * 4 + (threadIdx.x >> 6);
+    // the item index is uniform over the wavefront: keep it (and with it the
+    // tile origin, the list range and every block test) in scalar registers
+    const int it = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     const float hl2e = (float)A.half_inv_eps * 1.4426950408889634f;
     // whole wavefronts leave; no workgroup barrier below
     if (it < (int)B.meta[1]) {

@@ -61,24 +61,23 @@ struct Frags {
 __device__ __forceinline__ Frags beam_frags(const SplatRec &r, int i1, int i2, double x1,
                                             double x2, float hl2e)
 {
-    float ur = 0.f, nui = 0.f, vr = 0.f, vi = 0.f;
-    if (i1 >= r.lo1 && i1 <= r.hi1) {
-        double t = fma(r.B1, x1, r.A1);
-        float th = (float)(t - rint(t));
-        float rf = (float)(x1 - r.Q1);
-        float e = __builtin_amdgcn_exp2f(-rf * rf * hl2e);
-        float sn = __builtin_amdgcn_sinf(th), cs = __builtin_amdgcn_cosf(th);
-        ur = e * (r.car * cs - r.cai * sn);
-        nui = -e * (r.car * sn + r.cai * cs);
-    }
-    if (i2 >= r.lo2 && i2 <= r.hi2) {
-        double t = fma(r.B2, x2, r.A2);
-        float th = (float)(t - rint(t));
-        float rf = (float)(x2 - r.Q2);
-        float e = __builtin_amdgcn_exp2f(-rf * rf * hl2e);
-        vr = e * __builtin_amdgcn_cosf(th);
-        vi = e * __builtin_amdgcn_sinf(th);
-    }
+    // evaluated in every lane and zeroed outside the box (no branch: almost
+    // always some lane of the wavefront is inside)
+    const double t1 = fma(r.B1, x1, r.A1);
+    const float th1 = (float)(t1 - rint(t1));
+    const float rf1 = (float)(x1 - r.Q1);
+    const float e1 = __builtin_amdgcn_exp2f(-rf1 * rf1 * hl2e);
+    const float sn1 = __builtin_amdgcn_sinf(th1), cs1 = __builtin_amdgcn_cosf(th1);
+    const bool in1 = i1 >= r.lo1 && i1 <= r.hi1;
+    const float ur = in1 ? e1 * (r.car * cs1 - r.cai * sn1) : 0.f;
+    const float nui = in1 ? -e1 * (r.car * sn1 + r.cai * cs1) : 0.f;
+    const double t2 = fma(r.B2, x2, r.A2);
+    const float th2 = (float)(t2 - rint(t2));
+    const float rf2 = (float)(x2 - r.Q2);
+    const float e2 = __builtin_amdgcn_exp2f(-rf2 * rf2 * hl2e);
+    const bool in2 = i2 >= r.lo2 && i2 <= r.hi2;
+    const float vr = in2 ? e2 * __builtin_amdgcn_cosf(th2) : 0.f;
+    const float vi = in2 ? e2 * __builtin_amdgcn_sinf(th2) : 0.f;
     auto va = __builtin_amdgcn_permlane32_swap(__float_as_uint(vr), __float_as_uint(vi), false,
                                                false);
     auto ub = __builtin_amdgcn_permlane32_swap(__float_as_uint(ur), __float_as_uint(nui), false,
