@@ -283,11 +283,11 @@ k_splat_mfma(SplatArgs A, int nunits, const SplatRec *__restrict__ rec,
         Frags fr = beam_frags(r, i1, i2, x1, x2, hl2e);
         for (int k = 1; k < nhit; ++k) {
             SplatRec rn = st[k];
-            tile_update(fr, r, X0, Z0, acc00, acc01, acc10, acc11);
+            tile_update(fr, acc00, acc01, acc10, acc11);
             r = rn;
             fr = beam_frags(r, i1, i2, x1, x2, hl2e);
         }
-        tile_update(fr, r, X0, Z0, acc00, acc01, acc10, acc11);
+        tile_update(fr, acc00, acc01, acc10, acc11);
         __builtin_amdgcn_wave_barrier();
         // fold the FP32 sums (at most 256 beams) into FP64
         if (++chunks == 4 || base + 64 >= hi) {

@@ -24,7 +24,7 @@ struct SplatArgs {
 // ---------------------------------------------------------------------------
 // Mixed-precision splat on the matrix cores.
 //
-// One wavefront owns a 64 x 64 output tile and one slice of a shot's beams.
+// One wavefront owns a 64 x 64 output tile and a run of beams that meet it.
 // Per beam, lane l evaluates V at x2 = Z0 + l and U at x1 = X0 + l (phase in
 // FP64 revolutions reduced to [-1/2, 1/2], then the hardware FP32 sin, cos
 // and exp2), so every factor is computed once and never leaves registers.
@@ -35,7 +35,7 @@ struct SplatArgs {
 // B[l / 32][l % 32]; the halves of the wave swap their factors once
 // (xor 32) to build the two 32-row and two 32-column fragments.  Four MFMAs
 // per beam cover the tile; the FP32 accumulators are folded into FP64 ones
-// after every 64 candidate beams.
+// after at most 256 beams.
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 // Per-beam record of the mixed splat, formed once per reconstruction:
@@ -86,21 +86,14 @@ __device__ __forceinline__ Frags beam_frags(const SplatRec &r, int i1, int i2, d
             __uint_as_float(ub[1])};
 }
 
-// rank-one update of the 64 x 64 tile; 32 x 32 blocks that the beam's box
-// misses are skipped (the test is uniform across the wavefront)
-__device__ __forceinline__ void tile_update(const Frags &fr, const SplatRec &r, int X0, int Z0,
-                                            floatx16 &acc00, floatx16 &acc01, floatx16 &acc10,
-                                            floatx16 &acc11)
+// rank-one update of the 64 x 64 tile: four MFMAs.  Blocks that the beam's
+// box misses get zero factors and add exact zeros; testing for them costs
+// more scalar work and branches than the matrix cores spend on them.
+__device__ __forceinline__ void tile_update(const Frags &fr, floatx16 &acc00, floatx16 &acc01,
+                                            floatx16 &acc10, floatx16 &acc11)
 {
-    // the record is the same in every lane: make the box scalar so that the
-    // block tests are scalar branches
-    const int lo1 = __builtin_amdgcn_readfirstlane(r.lo1), hi1 = __builtin_amdgcn_readfirstlane(r.hi1);
-    const int lo2 = __builtin_amdgcn_readfirstlane(r.lo2), hi2 = __builtin_amdgcn_readfirstlane(r.hi2);
-    const bool c0 = lo1 <= X0 + 31 && hi1 >= X0, c1 = lo1 <= X0 + 63 && hi1 >= X0 + 32;
-    const bool w0 = lo2 <= Z0 + 31 && hi2 >= Z0, w1 = lo2 <= Z0 + 63 && hi2 >= Z0 + 32;
-    if (w0 && c0) acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(fr.a0, fr.b0, acc00, 0, 0, 0);
-    if (w0 && c1) acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(fr.a0, fr.b1, acc01, 0, 0, 0);
-    if (w1 && c0) acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(fr.a1, fr.b0, acc10, 0, 0, 0);
-    if (w1 && c1) acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(fr.a1, fr.b1, acc11, 0, 0, 0);
+    acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(fr.a0, fr.b0, acc00, 0, 0, 0);
+    acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(fr.a0, fr.b1, acc01, 0, 0, 0);
+    acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(fr.a1, fr.b0, acc10, 0, 0, 0);
+    acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(fr.a1, fr.b1, acc11, 0, 0, 0);
 }
-
