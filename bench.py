@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=3,
                     help="timed graph replays of the 64-shot batch (0 skips it)")
+    ap.add_argument("--large-steps", type=int, default=1,
+                    help="timed steps of the 2048x1024 configuration (0 skips it)")
     ap.add_argument("--topn-steps", type=int, default=5,
                     help="timed steps of the N-largest selection workload (0 skips it)")
     ap.add_argument("--adjoint-steps", type=int, default=3,
@@ -298,6 +300,38 @@ def fbi_flops(W, tau_fbi):
     return pass1, pass2
 
 
+def large_step(steps):
+    """The large configuration (2048 x 1024, eps = 1/1024, ~5e7 beams): ms per
+    mixed step and its stages, the FP64 GPU step on the same input, and the
+    mixed field's error against it."""
+    import torch
+    out = {"workload": "large2048: 2048x1024 smooth layered model, eps=1/1024, point source, "
+           "q 147x74, p 400x400, tau=1e-6"}
+    res = {}
+    for prec in ("mixed", "fp64"):
+        W = fi.workload("large2048", prec)
+        path = Path(W, prec, 8_000_000)
+        nb = path.fit_capacity()
+        ms, stage_ms, _ = time_path(path, steps if prec == "mixed" else 1, 1 if prec == "mixed" else 0)
+        res[prec] = (nb, ms, stage_ms, path.u[0].cpu().numpy())
+        st, _ = path.ctx.status()
+        path.ctx.close()
+        del path
+        torch.cuda.empty_cache()
+    nb, ms, stage_ms, um = res["mixed"]
+    nb64, ms64, stage64, u64 = res["fp64"]
+    out.update({"nbeams": nb, "ms_per_step": ms, "beams_per_s": nb / (ms * 1e-3),
+                "stages_ms": dict(zip(("decompose", "propagate", "reconstruct"),
+                                      stage_ms.tolist())),
+                "fp64_gpu": {"nbeams": nb64, "ms_per_step": ms64,
+                             "stages_ms": dict(zip(("decompose", "propagate", "reconstruct"),
+                                                   stage64.tolist()))},
+                "speedup_mixed_over_fp64": ms64 / ms,
+                "rel_l2_vs_fp64_gpu": float(np.linalg.norm(um - u64) / np.linalg.norm(u64)),
+                "status": st})
+    return out
+
+
 def box_pairs(f, nb, W, tau_win):
     """Number of (beam, node) pairs the windowed sum visits."""
     g, p = W.grid, W.params
@@ -476,6 +510,8 @@ def main():
         out["batched"] = batched_shots(args.batch_steps)
     if args.topn_steps > 0:
         out["topn"] = topn_step(args.topn_steps)
+    if args.large_steps > 0:
+        out["large"] = large_step(args.large_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Wd, nb, args.cpu_seconds)
     print(json.dumps(out), flush=True)
