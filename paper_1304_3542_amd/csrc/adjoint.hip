@@ -312,35 +312,87 @@ __device__ __forceinline__ St st_scale(double h, const St &x)
     return st_axpy(z, h, x);
 }
 
-// lambda <- (d y_{n+1} / d y_n)^T lambda for one classical RK4 step from y:
-// the stage inputs y2, y3, y4 are recomputed, then the four stages are
-// pulled back in reverse order (kbar_i = b_i dt lambda + a_{i+1,i} dt ybar_{i+1}).
-__device__ void step_vjp(const VelGrid &V, double s, const St &y, St &lam, double dt, DcAcc &dacc,
-                         double *dc, int n1, int n2)
+// Per-thread stash of the three recomputed stage inputs y2, y3, y4 in LDS:
+// [3][NSTATE][ADJ_BLOCK] per workgroup, thread index fastest.
+#define ADJ_BLOCK 128
+
+__device__ __forceinline__ void stash_put(double *st, int i, const St &x)
 {
-    St k;
-    rhs(V, s, y, k);
-    const St y2 = st_axpy(y, 0.5 * dt, k);
-    rhs(V, s, y2, k);
-    const St y3 = st_axpy(y, 0.5 * dt, k);
-    rhs(V, s, y3, k);
-    const St y4 = st_axpy(y, dt, k);
+    double *p = st + (size_t)i * FGA_NSTATE * ADJ_BLOCK;
+    p[0 * ADJ_BLOCK] = x.Q1;
+    p[1 * ADJ_BLOCK] = x.Q2;
+    p[2 * ADJ_BLOCK] = x.P1;
+    p[3 * ADJ_BLOCK] = x.P2;
+    p[4 * ADJ_BLOCK] = x.S;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            p[(5 + 2 * (2 * j + l)) * ADJ_BLOCK] = x.A[j][l].r;
+            p[(6 + 2 * (2 * j + l)) * ADJ_BLOCK] = x.A[j][l].i;
+            p[(13 + 2 * (2 * j + l)) * ADJ_BLOCK] = x.B[j][l].r;
+            p[(14 + 2 * (2 * j + l)) * ADJ_BLOCK] = x.B[j][l].i;
+        }
+    p[21 * ADJ_BLOCK] = x.a.r;
+    p[22 * ADJ_BLOCK] = x.a.i;
+}
+
+__device__ __forceinline__ void stash_get(const double *st, int i, St &x)
+{
+    const double *p = st + (size_t)i * FGA_NSTATE * ADJ_BLOCK;
+    x.Q1 = p[0 * ADJ_BLOCK];
+    x.Q2 = p[1 * ADJ_BLOCK];
+    x.P1 = p[2 * ADJ_BLOCK];
+    x.P2 = p[3 * ADJ_BLOCK];
+    x.S = p[4 * ADJ_BLOCK];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            x.A[j][l].r = p[(5 + 2 * (2 * j + l)) * ADJ_BLOCK];
+            x.A[j][l].i = p[(6 + 2 * (2 * j + l)) * ADJ_BLOCK];
+            x.B[j][l].r = p[(13 + 2 * (2 * j + l)) * ADJ_BLOCK];
+            x.B[j][l].i = p[(14 + 2 * (2 * j + l)) * ADJ_BLOCK];
+        }
+    x.a.r = p[21 * ADJ_BLOCK];
+    x.a.i = p[22 * ADJ_BLOCK];
+}
+
+// lambda <- (d y_{n+1} / d y_n)^T lambda for one classical RK4 step from y:
+// the stage inputs y2, y3, y4 are recomputed into the stash, then the four
+// stages are pulled back in reverse order,
+//   kbar_i = b_i dt lambda + a_{i+1,i} dt xbar_{i+1},  lambda' = lambda + sum xbar_i.
+// The stages run as loops that are not unrolled, so one copy of the
+// right-hand side and of its VJP is compiled and their live ranges do not
+// pile up.
+__device__ void step_vjp(const VelGrid &V, double s, const St &y, St &lam, double dt,
+                         double *stash, DcAcc &dacc, double *dc, int n1, int n2)
+{
+    const double ca[3] = {0.5 * dt, 0.5 * dt, dt};   // y_{i+2} = y + ca[i] k_{i+1}
+    St x = y;
+#pragma unroll 1
+    for (int i = 0; i < 3; ++i) {
+        St k;
+        rhs(V, s, x, k);
+        x = st_axpy(y, ca[i], k);
+        stash_put(stash, i, x);
+    }
+    const double wl[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};   // weight of lambda
+    const double wx[4] = {0.5 * dt, 0.5 * dt, dt, 0.0};             // weight of xbar_{i+2}
     St yb = lam, xb;
     st_zero(xb);
-    rhs_vjp(V, s, y4, st_scale(dt / 6.0, lam), xb, dacc, dc, n1, n2);
-    yb = st_axpy(yb, 1.0, xb);
-    St kbar = st_axpy(st_scale(dt / 3.0, lam), dt, xb);
-    st_zero(xb);
-    rhs_vjp(V, s, y3, kbar, xb, dacc, dc, n1, n2);
-    yb = st_axpy(yb, 1.0, xb);
-    kbar = st_axpy(st_scale(dt / 3.0, lam), 0.5 * dt, xb);
-    st_zero(xb);
-    rhs_vjp(V, s, y2, kbar, xb, dacc, dc, n1, n2);
-    yb = st_axpy(yb, 1.0, xb);
-    kbar = st_axpy(st_scale(dt / 6.0, lam), 0.5 * dt, xb);
-    st_zero(xb);
-    rhs_vjp(V, s, y, kbar, xb, dacc, dc, n1, n2);
-    lam = st_axpy(yb, 1.0, xb);
+#pragma unroll 1
+    for (int i = 3; i >= 0; --i) {
+        const St kbar = st_axpy(st_scale(wl[i], lam), wx[i], xb);
+        if (i > 0)
+            stash_get(stash, i - 1, x);
+        else
+            x = y;
+        st_zero(xb);
+        rhs_vjp(V, s, x, kbar, xb, dacc, dc, n1, n2);
+        yb = st_axpy(yb, 1.0, xb);
+    }
+    lam = yb;
 }
 
 struct TraceAdjArgs {
@@ -362,9 +414,11 @@ struct TraceAdjArgs {
     int Rw1, Rw2;
 };
 
-__global__ void __launch_bounds__(128)
+__global__ void __launch_bounds__(ADJ_BLOCK)
 k_trace_adjoint(TraceAdjArgs A)
 {
+    __shared__ double stash_all[3 * FGA_NSTATE * ADJ_BLOCK];
+    double *stash = stash_all + threadIdx.x;
     const int64_t nb = A.offsets[A.nshots];
     const int64_t cap = A.cap;
     const double inv_eps = 1.0 / A.eps;
@@ -421,7 +475,7 @@ k_trace_adjoint(TraceAdjArgs A)
             for (int j = A.rec_every - 1; j >= 0; --j) {
                 St yj;
                 load_state_raw(A.scratch + (size_t)j * FGA_NSTATE * cap, cap, b, yj);
-                step_vjp(A.V, s, yj, lam, A.dt, dacc, A.dc, A.n1, A.n2);
+                step_vjp(A.V, s, yj, lam, A.dt, stash, dacc, A.dc, A.n1, A.n2);
             }
         }
         dcacc_flush(dacc, A.dc, A.n1, A.n2);
@@ -466,7 +520,7 @@ fga_status fga_launch_trace_adjoint(fga_ctx *ctx, const fga_beams *beams, int ns
     A.dt = ctx->p.dt;
     A.Rw1 = ctx->Rw1;
     A.Rw2 = ctx->Rw2;
-    hipLaunchKernelGGL(k_trace_adjoint, dim3(ctx->num_cu * 4), dim3(128), 0, ctx->stream, A);
+    hipLaunchKernelGGL(k_trace_adjoint, dim3(ctx->num_cu * 4), dim3(ADJ_BLOCK), 0, ctx->stream, A);
     FGA_HIP(ctx, hipGetLastError());
     return FGA_OK;
 }
