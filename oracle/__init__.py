@@ -56,6 +56,7 @@ def lib():
         L.or_fbi.argtypes = [P, I32, I32, D, D, D, D, I32, I32, I32, I32, I32,
                              I32, I32, I32, D, D, P]
         L.or_propagate.argtypes = G + [I64, P, P, D, I32]
+        L.or_propagate_closed.argtypes = G + [I64, P, P, P, D, I32]
         L.or_rhs.argtypes = G + [D, P, P]
         L.or_reconstruct.argtypes = [I32, I32, D, D, D, D, D, D, I64, P, P, P, P]
         L.or_reconstruct_points.argtypes = [I32, I32, D, D, D, D, D, D, I64, P,
@@ -229,14 +230,32 @@ def decompose(f0: np.ndarray, f1: Optional[np.ndarray], c, grid, params,
 
 # ----------------------------------------------------- step 2: propagate
 
-def propagate(beams: Beams, c, grid, dt: float, nsteps: int) -> None:
+def beam_nodes(beams: Beams, grid, params) -> np.ndarray:
+    """The mesh node q [nb][2] of every beam, from its candidate index."""
+    nq, npp = params.nq1 * params.nq2, params.np1 * params.np2
+    qf = (beams.cand // npp) % nq
+    k1, k2 = qnodes(params)
+    return np.stack([grid.o1 + grid.d1 * k1[qf % params.nq1],
+                     grid.o2 + grid.d2 * k2[qf // params.nq1]], 1)
+
+
+def propagate(beams: Beams, c, grid, dt: float, nsteps: int, q=None) -> None:
     """Classical RK4 of the ray, dynamic ray tracing and amplitude equations,
-    in place on beams.state."""
+    in place on beams.state.  With q ([nb][2], the beams' mesh nodes) the
+    amplitude is instead a = c(Q)/c(q) (det Z)^{1/2} after every step, the
+    root continuous in time (the closed form following the amplitude
+    equation, Formulation section)."""
     c = np.ascontiguousarray(c, dtype=np.float64)
     sig = np.ascontiguousarray(beams.sigma, dtype=np.int8)
     assert beams.state.flags.c_contiguous and beams.state.dtype == np.float64
-    lib().or_propagate(*_grid_args(c, grid), beams.n, _p(sig), _p(beams.state),
-                       dt, nsteps)
+    if q is None:
+        lib().or_propagate(*_grid_args(c, grid), beams.n, _p(sig), _p(beams.state),
+                           dt, nsteps)
+    else:
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        assert q.shape == (beams.n, 2)
+        lib().or_propagate_closed(*_grid_args(c, grid), beams.n, _p(sig), _p(q),
+                                  _p(beams.state), dt, nsteps)
 
 
 def rhs(y, sigma: float, c, grid) -> np.ndarray:
@@ -289,8 +308,9 @@ def trace(beams: Beams, c, grid, params, receivers, rec_every: int,
     at t_k = k * rec_every * dt, k = 1..nrec (beams are advanced in place)."""
     ns = beams.offsets.size - 1
     out = np.empty((ns, nrec, len(receivers)))
+    q = beam_nodes(beams, grid, params) if params.amp_closed else None
     for k in range(nrec):
-        propagate(beams, c, grid, params.dt, rec_every)
+        propagate(beams, c, grid, params.dt, rec_every, q=q)
         for s in range(ns):
             out[s, k] = reconstruct_points(beams, grid, params, receivers, shot=s)
     return out
@@ -299,6 +319,7 @@ def trace(beams: Beams, c, grid, params, receivers, rec_every: int,
 def forward(f0, f1, c, grid, params, imag=False):
     """The whole three-step algorithm: u(T) for every shot."""
     b = decompose(f0, f1, c, grid, params)
-    propagate(b, c, grid, params.dt, params.nsteps)
+    q = beam_nodes(b, grid, params) if params.amp_closed else None
+    propagate(b, c, grid, params.dt, params.nsteps, q=q)
     us = [reconstruct(b, grid, params, shot=s, imag=imag) for s in range(f0.shape[0])]
     return b, us

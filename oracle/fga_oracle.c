@@ -301,6 +301,54 @@ void or_propagate(const double *c, int n1, int n2, double o1, double o2,
     }
 }
 
+/* The same RK4 for every state but the amplitude, which is instead set after
+ * every step from the conserved quantity a^2 / (c(Q)^2 det Z) (the closed
+ * form that follows the amplitude equation in the paper):
+ *   a = c(Q) / c(q) (det Z)^{1/2},  Z = A + iB,
+ * taking the square root nearest the previous step's, so that it varies
+ * continuously in time.  q: [nb][2] the beams' mesh nodes; the root at the
+ * start is recovered from the incoming a (2 at t = 0). */
+void or_propagate_closed(const double *c, int n1, int n2, double o1, double o2,
+                         double d1, double d2, int64_t nb, const int8_t *sigma,
+                         const double *q, double *state, double dt, int nsteps)
+{
+    vel_t v = {c, n1, n2, o1, o2, d1, d2};
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t b = 0; b < nb; ++b) {
+        double *y = state + (size_t)b * NSTATE;
+        double s = (double)sigma[b];
+        double k1[NSTATE], k2[NSTATE], k3[NSTATE], k4[NSTATE], t[NSTATE];
+        double cv[6];
+        velocity_n(c, n1, n2, o1, o2, d1, d2, q[2 * b], q[2 * b + 1], 1, cv);
+        const double cq = cv[0];
+        velocity_n(c, n1, n2, o1, o2, d1, d2, y[0], y[1], 1, cv);
+        double complex root = (y[21] + I * y[22]) * cq / cv[0];
+        for (int it = 0; it < nsteps; ++it) {
+            rhs(&v, s, y, k1);
+            for (int i = 0; i < NSTATE; ++i) t[i] = y[i] + 0.5 * dt * k1[i];
+            rhs(&v, s, t, k2);
+            for (int i = 0; i < NSTATE; ++i) t[i] = y[i] + 0.5 * dt * k2[i];
+            rhs(&v, s, t, k3);
+            for (int i = 0; i < NSTATE; ++i) t[i] = y[i] + dt * k3[i];
+            rhs(&v, s, t, k4);
+            for (int i = 0; i < NSTATE; ++i)
+                y[i] += dt / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+            double complex Z[2][2];
+            for (int j = 0; j < 2; ++j)
+                for (int k = 0; k < 2; ++k)
+                    Z[j][k] = (y[5 + 2 * (2 * j + k)] + I * y[6 + 2 * (2 * j + k)]) +
+                              I * (y[13 + 2 * (2 * j + k)] + I * y[14 + 2 * (2 * j + k)]);
+            double complex r = csqrt(Z[0][0] * Z[1][1] - Z[0][1] * Z[1][0]);
+            if (creal(r * conj(root)) < 0.0) r = -r;
+            root = r;
+            velocity_n(c, n1, n2, o1, o2, d1, d2, y[0], y[1], 1, cv);
+            double complex a = cv[0] / cq * r;
+            y[21] = creal(a);
+            y[22] = cimag(a);
+        }
+    }
+}
+
 /* The right-hand side alone, for tests of the equations themselves. */
 void or_rhs(const double *c, int n1, int n2, double o1, double o2, double d1,
             double d2, double sigma, const double *y, double *dy)

@@ -528,6 +528,63 @@ def test_invariants_in_heterogeneous_medium():
     np.testing.assert_allclose(a, root, rtol=1e-6)
 
 
+def _detZ(st):
+    Z = _A(st) + 1j * _B(st)
+    return Z[:, 0, 0] * Z[:, 1, 1] - Z[:, 0, 1] * Z[:, 1, 0]
+
+
+def test_closed_form_amplitude_matches_integrated():
+    """The closed-form amplitude mode (a = c(Q)/c(q) (det Z)^{1/2} after every
+    step) and the integrated amplitude equation converge to each other as dt
+    shrinks (third order: the B-spline is C^2) in a layered model; every other
+    state component is unchanged, and splitting the run in two segments gives
+    the same result."""
+    g, c, q, p, sig = _smooth_case(nb=32, seed=15)
+    T = 0.2
+    diffs = []
+    for nst in (100, 200, 400):
+        bi = _single_beams(q, p, sig)
+        oracle.propagate(bi, c, g, T / nst, nst)
+        bc = _single_beams(q, p, sig)
+        oracle.propagate(bc, c, g, T / nst, nst, q=q)
+        np.testing.assert_array_equal(bc.state[:, :21], bi.state[:, :21])
+        ai = bi.state[:, 21] + 1j * bi.state[:, 22]
+        ac = bc.state[:, 21] + 1j * bc.state[:, 22]
+        diffs.append(np.abs(ac - ai).max() / np.abs(ai).max())
+    assert diffs[0] / diffs[1] > 5 and diffs[1] / diffs[2] > 5 and diffs[2] < 5e-9, diffs
+    bs = _single_beams(q, p, sig)
+    oracle.propagate(bs, c, g, T / nst, nst // 2, q=q)
+    oracle.propagate(bs, c, g, T / nst, nst - nst // 2, q=q)
+    np.testing.assert_allclose(bs.state, bc.state, rtol=0, atol=1e-12)
+
+
+def test_closed_form_amplitude_tracks_the_root_through_caustics():
+    """Rays trapped in a parabolic low-velocity channel refocus repeatedly; det Z
+    winds by more than 2 pi, so the principal square root points the wrong way
+    while the continuously tracked one still matches the integrated amplitude."""
+    g = fi.Grid(96, 96, 0.0, 0.0, 1 / 96, 1 / 96)
+    x1, x2 = g.coords()
+    c = np.ones(g.shape) + 40.0 * (x2[:, None] - 0.5) ** 2 + 0.0 * x1[None, :]
+    r = fi.rng(12)
+    nb = 32
+    q = np.stack([np.full(nb, 0.08), r.uniform(0.45, 0.55, nb)], 1)
+    ang = r.uniform(-0.25, 0.25, nb)
+    p = np.stack([np.cos(ang), np.sin(ang)], 1) * r.uniform(0.7, 1.5, nb)[:, None]
+    sig = np.ones(nb, int)
+    nst, dt = 800, 1e-3
+    bi = _single_beams(q, p, sig)
+    oracle.propagate(bi, c, g, dt, nst)
+    bc = _single_beams(q, p, sig)
+    oracle.propagate(bc, c, g, dt, nst, q=q)
+    ai = bi.state[:, 21] + 1j * bi.state[:, 22]
+    ac = bc.state[:, 21] + 1j * bc.state[:, 22]
+    assert np.abs(ac - ai).max() <= 1e-7 * np.abs(ai).max()
+    cq = oracle.velocity(c, g, q[:, 0], q[:, 1])[:, 0]
+    cQ = oracle.velocity(c, g, bc.state[:, 0], bc.state[:, 1])[:, 0]
+    principal = cQ / cq * np.sqrt(_detZ(bc.state))
+    assert np.all(np.abs(principal + ai) < 1e-6 * np.abs(ai))   # opposite root
+
+
 def test_dynamic_ray_tracing_matches_divided_differences():
     """dzQ = dQ/dq - i dQ/dp and dzP likewise, with (j,k) entry d/dz_j of
     component k: central differences of the ray map in q and p reproduce the
