@@ -80,6 +80,12 @@ typedef struct {
  *              never |psi| = 0 (so fewer when fewer are nonzero).  The
  *              magnitudes are compared in the precision of the FBI (FP32 in
  *              FGA_MIXED)
+ *   amp_closed 0: integrate the amplitude equation (a_formu eq.); 1: set
+ *              a = c(Q)/c(q) (det Z)^{1/2} after every step instead (the
+ *              closed form the Formulation section derives from the
+ *              conserved a^2/(c(Q)^2 det Z)), the square root taken nearest
+ *              the previous step's so that it is continuous in time.  The
+ *              gradient entry points require 0.
  *   tau_fbi    the FBI box B_eps has half-width ceil(sqrt(2 eps ln(1/tau_fbi))/d)
  *   tau_win    each Gaussian is summed over the box of half-width
  *              ceil(sqrt(2 eps ln(1/tau_win))/d) around the node nearest Q
@@ -92,6 +98,7 @@ typedef struct {
     double tau, tau_fbi, tau_win;
     double dt;
     int32_t top_n;
+    int32_t amp_closed;
 } fga_params;
 
 /* Beam storage: structure of arrays in one float64 buffer

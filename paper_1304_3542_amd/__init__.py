@@ -40,7 +40,8 @@ class fga_params(ctypes.Structure):
                 ("nq2", ctypes.c_int32), ("np1", ctypes.c_int32), ("np2", ctypes.c_int32),
                 ("dp1", ctypes.c_double), ("dp2", ctypes.c_double), ("tau", ctypes.c_double),
                 ("tau_fbi", ctypes.c_double), ("tau_win", ctypes.c_double),
-                ("dt", ctypes.c_double), ("top_n", ctypes.c_int32)]
+                ("dt", ctypes.c_double), ("top_n", ctypes.c_int32),
+                ("amp_closed", ctypes.c_int32)]
 
 
 class fga_beams(ctypes.Structure):
@@ -112,7 +113,8 @@ def fga_create(grid, params, precision: int = FGA_FP64, max_shots: int = 1, stre
     g = fga_grid(grid.n1, grid.n2, grid.o1, grid.o2, grid.d1, grid.d2)
     p = fga_params(params.eps, params.qb1, params.qb2, params.qs1, params.qs2, params.nq1,
                    params.nq2, params.np1, params.np2, params.dp1, params.dp2, params.tau,
-                   params.tau_fbi, params.tau_win, params.dt, int(getattr(params, "top_n", 0)))
+                   params.tau_fbi, params.tau_win, params.dt, int(getattr(params, "top_n", 0)),
+                   int(getattr(params, "amp_closed", 0)))
     ctx = ctypes.c_void_p()
     st = load().fga_create(ctypes.byref(ctx), ctypes.byref(g), ctypes.byref(p), int(precision),
                            int(max_shots), _stream_handle(stream))

@@ -73,6 +73,8 @@ static fga_status check_params(fga_ctx *ctx, const fga_grid *g, const fga_params
         return fga_fail(ctx, FGA_EINVAL, "tau_fbi and tau_win must lie in (0, 1)");
     if (!(p->dt > 0) || !isfinite(p->dt)) return fga_fail(ctx, FGA_EINVAL, "dt must be positive");
     if (p->top_n < 0) return fga_fail(ctx, FGA_EINVAL, "top_n must be >= 0");
+    if (p->amp_closed != 0 && p->amp_closed != 1)
+        return fga_fail(ctx, FGA_EINVAL, "amp_closed must be 0 or 1");
     int R1 = fga_halfwidth(p->eps, p->tau_fbi, g->d1);
     int R2 = fga_halfwidth(p->eps, p->tau_fbi, g->d2);
     if (R1 > 8192 || R2 > 8192)
@@ -303,6 +305,8 @@ extern "C" fga_status fga_trace_adjoint(fga_ctx *ctx, const fga_beams *beams, in
         return fga_fail(ctx, FGA_EINVAL, "nshots %d outside [1, %d]", nshots, ctx->max_shots);
     if (!rec || nrec < 1 || rec_every < 1 || nrec_t < 1 || !ckpt || !gtr || !dc || !gcoef)
         return fga_fail(ctx, FGA_EINVAL, "bad trace-adjoint arguments");
+    if (ctx->p.amp_closed)
+        return fga_fail(ctx, FGA_EINVAL, "the trace adjoint needs the integrated amplitude");
     if (!ctx->have_c) return fga_fail(ctx, FGA_ESTATE, "fga_set_velocity was not called");
     return fga_launch_trace_adjoint(ctx, beams, nshots, rec, nrec, rec_every, nrec_t, ckpt, gtr,
                                     dc, gcoef);

@@ -114,9 +114,34 @@ struct VelDma {
     }
 };
 
+// Principal square root of x + iy (|z| > 0), in the cancellation-free form.
+__device__ __forceinline__ Cd csqrt_principal(Cd z)
+{
+    const double m = sqrt(fma(z.r, z.r, z.i * z.i));
+    const double t = sqrt(0.5 * (fabs(z.r) + m));
+    const double h = 0.5 * z.i / t;
+    return z.r >= 0.0 ? Cd{t, h} : Cd{fabs(h), copysign(t, z.i)};
+}
+
+// (det Z)^{1/2} of the state, Z = A + iB, the root taken nearest prev.
+__device__ __forceinline__ Cd det_root(const St &y, Cd prev)
+{
+    Cd Z[2][2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int l = 0; l < 2; ++l)
+            Z[j][l] = {y.A[j][l].r - y.B[j][l].i, y.A[j][l].i + y.B[j][l].r};
+    const Cd r = csqrt_principal(csub(cmul(Z[0][0], Z[1][1]), cmul(Z[0][1], Z[1][0])));
+    return r.r * prev.r + r.i * prev.i < 0.0 ? Cd{-r.r, -r.i} : r;
+}
+
 // One thread per beam; the state, the RK4 accumulator and the stage input
 // live in VGPRs (two wavefronts per SIMD), the cell coefficients in 8 KB of
-// LDS per wavefront.
+// LDS per wavefront.  CLOSED: the amplitude is not integrated; the root of
+// det Z is followed step by step (recovered at the start from the incoming
+// a = c(Q)/c(q) root, 2 at t = 0), and a = c(Q)/c(q) root at the end.
+template <bool CLOSED>
 __global__ void __launch_bounds__(RK_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
       const int64_t *__restrict__ offsets, int nshots, int64_t cap, int64_t NqNp, double dt,
@@ -137,15 +162,30 @@ k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
         if (ckpt) store_state(ckpt + b, cap, y);
         double s = ((id[b] / NqNp) & 1) ? -1.0 : 1.0;
         double h2 = 0.5 * dt, h6 = dt / 6.0, h3 = dt / 3.0;
+        double cq = 1.0;
+        Cd root = {0.0, 0.0};
+        if (CLOSED) {
+            double c0, d[5];
+            vel_eval(V, f[b], f[cap + b], cq, d[0], d[1], d[2], d[3], d[4]);
+            vel_eval(V, y.Q1, y.Q2, c0, d[0], d[1], d[2], d[3], d[4]);
+            root = cscale(y.a, cq / c0);
+        }
         vel.cur1 = vel.cur2 = INT_MIN;   // new beam: its slots hold nothing yet
         if (nsteps > 0) vel.prefetch(y.Q1, y.Q2);
         for (int it = 0; it < nsteps; ++it) {
             St t = y, acc = y;
-            rk_stage<false>(vel, s, t, acc, y, h6, h2);
-            rk_stage<false>(vel, s, t, acc, y, h3, h2);
-            rk_stage<false>(vel, s, t, acc, y, h3, dt);
-            rk_stage<true>(vel, s, t, acc, y, h6, 0.0);
+            rk_stage<false, VelDma, !CLOSED>(vel, s, t, acc, y, h6, h2);
+            rk_stage<false, VelDma, !CLOSED>(vel, s, t, acc, y, h3, h2);
+            rk_stage<false, VelDma, !CLOSED>(vel, s, t, acc, y, h3, dt);
+            rk_stage<true, VelDma, !CLOSED>(vel, s, t, acc, y, h6, 0.0);
             y = acc;
+            if (CLOSED) root = det_root(y, root);
+        }
+        if (CLOSED && nsteps > 0) {
+            // the last stage requested the coefficients at the final position
+            double cQ, d[5];
+            vel.eval(y.Q1, y.Q2, cQ, d[0], d[1], d[2], d[3], d[4]);
+            y.a = cscale(root, cQ / cq);
         }
         // no LDS transfer (the last step requests one more) may outlive the
         // wavefront's use of the slots
@@ -163,9 +203,14 @@ fga_status fga_launch_propagate(fga_ctx *ctx, fga_beams *beams, int nshots, int 
     int64_t NqNp = (int64_t)ctx->p.nq1 * ctx->p.nq2 * ctx->p.np1 * ctx->p.np2;
     // persistent grid: the beam count lives on the device
     int blocks = ctx->num_cu * 8;
-    hipLaunchKernelGGL(k_rk4, dim3(blocks), dim3(256), 0, ctx->stream, V, beams->f, beams->id,
-                       beams->offsets, nshots, beams->capacity, NqNp, ctx->p.dt, nsteps, ckpt,
-                       ctx->status);
+    if (ctx->p.amp_closed)
+        hipLaunchKernelGGL(k_rk4<true>, dim3(blocks), dim3(256), 0, ctx->stream, V, beams->f,
+                           beams->id, beams->offsets, nshots, beams->capacity, NqNp, ctx->p.dt,
+                           nsteps, ckpt, ctx->status);
+    else
+        hipLaunchKernelGGL(k_rk4<false>, dim3(blocks), dim3(256), 0, ctx->stream, V, beams->f,
+                           beams->id, beams->offsets, nshots, beams->capacity, NqNp, ctx->p.dt,
+                           nsteps, ckpt, ctx->status);
     FGA_HIP(ctx, hipGetLastError());
     return FGA_OK;
 }

@@ -187,7 +187,9 @@ struct VelDirect {
 // stage the next step's first) is known once the slope of Q is; it goes to
 // vel.prefetch before the rest of the stage is computed.  (The request after
 // the final step is not used; a branch around it would cost more registers.)
-template <bool LAST, class Vel>
+// With AMP false the amplitude is left alone (the caller sets it from the
+// closed form); its terms then drop out of the compiled stage.
+template <bool LAST, class Vel, bool AMP = true>
 __device__ __forceinline__ void rk_stage(Vel &vel, double s, St &t, St &acc, const St &y,
                                          double wacc, double hnext)
 {
@@ -258,11 +260,13 @@ __device__ __forceinline__ void rk_stage(Vel &vel, double s, St &t, St &acc, con
             t.B[j][1] = {fma(hnext, kB1.r, y.B[j][1].r), fma(hnext, kB1.i, y.B[j][1].i)};
         }
     }
-    double id2 = rcp64(det.r * det.r + det.i * det.i);
-    Cd tr = cscale(cmul(num, Cd{det.r, -det.i}), id2);
-    Cd ka = cmul(t.a, Cd{ug + 0.5 * tr.r, 0.5 * tr.i});
-    acc.a = {fma(wacc, ka.r, acc.a.r), fma(wacc, ka.i, acc.a.i)};
-    if (!LAST) t.a = {fma(hnext, ka.r, y.a.r), fma(hnext, ka.i, y.a.i)};
+    if (AMP) {
+        double id2 = rcp64(det.r * det.r + det.i * det.i);
+        Cd tr = cscale(cmul(num, Cd{det.r, -det.i}), id2);
+        Cd ka = cmul(t.a, Cd{ug + 0.5 * tr.r, 0.5 * tr.i});
+        acc.a = {fma(wacc, ka.r, acc.a.r), fma(wacc, ka.i, acc.a.i)};
+        if (!LAST) t.a = {fma(hnext, ka.r, y.a.r), fma(hnext, ka.i, y.a.i)};
+    }
 }
 
 // the stage with the taps read where c is evaluated
