@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=3,
                     help="timed graph replays of the 64-shot batch (0 skips it)")
+    ap.add_argument("--closed-steps", type=int, default=5,
+                    help="timed steps of point512 with the closed-form amplitude (0 skips it)")
     ap.add_argument("--large-steps", type=int, default=1,
                     help="timed steps of the 2048x1024 configuration (0 skips it)")
     ap.add_argument("--topn-steps", type=int, default=5,
@@ -300,6 +302,27 @@ def fbi_flops(W, tau_fbi):
     return pass1, pass2
 
 
+def closed_step(steps, u_integrated):
+    """point512 with the closed-form amplitude (amp_closed = 1, mixed): ms per
+    step and stages, and the field's difference from the integrated-amplitude
+    run of the same step."""
+    W = fi.workload("point512", "mixed")
+    W = fi.Workload(W.name, W.grid, W.params.replace(amp_closed=1), W.c, W.f0, W.f1)
+    path = Path(W, "mixed", 1_300_000)
+    nb = path.fit_capacity()
+    ms, stage_ms, per_step = time_path(path, steps, 1)
+    st, _ = path.ctx.status()
+    u = path.u.cpu().numpy()
+    return {"workload": "point512 with a = c(Q)/c(q) (det Z)^(1/2) (root tracked per step), "
+            "mixed", "nbeams": nb, "ms_per_step": ms,
+            "ms_per_step_device_median": float(np.median(per_step)),
+            "beams_per_s": nb / (ms * 1e-3),
+            "stages_ms": dict(zip(("decompose", "propagate", "reconstruct"), stage_ms.tolist())),
+            "rel_l2_vs_integrated_amplitude": float(np.linalg.norm(u - u_integrated) /
+                                                    np.linalg.norm(u_integrated)),
+            "status": st}
+
+
 def large_step(steps):
     """The large configuration (2048 x 1024, eps = 1/1024, ~5e7 beams): ms per
     mixed step and its stages, the FP64 GPU step on the same input, and the
@@ -510,6 +533,8 @@ def main():
         out["batched"] = batched_shots(args.batch_steps)
     if args.topn_steps > 0:
         out["topn"] = topn_step(args.topn_steps)
+    if args.closed_steps > 0:
+        out["closed_amplitude"] = closed_step(args.closed_steps, u_mixed)
     if args.large_steps > 0:
         out["large"] = large_step(args.large_steps)
     if not args.no_cpu_baseline:
