@@ -417,6 +417,7 @@ __global__ void __launch_bounds__(TR_BLOCK)
 k_trace_points(SplatArgs A, const int32_t *__restrict__ rec, int nrec, double *partial)
 {
     __shared__ double sb[7][TR_BLOCK];
+    __shared__ int4 sbox[TR_BLOCK];   // truncation box of each staged beam
     const int split = blockIdx.x, s = blockIdx.y;
     const int r = blockIdx.z * TR_BLOCK + threadIdx.x;
     int i1 = 0, i2 = 0;
@@ -444,14 +445,17 @@ k_trace_points(SplatArgs A, const int32_t *__restrict__ rec, int nrec, double *p
             sb[4][threadIdx.x] = p[(FGA_F_STATE + 4) * cap];
             sb[5][threadIdx.x] = Cr * ar - Ci * ai;
             sb[6][threadIdx.x] = Cr * ai + Ci * ar;
+            const BeamBox bx = beam_box(sb[0][threadIdx.x], sb[1][threadIdx.x], A.o1, A.o2, A.d1,
+                                        A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
+            sbox[threadIdx.x] = make_int4(bx.lo1, bx.hi1, bx.lo2, bx.hi2);
         }
         __syncthreads();
         int nb = (int)min((int64_t)TR_BLOCK, hi - base);
         if (r < nrec) {
             for (int k = 0; k < nb; ++k) {
+                const int4 bx = sbox[k];
+                if (i1 < bx.x || i1 > bx.y || i2 < bx.z || i2 > bx.w) continue;
                 double Q1 = sb[0][k], Q2 = sb[1][k];
-                BeamBox bx = beam_box(Q1, Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
-                if (i1 < bx.lo1 || i1 > bx.hi1 || i2 < bx.lo2 || i2 > bx.hi2) continue;
                 double r1 = x1 - Q1, r2 = x2 - Q2;
                 double th = (sb[4][k] + sb[2][k] * r1 + sb[3][k] * r2) * A.inv_eps;
                 double G = -(r1 * r1 + r2 * r2) * A.half_inv_eps;
