@@ -57,6 +57,7 @@ def lib():
                              I32, I32, I32, D, D, P]
         L.or_propagate.argtypes = G + [I64, P, P, D, I32]
         L.or_propagate_closed.argtypes = G + [I64, P, P, P, D, I32]
+        L.or_propagate_dd.argtypes = G + [I64, P, P, P, D, I32, P]
         L.or_rhs.argtypes = G + [D, P, P]
         L.or_reconstruct.argtypes = [I32, I32, D, D, D, D, D, D, I64, P, P, P, P]
         L.or_reconstruct_points.argtypes = [I32, I32, D, D, D, D, D, D, I64, P,
@@ -239,23 +240,45 @@ def beam_nodes(beams: Beams, grid, params) -> np.ndarray:
                      grid.o2 + grid.d2 * k2[qf // params.nq1]], 1)
 
 
-def propagate(beams: Beams, c, grid, dt: float, nsteps: int, q=None) -> None:
+def propagate(beams: Beams, c, grid, dt: float, nsteps: int, q=None, dd=None) -> None:
     """Classical RK4 of the ray, dynamic ray tracing and amplitude equations,
     in place on beams.state.  With q ([nb][2], the beams' mesh nodes) the
     amplitude is instead a = c(Q)/c(q) (det Z)^{1/2} after every step, the
     root continuous in time (the closed form following the amplitude
-    equation, Formulation section)."""
+    equation, Formulation section).  With dd = (h_q1, h_q2, h_p1, h_p2) as
+    well, dzQ and dzP come from central divided differences of the rays of
+    the neighbouring mesh nodes at these spacings instead of the dynamic ray
+    tracing equations (or_propagate_dd)."""
     c = np.ascontiguousarray(c, dtype=np.float64)
     sig = np.ascontiguousarray(beams.sigma, dtype=np.int8)
     assert beams.state.flags.c_contiguous and beams.state.dtype == np.float64
     if q is None:
+        assert dd is None, "the divided-difference mode takes the closed-form amplitude"
         lib().or_propagate(*_grid_args(c, grid), beams.n, _p(sig), _p(beams.state),
                            dt, nsteps)
-    else:
-        q = np.ascontiguousarray(q, dtype=np.float64)
-        assert q.shape == (beams.n, 2)
+        return
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    assert q.shape == (beams.n, 2)
+    if dd is None:
         lib().or_propagate_closed(*_grid_args(c, grid), beams.n, _p(sig), _p(q),
                                   _p(beams.state), dt, nsteps)
+    else:
+        h = np.ascontiguousarray(dd, dtype=np.float64)
+        assert h.shape == (4,) and np.all(h > 0)
+        lib().or_propagate_dd(*_grid_args(c, grid), beams.n, _p(sig), _p(q),
+                              _p(beams.state), dt, nsteps, _p(h))
+
+
+def dd_spacings(grid, params):
+    """Spacings of the divided differences: the mesh steps
+    (qs1 d1, qs2 d2, dp1, dp2), i.e. the neighbouring nodes of the mesh."""
+    return (params.qs1 * grid.d1, params.qs2 * grid.d2, params.dp1, params.dp2)
+
+
+def _prop_mode(beams, grid, params):
+    q = beam_nodes(beams, grid, params) if params.amp_closed else None
+    dd = dd_spacings(grid, params) if getattr(params, "dz_divided", 0) else None
+    return q, dd
 
 
 def rhs(y, sigma: float, c, grid) -> np.ndarray:
@@ -308,9 +331,9 @@ def trace(beams: Beams, c, grid, params, receivers, rec_every: int,
     at t_k = k * rec_every * dt, k = 1..nrec (beams are advanced in place)."""
     ns = beams.offsets.size - 1
     out = np.empty((ns, nrec, len(receivers)))
-    q = beam_nodes(beams, grid, params) if params.amp_closed else None
+    q, dd = _prop_mode(beams, grid, params)
     for k in range(nrec):
-        propagate(beams, c, grid, params.dt, rec_every, q=q)
+        propagate(beams, c, grid, params.dt, rec_every, q=q, dd=dd)
         for s in range(ns):
             out[s, k] = reconstruct_points(beams, grid, params, receivers, shot=s)
     return out
@@ -319,7 +342,7 @@ def trace(beams: Beams, c, grid, params, receivers, rec_every: int,
 def forward(f0, f1, c, grid, params, imag=False):
     """The whole three-step algorithm: u(T) for every shot."""
     b = decompose(f0, f1, c, grid, params)
-    q = beam_nodes(b, grid, params) if params.amp_closed else None
-    propagate(b, c, grid, params.dt, params.nsteps, q=q)
+    q, dd = _prop_mode(b, grid, params)
+    propagate(b, c, grid, params.dt, params.nsteps, q=q, dd=dd)
     us = [reconstruct(b, grid, params, shot=s, imag=imag) for s in range(f0.shape[0])]
     return b, us

@@ -349,6 +349,112 @@ void or_propagate_closed(const double *c, int n1, int n2, double o1, double o2,
     }
 }
 
+/* Right-hand side of the characteristic equations and the action alone (the
+ * rays, for the divided-difference mode): y = {Q1, Q2, P1, P2, S}. */
+static void ray_rhs(const vel_t *v, double sigma, const double *y, double *dy)
+{
+    double cv[3];
+    velocity_n(v->c, v->n1, v->n2, v->o1, v->o2, v->d1, v->d2, y[0], y[1], 3, cv);
+    double n = sqrt(y[2] * y[2] + y[3] * y[3]);
+    double H = sigma * cv[0] * n;
+    double HP[2] = {sigma * cv[0] * y[2] / n, sigma * cv[0] * y[3] / n};
+    dy[0] = HP[0];
+    dy[1] = HP[1];
+    dy[2] = -sigma * n * cv[1];
+    dy[3] = -sigma * n * cv[2];
+    dy[4] = y[2] * HP[0] + y[3] * HP[1] - H;
+}
+
+/* dzQ and dzP by divided differences instead of the dynamic ray tracing
+ * equations (the alternative the paper names next to the dzQ, dzP eqs.):
+ * besides its own ray every beam advances the rays of its eight neighbouring
+ * mesh nodes, (q +- h[j] e_j, p) and (q, p +- h[2+j] e_j), j = 1, 2, by the
+ * same RK4; after every step
+ *   dq_j Q_k = (Q_k(+q_j) - Q_k(-q_j)) / (2 h[j]),
+ *   dp_j Q_k = (Q_k(+p_j) - Q_k(-p_j)) / (2 h[2+j]),
+ * (likewise for P), A[j][k] = dq_j Q_k - i dp_j Q_k, B[j][k] = dq_j P_k -
+ * i dp_j P_k, and a = c(Q)/c(q) (det Z)^{1/2}, Z = A + iB, with the root
+ * nearest the previous step's (as in or_propagate_closed).  The neighbouring
+ * rays start from the incoming state along its A and B (dq_j Q = Re A[j],
+ * dp_j Q = -Im A[j], dq_j P = Re B[j], dp_j P = -Im B[j]): at t = 0 (A = I,
+ * B = -iI) they are exactly the rays of the neighbouring mesh nodes. */
+void or_propagate_dd(const double *c, int n1, int n2, double o1, double o2,
+                     double d1, double d2, int64_t nb, const int8_t *sigma,
+                     const double *q, double *state, double dt, int nsteps,
+                     const double *h)
+{
+    vel_t v = {c, n1, n2, o1, o2, d1, d2};
+    if (nsteps <= 0) return;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t b = 0; b < nb; ++b) {
+        double *y = state + (size_t)b * NSTATE;
+        double s = (double)sigma[b];
+        /* ray 0: the beam; 1 + 2j / 2 + 2j: +- q_j; 5 + 2j / 6 + 2j: +- p_j */
+        double ray[9][5];
+        for (int i = 0; i < 5; ++i) ray[0][i] = y[i];
+        for (int m = 0; m < 4; ++m) {
+            int j = m & 1, alongp = m >= 2;
+            for (int side = 0; side < 2; ++side) {
+                double *r = ray[1 + 2 * m + side];
+                double sh = (side == 0 ? 1.0 : -1.0) * h[m];
+                for (int k = 0; k < 2; ++k) {
+                    double dQ = alongp ? -y[6 + 2 * (2 * j + k)] : y[5 + 2 * (2 * j + k)];
+                    double dP = alongp ? -y[14 + 2 * (2 * j + k)] : y[13 + 2 * (2 * j + k)];
+                    r[k] = y[k] + sh * dQ;
+                    r[2 + k] = y[2 + k] + sh * dP;
+                }
+                r[4] = y[4];
+            }
+        }
+        double cv[3];
+        velocity_n(c, n1, n2, o1, o2, d1, d2, q[2 * b], q[2 * b + 1], 1, cv);
+        const double cq = cv[0];
+        velocity_n(c, n1, n2, o1, o2, d1, d2, y[0], y[1], 1, cv);
+        double complex root = (y[21] + I * y[22]) * cq / cv[0];
+        for (int it = 0; it < nsteps; ++it) {
+            for (int r = 0; r < 9; ++r) {
+                double *x = ray[r];
+                double k1[5], k2[5], k3[5], k4[5], t[5];
+                ray_rhs(&v, s, x, k1);
+                for (int i = 0; i < 5; ++i) t[i] = x[i] + 0.5 * dt * k1[i];
+                ray_rhs(&v, s, t, k2);
+                for (int i = 0; i < 5; ++i) t[i] = x[i] + 0.5 * dt * k2[i];
+                ray_rhs(&v, s, t, k3);
+                for (int i = 0; i < 5; ++i) t[i] = x[i] + dt * k3[i];
+                ray_rhs(&v, s, t, k4);
+                for (int i = 0; i < 5; ++i)
+                    x[i] += dt / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+            }
+            double complex A[2][2], B[2][2], Z[2][2];
+            for (int j = 0; j < 2; ++j)
+                for (int k = 0; k < 2; ++k) {
+                    double dqQ = (ray[1 + 2 * j][k] - ray[2 + 2 * j][k]) / (2.0 * h[j]);
+                    double dpQ = (ray[5 + 2 * j][k] - ray[6 + 2 * j][k]) / (2.0 * h[2 + j]);
+                    double dqP = (ray[1 + 2 * j][2 + k] - ray[2 + 2 * j][2 + k]) / (2.0 * h[j]);
+                    double dpP = (ray[5 + 2 * j][2 + k] - ray[6 + 2 * j][2 + k]) / (2.0 * h[2 + j]);
+                    A[j][k] = dqQ - I * dpQ;
+                    B[j][k] = dqP - I * dpP;
+                    Z[j][k] = A[j][k] + I * B[j][k];
+                }
+            double complex r = csqrt(Z[0][0] * Z[1][1] - Z[0][1] * Z[1][0]);
+            if (creal(r * conj(root)) < 0.0) r = -r;
+            root = r;
+            for (int i = 0; i < 5; ++i) y[i] = ray[0][i];
+            for (int j = 0; j < 2; ++j)
+                for (int k = 0; k < 2; ++k) {
+                    y[5 + 2 * (2 * j + k)] = creal(A[j][k]);
+                    y[6 + 2 * (2 * j + k)] = cimag(A[j][k]);
+                    y[13 + 2 * (2 * j + k)] = creal(B[j][k]);
+                    y[14 + 2 * (2 * j + k)] = cimag(B[j][k]);
+                }
+            velocity_n(c, n1, n2, o1, o2, d1, d2, y[0], y[1], 1, cv);
+            double complex a = cv[0] / cq * r;
+            y[21] = creal(a);
+            y[22] = cimag(a);
+        }
+    }
+}
+
 /* The right-hand side alone, for tests of the equations themselves. */
 void or_rhs(const double *c, int n1, int n2, double o1, double o2, double d1,
             double d2, double sigma, const double *y, double *dy)

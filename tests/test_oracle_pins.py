@@ -616,6 +616,118 @@ def test_dynamic_ray_tracing_matches_divided_differences():
     np.testing.assert_allclose(B, dP, atol=1e-7)
 
 
+def _dd_state(q, p, sig, c, g, T, nst, h):
+    b = _single_beams(q, p, sig)
+    oracle.propagate(b, c, g, T / nst, nst, q=q, dd=h)
+    return b.state
+
+
+def test_divided_difference_mode_uses_the_neighbouring_mesh_rays():
+    """The divided-difference mode from t = 0 (A = I, B = -iI) against the
+    rays of the eight neighbouring mesh nodes propagated on their own: its
+    Q, P, S are the beam's own ray and its A, B the central differences
+    (dq_j - i dp_j) of the neighbours' Q and P, each spacing its own."""
+    g, c, q, p, sig = _smooth_case(nb=12, seed=16)
+    T, nst = 0.1, 100
+    h = (0.05, 0.04, 0.06, 0.07)
+    st = _dd_state(q, p, sig, c, g, T, nst, h)
+    own = _single_beams(q, p, sig)
+    oracle.propagate(own, c, g, T / nst, nst)
+    np.testing.assert_allclose(st[:, 0:5], own.state[:, 0:5], rtol=0, atol=1e-13)
+    dQ = np.zeros((len(q), 2, 2), complex)
+    dP = np.zeros((len(q), 2, 2), complex)
+    for j in range(2):
+        for alongp, fac in ((0, 1.0), (1, -1j)):
+            e = np.zeros(2)
+            e[j] = h[2 * alongp + j]
+            qp, qm, pp, pm = q, q, p, p
+            if alongp:
+                pp, pm = p + e, p - e
+            else:
+                qp, qm = q + e, q - e
+            bp = _single_beams(qp, pp, sig)
+            bm = _single_beams(qm, pm, sig)
+            oracle.propagate(bp, c, g, T / nst, nst)
+            oracle.propagate(bm, c, g, T / nst, nst)
+            dQ[:, j, :] += fac * (bp.state[:, 0:2] - bm.state[:, 0:2]) / (2 * e[j])
+            dP[:, j, :] += fac * (bp.state[:, 2:4] - bm.state[:, 2:4]) / (2 * e[j])
+    np.testing.assert_allclose(_A(st), dQ, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(_B(st), dP, rtol=0, atol=1e-11)
+    cq = oracle.velocity(c, g, q[:, 0], q[:, 1])[:, 0]
+    cQ = oracle.velocity(c, g, st[:, 0], st[:, 1])[:, 0]
+    Z = dQ + 1j * dP
+    det = Z[:, 0, 0] * Z[:, 1, 1] - Z[:, 0, 1] * Z[:, 1, 0]
+    assert np.all(det.real > 0)        # no winding yet: the principal root
+    np.testing.assert_allclose(st[:, 21] + 1j * st[:, 22], cQ / cq * np.sqrt(det), rtol=1e-11)
+
+
+def test_divided_difference_mode_constant_velocity_closed_form():
+    """c = c0 at finite spacings: the rays are straight, so the q-differences
+    are exactly I (Q) and 0 (P), the p-differences of P exactly I, and the
+    p-differences of Q the central differences of sigma c0 t p/|p|;
+    Z = 2I - i dpQ and a = (det Z)^{1/2}."""
+    g = fi.Grid(64, 64, 0.0, 0.0, 1 / 64, 1 / 64)
+    c0 = 1.3
+    c = np.full(g.shape, c0)
+    r = fi.rng(17)
+    nb = 30
+    q = r.uniform(0.35, 0.65, (nb, 2))
+    p = r.uniform(-2, 2, (nb, 2))
+    p[np.linalg.norm(p, axis=1) < 0.6] *= 3.0
+    sig = np.where(np.arange(nb) % 2 == 0, 1, -1)
+    T, nst = 0.1, 100
+    h = (0.03, 0.05, 0.2, 0.15)
+    st = _dd_state(q, p, sig, c, g, T, nst, h)
+
+    def Qof(pp):
+        return (sig * c0 * T)[:, None] * pp / np.linalg.norm(pp, axis=1)[:, None]
+
+    dpQ = np.zeros((nb, 2, 2))
+    for j in range(2):
+        e = np.zeros(2)
+        e[j] = h[2 + j]
+        dpQ[:, j, :] = (Qof(p + e) - Qof(p - e)) / (2 * h[2 + j])
+    A = np.eye(2)[None] - 1j * dpQ
+    np.testing.assert_allclose(_A(st), A, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(_B(st), -1j * np.eye(2)[None].repeat(nb, 0), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(st[:, 0:2], q + Qof(p), rtol=0, atol=1e-13)
+    Z = 2 * np.eye(2)[None] - 1j * dpQ
+    det = Z[:, 0, 0] * Z[:, 1, 1] - Z[:, 0, 1] * Z[:, 1, 0]
+    np.testing.assert_allclose(st[:, 21] + 1j * st[:, 22], np.sqrt(det), rtol=1e-12)
+
+
+def test_divided_difference_mode_converges_to_dynamic_ray_tracing():
+    """In a smooth layered model the divided-difference A, B and amplitude
+    approach those of the dynamic ray tracing equations (with the same
+    closed-form amplitude) at second order in the spacing, and agree to
+    1e-7 at a spacing of 1e-5 (at small spacings the rays' right-hand side,
+    which holds the gradient of a C^2 spline, is only C^1 across knots, and
+    the order drops); a run split in two segments differs from the single
+    run only at the level of the differences themselves."""
+    g, c, q, p, sig = _smooth_case(nb=16, seed=18)
+    T, nst = 0.15, 150
+    ref = _single_beams(q, p, sig)
+    oracle.propagate(ref, c, g, T / nst, nst, q=q)
+    Ar, Br = _A(ref.state), _B(ref.state)
+    ar = ref.state[:, 21] + 1j * ref.state[:, 22]
+    errs = []
+    for hh in (0.08, 0.04, 0.02):
+        st = _dd_state(q, p, sig, c, g, T, nst, (hh,) * 4)
+        np.testing.assert_allclose(st[:, 0:5], ref.state[:, 0:5], rtol=0, atol=1e-13)
+        e = max(np.abs(_A(st) - Ar).max(), np.abs(_B(st) - Br).max(),
+                np.abs(st[:, 21] + 1j * st[:, 22] - ar).max())
+        errs.append(e)
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5, errs
+    st = _dd_state(q, p, sig, c, g, T, nst, (1e-5,) * 4)
+    assert np.abs(_A(st) - Ar).max() < 1e-7 and np.abs(_B(st) - Br).max() < 1e-7
+    b2 = _single_beams(q, p, sig)
+    oracle.propagate(b2, c, g, T / nst, nst // 2, q=q, dd=(0.02,) * 4)
+    oracle.propagate(b2, c, g, T / nst, nst - nst // 2, q=q, dd=(0.02,) * 4)
+    st1 = _dd_state(q, p, sig, c, g, T, nst, (0.02,) * 4)
+    d = np.abs(_A(b2.state) - _A(st1)).max()
+    assert 0 < d < errs[2], (d, errs)
+
+
 def test_rk4_fourth_order():
     """On a field the B-spline reproduces exactly (a quadratic, rays kept two
     cells inside the grid) the right-hand side is smooth, and halving dt
