@@ -75,6 +75,11 @@ static fga_status check_params(fga_ctx *ctx, const fga_grid *g, const fga_params
     if (p->top_n < 0) return fga_fail(ctx, FGA_EINVAL, "top_n must be >= 0");
     if (p->amp_closed != 0 && p->amp_closed != 1)
         return fga_fail(ctx, FGA_EINVAL, "amp_closed must be 0 or 1");
+    if (p->dz_divided != 0 && p->dz_divided != 1)
+        return fga_fail(ctx, FGA_EINVAL, "dz_divided must be 0 or 1");
+    if (p->dz_divided && !p->amp_closed)
+        return fga_fail(ctx, FGA_EINVAL,
+                        "dz_divided = 1 takes the closed-form amplitude (amp_closed = 1)");
     int R1 = fga_halfwidth(p->eps, p->tau_fbi, g->d1);
     int R2 = fga_halfwidth(p->eps, p->tau_fbi, g->d2);
     if (R1 > 8192 || R2 > 8192)

@@ -196,6 +196,184 @@ k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Divided-difference mode: dzQ and dzP from the rays of the neighbouring mesh
+// nodes instead of the dynamic ray tracing equations.
+//
+// One lane per ray: lanes 9m .. 9m + 8 of a wavefront carry beam m of the
+// wavefront's seven (role 0: the beam's own ray; roles 1 + 2r and 2 + 2r:
+// the rays displaced by +h_r and -h_r along direction r = q1, q2, p1, p2;
+// lane 63 repeats lane 54's ray and stores nothing).  A lane holds only the
+// five ray values, so the state of the RK4 is small; the cell coefficients
+// come through the same LDS prefetch as in k_rk4.  After every step the
+// lanes put Q and P into LDS and every lane reads the eight neighbours of its
+// beam, forms Z = dzQ + i dzP from the central differences and follows the
+// root of det Z; the beam's own lane finally stores Q, P, S, A, B and
+// a = c(Q)/c(q) root.
+
+#define DD_BEAMS 7   // beams per wavefront (9 lanes each)
+
+struct Ray {
+    double Q1, Q2, P1, P2, S;
+};
+
+// One RK4 stage of the characteristic equations and the action alone,
+// fused like rk_stage: k = f(t), acc += wacc k, t = y + hnext k.
+template <bool LAST, class Vel>
+__device__ __forceinline__ void ray_stage(Vel &vel, double s, Ray &t, Ray &acc, const Ray &y,
+                                          double wacc, double hnext)
+{
+    double c, g1, g2, K11, K12, K22;
+    vel.eval(t.Q1, t.Q2, c, g1, g2, K11, K12, K22);
+    const double n2 = fma(t.P1, t.P1, t.P2 * t.P2);
+    const double inv_n = rsq64(n2);
+    const double n = n2 * inv_n;
+    const double sc = s * c;
+    const double kQ1 = sc * (t.P1 * inv_n), kQ2 = sc * (t.P2 * inv_n);
+    const double kP1 = -s * n * g1, kP2 = -s * n * g2;
+    const double kS = t.P1 * kQ1 + t.P2 * kQ2 - sc * n;
+    acc.Q1 = fma(wacc, kQ1, acc.Q1);
+    acc.Q2 = fma(wacc, kQ2, acc.Q2);
+    acc.P1 = fma(wacc, kP1, acc.P1);
+    acc.P2 = fma(wacc, kP2, acc.P2);
+    acc.S = fma(wacc, kS, acc.S);
+    if (LAST) {
+        vel.prefetch(acc.Q1, acc.Q2);
+    } else {
+        t.Q1 = fma(hnext, kQ1, y.Q1);
+        t.Q2 = fma(hnext, kQ2, y.Q2);
+        vel.prefetch(t.Q1, t.Q2);
+        t.P1 = fma(hnext, kP1, y.P1);
+        t.P2 = fma(hnext, kP2, y.P2);
+        t.S = fma(hnext, kS, y.S);
+    }
+}
+
+// dzQ, dzP of the beam whose lanes start at lane `first`, from the rays in
+// LDS (xq: Q, xp: P of each lane): dq_j = (+q_j - -q_j) inv2h[j],
+// dp_j = (+p_j - -p_j) inv2h[2 + j]; A[j][k] = dq_j Q_k - i dp_j Q_k,
+// B[j][k] = dq_j P_k - i dp_j P_k.
+__device__ __forceinline__ void dd_AB(const double2 *xq, const double2 *xp, int first,
+                                      const double inv2h[4], Cd A[2][2], Cd B[2][2])
+{
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const double2 qa = xq[first + 1 + 2 * j], qb = xq[first + 2 + 2 * j];
+        const double2 qc = xq[first + 5 + 2 * j], qd = xq[first + 6 + 2 * j];
+        const double2 pa = xp[first + 1 + 2 * j], pb = xp[first + 2 + 2 * j];
+        const double2 pc = xp[first + 5 + 2 * j], pd = xp[first + 6 + 2 * j];
+        const double hq = inv2h[j], hp = inv2h[2 + j];
+        A[j][0] = {(qa.x - qb.x) * hq, -(qc.x - qd.x) * hp};
+        A[j][1] = {(qa.y - qb.y) * hq, -(qc.y - qd.y) * hp};
+        B[j][0] = {(pa.x - pb.x) * hq, -(pc.x - pd.x) * hp};
+        B[j][1] = {(pa.y - pb.y) * hq, -(pc.y - pd.y) * hp};
+    }
+}
+
+__device__ __forceinline__ Cd det_Z(const Cd A[2][2], const Cd B[2][2])
+{
+    Cd Z[2][2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int l = 0; l < 2; ++l) Z[j][l] = {A[j][l].r - B[j][l].i, A[j][l].i + B[j][l].r};
+    return csub(cmul(Z[0][0], Z[1][1]), cmul(Z[0][1], Z[1][0]));
+}
+
+__global__ void __launch_bounds__(RK_BLOCK)
+k_rk4_dd(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
+         const int64_t *__restrict__ offsets, int nshots, int64_t cap, int64_t NqNp, double dt,
+         int nsteps, double4 hmesh, double *__restrict__ ckpt, int64_t *status)
+{
+    __shared__ double2 slots[RK_BLOCK / 64][8 * 64];
+    __shared__ double2 xq[RK_BLOCK / 64][64], xp[RK_BLOCK / 64][64];
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int m = lane == 63 ? DD_BEAMS - 1 : lane / 9;       // beam of the lane in the wave
+    const int role = lane == 63 ? 0 : lane % 9;
+    const int first = 9 * m;
+    const bool owner = role == 0 && lane != 63;
+    const double h[4] = {hmesh.x, hmesh.y, hmesh.z, hmesh.w};
+    const double inv2h[4] = {0.5 / hmesh.x, 0.5 / hmesh.y, 0.5 / hmesh.z, 0.5 / hmesh.w};
+    // displacement of this lane's ray: direction r, side +-1 (none for role 0)
+    const int r = role == 0 ? 0 : (role - 1) >> 1;
+    const double hs = role == 0 ? 0.0 : (((role - 1) & 1) ? -h[r] : h[r]);
+    const int dj = r & 1;
+    const bool alongp = r >= 2;
+    VelDma vel{V, slots[wave], lane, INT_MIN, INT_MIN};
+    double2 *wq = xq[wave], *wp = xp[wave];
+    const int64_t nb = offsets[nshots];
+    const int64_t per_block = (int64_t)(RK_BLOCK / 64) * DD_BEAMS;
+    for (int64_t b0 = (int64_t)blockIdx.x * per_block; b0 < nb;
+         b0 += (int64_t)gridDim.x * per_block) {
+        const int64_t wb = b0 + (int64_t)wave * DD_BEAMS;
+        if (wb >= nb) continue;                                 // uniform in the wavefront
+        const int64_t braw = wb + m;
+        const bool valid = braw < nb;
+        const int64_t b = valid ? braw : nb - 1;
+        const double *st = f + (size_t)FGA_F_STATE * cap + b;
+        if (ckpt && owner && valid)
+            for (int k = 0; k < FGA_NSTATE; ++k) ckpt[(size_t)k * cap + b] = st[(size_t)k * cap];
+        // the displaced ray starts along the incoming A, B:
+        // dq_j Q_k = Re A[j][k], dp_j Q_k = -Im A[j][k] (P alike with B)
+        const int fa = 5 + 4 * dj + (alongp ? 1 : 0);
+        const double sg = alongp ? -hs : hs;
+        Ray y;
+        y.Q1 = fma(sg, st[(size_t)fa * cap], st[0]);
+        y.Q2 = fma(sg, st[(size_t)(fa + 2) * cap], st[cap]);
+        y.P1 = fma(sg, st[(size_t)(fa + 8) * cap], st[2 * cap]);
+        y.P2 = fma(sg, st[(size_t)(fa + 10) * cap], st[3 * cap]);
+        y.S = st[4 * cap];
+        const double s = ((id[b] / NqNp) & 1) ? -1.0 : 1.0;
+        const double h2 = 0.5 * dt, h6 = dt / 6.0, h3 = dt / 3.0;
+        double cq, c0, d[5];
+        vel_eval(V, f[b], f[cap + b], cq, d[0], d[1], d[2], d[3], d[4]);
+        vel_eval(V, st[0], st[cap], c0, d[0], d[1], d[2], d[3], d[4]);
+        Cd root = cscale(Cd{st[21 * cap], st[22 * cap]}, cq / c0);
+        vel.cur1 = vel.cur2 = INT_MIN;
+        vel.prefetch(y.Q1, y.Q2);
+        for (int it = 0; it < nsteps; ++it) {
+            Ray t = y, acc = y;
+            ray_stage<false>(vel, s, t, acc, y, h6, h2);
+            ray_stage<false>(vel, s, t, acc, y, h3, h2);
+            ray_stage<false>(vel, s, t, acc, y, h3, dt);
+            ray_stage<true>(vel, s, t, acc, y, h6, 0.0);
+            y = acc;
+            // exchange within the wavefront: the previous step's reads are
+            // done before these writes, and these writes before the reads
+            __builtin_amdgcn_wave_barrier();
+            wq[lane] = double2{y.Q1, y.Q2};
+            wp[lane] = double2{y.P1, y.P2};
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            Cd A[2][2], B[2][2];
+            dd_AB(wq, wp, first, inv2h, A, B);
+            const Cd rt = csqrt_principal(det_Z(A, B));
+            root = rt.r * root.r + rt.i * root.i < 0.0 ? Cd{-rt.r, -rt.i} : rt;
+        }
+        double cQ;
+        vel.eval(y.Q1, y.Q2, cQ, d[0], d[1], d[2], d[3], d[4]);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        if (owner && valid) {
+            St o;
+            o.Q1 = y.Q1;
+            o.Q2 = y.Q2;
+            o.P1 = y.P1;
+            o.P2 = y.P2;
+            o.S = y.S;
+            dd_AB(wq, wp, first, inv2h, o.A, o.B);
+            o.a = cscale(root, cQ / cq);
+            if (!isfinite(o.Q1) || !isfinite(o.Q2) || !isfinite(o.a.r) || !isfinite(o.a.i))
+                atomicOr((unsigned long long *)status, FGA_STATUS_NUMERIC);
+            store_state(f + (size_t)FGA_F_STATE * cap + b, cap, o);
+        }
+        // the next beam's first exchange must not overwrite what is read here
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 fga_status fga_launch_propagate(fga_ctx *ctx, fga_beams *beams, int nshots, int nsteps,
                                 double *ckpt)
 {
@@ -203,7 +381,14 @@ fga_status fga_launch_propagate(fga_ctx *ctx, fga_beams *beams, int nshots, int 
     int64_t NqNp = (int64_t)ctx->p.nq1 * ctx->p.nq2 * ctx->p.np1 * ctx->p.np2;
     // persistent grid: the beam count lives on the device
     int blocks = ctx->num_cu * 8;
-    if (ctx->p.amp_closed)
+    if (ctx->p.dz_divided) {
+        if (nsteps <= 0) return FGA_OK;
+        const fga_grid &g = ctx->g;
+        double4 hm = make_double4(ctx->p.qs1 * g.d1, ctx->p.qs2 * g.d2, ctx->p.dp1, ctx->p.dp2);
+        hipLaunchKernelGGL(k_rk4_dd, dim3(blocks), dim3(RK_BLOCK), 0, ctx->stream, V, beams->f,
+                           beams->id, beams->offsets, nshots, beams->capacity, NqNp, ctx->p.dt,
+                           nsteps, hm, ckpt, ctx->status);
+    } else if (ctx->p.amp_closed)
         hipLaunchKernelGGL(k_rk4<true>, dim3(blocks), dim3(256), 0, ctx->stream, V, beams->f,
                            beams->id, beams->offsets, nshots, beams->capacity, NqNp, ctx->p.dt,
                            nsteps, ckpt, ctx->status);

@@ -38,7 +38,8 @@ def _structs(grid, params):
     g = fga.fga_grid(grid.n1, grid.n2, grid.o1, grid.o2, grid.d1, grid.d2)
     p = fga.fga_params(params.eps, params.qb1, params.qb2, params.qs1, params.qs2, params.nq1,
                        params.nq2, params.np1, params.np2, params.dp1, params.dp2, params.tau,
-                       params.tau_fbi, params.tau_win, params.dt, params.top_n, params.amp_closed)
+                       params.tau_fbi, params.tau_win, params.dt, params.top_n, params.amp_closed,
+                       params.dz_divided)
     return g, p
 
 
@@ -46,6 +47,7 @@ def _structs(grid, params):
     dict(np1=7), dict(np2=0), dict(eps=0.0), dict(eps=float("nan")), dict(nq1=0),
     dict(qs2=0), dict(qb1=-1), dict(nq1=1000), dict(tau=1.5), dict(tau_fbi=0.0),
     dict(tau_win=1.0), dict(dt=-1e-3), dict(dp1=0.0), dict(top_n=-1), dict(amp_closed=2),
+    dict(dz_divided=2, amp_closed=1), dict(dz_divided=1),
 ])
 def test_create_rejects_bad_params(bad):
     import paper_1304_3542_amd as fga
