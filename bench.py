@@ -81,6 +81,8 @@ def parse():
                     help="timed graph replays of the 64-shot batch (0 skips it)")
     ap.add_argument("--closed-steps", type=int, default=5,
                     help="timed steps of point512 with the closed-form amplitude (0 skips it)")
+    ap.add_argument("--dd-steps", type=int, default=3,
+                    help="timed steps of point512 with divided-difference dzQ, dzP (0 skips it)")
     ap.add_argument("--large-steps", type=int, default=1,
                     help="timed steps of the 2048x1024 configuration (0 skips it)")
     ap.add_argument("--topn-steps", type=int, default=5,
@@ -323,6 +325,41 @@ def closed_step(steps, u_integrated):
             "status": st}
 
 
+def dd_step(steps, u_integrated):
+    """point512 with dzQ, dzP from divided differences (dz_divided = 1,
+    closed-form amplitude, mixed), at the neighbouring mesh nodes
+    (dz_scale = 1) and at rays 1e-3 mesh steps apart: ms per step and stages,
+    and each field's difference from the dynamic ray tracing run of the same
+    step (over the mesh steps the divided differences are an approximation
+    of their own)."""
+    import torch
+    out = {"workload": "point512 with dzQ, dzP from divided differences (9 rays per beam), "
+           "closed-form amplitude, mixed"}
+    for scale in (1.0, 1e-3):
+        W = fi.workload("point512", "mixed")
+        W = fi.Workload(W.name, W.grid,
+                        W.params.replace(amp_closed=1, dz_divided=1, dz_scale=scale),
+                        W.c, W.f0, W.f1)
+        path = Path(W, "mixed", 1_300_000)
+        nb = path.fit_capacity()
+        ms, stage_ms, per_step = time_path(path, steps, 1)
+        st, _ = path.ctx.status()
+        u = path.u.cpu().numpy()
+        out["dz_scale=%g" % scale] = {
+            "nbeams": nb, "ms_per_step": ms,
+            "ms_per_step_device_median": float(np.median(per_step)),
+            "beams_per_s": nb / (ms * 1e-3),
+            "ray_steps_per_s": 9 * nb * W.params.nsteps / (stage_ms[1] * 1e-3),
+            "stages_ms": dict(zip(("decompose", "propagate", "reconstruct"), stage_ms.tolist())),
+            "rel_l2_vs_dynamic_ray_tracing": float(np.linalg.norm(u - u_integrated) /
+                                                   np.linalg.norm(u_integrated)),
+            "status": st}
+        path.ctx.close()
+        del path
+        torch.cuda.empty_cache()
+    return out
+
+
 def large_step(steps):
     """The large configuration (2048 x 1024, eps = 1/1024, ~5e7 beams): ms per
     mixed step and its stages, the FP64 GPU step on the same input, and the
@@ -535,6 +572,8 @@ def main():
         out["topn"] = topn_step(args.topn_steps)
     if args.closed_steps > 0:
         out["closed_amplitude"] = closed_step(args.closed_steps, u_mixed)
+    if args.dd_steps > 0:
+        out["divided_differences"] = dd_step(args.dd_steps, u_mixed)
     if args.large_steps > 0:
         out["large"] = large_step(args.large_steps)
     if not args.no_cpu_baseline:

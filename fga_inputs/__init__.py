@@ -84,6 +84,7 @@ class Params:
     top_n: int = 0      # > 0: keep the top_n largest |psi| per branch and shot instead
     amp_closed: int = 0  # 1: a = c(Q)/c(q) (det Z)^(1/2) instead of integrating a
     dz_divided: int = 0  # 1: dzQ, dzP from divided differences of neighbouring rays
+    dz_scale: float = 1.0  # their spacing in mesh steps (1: the neighbouring mesh nodes)
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)

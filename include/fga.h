@@ -90,15 +90,20 @@ typedef struct {
  *              eqs.) for A = dzQ, B = dzP; 1: take them by divided
  *              differences instead (the alternative named next to those
  *              equations): every beam also advances, by the same RK4, the
- *              rays of its eight neighbouring mesh nodes (q +- qs_j d_j e_j,
- *              p) and (q, p +- dp_j e_j), and after every step
- *              dq_j Q_k = (Q_k(+q_j) - Q_k(-q_j)) / (2 qs_j d_j),
- *              dp_j Q_k likewise over 2 dp_j (and P alike),
+ *              eight rays started at (q +- h_j e_j, p) and (q, p +- h_{2+j}
+ *              e_j), h = dz_scale (qs1 d1, qs2 d2, dp1, dp2), and after
+ *              every step
+ *              dq_j Q_k = (Q_k(+q_j) - Q_k(-q_j)) / (2 h_j),
+ *              dp_j Q_k likewise over 2 h_{2+j} (and P alike),
  *              A[j][k] = dq_j Q_k - i dp_j Q_k, B[j][k] = dq_j P_k - i dp_j P_k.
- *              The neighbouring rays start from the incoming state along its
- *              A and B (exactly the neighbouring nodes' rays at t = 0), so a
- *              run in segments restarts them from the stored A, B.  Requires
+ *              The extra rays start from the incoming state along its A and
+ *              B (exactly the displaced nodes' rays at t = 0), so a run in
+ *              segments restarts them from the stored A, B.  Requires
  *              amp_closed = 1 (the amplitude follows from det Z).
+ *   dz_scale   spacing of the divided differences in mesh steps (> 0;
+ *              read when dz_divided = 1): 1 takes the neighbouring mesh
+ *              nodes; smaller values take rays closer than the mesh, which
+ *              approach the dynamic ray tracing values at second order
  *   tau_fbi    the FBI box B_eps has half-width ceil(sqrt(2 eps ln(1/tau_fbi))/d)
  *   tau_win    each Gaussian is summed over the box of half-width
  *              ceil(sqrt(2 eps ln(1/tau_win))/d) around the node nearest Q
@@ -113,6 +118,7 @@ typedef struct {
     int32_t top_n;
     int32_t amp_closed;
     int32_t dz_divided;
+    double dz_scale;
 } fga_params;
 
 /* Beam storage: structure of arrays in one float64 buffer

@@ -270,9 +270,12 @@ def propagate(beams: Beams, c, grid, dt: float, nsteps: int, q=None, dd=None) ->
 
 
 def dd_spacings(grid, params):
-    """Spacings of the divided differences: the mesh steps
-    (qs1 d1, qs2 d2, dp1, dp2), i.e. the neighbouring nodes of the mesh."""
-    return (params.qs1 * grid.d1, params.qs2 * grid.d2, params.dp1, params.dp2)
+    """Spacings of the divided differences: dz_scale times the mesh steps
+    (qs1 d1, qs2 d2, dp1, dp2); dz_scale = 1 gives the neighbouring nodes of
+    the mesh."""
+    s = float(getattr(params, "dz_scale", 1.0))
+    return (s * (params.qs1 * grid.d1), s * (params.qs2 * grid.d2), s * params.dp1,
+            s * params.dp2)
 
 
 def _prop_mode(beams, grid, params):

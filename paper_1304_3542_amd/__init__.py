@@ -41,7 +41,8 @@ class fga_params(ctypes.Structure):
                 ("dp1", ctypes.c_double), ("dp2", ctypes.c_double), ("tau", ctypes.c_double),
                 ("tau_fbi", ctypes.c_double), ("tau_win", ctypes.c_double),
                 ("dt", ctypes.c_double), ("top_n", ctypes.c_int32),
-                ("amp_closed", ctypes.c_int32), ("dz_divided", ctypes.c_int32)]
+                ("amp_closed", ctypes.c_int32), ("dz_divided", ctypes.c_int32),
+                ("dz_scale", ctypes.c_double)]
 
 
 class fga_beams(ctypes.Structure):
@@ -114,7 +115,8 @@ def fga_create(grid, params, precision: int = FGA_FP64, max_shots: int = 1, stre
     p = fga_params(params.eps, params.qb1, params.qb2, params.qs1, params.qs2, params.nq1,
                    params.nq2, params.np1, params.np2, params.dp1, params.dp2, params.tau,
                    params.tau_fbi, params.tau_win, params.dt, int(getattr(params, "top_n", 0)),
-                   int(getattr(params, "amp_closed", 0)), int(getattr(params, "dz_divided", 0)))
+                   int(getattr(params, "amp_closed", 0)), int(getattr(params, "dz_divided", 0)),
+                   float(getattr(params, "dz_scale", 1.0)))
     ctx = ctypes.c_void_p()
     st = load().fga_create(ctypes.byref(ctx), ctypes.byref(g), ctypes.byref(p), int(precision),
                            int(max_shots), _stream_handle(stream))

@@ -80,6 +80,8 @@ static fga_status check_params(fga_ctx *ctx, const fga_grid *g, const fga_params
     if (p->dz_divided && !p->amp_closed)
         return fga_fail(ctx, FGA_EINVAL,
                         "dz_divided = 1 takes the closed-form amplitude (amp_closed = 1)");
+    if (p->dz_divided && !(p->dz_scale > 0 && isfinite(p->dz_scale)))
+        return fga_fail(ctx, FGA_EINVAL, "dz_scale must be positive");
     int R1 = fga_halfwidth(p->eps, p->tau_fbi, g->d1);
     int R2 = fga_halfwidth(p->eps, p->tau_fbi, g->d2);
     if (R1 > 8192 || R2 > 8192)

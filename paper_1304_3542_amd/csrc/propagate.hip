@@ -384,7 +384,9 @@ fga_status fga_launch_propagate(fga_ctx *ctx, fga_beams *beams, int nshots, int 
     if (ctx->p.dz_divided) {
         if (nsteps <= 0) return FGA_OK;
         const fga_grid &g = ctx->g;
-        double4 hm = make_double4(ctx->p.qs1 * g.d1, ctx->p.qs2 * g.d2, ctx->p.dp1, ctx->p.dp2);
+        const double sc = ctx->p.dz_scale;
+        double4 hm = make_double4(sc * (ctx->p.qs1 * g.d1), sc * (ctx->p.qs2 * g.d2),
+                                  sc * ctx->p.dp1, sc * ctx->p.dp2);
         hipLaunchKernelGGL(k_rk4_dd, dim3(blocks), dim3(RK_BLOCK), 0, ctx->stream, V, beams->f,
                            beams->id, beams->offsets, nshots, beams->capacity, NqNp, ctx->p.dt,
                            nsteps, hm, ckpt, ctx->status);

@@ -33,6 +33,22 @@ def test_dd_fp64_matches_oracle():
     assert np.abs(r["fT"][11:27] - rc["fT"][11:27]).max() > 1e-3
 
 
+def test_dd_fine_spacing_matches_oracle_and_dynamic_ray_tracing():
+    """dz_scale = 1e-3 (rays 1e-3 mesh steps apart): the GPU equals the
+    oracle (differences of rays 8e-5 apart magnify rounding by ~1e4, hence
+    1e-9 on the state), and the field is within 1e-6 of the dynamic ray
+    tracing run (the oracle gives 2.4e-7 for this case)."""
+    g, p, c, f0, f1 = small_case(seed=84)
+    p = p.replace(nsteps=40, dz_scale=1e-3, **DD)
+    r = gpu_run(g, p, c, f0, f1, "fp64")
+    assert r["status"] == 0 and r["status_end"][0] == 0
+    b, us = oracle.forward(f0, f1, c, g, p)
+    assert pairwise_state_err(r["fT"][6:].T, b.state) <= 1e-9
+    assert rel_l2(r["u"][0], us[0]) <= 1e-10
+    rc = gpu_run(g, p.replace(dz_divided=0), c, f0, f1, "fp64")
+    assert rel_l2(r["u"][0], rc["u"][0]) <= 1e-6
+
+
 def test_dd_mixed_within_1e5():
     g, p, c, f0, f1 = small_case(seed=82)
     p = mixed_params(p.replace(nsteps=40, **DD))
