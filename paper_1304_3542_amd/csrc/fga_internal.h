@@ -241,33 +241,36 @@ __device__ __forceinline__ const double *vel_cell_coef(const VelGrid &V, const V
 }
 
 // c, grad c and the Hessian from the cell's coefficients C[b][a] by Horner's
-// rule: first in f2 for every power of f1 (value, first and second
-// derivative), then in f1.
+// rule: first in f2 for every power of f1 (value, first and half the second
+// derivative), then in f1.  The derivative forms carry their factors in the
+// multipliers, e.g. 3 C3 f^2 + 2 C2 f + C1 = (C3 (1.5 f) + C2)(2 f) + C1 and
+// (6 C3 f + 2 C2) / 2 = C3 (3 f) + C2, so every step is one FMA; the halves
+// are doubled in the final scaling.
 __device__ __forceinline__ void vel_poly(const VelGrid &V, const VelCell &k,
                                          const double C[4][4], double &c, double &c1, double &c2,
                                          double &c11, double &c12, double &c22)
 {
     const double f1 = k.f1, f2 = k.f2;
-    double q[4], q1[4], q2[4];
+    const double f2h = 1.5 * f2, f2d = 2.0 * f2, f2t = 3.0 * f2;
+    double q[4], q1[4], q2h[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         q[a] = fma(fma(fma(C[3][a], f2, C[2][a]), f2, C[1][a]), f2, C[0][a]);
-        const double t3 = 3.0 * C[3][a], t2 = 2.0 * C[2][a];
-        q1[a] = fma(fma(t3, f2, t2), f2, C[1][a]);
-        q2[a] = fma(2.0 * t3, f2, t2);
+        q1[a] = fma(fma(C[3][a], f2h, C[2][a]), f2d, C[1][a]);
+        q2h[a] = fma(C[3][a], f2t, C[2][a]);
     }
-    const double u3 = 3.0 * q[3], u2 = 2.0 * q[2];
+    const double f1h = 1.5 * f1, f1d = 2.0 * f1, f1t = 3.0 * f1;
     c = fma(fma(fma(q[3], f1, q[2]), f1, q[1]), f1, q[0]);
-    const double d1 = fma(fma(u3, f1, u2), f1, q[1]);
-    const double d11 = fma(2.0 * u3, f1, u2);
+    const double d1 = fma(fma(q[3], f1h, q[2]), f1d, q[1]);
+    const double d11h = fma(q[3], f1t, q[2]);
     const double d2 = fma(fma(fma(q1[3], f1, q1[2]), f1, q1[1]), f1, q1[0]);
-    const double d12 = fma(fma(3.0 * q1[3], f1, 2.0 * q1[2]), f1, q1[1]);
-    const double d22 = fma(fma(fma(q2[3], f1, q2[2]), f1, q2[1]), f1, q2[0]);
+    const double d12 = fma(fma(q1[3], f1h, q1[2]), f1d, q1[1]);
+    const double d22h = fma(fma(fma(q2h[3], f1, q2h[2]), f1, q2h[1]), f1, q2h[0]);
     c1 = d1 * V.inv_d1;
     c2 = d2 * V.inv_d2;
-    c11 = d11 * (V.inv_d1 * V.inv_d1);
+    c11 = d11h * (2.0 * V.inv_d1 * V.inv_d1);
     c12 = d12 * (V.inv_d1 * V.inv_d2);
-    c22 = d22 * (V.inv_d2 * V.inv_d2);
+    c22 = d22h * (2.0 * V.inv_d2 * V.inv_d2);
 }
 
 // Truncation box of a Gaussian centred at Q: the nodes within Rw cells of the

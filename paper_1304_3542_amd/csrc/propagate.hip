@@ -24,47 +24,47 @@
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-// The eight transfers of one request for the lanes in mask: 16 bytes from
-// each of a[0..7] into the slots at LDS address lds, 1 KB apart.  (No
-// instruction offset: on these transfers it would move the LDS destination
-// as well.)  Written as one block so that the EXEC change leaves no branch
-// in the compiled loop (a branch there makes the register allocator spill
-// the RK4 state); each M0 write is followed by the wait state that an LDS
-// transfer after it requires.  No VGPR receives data.
-__device__ __forceinline__ void cell_dma(const double *const a[8], unsigned lds,
-                                         unsigned long long mask)
+// The eight transfers of one request for the lanes in mask: the 128 bytes at
+// a, 16 per transfer, into the slots at LDS address lds, 1 KB apart.  A
+// transfer lands at M0 + instruction offset + 16 lane and reads address +
+// instruction offset, so one address register serves all eight: transfer s
+// takes offset 16 s and M0 = lds + 1024 s - 16 s.  Written as one block so
+// that the EXEC change leaves no branch in the compiled loop (a branch there
+// makes the register allocator spill the RK4 state); each M0 write is
+// followed by the wait state that an LDS transfer after it requires.  No
+// VGPR receives data.
+__device__ __forceinline__ void cell_dma(const double *a, unsigned lds, unsigned long long mask)
 {
     unsigned long long saved;
     asm volatile(
-        "s_and_saveexec_b64 %0, %9\n\t"
-        "s_mov_b32 m0, %10\n\t"
+        "s_and_saveexec_b64 %0, %2\n\t"
+        "s_mov_b32 m0, %3\n\t"
         "s_nop 0\n\t"
         "global_load_lds_dwordx4 %1, off\n\t"
-        "s_add_u32 m0, %10, 0x400\n\t"
+        "s_add_u32 m0, %3, 0x3f0\n\t"
         "s_nop 0\n\t"
-        "global_load_lds_dwordx4 %2, off\n\t"
-        "s_add_u32 m0, %10, 0x800\n\t"
+        "global_load_lds_dwordx4 %1, off offset:16\n\t"
+        "s_add_u32 m0, %3, 0x7e0\n\t"
         "s_nop 0\n\t"
-        "global_load_lds_dwordx4 %3, off\n\t"
-        "s_add_u32 m0, %10, 0xc00\n\t"
+        "global_load_lds_dwordx4 %1, off offset:32\n\t"
+        "s_add_u32 m0, %3, 0xbd0\n\t"
         "s_nop 0\n\t"
-        "global_load_lds_dwordx4 %4, off\n\t"
-        "s_add_u32 m0, %10, 0x1000\n\t"
+        "global_load_lds_dwordx4 %1, off offset:48\n\t"
+        "s_add_u32 m0, %3, 0xfc0\n\t"
         "s_nop 0\n\t"
-        "global_load_lds_dwordx4 %5, off\n\t"
-        "s_add_u32 m0, %10, 0x1400\n\t"
+        "global_load_lds_dwordx4 %1, off offset:64\n\t"
+        "s_add_u32 m0, %3, 0x13b0\n\t"
         "s_nop 0\n\t"
-        "global_load_lds_dwordx4 %6, off\n\t"
-        "s_add_u32 m0, %10, 0x1800\n\t"
+        "global_load_lds_dwordx4 %1, off offset:80\n\t"
+        "s_add_u32 m0, %3, 0x17a0\n\t"
         "s_nop 0\n\t"
-        "global_load_lds_dwordx4 %7, off\n\t"
-        "s_add_u32 m0, %10, 0x1c00\n\t"
+        "global_load_lds_dwordx4 %1, off offset:96\n\t"
+        "s_add_u32 m0, %3, 0x1b90\n\t"
         "s_nop 0\n\t"
-        "global_load_lds_dwordx4 %8, off\n\t"
+        "global_load_lds_dwordx4 %1, off offset:112\n\t"
         "s_mov_b64 exec, %0"
         : "=&s"(saved)
-        : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]),
-          "v"(a[7]), "s"(mask), "s"(lds)
+        : "v"(a), "s"(mask), "s"(lds)
         : "m0", "scc", "memory");
 }
 
@@ -91,11 +91,7 @@ struct VelDma {
         const bool changed = k.i1 != cur1 || k.i2 != cur2;
         cur1 = k.i1;
         cur2 = k.i2;
-        const double *cc = vel_cell_coef(V, k);
-        const double *a[8];
-#pragma unroll
-        for (int sl = 0; sl < 8; ++sl) a[sl] = cc + 2 * sl;
-        cell_dma(a, (unsigned)(size_t)(lds_void *)buf, __ballot(changed));
+        cell_dma(vel_cell_coef(V, k), (unsigned)(size_t)(lds_void *)buf, __ballot(changed));
     }
     __device__ __forceinline__ void eval(double x1, double x2, double &c, double &c1, double &c2,
                                          double &c11, double &c12, double &c22) const
@@ -160,8 +156,12 @@ k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
         St y;
         load_state(f, cap, b, y);
         if (ckpt) store_state(ckpt + b, cap, y);
-        double s = ((id[b] / NqNp) & 1) ? -1.0 : 1.0;
-        double h2 = 0.5 * dt, h6 = dt / 6.0, h3 = dt / 3.0;
+        // H of branch - is -H of branch +, so every slope of the - branch is
+        // exactly the negative of the + branch's: the stages run the + branch
+        // with signed steps (bit-identical to signed slopes, no sign products)
+        const double s = ((id[b] / NqNp) & 1) ? -1.0 : 1.0;
+        const double sdt = s * dt;
+        const double h2 = 0.5 * sdt, h6 = sdt / 6.0, h3 = sdt / 3.0;
         double cq = 1.0;
         Cd root = {0.0, 0.0};
         if (CLOSED) {
@@ -174,10 +174,10 @@ k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
         if (nsteps > 0) vel.prefetch(y.Q1, y.Q2);
         for (int it = 0; it < nsteps; ++it) {
             St t = y, acc = y;
-            rk_stage<false, VelDma, !CLOSED>(vel, s, t, acc, y, h6, h2);
-            rk_stage<false, VelDma, !CLOSED>(vel, s, t, acc, y, h3, h2);
-            rk_stage<false, VelDma, !CLOSED>(vel, s, t, acc, y, h3, dt);
-            rk_stage<true, VelDma, !CLOSED>(vel, s, t, acc, y, h6, 0.0);
+            rk_stage<false, VelDma, !CLOSED>(vel, 1.0, t, acc, y, h6, h2);
+            rk_stage<false, VelDma, !CLOSED>(vel, 1.0, t, acc, y, h3, h2);
+            rk_stage<false, VelDma, !CLOSED>(vel, 1.0, t, acc, y, h3, sdt);
+            rk_stage<true, VelDma, !CLOSED>(vel, 1.0, t, acc, y, h6, 0.0);
             y = acc;
             if (CLOSED) root = det_root(y, root);
         }
