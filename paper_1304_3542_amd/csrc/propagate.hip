@@ -325,8 +325,9 @@ k_rk4_dd(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
         y.P1 = fma(sg, st[(size_t)(fa + 8) * cap], st[2 * cap]);
         y.P2 = fma(sg, st[(size_t)(fa + 10) * cap], st[3 * cap]);
         y.S = st[4 * cap];
-        const double s = ((id[b] / NqNp) & 1) ? -1.0 : 1.0;
-        const double h2 = 0.5 * dt, h6 = dt / 6.0, h3 = dt / 3.0;
+        // branch - runs as branch + with signed steps (as in k_rk4)
+        const double sdt = ((id[b] / NqNp) & 1) ? -dt : dt;
+        const double h2 = 0.5 * sdt, h6 = sdt / 6.0, h3 = sdt / 3.0;
         double cq, c0, d[5];
         vel_eval(V, f[b], f[cap + b], cq, d[0], d[1], d[2], d[3], d[4]);
         vel_eval(V, st[0], st[cap], c0, d[0], d[1], d[2], d[3], d[4]);
@@ -335,10 +336,10 @@ k_rk4_dd(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
         vel.prefetch(y.Q1, y.Q2);
         for (int it = 0; it < nsteps; ++it) {
             Ray t = y, acc = y;
-            ray_stage<false>(vel, s, t, acc, y, h6, h2);
-            ray_stage<false>(vel, s, t, acc, y, h3, h2);
-            ray_stage<false>(vel, s, t, acc, y, h3, dt);
-            ray_stage<true>(vel, s, t, acc, y, h6, 0.0);
+            ray_stage<false>(vel, 1.0, t, acc, y, h6, h2);
+            ray_stage<false>(vel, 1.0, t, acc, y, h3, h2);
+            ray_stage<false>(vel, 1.0, t, acc, y, h3, sdt);
+            ray_stage<true>(vel, 1.0, t, acc, y, h6, 0.0);
             y = acc;
             // exchange within the wavefront: the previous step's reads are
             // done before these writes, and these writes before the reads
