@@ -185,34 +185,62 @@ def traces(cgrid, f0, f1, grid, params, cand, receivers, rec_every, nrec, nshots
     eye = torch.eye(2, dtype=torch.complex128).expand(nb, 2, 2)
     y = (q.clone(), p.clone(), torch.zeros(nb, dtype=DT), eye.clone(), -1j * eye,
          torch.full((nb,), 2.0, dtype=torch.complex128))
-    rec = np.asarray(receivers)
-    xr = torch.as_tensor(np.stack([grid.o1 + grid.d1 * (rec % grid.n1),
-                                   grid.o2 + grid.d2 * (rec // grid.n1)], 1), dtype=DT)
-    ri1 = torch.as_tensor(rec % grid.n1)
-    ri2 = torch.as_tensor(rec // grid.n1)
-    Rw1 = math.ceil(math.sqrt(2 * params.eps * math.log(1 / params.tau_win)) / grid.d1)
-    Rw2 = math.ceil(math.sqrt(2 * params.eps * math.log(1 / params.tau_win)) / grid.d2)
     shot_t = torch.as_tensor(shot)
     out = []
     for k in range(nrec):
         for _ in range(rec_every):
             y = rk4_step(cgrid, grid, sigma, y, params.dt)
         Q, P, S, _, _, a = y
-        # truncation boxes from the current centres (held fixed: no gradient)
-        c1 = torch.floor((Q[:, 0].detach() - grid.o1) / grid.d1 + 0.5).long()
-        c2 = torch.floor((Q[:, 1].detach() - grid.o2) / grid.d2 + 0.5).long()
-        inbox = ((ri1[None, :] >= (c1 - Rw1).clamp(min=0)[:, None])
-                 & (ri1[None, :] <= (c1 + Rw1).clamp(max=grid.n1 - 1)[:, None])
-                 & (ri2[None, :] >= (c2 - Rw2).clamp(min=0)[:, None])
-                 & (ri2[None, :] <= (c2 + Rw2).clamp(max=grid.n2 - 1)[:, None]))
-        rx = xr[None, :, :] - Q[:, None, :]                          # [nb, nrec, 2]
-        phase = (S[:, None] + (P[:, None, :] * rx).sum(-1)) / params.eps
-        gauss = -(rx * rx).sum(-1) / (2 * params.eps)
-        term = (C * a)[:, None] * torch.exp(1j * phase + gauss)
-        term = torch.where(inbox, term.real, torch.zeros_like(term.real))
-        per_shot = torch.zeros((nshots, len(rec)), dtype=DT).index_add(0, shot_t, term)
-        out.append(per_shot)
+        out.append(recons_at(Q, P, S, C * a, shot_t, receivers, grid, params, nshots))
     return torch.stack(out, 1)
+
+
+def recons_at(Q, P, S, Ca, shot_t, nodes, grid, params, nshots):
+    """The recons eq. at the listed nodes (flat i2*n1 + i1): [nshots][len(nodes)],
+    each beam summed over the box of half-width Rw around the node nearest Q
+    (the boxes come from the detached centres: held fixed, no gradient).
+    Q, P: [nb][2]; S: [nb]; Ca: [nb] complex (C a)."""
+    rec = np.asarray(nodes)
+    xr = torch.as_tensor(np.stack([grid.o1 + grid.d1 * (rec % grid.n1),
+                                   grid.o2 + grid.d2 * (rec // grid.n1)], 1), dtype=DT)
+    ri1 = torch.as_tensor(rec % grid.n1)
+    ri2 = torch.as_tensor(rec // grid.n1)
+    Rw1 = math.ceil(math.sqrt(2 * params.eps * math.log(1 / params.tau_win)) / grid.d1)
+    Rw2 = math.ceil(math.sqrt(2 * params.eps * math.log(1 / params.tau_win)) / grid.d2)
+    c1 = torch.floor((Q[:, 0].detach() - grid.o1) / grid.d1 + 0.5).long()
+    c2 = torch.floor((Q[:, 1].detach() - grid.o2) / grid.d2 + 0.5).long()
+    inbox = ((ri1[None, :] >= (c1 - Rw1).clamp(min=0)[:, None])
+             & (ri1[None, :] <= (c1 + Rw1).clamp(max=grid.n1 - 1)[:, None])
+             & (ri2[None, :] >= (c2 - Rw2).clamp(min=0)[:, None])
+             & (ri2[None, :] <= (c2 + Rw2).clamp(max=grid.n2 - 1)[:, None]))
+    rx = xr[None, :, :] - Q[:, None, :]                          # [nb, nnodes, 2]
+    phase = (S[:, None] + (P[:, None, :] * rx).sum(-1)) / params.eps
+    gauss = -(rx * rx).sum(-1) / (2 * params.eps)
+    term = Ca[:, None] * torch.exp(1j * phase + gauss)
+    term = torch.where(inbox, term.real, torch.zeros_like(term.real))
+    return torch.zeros((nshots, len(rec)), dtype=DT).index_add(0, shot_t, term)
+
+
+def recons_vjp(state, coef, shot, grid, params, nshots, du):
+    """Reverse-mode derivative of the field reconstruction (recons eq. on
+    the whole grid, boxes held fixed) for J = sum du * u: returns
+    (dstate [nb][23], dcoef [nb][2]) with the cotangents of Q, P, S and
+    (Re a, Im a) in the state layout (zero for dzQ, dzP, which u does not
+    read) and of (Re C, Im C).  state: [nb][23]; coef: [nb][2];
+    du: [nshots][n2][n1]."""
+    st = torch.tensor(np.asarray(state)[:, [0, 1, 2, 3, 4, 21, 22]], dtype=DT, requires_grad=True)
+    cf = torch.tensor(np.asarray(coef), dtype=DT, requires_grad=True)
+    Q, P, S = st[:, 0:2], st[:, 2:4], st[:, 4]
+    a = torch.complex(st[:, 5], st[:, 6])
+    C = torch.complex(cf[:, 0], cf[:, 1])
+    nodes = np.arange(grid.n1 * grid.n2)
+    u = recons_at(Q, P, S, C * a, torch.as_tensor(np.asarray(shot, dtype=np.int64)), nodes,
+                  grid, params, nshots)
+    J = (u * torch.as_tensor(np.asarray(du), dtype=DT).reshape(nshots, -1)).sum()
+    gs, gc = torch.autograd.grad(J, [st, cf])
+    ds = np.zeros((len(coef), 23))
+    ds[:, [0, 1, 2, 3, 4, 21, 22]] = gs.numpy()
+    return ds, gc.numpy()
 
 
 def gradient(c, f0, f1, grid, params, cand, receivers, rec_every, nrec, data):

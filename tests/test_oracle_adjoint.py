@@ -121,3 +121,62 @@ def test_gradient_matches_finite_differences(with_f1):
         fm[s, i2, i1] -= 1e-6
         fd = (Jc(c, f0, fp) - Jc(c, f0, fm)) / 2e-6
         assert abs(fd - df1[s, i2, i1]) <= 1e-6 * np.abs(df1).max()
+
+
+def _propagated_case():
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(True)
+    b = oracle.decompose(f0, f1, c, g, p)
+    oracle.propagate(b, c, g, p.dt, p.nsteps)
+    return g, p, c, b, f0.shape[0]
+
+
+def _field_J(b, g, p, ns, du):
+    return sum(float((oracle.reconstruct(b, g, p, shot=s) * du[s]).sum()) for s in range(ns))
+
+
+def test_recons_oracle_matches_c_oracle_field():
+    """The torch windowed sum at every node (recons_at) equals the C oracle's
+    field reconstruction (recons eq.)."""
+    import torch
+    g, p, c, b, ns = _propagated_case()
+    st = torch.tensor(b.state)
+    Ca = torch.tensor(b.coef[:, 0] + 1j * b.coef[:, 1]) * torch.complex(st[:, 21], st[:, 22])
+    u = oadj.recons_at(st[:, 0:2], st[:, 2:4], st[:, 4], Ca, torch.as_tensor(b.shot.astype(np.int64)),
+                       np.arange(g.n1 * g.n2), g, p, ns).numpy().reshape(ns, g.n2, g.n1)
+    for s in range(ns):
+        ref = oracle.reconstruct(b, g, p, shot=s)
+        assert np.abs(ref).max() > 1e-3
+        np.testing.assert_allclose(u[s], ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_recons_vjp_matches_finite_differences_and_is_bilinear_in_C():
+    """dJ/d(Q, P, S, a, C) of J = sum du u from recons_vjp against central
+    differences of the C oracle's reconstruction for seeded beams and every
+    component (boxes unchanged by the small steps), and <u(C = v), du> =
+    <v, dJ/dC> exactly (u is linear in C)."""
+    g, p, c, b, ns = _propagated_case()
+    r = fi.rng(61)
+    du = r.standard_normal((ns, g.n2, g.n1))
+    ds, dcf = oadj.recons_vjp(b.state, b.coef, b.shot, g, p, ns, du)
+    assert np.all(ds[:, 5:21] == 0)
+    for bi in r.choice(b.n, 6, replace=False):
+        for comp in (0, 1, 2, 3, 4, 21, 22, "C0", "C1"):
+            arr, j = (b.coef, int(comp[1])) if isinstance(comp, str) else (b.state, comp)
+            x0 = arr[bi, j]
+            h = 1e-6 * max(abs(x0), 1e-3 if isinstance(comp, str) else 1.0)
+            if isinstance(comp, str):
+                h = 1e-6 * np.abs(b.coef).max()
+            arr[bi, j] = x0 + h
+            jp = _field_J(b, g, p, ns, du)
+            arr[bi, j] = x0 - h
+            jm = _field_J(b, g, p, ns, du)
+            arr[bi, j] = x0
+            fd = (jp - jm) / (2 * h)
+            got = dcf[bi, j] if isinstance(comp, str) else ds[bi, j]
+            scale = np.abs(dcf).max() if isinstance(comp, str) else np.abs(ds[:, j]).max()
+            assert abs(fd - got) <= 1e-6 * scale, (bi, comp, fd, got, scale)
+    v = r.standard_normal(b.coef.shape)
+    bv = oracle.Beams(b.shot, b.sigma, b.cand, b.psi, v, b.state, b.offsets)
+    lhs = _field_J(bv, g, p, ns, du)
+    rhs = float((v * dcf).sum())
+    assert abs(lhs - rhs) <= 1e-12 * np.abs(v).sum() * np.abs(dcf).max() + 1e-12 * abs(lhs)
