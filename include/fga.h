@@ -17,7 +17,11 @@
  *   fga_trace        step 3 at receiver nodes at every rec_every-th step;
  *   fga_trace_adjoint, fga_decompose_adjoint
  *                    the gradient of a receiver misfit with respect to the
- *                    velocity samples and the initial wavefield.
+ *                    velocity samples and the initial wavefield;
+ *   fga_reconstruct_adjoint, fga_propagate_ckpt, fga_propagate_adjoint
+ *                    the same for a misfit of the whole field u(T): the
+ *                    transposes of step 3 and step 2, chained with
+ *                    fga_decompose_adjoint.
  *
  * Conventions shared by every entry point
  *   - All pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
@@ -198,6 +202,38 @@ fga_status fga_trace_adjoint(fga_ctx *ctx, const fga_beams *beams, int32_t nshot
                              const int32_t *rec_dev, int32_t nrec, int32_t rec_every,
                              int32_t nrec_t, const double *ckpt_dev, const double *gtr_dev,
                              double *dc_dev, double *gcoef_dev);
+
+/* Adjoint of fga_reconstruct for a misfit J(u) of the field: from
+ * du_dev = dJ/du [nshots][n2][n1] to the cotangents of every beam's current
+ * state and coefficient, through the recons eq. with every truncation box
+ * held fixed (FP64 in both precision modes; the boxes are those of the
+ * context's tau_win, as in the forward call).
+ *   dstate_dev [FGA_NSTATE][capacity], overwritten for the beams in offsets:
+ *              dJ/dQ1, dQ2, dP1, dP2, dS, zeros for dzQ and dzP (u does not
+ *              read them), dJ/d(Re a), dJ/d(Im a)
+ *   dcoef_dev  [2][capacity]: dJ/d(Re C, Im C), overwritten
+ * The beams are read, not changed.                                         */
+fga_status fga_reconstruct_adjoint(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
+                                   const double *du_dev, double *dstate_dev, double *dcoef_dev);
+
+/* Propagation that keeps checkpoints for fga_propagate_adjoint: nseg
+ * segments of seg RK4 steps each (as nseg calls of fga_propagate), the state
+ * at the start of segment k written to ckpt_dev[k][FGA_NSTATE][capacity].  */
+fga_status fga_propagate_ckpt(fga_ctx *ctx, fga_beams *beams, int32_t nshots, int32_t seg,
+                              int32_t nseg, double *ckpt_dev);
+
+/* Adjoint of fga_propagate_ckpt: the cotangent of the state after the
+ * nseg*seg steps (dstate_dev [FGA_NSTATE][capacity] on entry, e.g. from
+ * fga_reconstruct_adjoint) is pulled back through the RK4 of the ray,
+ * dynamic ray tracing and amplitude equations to the cotangent of the state
+ * before them (dstate_dev on return); dJ/dc through the velocity in every
+ * step is ADDED to dc_dev [n2][n1] (device atomics: rounding order not
+ * fixed).  ckpt_dev as written by the forward call.  Requires amp_closed = 0
+ * (hence dz_divided = 0).  Scratch of seg * 23 doubles per beam capacity is
+ * held by the context.                                                     */
+fga_status fga_propagate_adjoint(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
+                                 int32_t seg, int32_t nseg, const double *ckpt_dev,
+                                 double *dstate_dev, double *dc_dev);
 
 /* Adjoint of fga_decompose for the beams it kept (the threshold set is held
  * fixed): from dJ/dC (gcoef_dev, [2][capacity]) to dJ/df0 (df0_dev

@@ -76,6 +76,9 @@ def load(path: str = LIB_PATH):
         "fga_trace": [C, ctypes.POINTER(fga_beams), I32, P, I32, I32, I32, P, P],
         "fga_trace_adjoint": [C, ctypes.POINTER(fga_beams), I32, P, I32, I32, I32, P, P, P, P],
         "fga_decompose_adjoint": [C, ctypes.POINTER(fga_beams), I32, P, P, P, P],
+        "fga_reconstruct_adjoint": [C, ctypes.POINTER(fga_beams), I32, P, P, P],
+        "fga_propagate_ckpt": [C, ctypes.POINTER(fga_beams), I32, I32, I32, P],
+        "fga_propagate_adjoint": [C, ctypes.POINTER(fga_beams), I32, I32, I32, P, P, P],
         "fga_graph_capture": [C, I32, P, P, ctypes.POINTER(fga_beams), I32, P],
         "fga_graph_launch": [C],
         "fga_autotune": [C, ctypes.POINTER(fga_beams), I32, P, ctypes.c_char_p,
@@ -176,6 +179,27 @@ def fga_decompose_adjoint(ctx, beams: "Beams", nshots: int, gcoef, df0, df1=None
         _require(t, n, "float64")
     _check(ctx, load().fga_decompose_adjoint(ctx, beams.c_struct(), int(nshots), _ptr(gcoef),
                                              _ptr(df0), _ptr(df1), _ptr(dc)))
+
+
+def fga_reconstruct_adjoint(ctx, beams: "Beams", nshots: int, du, dstate, dcoef):
+    for t, n in ((du, "du"), (dstate, "dstate"), (dcoef, "dcoef")):
+        _require(t, n, "float64")
+    _check(ctx, load().fga_reconstruct_adjoint(ctx, beams.c_struct(), int(nshots), _ptr(du),
+                                               _ptr(dstate), _ptr(dcoef)))
+
+
+def fga_propagate_ckpt(ctx, beams: "Beams", nshots: int, seg: int, nseg: int, ckpt):
+    _require(ckpt, "ckpt", "float64")
+    _check(ctx, load().fga_propagate_ckpt(ctx, beams.c_struct(), int(nshots), int(seg), int(nseg),
+                                          _ptr(ckpt)))
+
+
+def fga_propagate_adjoint(ctx, beams: "Beams", nshots: int, seg: int, nseg: int, ckpt, dstate,
+                          dc):
+    for t, n in ((ckpt, "ckpt"), (dstate, "dstate"), (dc, "dc")):
+        _require(t, n, "float64")
+    _check(ctx, load().fga_propagate_adjoint(ctx, beams.c_struct(), int(nshots), int(seg),
+                                             int(nseg), _ptr(ckpt), _ptr(dstate), _ptr(dc)))
 
 
 def fga_graph_capture(ctx, nshots: int, f0, f1, beams: "Beams", nsteps: int, u):
@@ -306,6 +330,27 @@ class FGA:
                           device=beams.f.device)
         fga_decompose_adjoint(self.ctx, beams, nshots, gcoef, df0, df1, dc)
         return df0
+
+    def reconstruct_adjoint(self, beams: Beams, nshots: int, du):
+        """(dstate [FGA_NSTATE][capacity], dcoef [2][capacity]) for dJ/du."""
+        import torch
+        dstate = torch.zeros((FGA_NSTATE, beams.capacity), dtype=torch.float64,
+                             device=beams.f.device)
+        dcoef = torch.zeros((2, beams.capacity), dtype=torch.float64, device=beams.f.device)
+        fga_reconstruct_adjoint(self.ctx, beams, nshots, du, dstate, dcoef)
+        return dstate, dcoef
+
+    def propagate_ckpt(self, beams: Beams, nshots: int, seg: int, nseg: int, ckpt=None):
+        import torch
+        if ckpt is None:
+            ckpt = torch.empty((nseg, FGA_NSTATE, beams.capacity), dtype=torch.float64,
+                               device=beams.f.device)
+        fga_propagate_ckpt(self.ctx, beams, nshots, seg, nseg, ckpt)
+        return ckpt
+
+    def propagate_adjoint(self, beams: Beams, nshots: int, seg: int, nseg: int, ckpt, dstate, dc):
+        fga_propagate_adjoint(self.ctx, beams, nshots, seg, nseg, ckpt, dstate, dc)
+        return dstate
 
     def graph_capture(self, f0, f1, beams: Beams, nsteps: int, u):
         fga_graph_capture(self.ctx, f0.shape[0], f0, f1, beams, nsteps, u)

@@ -408,7 +408,9 @@ struct TraceAdjArgs {
     const double *gtr;        // [nshots][nrec_t][nrec]
     double *scratch;          // [rec_every][NSTATE][cap]
     double *dc;               // [n2][n1]
-    double *gcoef;            // [2][cap]
+    double *gcoef;            // [2][cap] (may be null)
+    const double *lam0;       // [NSTATE][cap]: cotangent of the final state (may be null)
+    double *lam_out;          // [NSTATE][cap]: cotangent of the initial state (may be null)
     int n1, n2;
     double o1, o2, d1, d2, eps, dt;
     int Rw1, Rw2;
@@ -430,6 +432,7 @@ k_trace_adjoint(TraceAdjArgs A)
         const Cd C = {A.f[4 * cap + b], A.f[5 * cap + b]};
         St lam;
         st_zero(lam);
+        if (A.lam0) load_state_raw(A.lam0, cap, b, lam);
         Cd gC = {0.0, 0.0};
         DcAcc dacc;
         dcacc_init(dacc);
@@ -447,7 +450,7 @@ k_trace_adjoint(TraceAdjArgs A)
                 y = acc;
             }
             // cotangent of the traces of record k (boxes held fixed)
-            const double *R = A.gtr + ((size_t)shot * A.nrec_t + k) * A.nrec;
+            const double *R = A.nrec > 0 ? A.gtr + ((size_t)shot * A.nrec_t + k) * A.nrec : A.gtr;
             BeamBox bx = beam_box(y.Q1, y.Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
             for (int r = 0; r < A.nrec; ++r) {
                 int node = A.rec[r];
@@ -479,8 +482,11 @@ k_trace_adjoint(TraceAdjArgs A)
             }
         }
         dcacc_flush(dacc, A.dc, A.n1, A.n2);
-        A.gcoef[b] = gC.r;
-        A.gcoef[cap + b] = gC.i;
+        if (A.gcoef) {
+            A.gcoef[b] = gC.r;
+            A.gcoef[cap + b] = gC.i;
+        }
+        if (A.lam_out) store_state(A.lam_out + b, cap, lam);
     }
 }
 
@@ -488,6 +494,19 @@ fga_status fga_launch_trace_adjoint(fga_ctx *ctx, const fga_beams *beams, int ns
                                     const int32_t *rec, int nrec, int rec_every, int nrec_t,
                                     const double *ckpt, const double *gtr, double *dc,
                                     double *gcoef)
+{
+    return fga_launch_rk4_adjoint(ctx, beams, nshots, rec, nrec, rec_every, nrec_t, ckpt, gtr, dc,
+                                  gcoef, nullptr, nullptr);
+}
+
+// The pull-back through nseg segments of seg RK4 steps (the checkpoints hold
+// the states at the segment starts), with the receiver cotangents of every
+// record (nrec > 0) and/or an initial cotangent lam0 of the final state;
+// lam_out receives the cotangent of the initial state.
+fga_status fga_launch_rk4_adjoint(fga_ctx *ctx, const fga_beams *beams, int nshots,
+                                  const int32_t *rec, int nrec, int rec_every, int nrec_t,
+                                  const double *ckpt, const double *gtr, double *dc,
+                                  double *gcoef, const double *lam0, double *lam_out)
 {
     size_t need = (size_t)rec_every * FGA_NSTATE * beams->capacity * sizeof(double);
     fga_status rc = fga_ensure(ctx, &ctx->adj_scratch, &ctx->adj_scratch_bytes, need,
@@ -510,6 +529,8 @@ fga_status fga_launch_trace_adjoint(fga_ctx *ctx, const fga_beams *beams, int ns
     A.scratch = (double *)ctx->adj_scratch;
     A.dc = dc;
     A.gcoef = gcoef;
+    A.lam0 = lam0;
+    A.lam_out = lam_out;
     A.n1 = ctx->g.n1;
     A.n2 = ctx->g.n2;
     A.o1 = ctx->g.o1;
@@ -521,6 +542,133 @@ fga_status fga_launch_trace_adjoint(fga_ctx *ctx, const fga_beams *beams, int ns
     A.Rw1 = ctx->Rw1;
     A.Rw2 = ctx->Rw2;
     hipLaunchKernelGGL(k_trace_adjoint, dim3(ctx->num_cu * 4), dim3(ADJ_BLOCK), 0, ctx->stream, A);
+    FGA_HIP(ctx, hipGetLastError());
+    return FGA_OK;
+}
+
+// ------------------------------------------------------ reconstruction adjoint
+//
+// dJ/d(beam) for J = sum_x du(x) u(x), u the recons eq. over the truncation
+// boxes (held fixed).  With r = x - Q, the term of a beam is
+//   E(x) = C a e^{iS/eps} g1(x1) g2(x2),  g_k = e^{i P_k r_k / eps - r_k^2 / (2 eps)},
+// so every derivative of Re E summed against du needs only the three sums
+//   F = sum du g1 g2,  F1 = sum du g1 r1 g2,  F2 = sum du g1 g2 r2,
+// taken as column sums: a lane owns one x1 of the box and runs down the rows
+// (coalesced du loads), g2 and g2 r2 of 256 rows at a time sit in LDS.  Then
+// with W = C a e^{iS/eps}:
+//   dQ_k = (P_k Im(W F) + Re(W F_k)) / eps,  dP_k = -Im(W F_k) / eps,
+//   dS = -Im(W F) / eps,  d(Re a, Im a) = (Re X, -Im X) with X = C e^{iS/eps} F,
+//   d(Re C, Im C) = (Re Y, -Im Y) with Y = a e^{iS/eps} F.
+// One wavefront per beam; FP64.
+#define RA_ROWS 256
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(256)
+k_reconstruct_adjoint(const double *__restrict__ f, const int64_t *__restrict__ id,
+                      const int64_t *__restrict__ offsets, int nshots, int64_t cap, int64_t NqNp,
+                      const double *__restrict__ du, int n1, int n2, double o1, double o2,
+                      double d1, double d2, double eps, int Rw1, int Rw2,
+                      double *__restrict__ dstate, double *__restrict__ dcoef)
+{
+    __shared__ double2 gv[4][RA_ROWS], gr[4][RA_ROWS];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double2 *V = gv[wave], *Vr = gr[wave];
+    const int64_t nb = offsets[nshots];
+    const double inv_eps = 1.0 / eps, h_inv_eps = 0.5 / eps;
+    for (int64_t b = (int64_t)blockIdx.x * 4 + wave; b < nb; b += (int64_t)gridDim.x * 4) {
+        const double *st = f + (size_t)FGA_F_STATE * cap + b;
+        const double Q1 = st[0], Q2 = st[cap], P1 = st[2 * cap], P2 = st[3 * cap];
+        const double S = st[4 * cap];
+        const Cd a = {st[21 * cap], st[22 * cap]};
+        const Cd C = {f[4 * cap + b], f[5 * cap + b]};
+        const int shot = (int)(id[b] / (2 * NqNp));
+        const double *dus = du + (size_t)shot * n1 * n2;
+        const BeamBox bx = beam_box(Q1, Q2, o1, o2, d1, d2, Rw1, Rw2, n1, n2);
+        Cd F = {0.0, 0.0}, F1 = {0.0, 0.0}, F2 = {0.0, 0.0};
+        for (int c0 = bx.lo1; c0 <= bx.hi1; c0 += 64) {
+            const int x1 = c0 + lane;
+            const bool in1 = x1 <= bx.hi1;
+            const double r1 = (o1 + x1 * d1) - Q1;
+            double sn, cs;
+            sincos(P1 * r1 * inv_eps, &sn, &cs);
+            const double e1 = exp(-r1 * r1 * h_inv_eps);
+            const Cd g1 = {e1 * cs, e1 * sn};
+            Cd col = {0.0, 0.0}, colr = {0.0, 0.0};
+            for (int r0 = bx.lo2; r0 <= bx.hi2; r0 += RA_ROWS) {
+                const int nr = min(RA_ROWS, bx.hi2 - r0 + 1);
+                __builtin_amdgcn_wave_barrier();
+                for (int i = lane; i < nr; i += 64) {
+                    const double r2 = (o2 + (r0 + i) * d2) - Q2;
+                    double s2, c2;
+                    sincos(P2 * r2 * inv_eps, &s2, &c2);
+                    const double e2 = exp(-r2 * r2 * h_inv_eps);
+                    V[i] = double2{e2 * c2, e2 * s2};
+                    Vr[i] = double2{e2 * c2 * r2, e2 * s2 * r2};
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (in1) {
+                    const double *p = dus + (size_t)r0 * n1 + x1;
+#pragma unroll 4
+                    for (int i = 0; i < nr; ++i) {
+                        const double d = p[(size_t)i * n1];
+                        const double2 v = V[i], w = Vr[i];
+                        col.r = fma(v.x, d, col.r);
+                        col.i = fma(v.y, d, col.i);
+                        colr.r = fma(w.x, d, colr.r);
+                        colr.i = fma(w.y, d, colr.i);
+                    }
+                }
+            }
+            if (in1) {
+                const Cd t = cmul(g1, col);
+                F = cadd(F, t);
+                F1 = cadd(F1, cscale(t, r1));
+                F2 = cadd(F2, cmul(g1, colr));
+            }
+        }
+        F = {wave_sum(F.r), wave_sum(F.i)};
+        F1 = {wave_sum(F1.r), wave_sum(F1.i)};
+        F2 = {wave_sum(F2.r), wave_sum(F2.i)};
+        if (lane == 0) {
+            double sn, cs;
+            sincos(S * inv_eps, &sn, &cs);
+            const Cd H = {cs, sn};
+            const Cd W = cmul(cmul(C, a), H);
+            const Cd E = cmul(W, F), E1 = cmul(W, F1), E2 = cmul(W, F2);
+            const Cd X = cmul(cmul(C, H), F), Y = cmul(cmul(a, H), F);
+            double *o = dstate + b;
+            o[0] = (P1 * E.i + E1.r) * inv_eps;
+            o[cap] = (P2 * E.i + E2.r) * inv_eps;
+            o[2 * cap] = -E1.i * inv_eps;
+            o[3 * cap] = -E2.i * inv_eps;
+            o[4 * cap] = -E.i * inv_eps;
+            for (int k = 5; k < 21; ++k) o[(size_t)k * cap] = 0.0;
+            o[21 * cap] = X.r;
+            o[22 * cap] = -X.i;
+            dcoef[b] = Y.r;
+            dcoef[cap + b] = -Y.i;
+        }
+    }
+}
+
+fga_status fga_launch_reconstruct_adjoint(fga_ctx *ctx, const fga_beams *beams, int nshots,
+                                          const double *du, double *dstate, double *dcoef)
+{
+    const int64_t NqNp = (int64_t)ctx->p.nq1 * ctx->p.nq2 * ctx->p.np1 * ctx->p.np2;
+    const fga_grid &g = ctx->g;
+    hipLaunchKernelGGL(k_reconstruct_adjoint, dim3(ctx->num_cu * 8), dim3(256), 0, ctx->stream,
+                       beams->f, beams->id, beams->offsets, nshots, beams->capacity, NqNp, du,
+                       g.n1, g.n2, g.o1, g.o2, g.d1, g.d2, ctx->p.eps, ctx->Rw1, ctx->Rw2,
+                       dstate, dcoef);
     FGA_HIP(ctx, hipGetLastError());
     return FGA_OK;
 }

@@ -319,6 +319,57 @@ extern "C" fga_status fga_trace_adjoint(fga_ctx *ctx, const fga_beams *beams, in
                                     dc, gcoef);
 }
 
+extern "C" fga_status fga_propagate_ckpt(fga_ctx *ctx, fga_beams *beams, int32_t nshots,
+                                         int32_t seg, int32_t nseg, double *ckpt)
+{
+    if (!ctx) return FGA_EINVAL;
+    fga_status st = check_beams(ctx, beams);
+    if (st != FGA_OK) return st;
+    if (nshots < 1 || nshots > ctx->max_shots)
+        return fga_fail(ctx, FGA_EINVAL, "nshots %d outside [1, %d]", nshots, ctx->max_shots);
+    if (seg < 1 || nseg < 1 || !ckpt)
+        return fga_fail(ctx, FGA_EINVAL, "bad checkpoint arguments");
+    if (!ctx->have_c) return fga_fail(ctx, FGA_ESTATE, "fga_set_velocity was not called");
+    for (int k = 0; k < nseg; ++k) {
+        st = fga_launch_propagate(ctx, beams, nshots, seg,
+                                  ckpt + (size_t)k * FGA_NSTATE * beams->capacity);
+        if (st != FGA_OK) return st;
+    }
+    return FGA_OK;
+}
+
+extern "C" fga_status fga_propagate_adjoint(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
+                                            int32_t seg, int32_t nseg, const double *ckpt,
+                                            double *dstate, double *dc)
+{
+    if (!ctx) return FGA_EINVAL;
+    fga_status st = check_beams(ctx, beams);
+    if (st != FGA_OK) return st;
+    if (nshots < 1 || nshots > ctx->max_shots)
+        return fga_fail(ctx, FGA_EINVAL, "nshots %d outside [1, %d]", nshots, ctx->max_shots);
+    if (seg < 1 || nseg < 1 || !ckpt || !dstate || !dc)
+        return fga_fail(ctx, FGA_EINVAL, "bad propagate-adjoint arguments");
+    if (ctx->p.amp_closed)
+        return fga_fail(ctx, FGA_EINVAL, "the propagation adjoint needs the integrated amplitude");
+    if (!ctx->have_c) return fga_fail(ctx, FGA_ESTATE, "fga_set_velocity was not called");
+    return fga_launch_rk4_adjoint(ctx, beams, nshots, nullptr, 0, seg, nseg, ckpt, nullptr, dc,
+                                  nullptr, dstate, dstate);
+}
+
+extern "C" fga_status fga_reconstruct_adjoint(fga_ctx *ctx, const fga_beams *beams,
+                                              int32_t nshots, const double *du, double *dstate,
+                                              double *dcoef)
+{
+    if (!ctx) return FGA_EINVAL;
+    fga_status st = check_beams(ctx, beams);
+    if (st != FGA_OK) return st;
+    if (nshots < 1 || nshots > ctx->max_shots)
+        return fga_fail(ctx, FGA_EINVAL, "nshots %d outside [1, %d]", nshots, ctx->max_shots);
+    if (!du || !dstate || !dcoef)
+        return fga_fail(ctx, FGA_EINVAL, "du, dstate and dcoef must be non-null");
+    return fga_launch_reconstruct_adjoint(ctx, beams, nshots, du, dstate, dcoef);
+}
+
 extern "C" fga_status fga_decompose_adjoint(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
                                             const double *gcoef, double *df0, double *df1,
                                             double *dc)

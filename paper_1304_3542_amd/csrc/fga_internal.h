@@ -96,6 +96,12 @@ fga_status fga_launch_trace_adjoint(fga_ctx *ctx, const fga_beams *beams, int ns
                                     const int32_t *rec, int nrec, int rec_every, int nrec_t,
                                     const double *ckpt, const double *gtr, double *dc,
                                     double *gcoef);
+fga_status fga_launch_rk4_adjoint(fga_ctx *ctx, const fga_beams *beams, int nshots,
+                                  const int32_t *rec, int nrec, int rec_every, int nrec_t,
+                                  const double *ckpt, const double *gtr, double *dc,
+                                  double *gcoef, const double *lam0, double *lam_out);
+fga_status fga_launch_reconstruct_adjoint(fga_ctx *ctx, const fga_beams *beams, int nshots,
+                                          const double *du, double *dstate, double *dcoef);
 fga_status fga_launch_decompose_adjoint(fga_ctx *ctx, const fga_beams *beams, int nshots,
                                         const double *gcoef, double *df0, double *df1,
                                         double *dc);

@@ -1,0 +1,180 @@
+"""The adjoint for a misfit of the whole field u(T), through the C ABI:
+fga_reconstruct_adjoint (the recons eq. transposed) against the gradient
+oracle's reverse-mode derivative and by a dot product, and the chain
+fga_propagate_ckpt -> fga_reconstruct -> fga_reconstruct_adjoint ->
+fga_propagate_adjoint -> fga_decompose_adjoint against the gradient oracle
+(every grid node a receiver) and against fga_trace_adjoint of the same
+misfit."""
+import numpy as np
+import pytest
+
+import fga_inputs as fi
+import oracle
+import oracle.adjoint as oadj
+from test_oracle_adjoint import adjoint_case, c_oracle_traces
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_max(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _ctx(g, p, c, ns, precision="fp64"):
+    import torch
+    import paper_1304_3542_amd as fga
+    ctx = fga.FGA(g, p, precision, max_shots=ns)
+    ctx.set_velocity(torch.from_numpy(c).cuda())
+    beams = fga.Beams(2 * p.nq1 * p.nq2 * p.np1 * p.np2 * ns, ns)
+    return ctx, beams
+
+
+def test_reconstruct_adjoint_matches_oracle():
+    import torch
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(True)
+    ns = f0.shape[0]
+    ctx, beams = _ctx(g, p, c, ns)
+    ctx.decompose(torch.from_numpy(f0).cuda(), torch.from_numpy(f1).cuda(), beams)
+    ctx.propagate(beams, ns, p.nsteps)
+    nb = int(ctx.offsets(beams, ns)[-1])
+    du = fi.rng(71).standard_normal((ns, g.n2, g.n1))
+    dstate, dcoef = ctx.reconstruct_adjoint(beams, ns, torch.from_numpy(du).cuda())
+    assert ctx.status()[0] == 0
+    f = beams.f[:, :nb].cpu().numpy()
+    ids = beams.id[:nb].cpu().numpy()
+    NqNp = p.nq1 * p.nq2 * p.np1 * p.np2
+    ds, dcf = oadj.recons_vjp(f[6:].T, f[4:6].T, ids // (2 * NqNp), g, p, ns, du)
+    got = dstate[:, :nb].cpu().numpy().T
+    for k in (0, 1, 2, 3, 4, 21, 22):
+        assert rel_max(got[:, k], ds[:, k]) <= 1e-10, k
+    assert np.all(got[:, 5:21] == 0)
+    assert rel_max(dcoef[:, :nb].cpu().numpy().T, dcf) <= 1e-10
+
+
+def test_reconstruct_adjoint_dot_product_in_coefficients():
+    """<R v, w> = <v, R^T w> for R: C -> u (fixed states) at random v, w."""
+    import torch
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(False)
+    ns = f0.shape[0]
+    ctx, beams = _ctx(g, p, c, ns)
+    ctx.decompose(torch.from_numpy(f0).cuda(), None, beams)
+    ctx.propagate(beams, ns, p.nsteps)
+    nb = int(ctx.offsets(beams, ns)[-1])
+    r = np.random.default_rng(72)
+    v = r.standard_normal((2, nb))
+    beams.f[4:6, :nb] = torch.from_numpy(v).cuda()
+    u = ctx.reconstruct(beams, ns).cpu().numpy()
+    w = r.standard_normal(u.shape)
+    _, dcoef = ctx.reconstruct_adjoint(beams, ns, torch.from_numpy(w).cuda())
+    lhs = float((u * w).sum())
+    rhs = float((v * dcoef[:, :nb].cpu().numpy()).sum())
+    norm = np.linalg.norm(u) * np.linalg.norm(w)
+    assert abs(lhs) > 1e-4 * norm
+    assert abs(lhs - rhs) <= 1e-13 * norm, (lhs, rhs, norm)
+
+
+def _field_chain(g, p, c, f0, f1, d, seg, nseg):
+    import torch
+    ns = f0.shape[0]
+    ctx, beams = _ctx(g, p, c, ns)
+    f1t = None if f1 is None else torch.from_numpy(f1).cuda()
+    ctx.decompose(torch.from_numpy(f0).cuda(), f1t, beams)
+    ckpt = ctx.propagate_ckpt(beams, ns, seg, nseg)
+    u = ctx.reconstruct(beams, ns)
+    du = (u - torch.from_numpy(d).cuda()).contiguous()
+    dstate, dcoef = ctx.reconstruct_adjoint(beams, ns, du)
+    dc = torch.zeros((g.n2, g.n1), dtype=torch.float64, device="cuda")
+    ctx.propagate_adjoint(beams, ns, seg, nseg, ckpt, dstate, dc)
+    df1 = None if f1 is None else torch.empty_like(f1t)
+    df0 = ctx.decompose_adjoint(beams, ns, dcoef, df1, dc if f1 is not None else None)
+    assert ctx.status()[0] == 0
+    nb = int(ctx.offsets(beams, ns)[-1])
+    return dict(ids=beams.id[:nb].cpu().numpy(), u=u.cpu().numpy(), dc=dc.cpu().numpy(),
+                df0=df0.cpu().numpy(), df1=None if df1 is None else df1.cpu().numpy(),
+                lam0=dstate[:, :nb].cpu().numpy(), ctx=ctx, beams=beams)
+
+
+@pytest.mark.parametrize("with_f1", [False, True])
+def test_field_gradient_chain_matches_oracle(with_f1):
+    """J = 1/2 |u(T) - d|^2 over the grid: dJ/dc, dJ/df0 (and dJ/df1) of the
+    chained entry points equal the gradient oracle's with every node a
+    receiver and one record at T (15 steps in 3 checkpoint segments)."""
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(with_f1)
+    ns = f0.shape[0]
+    b = oracle.decompose(f0, f1, c, g, p)
+    nodes = np.arange(g.n1 * g.n2, dtype=np.int32)
+    d = 0.5 * c_oracle_traces(c * 1.02, f0, f1, g, p, b.cand, nodes, p.nsteps, 1)
+    J, dc, df0, df1, tr = oadj.gradient(c, f0, f1, g, p, b.cand, nodes, p.nsteps, 1, d)
+    r = _field_chain(g, p, c, f0, f1, d.reshape(ns, g.n2, g.n1), 5, 3)
+    np.testing.assert_array_equal(r["ids"], b.cand)
+    assert rel_max(r["u"].reshape(ns, 1, -1), tr) <= 1e-10
+    assert rel_max(r["dc"], dc) <= 1e-10, rel_max(r["dc"], dc)
+    assert rel_max(r["df0"], df0) <= 1e-10
+    if with_f1:
+        assert rel_max(r["df1"], df1) <= 1e-10
+
+
+def test_field_chain_equals_trace_adjoint_with_every_node():
+    """The same misfit through fga_trace_adjoint (every node a receiver, one
+    record, one segment of 15 steps) gives the same dJ/dc and dJ/dC as the
+    chain with three checkpoint segments."""
+    import torch
+    import paper_1304_3542_amd as fga
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(False)
+    ns = f0.shape[0]
+    d = fi.rng(73).standard_normal((ns, g.n2, g.n1)) * 1e-3
+    r = _field_chain(g, p, c, f0, None, d, 5, 3)
+    ctx, beams = _ctx(g, p, c, ns)
+    ctx.decompose(torch.from_numpy(f0).cuda(), None, beams)
+    nodes = torch.arange(g.n1 * g.n2, dtype=torch.int32, device="cuda")
+    ckpt = torch.empty((1, fga.FGA_NSTATE, beams.capacity), dtype=torch.float64, device="cuda")
+    tr = ctx.trace(beams, ns, nodes, p.nsteps, 1, ckpt)
+    gtr = (tr - torch.from_numpy(d.reshape(ns, 1, -1)).cuda()).contiguous()
+    dc = torch.zeros((g.n2, g.n1), dtype=torch.float64, device="cuda")
+    gcoef = ctx.trace_adjoint(beams, ns, nodes, p.nsteps, 1, ckpt, gtr, dc)
+    df0 = ctx.decompose_adjoint(beams, ns, gcoef)
+    assert ctx.status()[0] == 0
+    assert rel_max(r["dc"], dc.cpu().numpy()) <= 1e-12
+    assert rel_max(r["df0"], df0.cpu().numpy()) <= 1e-12
+
+
+def test_propagate_adjoint_refusals():
+    import torch
+    import paper_1304_3542_amd as fga
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(False)
+    ns = f0.shape[0]
+    ctx, beams = _ctx(g, p.replace(amp_closed=1), c, ns)
+    ctx.decompose(torch.from_numpy(f0).cuda(), None, beams)
+    ckpt = ctx.propagate_ckpt(beams, ns, 5, 2)
+    ds = torch.zeros((fga.FGA_NSTATE, beams.capacity), dtype=torch.float64, device="cuda")
+    dc = torch.zeros((g.n2, g.n1), dtype=torch.float64, device="cuda")
+    with pytest.raises(fga.FGAError):
+        ctx.propagate_adjoint(beams, ns, 5, 2, ckpt, ds, dc)
+    ctx2, beams2 = _ctx(g, p, c, ns)
+    with pytest.raises(fga.FGAError):
+        ctx2.propagate_ckpt(beams2, ns, 0, 2)
+
+
+def test_reconstruct_adjoint_point512_sampled_beams():
+    """point512 (FP64 boxes, 1.2e6 beams after 250 steps): the cotangents of
+    16 seeded beams against the oracle's reverse-mode derivative of their
+    own terms (a beam's cotangents depend only on du and the beam)."""
+    import torch
+    W = fi.workload("point512", "fp64")
+    g, p = W.grid, W.params
+    ctx, _ = _ctx(g, p, W.c, 1)
+    import paper_1304_3542_amd as fga
+    beams = fga.Beams(1_500_000, 1)
+    ctx.decompose(torch.from_numpy(np.ascontiguousarray(W.f0)).cuda(), None, beams)
+    ctx.propagate(beams, 1, p.nsteps)
+    nb = int(ctx.offsets(beams, 1)[-1])
+    du = fi.rng(74).standard_normal((1, g.n2, g.n1))
+    dstate, dcoef = ctx.reconstruct_adjoint(beams, 1, torch.from_numpy(du).cuda())
+    assert ctx.status()[0] == 0 and nb > 1_000_000
+    idx = np.sort(fi.rng(75).choice(nb, 16, replace=False))
+    f = beams.f[:, idx].cpu().numpy()
+    ds, dcf = oadj.recons_vjp(f[6:].T, f[4:6].T, np.zeros(16, np.int64), g, p, 1, du)
+    got = dstate[:, idx].cpu().numpy().T
+    for k in (0, 1, 2, 3, 4, 21, 22):
+        assert rel_max(got[:, k], ds[:, k]) <= 1e-9, k
+    assert rel_max(dcoef[:, idx].cpu().numpy().T, dcf) <= 1e-9
