@@ -73,7 +73,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="point512")
     ap.add_argument("--fp64-steps", type=int, default=1,
-                    help="timed steps of the FP64 GPU path on the same input")
+                    help="timed steps of the FP64 GPU path on the same input (at least 1: "
+                         "the mixed field is checked against it)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="rough budget of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -219,10 +220,41 @@ def adjoint_iteration(steps):
     ev[1].record()
     torch.cuda.synchronize()
     st, _ = ctx.status()
-    return {"ms_per_iter": ev[0].elapsed_time(ev[1]) / steps, "nbeams": nb, "nshots": ns,
-            "status": st, "workload": "adjoint256: 256x256 on [0,2]x[0,1], eps=1/128, 8 surface "
-            "shots, 256 receivers on the top row every 10 steps, T=0.25 s, FP64 gradient "
-            "w.r.t. c and f0"}
+    out = {"ms_per_iter": ev[0].elapsed_time(ev[1]) / steps, "nbeams": nb, "nshots": ns,
+           "status": st, "workload": "adjoint256: 256x256 on [0,2]x[0,1], eps=1/128, 8 surface "
+           "shots, 256 receivers on the top row every 10 steps, T=0.25 s, FP64 gradient "
+           "w.r.t. c and f0"}
+
+    # the same gradient for a misfit of the whole field u(T): reconstruction
+    # and propagation transposed, 25 checkpoint segments of 10 steps
+    u_data = torch.zeros((ns, g.n2, g.n1), dtype=torch.float64, device="cuda")
+    ctx.set_velocity(torch.from_numpy(W.c_true).cuda())
+    ctx.decompose(f0, None, beams)
+    ctx.propagate(beams, ns, p.nsteps)
+    ctx.reconstruct(beams, ns, u_data)
+    ctx.set_velocity(c)
+    u = torch.empty_like(u_data)
+
+    def it_field():
+        ctx.decompose(f0, None, beams)
+        ctx.propagate_ckpt(beams, ns, W.rec_every, nrec_t, ckpt)
+        ctx.reconstruct(beams, ns, u)
+        dstate, dcoef = ctx.reconstruct_adjoint(beams, ns, (u - u_data).contiguous())
+        dc.zero_()
+        ctx.propagate_adjoint(beams, ns, W.rec_every, nrec_t, ckpt, dstate, dc)
+        return ctx.decompose_adjoint(beams, ns, dcoef)
+
+    it_field()
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(steps):
+        it_field()
+    ev[1].record()
+    torch.cuda.synchronize()
+    st, _ = ctx.status()
+    out["field_misfit"] = {"ms_per_iter": ev[0].elapsed_time(ev[1]) / steps, "status": st,
+                           "misfit": "1/2 |u(T) - u_data(T)|^2 over the grid"}
+    return out
 
 
 def batched_shots(steps):
@@ -481,7 +513,7 @@ def main():
 
     fp64 = Path(Wd, "fp64", min(cand, 4_000_000))
     nb64 = fp64.fit_capacity()
-    ms64, stage64, _ = time_path(fp64, args.fp64_steps, 0)
+    ms64, stage64, _ = time_path(fp64, max(1, args.fp64_steps), 0)
     u64 = fp64.u.cpu().numpy()
     rel_vs_fp64 = float(np.linalg.norm(u_mixed - u64) / np.linalg.norm(u64))
 
