@@ -85,6 +85,7 @@ class Params:
     amp_closed: int = 0  # 1: a = c(Q)/c(q) (det Z)^(1/2) instead of integrating a
     dz_divided: int = 0  # 1: dzQ, dzP from divided differences of neighbouring rays
     dz_scale: float = 1.0  # their spacing in mesh steps (1: the neighbouring mesh nodes)
+    deterministic: int = 0  # 1: gradients reduce dJ/dc in a fixed order (bit-identical runs)
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)

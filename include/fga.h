@@ -108,6 +108,13 @@ typedef struct {
  *              read when dz_divided = 1): 1 takes the neighbouring mesh
  *              nodes; smaller values take rays closer than the mesh, which
  *              approach the dynamic ray tracing values at second order
+ *   deterministic  0: the gradient entry points add dJ/dc with FP64 atomics
+ *              (rounding order not fixed); 1: every beam logs its dJ/dc
+ *              contributions in its own slots and the logs are reduced in a
+ *              fixed order (stable sort by knot cell, then by beam and
+ *              sequence; every knot sums its cells in a fixed order), so
+ *              repeated calls give bit-identical dc.  The gradient calls then
+ *              synchronise the stream once to size the reduction.
  *   tau_fbi    the FBI box B_eps has half-width ceil(sqrt(2 eps ln(1/tau_fbi))/d)
  *   tau_win    each Gaussian is summed over the box of half-width
  *              ceil(sqrt(2 eps ln(1/tau_win))/d) around the node nearest Q
@@ -123,6 +130,7 @@ typedef struct {
     int32_t amp_closed;
     int32_t dz_divided;
     double dz_scale;
+    int32_t deterministic;
 } fga_params;
 
 /* Beam storage: structure of arrays in one float64 buffer

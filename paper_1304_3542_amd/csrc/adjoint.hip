@@ -17,6 +17,8 @@
 //    given), then through the two windowed DFT passes in transpose.
 #include <math.h>
 
+#include <algorithm>
+
 #include "rk4.h"
 
 __device__ __forceinline__ Cd cconj(Cd a) { return {a.r, -a.i}; }
@@ -113,27 +115,57 @@ __device__ __forceinline__ void vel_eval3(const VelGrid &V, double x1, double x2
 struct DcAcc {
     double v[16];
     int i1, i2;   // knot base of the held sums (i1 = INT_MIN: empty)
+    int64_t b;    // the beam (slot of its log in deterministic mode)
+    int cnt;      // records logged so far
 };
 
-__device__ __forceinline__ void dcacc_init(DcAcc &a)
+// Where dJ/dc goes: added to dc with FP64 atomics, or (deterministic mode,
+// rec != null) logged in the beam's own slots as records of one knot cell's
+// 16 sums, rec[k][16][cap] and cell[k][cap] = (i2 + 4)(n1 + 8) + (i1 + 4) for
+// the k-th flush of beam b; a log longer than R only counts (the caller
+// reruns with the length found).
+struct DcOut {
+    double *dc;
+    double *rec;
+    int *cell;
+    int64_t cap;
+    int R, n1, n2;
+};
+
+__device__ __forceinline__ void dcacc_init(DcAcc &a, int64_t b = 0)
 {
 #pragma unroll
     for (int k = 0; k < 16; ++k) a.v[k] = 0.0;
     a.i1 = -2147483647 - 1;
     a.i2 = 0;
+    a.b = b;
+    a.cnt = 0;
 }
 
-__device__ __forceinline__ void dcacc_flush(DcAcc &a, double *dc, int n1, int n2)
+__device__ __forceinline__ void dcacc_flush(DcAcc &a, const DcOut &o)
 {
     if (a.i1 == -2147483647 - 1) return;
+    if (o.rec) {
+        if (a.cnt < o.R) {
+            double *r = o.rec + (size_t)a.cnt * 16 * o.cap + a.b;
 #pragma unroll
-    for (int kz = 0; kz < 4; ++kz) {
-        int r = min(max(a.i2 - 1 + kz, 0), n2 - 1);
+            for (int k = 0; k < 16; ++k) r[(size_t)k * o.cap] = a.v[k];
+            o.cell[(size_t)a.cnt * o.cap + a.b] = (a.i2 + 4) * (o.n1 + 8) + (a.i1 + 4);
+        }
+        ++a.cnt;
 #pragma unroll
-        for (int kx = 0; kx < 4; ++kx) {
-            int q = min(max(a.i1 - 1 + kx, 0), n1 - 1);
-            if (a.v[4 * kz + kx] != 0.0) atomicAdd(&dc[(size_t)r * n1 + q], a.v[4 * kz + kx]);
-            a.v[4 * kz + kx] = 0.0;
+        for (int k = 0; k < 16; ++k) a.v[k] = 0.0;
+    } else {
+#pragma unroll
+        for (int kz = 0; kz < 4; ++kz) {
+            int r = min(max(a.i2 - 1 + kz, 0), o.n2 - 1);
+#pragma unroll
+            for (int kx = 0; kx < 4; ++kx) {
+                int q = min(max(a.i1 - 1 + kx, 0), o.n1 - 1);
+                if (a.v[4 * kz + kx] != 0.0)
+                    atomicAdd(&o.dc[(size_t)r * o.n1 + q], a.v[4 * kz + kx]);
+                a.v[4 * kz + kx] = 0.0;
+            }
         }
     }
     a.i1 = -2147483647 - 1;
@@ -141,10 +173,10 @@ __device__ __forceinline__ void dcacc_flush(DcAcc &a, double *dc, int n1, int n2
 
 // acc += d(c, g1, g2, K11, K12, K22)/d(samples)^T vb at the knots of v
 __device__ __forceinline__ void scatter_dc(const Vel3 &v, const double vb[6], DcAcc &acc,
-                                           double *dc, int n1, int n2)
+                                           const DcOut &out)
 {
     if (v.i1 != acc.i1 || v.i2 != acc.i2) {
-        dcacc_flush(acc, dc, n1, n2);
+        dcacc_flush(acc, out);
         acc.i1 = v.i1;
         acc.i2 = v.i2;
     }
@@ -163,7 +195,7 @@ __device__ __forceinline__ void scatter_dc(const Vel3 &v, const double vb[6], Dc
 // of rk4.h.  The action slope is identically zero as a function of the
 // state (H is homogeneous of degree one in P), so it carries no cotangent.
 __device__ void rhs_vjp(const VelGrid &V, double s, const St &x, const St &kb, St &xb, DcAcc &dacc,
-                        double *dc, int n1, int n2)
+                        const DcOut &out)
 {
     // ---- forward quantities
     Vel3 v;
@@ -302,7 +334,7 @@ __device__ void rhs_vjp(const VelGrid &V, double s, const St &x, const St &kb, S
     xb.Q2 += cb * v.g2 + gbv[0] * v.K12 + gbv[1] * v.K22 + K11b * v.T112 + K12b * v.T122 +
              K22b * v.T222;
     const double vb[6] = {cb, gbv[0], gbv[1], K11b, K12b, K22b};
-    scatter_dc(v, vb, dacc, dc, n1, n2);
+    scatter_dc(v, vb, dacc, out);
 }
 
 __device__ __forceinline__ St st_scale(double h, const St &x)
@@ -366,7 +398,7 @@ __device__ __forceinline__ void stash_get(const double *st, int i, St &x)
 // right-hand side and of its VJP is compiled and their live ranges do not
 // pile up.
 __device__ void step_vjp(const VelGrid &V, double s, const St &y, St &lam, double dt,
-                         double *stash, DcAcc &dacc, double *dc, int n1, int n2)
+                         double *stash, DcAcc &dacc, const DcOut &out)
 {
     const double ca[3] = {0.5 * dt, 0.5 * dt, dt};   // y_{i+2} = y + ca[i] k_{i+1}
     St x = y;
@@ -389,7 +421,7 @@ __device__ void step_vjp(const VelGrid &V, double s, const St &y, St &lam, doubl
         else
             x = y;
         st_zero(xb);
-        rhs_vjp(V, s, x, kbar, xb, dacc, dc, n1, n2);
+        rhs_vjp(V, s, x, kbar, xb, dacc, out);
         yb = st_axpy(yb, 1.0, xb);
     }
     lam = yb;
@@ -407,7 +439,8 @@ struct TraceAdjArgs {
     const double *ckpt;       // [nrec_t][NSTATE][cap]
     const double *gtr;        // [nshots][nrec_t][nrec]
     double *scratch;          // [rec_every][NSTATE][cap]
-    double *dc;               // [n2][n1]
+    DcOut out;                // dJ/dc: atomics into [n2][n1], or the per-beam logs
+    int *logcnt;              // deterministic mode: [cap] log length per beam
     double *gcoef;            // [2][cap] (may be null)
     const double *lam0;       // [NSTATE][cap]: cotangent of the final state (may be null)
     double *lam_out;          // [NSTATE][cap]: cotangent of the initial state (may be null)
@@ -435,7 +468,7 @@ k_trace_adjoint(TraceAdjArgs A)
         if (A.lam0) load_state_raw(A.lam0, cap, b, lam);
         Cd gC = {0.0, 0.0};
         DcAcc dacc;
-        dcacc_init(dacc);
+        dcacc_init(dacc, b);
         for (int k = A.nrec_t - 1; k >= 0; --k) {
             // recompute the segment from its checkpoint
             St y;
@@ -478,10 +511,11 @@ k_trace_adjoint(TraceAdjArgs A)
             for (int j = A.rec_every - 1; j >= 0; --j) {
                 St yj;
                 load_state_raw(A.scratch + (size_t)j * FGA_NSTATE * cap, cap, b, yj);
-                step_vjp(A.V, s, yj, lam, A.dt, stash, dacc, A.dc, A.n1, A.n2);
+                step_vjp(A.V, s, yj, lam, A.dt, stash, dacc, A.out);
             }
         }
-        dcacc_flush(dacc, A.dc, A.n1, A.n2);
+        dcacc_flush(dacc, A.out);
+        if (A.logcnt) A.logcnt[b] = dacc.cnt;
         if (A.gcoef) {
             A.gcoef[b] = gC.r;
             A.gcoef[cap + b] = gC.i;
@@ -508,7 +542,8 @@ fga_status fga_launch_rk4_adjoint(fga_ctx *ctx, const fga_beams *beams, int nsho
                                   const double *ckpt, const double *gtr, double *dc,
                                   double *gcoef, const double *lam0, double *lam_out)
 {
-    size_t need = (size_t)rec_every * FGA_NSTATE * beams->capacity * sizeof(double);
+    const int64_t cap = beams->capacity;
+    size_t need = (size_t)rec_every * FGA_NSTATE * cap * sizeof(double);
     fga_status rc = fga_ensure(ctx, &ctx->adj_scratch, &ctx->adj_scratch_bytes, need,
                                "adjoint segment scratch");
     if (rc != FGA_OK) return rc;
@@ -518,7 +553,7 @@ fga_status fga_launch_rk4_adjoint(fga_ctx *ctx, const fga_beams *beams, int nsho
     A.id = beams->id;
     A.offsets = beams->offsets;
     A.nshots = nshots;
-    A.cap = beams->capacity;
+    A.cap = cap;
     A.NqNp = (int64_t)ctx->p.nq1 * ctx->p.nq2 * ctx->p.np1 * ctx->p.np2;
     A.rec = rec;
     A.nrec = nrec;
@@ -527,7 +562,8 @@ fga_status fga_launch_rk4_adjoint(fga_ctx *ctx, const fga_beams *beams, int nsho
     A.ckpt = ckpt;
     A.gtr = gtr;
     A.scratch = (double *)ctx->adj_scratch;
-    A.dc = dc;
+    A.out = DcOut{dc, nullptr, nullptr, cap, 0, ctx->g.n1, ctx->g.n2};
+    A.logcnt = nullptr;
     A.gcoef = gcoef;
     A.lam0 = lam0;
     A.lam_out = lam_out;
@@ -541,9 +577,45 @@ fga_status fga_launch_rk4_adjoint(fga_ctx *ctx, const fga_beams *beams, int nsho
     A.dt = ctx->p.dt;
     A.Rw1 = ctx->Rw1;
     A.Rw2 = ctx->Rw2;
-    hipLaunchKernelGGL(k_trace_adjoint, dim3(ctx->num_cu * 4), dim3(ADJ_BLOCK), 0, ctx->stream, A);
-    FGA_HIP(ctx, hipGetLastError());
-    return FGA_OK;
+    const dim3 grid(ctx->num_cu * 4), block(ADJ_BLOCK);
+    if (!ctx->p.deterministic) {
+        hipLaunchKernelGGL(k_trace_adjoint, grid, block, 0, ctx->stream, A);
+        FGA_HIP(ctx, hipGetLastError());
+        return FGA_OK;
+    }
+    // deterministic: log, check the longest log (rerun with that length if
+    // some beam ran past the slots), then reduce in a fixed order.  A rerun
+    // must start from the same initial cotangent, so an aliased lam0 is kept.
+    if (lam0 && lam0 == lam_out) {
+        rc = fga_ensure(ctx, &ctx->det_lam, &ctx->det_lam_bytes,
+                        (size_t)FGA_NSTATE * cap * sizeof(double), "initial cotangent copy");
+        if (rc != FGA_OK) return rc;
+        FGA_HIP(ctx, hipMemcpyAsync(ctx->det_lam, lam0, (size_t)FGA_NSTATE * cap * sizeof(double),
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+        A.lam0 = (const double *)ctx->det_lam;
+    }
+    const int64_t steps = (int64_t)rec_every * nrec_t;
+    int R = ctx->det_R > 0 ? ctx->det_R : (int)std::min<int64_t>(4 * steps + 1, 64);
+    int64_t st[3];
+    for (;;) {
+        const size_t rec_bytes = (size_t)R * 16 * cap * sizeof(double);
+        const size_t cell_bytes = (size_t)R * cap * sizeof(int);
+        rc = fga_ensure(ctx, &ctx->det_log, &ctx->det_log_bytes,
+                        rec_bytes + cell_bytes + (size_t)cap * sizeof(int), "dJ/dc logs");
+        if (rc != FGA_OK) return rc;
+        char *base = (char *)ctx->det_log;
+        A.out = DcOut{nullptr, (double *)base, (int *)(base + rec_bytes), cap, R, ctx->g.n1,
+                      ctx->g.n2};
+        A.logcnt = (int *)(base + rec_bytes + cell_bytes);
+        hipLaunchKernelGGL(k_trace_adjoint, grid, block, 0, ctx->stream, A);
+        FGA_HIP(ctx, hipGetLastError());
+        rc = fga_det_stats(ctx, beams, nshots, R, st);
+        if (rc != FGA_OK) return rc;
+        if (st[2] <= R) break;
+        R = (int)st[2];
+        ctx->det_R = R;
+    }
+    return fga_det_reduce(ctx, cap, R, st[0], st[1], dc);
 }
 
 // ------------------------------------------------------ reconstruction adjoint
@@ -696,7 +768,8 @@ __global__ void k_scatter_psib(const int64_t *__restrict__ id, const int64_t *__
                                int nshots, const double *__restrict__ gcoef, int64_t cap,
                                const cplxR<R> *__restrict__ Psi, const double *__restrict__ cq,
                                int nq1, int nq2, int np1, int np2, int nfj, double dp1,
-                               double dp2, double eps, double norm, double *psib, double *cqb)
+                               double dp2, double eps, double norm, double *psib, double *cqb,
+                               double *cqc)
 {
     const int64_t nb = offsets[nshots];
     const int64_t Nq = (int64_t)nq1 * nq2, Np = (int64_t)np1 * np2, NqNp = Nq * Np;
@@ -731,7 +804,10 @@ __global__ void k_scatter_psib(const int64_t *__restrict__ id, const int64_t *__
             cplxR<R> v = Psi[(size_t)(s * nfj + 1) * plane + off];
             double wr = -0.5 * sg * (double)v.im, wi = 0.5 * sg * (double)v.re;
             double rb = wr * pr + wi * pi;
-            atomicAdd(&cqb[qf], rb * (-r / cqv));
+            if (cqc)
+                cqc[b] = rb * (-r / cqv);
+            else
+                atomicAdd(&cqb[qf], rb * (-r / cqv));
         }
     }
 }
@@ -741,17 +817,45 @@ __global__ void k_cq_adjoint(VelGrid V, const double *cqb, double o1, double o2,
                              double d2, int qb1, int qb2, int qs1, int qs2, int nq1, int nq2,
                              double *dc)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nq1 * nq2) return;
-    int j1 = i % nq1, j2 = i / nq1;
-    double x1 = o1 + (qb1 + j1 * qs1) * d1, x2 = o2 + (qb2 + j2 * qs2) * d2;
-    Vel3 v;
-    vel_eval3(V, x1, x2, v);
-    double vb[6] = {cqb[i], 0, 0, 0, 0, 0};
-    DcAcc dacc;
-    dcacc_init(dacc);
-    scatter_dc(v, vb, dacc, dc, V.n1, V.n2);
-    dcacc_flush(dacc, dc, V.n1, V.n2);
+    // one thread per node, or (deterministic mode, a 1 x 1 launch) one thread
+    // walking the nodes in order, so that the additions come in a fixed order
+    const DcOut out = {dc, nullptr, nullptr, 0, 0, V.n1, V.n2};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nq1 * nq2;
+         i += gridDim.x * blockDim.x) {
+        int j1 = i % nq1, j2 = i / nq1;
+        double x1 = o1 + (qb1 + j1 * qs1) * d1, x2 = o2 + (qb2 + j2 * qs2) * d2;
+        Vel3 v;
+        vel_eval3(V, x1, x2, v);
+        double vb[6] = {cqb[i], 0, 0, 0, 0, 0};
+        DcAcc dacc;
+        dcacc_init(dacc);
+        scatter_dc(v, vb, dacc, out);
+        dcacc_flush(dacc, out);
+    }
+}
+
+// Deterministic dJ/dc(q): the per-beam contributions (cqc) summed for every q
+// node over the shots and branches in order, each over its beams in id order
+// (the beams of one (shot, branch, q) are contiguous: ids sorted ascending).
+__global__ void k_cqb_gather(const int64_t *__restrict__ id, const int64_t *__restrict__ offsets,
+                             int nshots, const double *__restrict__ cqc, int64_t Nq, int64_t Np,
+                             double *cqb)
+{
+    const int64_t qf = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (qf >= Nq) return;
+    const int64_t nb = offsets[nshots];
+    double acc = 0.0;
+    for (int s = 0; s < nshots; ++s)
+        for (int br = 0; br < 2; ++br) {
+            const int64_t lo = ((int64_t)(2 * s + br) * Nq + qf) * Np, hi = lo + Np;
+            int64_t a = 0, z = nb;   // first beam with id >= lo
+            while (a < z) {
+                const int64_t m = (a + z) >> 1;
+                if (id[m] < lo) a = m + 1; else z = m;
+            }
+            for (int64_t b = a; b < nb && id[b] < hi; ++b) acc += cqc[b];
+        }
+    cqb[qf] = acc;
 }
 
 // Transposed pass 2: Tb[sf][i2][c] = d2 sum_{j2, l2} conj(E2[l2][i2 - k2(j2)]) psib[sf][j2][l2][c]
@@ -828,6 +932,12 @@ static fga_status decompose_adjoint_impl(fga_ctx *ctx, const fga_beams *beams, i
                                (psib_elems + tb_elems + (size_t)p.nq1 * p.nq2) * sizeof(double),
                                "decomposition adjoint workspace");
     if (rc != FGA_OK) return rc;
+    const bool det = ctx->p.deterministic && nfj == 2 && dc;
+    if (det) {
+        rc = fga_ensure(ctx, &ctx->det_cqc, &ctx->det_cqc_bytes,
+                        (size_t)beams->capacity * sizeof(double), "c(q) cotangents");
+        if (rc != FGA_OK) return rc;
+    }
     double *psib = (double *)ctx->adj_psib;
     double *Tb = psib + psib_elems;
     double *cqb = Tb + tb_elems;
@@ -836,7 +946,8 @@ static fga_status decompose_adjoint_impl(fga_ctx *ctx, const fga_beams *beams, i
     hipLaunchKernelGGL(k_scatter_psib<R>, dim3(ctx->num_cu * 4), dim3(256), 0, st, beams->id,
                        beams->offsets, nshots, gcoef, beams->capacity,
                        (const cplxR<R> *)ctx->Psi, ctx->cq, p.nq1, p.nq2, p.np1, p.np2, nfj,
-                       p.dp1, p.dp2, p.eps, ctx->norm, psib, cqb);
+                       p.dp1, p.dp2, p.eps, ctx->norm, psib, cqb,
+                       det ? (double *)ctx->det_cqc : nullptr);
     hipLaunchKernelGGL(k_fbi_pass2_t<R>, dim3((unsigned)((NC + 255) / 256), g.n2, S), dim3(256),
                        0, st, psib, (const cplxR<R> *)ctx->E2, Tb, g.n2, ctx->R2, p.qb2, p.qs2,
                        p.nq2, p.np2, (int)NC, g.d2);
@@ -845,7 +956,12 @@ static fga_status decompose_adjoint_impl(fga_ctx *ctx, const fga_beams *beams, i
                        p.qs1, p.nq1, p.np1, g.d1);
     if (nfj == 2 && dc) {
         int nq = p.nq1 * p.nq2;
-        hipLaunchKernelGGL(k_cq_adjoint, dim3((nq + 255) / 256), dim3(256), 0, st,
+        if (det)
+            hipLaunchKernelGGL(k_cqb_gather, dim3((nq + 255) / 256), dim3(256), 0, st, beams->id,
+                               beams->offsets, nshots, (const double *)ctx->det_cqc, (int64_t)nq,
+                               (int64_t)p.np1 * p.np2, cqb);
+        hipLaunchKernelGGL(k_cq_adjoint, det ? dim3(1) : dim3((nq + 255) / 256),
+                           det ? dim3(1) : dim3(256), 0, st,
                            fga_velgrid(ctx), cqb, g.o1, g.o2, g.d1, g.d2, p.qb1, p.qb2, p.qs1,
                            p.qs2, p.nq1, p.nq2, dc);
     }

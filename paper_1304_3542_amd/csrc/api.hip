@@ -82,6 +82,8 @@ static fga_status check_params(fga_ctx *ctx, const fga_grid *g, const fga_params
                         "dz_divided = 1 takes the closed-form amplitude (amp_closed = 1)");
     if (p->dz_divided && !(p->dz_scale > 0 && isfinite(p->dz_scale)))
         return fga_fail(ctx, FGA_EINVAL, "dz_scale must be positive");
+    if (p->deterministic != 0 && p->deterministic != 1)
+        return fga_fail(ctx, FGA_EINVAL, "deterministic must be 0 or 1");
     int R1 = fga_halfwidth(p->eps, p->tau_fbi, g->d1);
     int R2 = fga_halfwidth(p->eps, p->tau_fbi, g->d2);
     if (R1 > 8192 || R2 > 8192)
@@ -151,7 +153,8 @@ extern "C" fga_status fga_destroy(fga_ctx *ctx)
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     void *bufs[] = {ctx->c, ctx->cpad, ctx->ccoef, ctx->status, ctx->cq, ctx->maxbits, ctx->E1t, ctx->E2,
                     ctx->T, ctx->Psi, ctx->blk, ctx->partial, ctx->srec, ctx->sbox,
-                    ctx->adj_scratch, ctx->adj_psib, ctx->trace_part, ctx->bin};
+                    ctx->adj_scratch, ctx->adj_psib, ctx->trace_part, ctx->bin,
+                    ctx->det_log, ctx->det_sort, ctx->det_cell, ctx->det_cqc, ctx->det_lam};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     free(ctx);

@@ -55,6 +55,13 @@ struct fga_ctx {
     size_t adj_scratch_bytes, adj_psib_bytes;
     int last_nfj, last_nshots;
 
+    // deterministic gradient: per-beam dJ/dc logs, the sort and cell
+    // reductions, per-beam c(q) cotangents, a copy of an initial cotangent;
+    // det_R is the log length per beam found sufficient so far
+    void *det_log, *det_sort, *det_cell, *det_cqc, *det_lam;
+    size_t det_log_bytes, det_sort_bytes, det_cell_bytes, det_cqc_bytes, det_lam_bytes;
+    int det_R;
+
     // sticky device status: [0] flags, [1] needed capacity
     int64_t *status;
 
@@ -102,6 +109,12 @@ fga_status fga_launch_rk4_adjoint(fga_ctx *ctx, const fga_beams *beams, int nsho
                                   double *gcoef, const double *lam0, double *lam_out);
 fga_status fga_launch_reconstruct_adjoint(fga_ctx *ctx, const fga_beams *beams, int nshots,
                                           const double *du, double *dstate, double *dcoef);
+// deterministic mode: (nb, total records, longest log) of the logs of the
+// last adjoint kernel (synchronises), and the fixed-order reduction into dc
+fga_status fga_det_stats(fga_ctx *ctx, const fga_beams *beams, int nshots, int R,
+                         int64_t out[3]);
+fga_status fga_det_reduce(fga_ctx *ctx, int64_t cap, int R, int64_t nb, int64_t total,
+                          double *dc);
 fga_status fga_launch_decompose_adjoint(fga_ctx *ctx, const fga_beams *beams, int nshots,
                                         const double *gcoef, double *df0, double *df1,
                                         double *dc);
