@@ -254,6 +254,29 @@ def adjoint_iteration(steps):
     st, _ = ctx.status()
     out["field_misfit"] = {"ms_per_iter": ev[0].elapsed_time(ev[1]) / steps, "status": st,
                            "misfit": "1/2 |u(T) - u_data(T)|^2 over the grid"}
+
+    # the receiver-misfit iteration in deterministic mode (fixed-order dJ/dc;
+    # synchronises once per adjoint call)
+    ctx_d = fga.FGA(g, p.replace(deterministic=1), "fp64", max_shots=ns)
+    ctx_d.set_velocity(c)
+
+    def it_det():
+        ctx_d.decompose(f0, None, beams)
+        tr = ctx_d.trace(beams, ns, rec, W.rec_every, nrec_t, ckpt)
+        dc.zero_()
+        gcoef = ctx_d.trace_adjoint(beams, ns, rec, W.rec_every, nrec_t, ckpt,
+                                    (tr - data).contiguous(), dc)
+        return ctx_d.decompose_adjoint(beams, ns, gcoef)
+
+    it_det()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        it_det()
+    torch.cuda.synchronize()
+    st, _ = ctx_d.status()
+    out["deterministic"] = {"ms_per_iter": (time.perf_counter() - t0) * 1e3 / steps,
+                            "status": st, "clock": "host (the mode synchronises)"}
     return out
 
 
