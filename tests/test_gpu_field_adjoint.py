@@ -178,3 +178,74 @@ def test_reconstruct_adjoint_point512_sampled_beams():
     for k in (0, 1, 2, 3, 4, 21, 22):
         assert rel_max(got[:, k], ds[:, k]) <= 1e-9, k
     assert rel_max(dcoef[:, idx].cpu().numpy().T, dcf) <= 1e-9
+
+
+def _oracle_flow_jvp(c, g, p, y0, sigma, nsteps, v):
+    """(y(T), (dy(T)/dy0) v) of the oracle's RK4 of the ray, dynamic ray
+    tracing and amplitude equations (plain torch), by forward-mode automatic
+    differentiation; y0, v: [nb][23] in the state layout."""
+    import torch
+    cg = torch.tensor(c)
+    sg = torch.tensor(np.asarray(sigma, dtype=np.float64))
+
+    def unpack(y):
+        A = torch.complex(y[:, 5:13:2], y[:, 6:13:2]).reshape(-1, 2, 2)
+        B = torch.complex(y[:, 13:21:2], y[:, 14:21:2]).reshape(-1, 2, 2)
+        return (y[:, 0:2], y[:, 2:4], y[:, 4], A, B, torch.complex(y[:, 21], y[:, 22]))
+
+    def pack(t):
+        Q, P, S, A, B, a = t
+        Af, Bf = A.reshape(-1, 4), B.reshape(-1, 4)
+        return torch.cat([Q, P, S[:, None], torch.stack([Af.real, Af.imag], -1).reshape(-1, 8),
+                          torch.stack([Bf.real, Bf.imag], -1).reshape(-1, 8),
+                          torch.stack([a.real, a.imag], -1)], 1)
+
+    def flow(y):
+        t = unpack(y)
+        for _ in range(nsteps):
+            t = oadj.rk4_step(cg, g, sg, t, p.dt)
+        return pack(t)
+
+    yT, Mv = torch.func.jvp(flow, (torch.tensor(y0),), (torch.tensor(v),))
+    return yT.numpy(), Mv.numpy()
+
+
+def test_propagate_adjoint_dot_product_with_oracle_tangent():
+    """<M v, w> = <v, M^T w> for the discrete flow map M = dy(T)/dy(0) of 15
+    RK4 steps (ray, dynamic ray tracing, amplitude): M^T w from
+    fga_propagate_adjoint (3 checkpoint segments), M v from forward-mode
+    differentiation of the oracle's plain RK4, at random v, w on 300 seeded
+    beams.  The states start three steps in, so that no evaluation sits
+    exactly on a knot (where the third derivative of the B-spline, in the
+    state Jacobian, jumps)."""
+    import torch
+    import paper_1304_3542_amd as fga
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(False)
+    ns = f0.shape[0]
+    ctx, beams = _ctx(g, p, c, ns)
+    ctx.decompose(torch.from_numpy(f0).cuda(), None, beams)
+    ctx.propagate(beams, ns, 3)
+    nb = int(ctx.offsets(beams, ns)[-1])
+    r = np.random.default_rng(76)
+    sel = np.sort(r.choice(nb, 300, replace=False))
+    y0 = beams.f[fga.FGA_F_STATE:, sel].cpu().numpy().T.copy()
+    ids = beams.id[sel].cpu().numpy()
+    NqNp = p.nq1 * p.nq2 * p.np1 * p.np2
+    sigma = np.where((ids // NqNp) % 2 == 0, 1.0, -1.0)
+    ckpt = ctx.propagate_ckpt(beams, ns, 5, 3)
+    yT_gpu = beams.f[fga.FGA_F_STATE:, sel].cpu().numpy().T
+    w = np.zeros((fga.FGA_NSTATE, beams.capacity))
+    w[:, sel] = r.standard_normal((fga.FGA_NSTATE, sel.size))
+    dstate = torch.from_numpy(w).cuda()
+    dc = torch.zeros((g.n2, g.n1), dtype=torch.float64, device="cuda")
+    ctx.propagate_adjoint(beams, ns, 5, 3, ckpt, dstate, dc)
+    assert ctx.status()[0] == 0
+    Mtw = dstate[:, sel].cpu().numpy().T
+    v = r.standard_normal(y0.shape)
+    yT, Mv = _oracle_flow_jvp(c, g, p, y0, sigma, 15, v)
+    assert np.abs(yT - yT_gpu).max() <= 1e-10 * np.abs(yT).max()
+    lhs = float((Mv * w[:, sel].T).sum())
+    rhs = float((v * Mtw).sum())
+    norm = np.linalg.norm(Mv) * np.linalg.norm(w)
+    assert abs(lhs) > 1e-4 * norm
+    assert abs(lhs - rhs) <= 1e-12 * norm, (lhs, rhs, norm)
