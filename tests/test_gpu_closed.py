@@ -112,3 +112,33 @@ def test_closed_root_tracking_through_caustics():
     cQ = oracle.velocity(c, g, out[:, 0], out[:, 1])[:, 0]
     principal = cQ / cq * np.sqrt(Z[:, 0] * Z[:, 3] - Z[:, 1] * Z[:, 2])
     assert np.all(np.abs(principal + a_gpu) < 1e-6 * np.abs(a_gpu))
+
+
+def test_closed_point512_sampled_beams_match_oracle():
+    """point512 in FP64 at full size (250 steps, every kept beam, the launch
+    the bench times) with the closed-form amplitude: 96 seeded beams against
+    the oracle's closed-form propagation of the same initial states."""
+    import torch
+    import paper_1304_3542_amd as fga
+    W = fi.workload("point512", "fp64")
+    g, p = W.grid, W.params.replace(amp_closed=1)
+    ctx = fga.FGA(g, p, "fp64")
+    ctx.set_velocity(torch.from_numpy(W.c).cuda())
+    beams = fga.Beams(1_500_000, 1)
+    ctx.decompose(torch.from_numpy(np.ascontiguousarray(W.f0)).cuda(), None, beams)
+    nb = int(ctx.offsets(beams, 1)[-1])
+    assert ctx.status()[0] == 0 and nb > 1_000_000
+    idx = np.sort(fi.rng(91).choice(nb, 96, replace=False))
+    f_init = beams.f[:, idx].cpu().numpy()
+    ids = beams.id[idx].cpu().numpy()
+    ctx.propagate(beams, 1, p.nsteps)
+    assert ctx.status()[0] == 0
+    got = beams.f[fga.FGA_F_STATE:, idx].cpu().numpy().T
+    NqNp = p.nq1 * p.nq2 * p.np1 * p.np2
+    sig = np.where((ids // NqNp) % 2 == 0, 1, -1).astype(np.int8)
+    b = oracle.Beams(np.zeros(96, np.int32), sig, ids, np.ones(96, complex), np.zeros((96, 2)),
+                     np.ascontiguousarray(f_init[fga.FGA_F_STATE:].T),
+                     np.array([0, 96], np.int64))
+    oracle.propagate(b, W.c, g, p.dt, p.nsteps, q=np.ascontiguousarray(f_init[0:2].T))
+    from gpu_helpers import pairwise_state_err
+    assert pairwise_state_err(got, b.state) <= 1e-9
