@@ -8,7 +8,8 @@
 //   2. the records are listed as (cell, log slot) in beam-then-sequence order
 //      and sorted by cell with a stable radix sort, so every cell's records
 //      stay in beam-then-sequence order,
-//   3. one thread per cell sums its records in that order,
+//   3. one wavefront per cell sums its records (lane l takes every 64th from
+//      the l-th, in order; then a fixed butterfly over the lanes),
 //   4. one thread per grid knot adds the sums of the cells that reach it (the
 //      clamped 4 x 4 knot stencil of the B-spline) in a fixed cell order.
 // Integer atomics only count; every floating-point sum has a fixed order.
@@ -79,18 +80,21 @@ __global__ void k_det_bounds(const unsigned *__restrict__ keys, int64_t total, i
     }
 }
 
-// the 16 knot sums of every cell, its records added in sorted order
-__global__ void k_det_cellsum(const int *__restrict__ begin, const int *__restrict__ end,
-                              const unsigned long long *__restrict__ slots,
-                              const double *__restrict__ rec, int64_t cap, int ncell,
-                              double *__restrict__ tot)
+// the 16 knot sums of every cell: one wavefront per cell, lane l adding the
+// records l, l + 64, ... of the cell's run in order, then a butterfly over
+// the lanes (a fixed tree), so the result does not depend on scheduling
+__global__ void __launch_bounds__(256)
+k_det_cellsum(const int *__restrict__ begin, const int *__restrict__ end,
+              const unsigned long long *__restrict__ slots, const double *__restrict__ rec,
+              int64_t cap, int ncell, double *__restrict__ tot)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);   // uniform in the wavefront
+    const int lane = threadIdx.x & 63;
     if (c >= ncell) return;
     double t[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) t[m] = 0.0;
-    for (int j = begin[c]; j < end[c]; ++j) {
+    for (int j = begin[c] + lane; j < end[c]; j += 64) {
         const unsigned long long s = slots[j];
         const unsigned long long k = s / (unsigned long long)cap, b = s - k * cap;
         const double *r = rec + (size_t)k * 16 * cap + b;
@@ -98,7 +102,12 @@ __global__ void k_det_cellsum(const int *__restrict__ begin, const int *__restri
         for (int m = 0; m < 16; ++m) t[m] += r[(size_t)m * cap];
     }
 #pragma unroll
-    for (int m = 0; m < 16; ++m) tot[(size_t)m * ncell + c] = t[m];
+    for (int m = 0; m < 16; ++m)
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) t[m] += __shfl_xor(t[m], o, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int m = 0; m < 16; ++m) tot[(size_t)m * ncell + c] = t[m];
 }
 
 // dc[r][q] += the entries (kz, kx) of the cells (i2, i1) whose clamped knot
@@ -217,7 +226,7 @@ fga_status fga_det_reduce(fga_ctx *ctx, int64_t cap, int R, int64_t nb, int64_t 
                                            (size_t)total, 0, nbits, st));
     hipLaunchKernelGGL(k_det_zero_i32, dim3(blocks), dim3(256), 0, st, begin, (int64_t)2 * ncell);
     hipLaunchKernelGGL(k_det_bounds, dim3(blocks), dim3(256), 0, st, keys_s, total, begin, end);
-    hipLaunchKernelGGL(k_det_cellsum, dim3((ncell + 255) / 256), dim3(256), 0, st, begin, end,
+    hipLaunchKernelGGL(k_det_cellsum, dim3((ncell + 3) / 4), dim3(256), 0, st, begin, end,
                        slots_s, rec, cap, ncell, tot);
     hipLaunchKernelGGL(k_det_gather, dim3((n1 + 255) / 256, n2), dim3(256), 0, st, tot, n1, n2,
                        dc);
