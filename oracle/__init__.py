@@ -36,7 +36,7 @@ _lib = None
 def build() -> str:
     """Compile the C oracle with gcc (OpenMP, -O2, no fast-math)."""
     cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-           "-o", LIB + ".tmp", SRC, "-lm"]
+           "-o", LIB + ".tmp", SRC, os.path.join(HERE, "fga_oracle3.c"), "-lm"]
     subprocess.check_call(cmd)
     os.replace(LIB + ".tmp", LIB)
     return LIB
