@@ -123,13 +123,13 @@ def wavepacket_source3(grid: Grid3, center, sigma: float, k, eps: float) -> np.n
 
 def workload3(name: str) -> Workload3:
     """point3d: 96 x 96 x 64 smooth layered model, eps = 1/64, point source,
-    q every 6 nodes, p 20^3 over [-2, 2]^3, 100 RK4 steps of 1 ms."""
+    q every 6 nodes, p 20^3 over [-2, 2]^3, tau = 1e-3, 100 RK4 steps of 1 ms."""
     if name == "point3d":
         grid = Grid3(96, 96, 64, 0.0, 0.0, 0.0, 1 / 64, 1 / 64, 1 / 64)
         eps = 1 / 64
         c = smooth_layered_velocity3(grid, seed=7)
         f0 = gaussian_source3(grid, (0.75, 0.75, 0.5), 2 * grid.d1)
         p = Params3(eps, (3, 3, 2), (6, 6, 6), (15, 15, 10), (20, 20, 20), (0.2, 0.2, 0.2),
-                    1e-4, 1e-16, 1e-16, 1e-3, 100)
+                    1e-3, 1e-16, 1e-16, 1e-3, 100)
         return Workload3(name, grid, p, c, f0[None], None)
     raise KeyError(name)

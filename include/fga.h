@@ -290,6 +290,65 @@ fga_status fga_copy_offsets(fga_ctx *ctx, const fga_beams *beams, int32_t nshots
  * last fga_create failure when ctx is NULL).                               */
 const char *fga_last_error(const fga_ctx *ctx);
 
+/* ---------------------------------------------------------------------
+ * Three space dimensions (FP64): the same three steps for the 3-D acoustic
+ * wave equation (the paper states the method for general d; d = 3 here).
+ * Grid arrays are C-ordered [n3][n2][n1] float64 on x = o + i*d per axis.
+ * Beams use fga_beams with f[FGA3_NFIELD][capacity]:
+ *   field 0..2   q1, q2, q3        field 3..5   p1, p2, p3
+ *   field 6..7   C = w psi / (2 pi eps)^{9/2} (re, im),
+ *                w = prod_a (qs_a d_a) prod_a dp_a
+ *   field 8..52  state: Q(3), P(3), S, A = dzQ (3x3 complex, row-major,
+ *                re/im interleaved), B = dzP (same), a (re, im);
+ *                at t = 0: Q = q, P = p, S = 0, A = I, B = -iI, a = 2^{3/2}
+ * id = ((shot*2 + (branch == -1)) * NQ + qflat) * NP + pflat with
+ * qflat = (j3*nq2 + j2)*nq1 + j1, pflat = (l3*np2 + l2)*np1 + l1; beams in
+ * increasing id; offsets[nshots+1] as in 2-D.  The p-mesh per axis is
+ * p_l = (l - (np-1)/2) dp (np even); thresholding, truncation boxes and
+ * their half-widths follow the 2-D rules per axis.  Errors as in 2-D; the
+ * device status is read by fga3_sync_status.                            */
+typedef struct fga3_ctx fga3_ctx;
+
+typedef struct {
+    int32_t n1, n2, n3;
+    double o1, o2, o3, d1, d2, d3;
+} fga3_grid;
+
+typedef struct {
+    double eps;
+    int32_t qb[3], qs[3], nq[3];   /* q-mesh nodes qb + j*qs per axis   */
+    int32_t np[3];
+    double dp[3];
+    double tau, tau_fbi, tau_win;
+    double dt;
+} fga3_params;
+
+#define FGA3_NSTATE 45
+#define FGA3_NFIELD 53
+#define FGA3_F_STATE 8
+
+/* Context for one 3-D grid and parameter set; max_shots bounds nshots.     */
+fga_status fga3_create(fga3_ctx **ctx, const fga3_grid *grid, const fga3_params *params,
+                       int32_t max_shots, void *stream);
+fga_status fga3_destroy(fga3_ctx *ctx);
+/* c[n3][n2][n1] (device, c > 0): the tricubic B-spline with these samples
+ * as coefficients, indices clamped to the grid.                            */
+fga_status fga3_set_velocity(fga3_ctx *ctx, const double *c_dev);
+/* Step 1 for nshots shots: f0_dev, f1_dev [nshots][n3][n2][n1] (f1 may be
+ * NULL): FBI (psi eq., three separable windowed DFTs over the box),
+ * u_{+-,0}, |psi| >= tau max|psi| per shot, beams written in id order.     */
+fga_status fga3_decompose(fga3_ctx *ctx, int32_t nshots, const double *f0_dev,
+                          const double *f1_dev, fga_beams *beams);
+/* Step 2: nsteps classical RK4 steps of the ray, dynamic ray tracing and
+ * amplitude equations, in place.                                           */
+fga_status fga3_propagate(fga3_ctx *ctx, fga_beams *beams, int32_t nshots, int32_t nsteps);
+/* Step 3: u_dev[nshots][n3][n2][n1] = Re of the recons eq. over the boxes
+ * (overwritten).                                                           */
+fga_status fga3_reconstruct(fga3_ctx *ctx, const fga_beams *beams, int32_t nshots,
+                            double *u_dev);
+fga_status fga3_sync_status(fga3_ctx *ctx, int64_t *needed);
+const char *fga3_last_error(const fga3_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

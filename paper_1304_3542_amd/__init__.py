@@ -45,6 +45,20 @@ class fga_params(ctypes.Structure):
                 ("dz_scale", ctypes.c_double), ("deterministic", ctypes.c_int32)]
 
 
+class fga3_grid(ctypes.Structure):
+    _fields_ = [("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("n3", ctypes.c_int32),
+                ("o1", ctypes.c_double), ("o2", ctypes.c_double), ("o3", ctypes.c_double),
+                ("d1", ctypes.c_double), ("d2", ctypes.c_double), ("d3", ctypes.c_double)]
+
+
+class fga3_params(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("qb", ctypes.c_int32 * 3), ("qs", ctypes.c_int32 * 3),
+                ("nq", ctypes.c_int32 * 3), ("np", ctypes.c_int32 * 3),
+                ("dp", ctypes.c_double * 3), ("tau", ctypes.c_double),
+                ("tau_fbi", ctypes.c_double), ("tau_win", ctypes.c_double),
+                ("dt", ctypes.c_double)]
+
+
 class fga_beams(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int64), ("f", ctypes.c_void_p), ("id", ctypes.c_void_p),
                 ("offsets", ctypes.c_void_p)]
@@ -86,11 +100,20 @@ def load(path: str = LIB_PATH):
         "fga_sync_status": [C, ctypes.POINTER(ctypes.c_int64)],
         "fga_copy_offsets": [C, ctypes.POINTER(fga_beams), I32, P],
         "fga_last_error": [C],
+        "fga3_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(fga3_grid),
+                        ctypes.POINTER(fga3_params), I32, P],
+        "fga3_destroy": [C],
+        "fga3_set_velocity": [C, P],
+        "fga3_decompose": [C, I32, P, P, ctypes.POINTER(fga_beams)],
+        "fga3_propagate": [C, ctypes.POINTER(fga_beams), I32, I32],
+        "fga3_reconstruct": [C, ctypes.POINTER(fga_beams), I32, P],
+        "fga3_sync_status": [C, ctypes.POINTER(ctypes.c_int64)],
+        "fga3_last_error": [C],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
         fn.argtypes = args
-        fn.restype = ctypes.c_char_p if name == "fga_last_error" else ctypes.c_int
+        fn.restype = ctypes.c_char_p if name.endswith("last_error") else ctypes.c_int
     _lib = L
     return L
 
@@ -425,3 +448,87 @@ def traces(c, f0, f1, fga: FGA, beams: Beams, rec, rec_every: int, nrec_t: int):
     if _TRACE_FN is None:
         _TRACE_FN = _trace_function()
     return _TRACE_FN.apply(c, f0, f1, fga, beams, rec, rec_every, nrec_t)
+
+
+# ------------------------------------------------------ three space dimensions
+
+FGA3_NSTATE = 45
+FGA3_NFIELD = 53
+FGA3_F_STATE = 8
+
+
+class Beams3(Beams):
+    """Caller-owned beam storage of the 3-D path: f[53][capacity] float64."""
+
+    def __init__(self, capacity: int, max_shots: int = 1, device="cuda"):
+        import torch
+        self.capacity = int(capacity)
+        self.f = torch.zeros((FGA3_NFIELD, self.capacity), dtype=torch.float64, device=device)
+        self.id = torch.zeros(self.capacity, dtype=torch.int64, device=device)
+        self.offsets = torch.zeros(max_shots + 1, dtype=torch.int64, device=device)
+        self._c = fga_beams(self.capacity, self.f.data_ptr(), self.id.data_ptr(),
+                            self.offsets.data_ptr())
+
+
+def _check3(ctx, status: int):
+    if status != FGA_OK:
+        raise FGAError(status, load().fga3_last_error(ctx).decode())
+
+
+class FGA3:
+    """Context of the 3-D path (FP64): names follow the C entry points."""
+
+    def __init__(self, grid, params, max_shots: int = 1, stream=None):
+        g = fga3_grid(grid.n1, grid.n2, grid.n3, grid.o1, grid.o2, grid.o3, grid.d1, grid.d2,
+                      grid.d3)
+        p = fga3_params(params.eps, (ctypes.c_int32 * 3)(*params.qb),
+                        (ctypes.c_int32 * 3)(*params.qs), (ctypes.c_int32 * 3)(*params.nq),
+                        (ctypes.c_int32 * 3)(*params.np), (ctypes.c_double * 3)(*params.dp),
+                        params.tau, params.tau_fbi, params.tau_win, params.dt)
+        self.grid, self.params = grid, params
+        ctx = ctypes.c_void_p()
+        st = load().fga3_create(ctypes.byref(ctx), ctypes.byref(g), ctypes.byref(p),
+                                int(max_shots), _stream_handle(stream))
+        _check3(None, st)
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            load().fga3_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_velocity(self, c):
+        _require(c, "c", "float64")
+        _check3(self.ctx, load().fga3_set_velocity(self.ctx, _ptr(c)))
+
+    def decompose(self, f0, f1, beams: Beams3):
+        _require(f0, "f0", "float64")
+        ns = f0.shape[0]
+        _check3(self.ctx, load().fga3_decompose(self.ctx, int(ns), _ptr(f0), _ptr(f1),
+                                                beams.c_struct()))
+
+    def propagate(self, beams: Beams3, nshots: int, nsteps: int):
+        _check3(self.ctx, load().fga3_propagate(self.ctx, beams.c_struct(), int(nshots),
+                                                int(nsteps)))
+
+    def reconstruct(self, beams: Beams3, nshots: int, u=None):
+        import torch
+        g = self.grid
+        if u is None:
+            u = torch.empty((nshots, g.n3, g.n2, g.n1), dtype=torch.float64,
+                            device=beams.f.device)
+        _require(u, "u", "float64")
+        _check3(self.ctx, load().fga3_reconstruct(self.ctx, beams.c_struct(), int(nshots),
+                                                  _ptr(u)))
+        return u
+
+    def status(self):
+        needed = ctypes.c_int64(0)
+        st = load().fga3_sync_status(self.ctx, ctypes.byref(needed))
+        return st, needed.value
