@@ -84,6 +84,8 @@ def parse():
                     help="timed steps of point512 with the closed-form amplitude (0 skips it)")
     ap.add_argument("--dd-steps", type=int, default=3,
                     help="timed steps of point512 with divided-difference dzQ, dzP (0 skips it)")
+    ap.add_argument("--d3-steps", type=int, default=2,
+                    help="timed steps of the three-dimensional point3d workload (0 skips it)")
     ap.add_argument("--large-steps", type=int, default=1,
                     help="timed steps of the 2048x1024 configuration (0 skips it)")
     ap.add_argument("--topn-steps", type=int, default=5,
@@ -415,6 +417,50 @@ def dd_step(steps, u_integrated):
     return out
 
 
+def d3_step(steps):
+    """point3d (FP64, three space dimensions): ms per step of decompose +
+    propagate (100 RK4 steps) + reconstruct, and per stage (HIP events)."""
+    import torch
+    import fga_inputs.d3 as i3
+    import paper_1304_3542_amd as fga
+    W = i3.workload3("point3d")
+    g, p = W.grid, W.params
+    ctx = fga.FGA3(g, p)
+    ctx.set_velocity(torch.from_numpy(W.c).cuda())
+    f0 = torch.from_numpy(np.ascontiguousarray(W.f0)).cuda()
+    beams = fga.Beams3(4_000_000, 1)
+    u = torch.empty((1, g.n3, g.n2, g.n1), dtype=torch.float64, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def step():
+        ev[0].record()
+        ctx.decompose(f0, None, beams)
+        ev[1].record()
+        ctx.propagate(beams, 1, p.nsteps)
+        ev[2].record()
+        ctx.reconstruct(beams, 1, u)
+        ev[3].record()
+
+    step()
+    torch.cuda.synchronize()
+    st0 = ctx.status()
+    stages = np.zeros(3)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+        torch.cuda.synchronize()
+        stages += [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    nb = int(beams.offsets[1].item())
+    st, _ = ctx.status()
+    return {"workload": "point3d: 96x96x64 smooth layered 3-D model, eps=1/64, point source, "
+            "q 15x15x10, p 20^3, tau=1e-3, 100 RK4 steps, FP64", "nbeams": nb,
+            "ms_per_step": ms, "beams_per_s": nb / (ms * 1e-3),
+            "stages_ms": dict(zip(("decompose", "propagate", "reconstruct"),
+                                  (stages / steps).tolist())),
+            "status": st if st0[0] == 0 else st0[0]}
+
+
 def large_step(steps):
     """The large configuration (2048 x 1024, eps = 1/1024, ~5e7 beams): ms per
     mixed step and its stages, the FP64 GPU step on the same input, and the
@@ -629,6 +675,8 @@ def main():
         out["closed_amplitude"] = closed_step(args.closed_steps, u_mixed)
     if args.dd_steps > 0:
         out["divided_differences"] = dd_step(args.dd_steps, u_mixed)
+    if args.d3_steps > 0:
+        out["d3"] = d3_step(args.d3_steps)
     if args.large_steps > 0:
         out["large"] = large_step(args.large_steps)
     if not args.no_cpu_baseline:

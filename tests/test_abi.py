@@ -104,3 +104,26 @@ def test_every_workload_passes_host_validation(name, precision):
     assert st != fga.FGA_EINVAL, lib.fga_last_error(None)
     if st == fga.FGA_OK:
         lib.fga_destroy(ctx)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(np=(7, 8, 8)), dict(nq=(8, 5, 50)), dict(eps=0.0), dict(dp=(0.3, 0.0, 0.3)),
+    dict(tau=2.0), dict(tau_win=1.0), dict(dt=0.0), dict(qs=(3, 0, 3)),
+])
+def test_create3_rejects_bad_params(bad):
+    """The 3-D context checks its arguments on the host (no GPU needed)."""
+    import paper_1304_3542_amd as fga
+    import fga_inputs.d3 as i3
+    g = i3.Grid3(26, 22, 19, 0.0, 0.1, -0.05, 1 / 24, 1 / 22, 1 / 20)
+    p = i3.Params3(1 / 48, (2, 1, 3), (3, 4, 3), (8, 5, 5), (8, 6, 8), (0.3, 0.35, 0.28), 1e-5,
+                   1e-16, 1e-16, 1e-3, 20).replace(**bad)
+    gs = fga.fga3_grid(g.n1, g.n2, g.n3, g.o1, g.o2, g.o3, g.d1, g.d2, g.d3)
+    ps = fga.fga3_params(p.eps, (ctypes.c_int32 * 3)(*p.qb), (ctypes.c_int32 * 3)(*p.qs),
+                         (ctypes.c_int32 * 3)(*p.nq), (ctypes.c_int32 * 3)(*p.np),
+                         (ctypes.c_double * 3)(*p.dp), p.tau, p.tau_fbi, p.tau_win, p.dt)
+    lib = fga.load()
+    ctx = ctypes.c_void_p()
+    st = lib.fga3_create(ctypes.byref(ctx), ctypes.byref(gs), ctypes.byref(ps), 1, None)
+    assert st == fga.FGA_EINVAL
+    assert not ctx.value
+    assert lib.fga3_last_error(None)
