@@ -86,6 +86,7 @@ class Params:
     dz_divided: int = 0  # 1: dzQ, dzP from divided differences of neighbouring rays
     dz_scale: float = 1.0  # their spacing in mesh steps (1: the neighbouring mesh nodes)
     deterministic: int = 0  # 1: gradients reduce dJ/dc in a fixed order (bit-identical runs)
+    grad_log: int = 0  # dJ/dc logs per beam when not deterministic (0 auto, -1 none, n slots)
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)

@@ -115,6 +115,20 @@ typedef struct {
  *              sequence; every knot sums its cells in a fixed order), so
  *              repeated calls give bit-identical dc.  The gradient calls then
  *              synchronise the stream once to size the reduction.
+ *   grad_log   (deterministic = 0) where the gradient kernels put dJ/dc
+ *              (a record = the 16 knot sums of one B-spline cell):
+ *              0 (automatic): each beam logs its records in its own slots,
+ *              up to min(4 steps + 1, what fits FGA_GRAD_LOG_BYTES for the
+ *              beam capacity) of them; the logs are then summed by cell in a
+ *              fixed order (the deterministic mode's reduction, which
+ *              synchronises the stream once per call to size its sort);
+ *              records past a beam's slots are added with FP64 atomics where
+ *              they are made.  n > 0: at most n slots per beam (no size
+ *              cap).  -1: no logs, every record is added with atomics where
+ *              it is made, and the call does not synchronise.  The three give
+ *              the same dc up to the rounding order.  The logged form is the
+ *              faster one here: atomics from many rays into the same cells
+ *              contend, and the integrating waves wait on them.
  *   tau_fbi    the FBI box B_eps has half-width ceil(sqrt(2 eps ln(1/tau_fbi))/d)
  *   tau_win    each Gaussian is summed over the box of half-width
  *              ceil(sqrt(2 eps ln(1/tau_win))/d) around the node nearest Q
@@ -131,7 +145,11 @@ typedef struct {
     int32_t dz_divided;
     double dz_scale;
     int32_t deterministic;
+    int32_t grad_log;
 } fga_params;
+
+/* Size cap of the automatic dJ/dc logs of one context (grad_log = 0).     */
+#define FGA_GRAD_LOG_BYTES (8LL << 30)
 
 /* Beam storage: structure of arrays in one float64 buffer
  * f[FGA_NFIELD][capacity] (field-major), caller-allocated on the device.

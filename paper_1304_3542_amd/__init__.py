@@ -42,7 +42,8 @@ class fga_params(ctypes.Structure):
                 ("tau_fbi", ctypes.c_double), ("tau_win", ctypes.c_double),
                 ("dt", ctypes.c_double), ("top_n", ctypes.c_int32),
                 ("amp_closed", ctypes.c_int32), ("dz_divided", ctypes.c_int32),
-                ("dz_scale", ctypes.c_double), ("deterministic", ctypes.c_int32)]
+                ("dz_scale", ctypes.c_double), ("deterministic", ctypes.c_int32),
+                ("grad_log", ctypes.c_int32)]
 
 
 class fga3_grid(ctypes.Structure):
@@ -142,7 +143,8 @@ def fga_create(grid, params, precision: int = FGA_FP64, max_shots: int = 1, stre
                    params.nq2, params.np1, params.np2, params.dp1, params.dp2, params.tau,
                    params.tau_fbi, params.tau_win, params.dt, int(getattr(params, "top_n", 0)),
                    int(getattr(params, "amp_closed", 0)), int(getattr(params, "dz_divided", 0)),
-                   float(getattr(params, "dz_scale", 1.0)), int(getattr(params, "deterministic", 0)))
+                   float(getattr(params, "dz_scale", 1.0)), int(getattr(params, "deterministic", 0)),
+                   int(getattr(params, "grad_log", 0)))
     ctx = ctypes.c_void_p()
     st = load().fga_create(ctypes.byref(ctx), ctypes.byref(g), ctypes.byref(p), int(precision),
                            int(max_shots), _stream_handle(stream))

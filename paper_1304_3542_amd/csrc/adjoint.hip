@@ -119,11 +119,13 @@ struct DcAcc {
     int cnt;      // records logged so far
 };
 
-// Where dJ/dc goes: added to dc with FP64 atomics, or (deterministic mode,
-// rec != null) logged in the beam's own slots as records of one knot cell's
-// 16 sums, rec[k][16][cap] and cell[k][cap] = (i2 + 4)(n1 + 8) + (i1 + 4) for
-// the k-th flush of beam b; a log longer than R only counts (the caller
-// reruns with the length found).
+// Where dJ/dc goes: added to dc with FP64 atomics (rec = null), or logged in
+// the beam's own slots as records of one knot cell's 16 sums,
+// rec[k][cap][16] (a record is one 128-byte line) and
+// cell[k][cap] = (i2 + 4)(n1 + 8) + (i1 + 4) for the k-th logged flush of
+// beam b.  Past R records a deterministic log (dc = null)
+// only counts (the caller reruns with the length found); a non-deterministic
+// one (dc set) adds the rest with atomics, and its count stops at R.
 struct DcOut {
     double *dc;
     double *rec;
@@ -145,11 +147,11 @@ __device__ __forceinline__ void dcacc_init(DcAcc &a, int64_t b = 0)
 __device__ __forceinline__ void dcacc_flush(DcAcc &a, const DcOut &o)
 {
     if (a.i1 == -2147483647 - 1) return;
-    if (o.rec) {
+    if (o.rec && (a.cnt < o.R || !o.dc)) {
         if (a.cnt < o.R) {
-            double *r = o.rec + (size_t)a.cnt * 16 * o.cap + a.b;
+            double2 *r = (double2 *)(o.rec + ((size_t)a.cnt * o.cap + a.b) * 16);
 #pragma unroll
-            for (int k = 0; k < 16; ++k) r[(size_t)k * o.cap] = a.v[k];
+            for (int k = 0; k < 8; ++k) r[k] = make_double2(a.v[2 * k], a.v[2 * k + 1]);
             o.cell[(size_t)a.cnt * o.cap + a.b] = (a.i2 + 4) * (o.n1 + 8) + (a.i1 + 4);
         }
         ++a.cnt;
@@ -440,14 +442,24 @@ struct TraceAdjArgs {
     const double *gtr;        // [nshots][nrec_t][nrec]
     double *scratch;          // [rec_every][NSTATE][cap]
     DcOut out;                // dJ/dc: atomics into [n2][n1], or the per-beam logs
-    int *logcnt;              // deterministic mode: [cap] log length per beam
+    int *logcnt;              // with logs: [cap] log length per beam
     double *gcoef;            // [2][cap] (may be null)
+    const int *rshape;        // receivers: {1, first column, row} for one run of a row, else 0
     const double *lam0;       // [NSTATE][cap]: cotangent of the final state (may be null)
     double *lam_out;          // [NSTATE][cap]: cotangent of the initial state (may be null)
     int n1, n2;
     double o1, o2, d1, d2, eps, dt;
     int Rw1, Rw2;
 };
+
+// e^{(g + i th) / eps}
+__device__ __forceinline__ Cd gauss_phase(double th, double g, double inv_eps)
+{
+    double sn, cs;
+    sincos(th * inv_eps, &sn, &cs);
+    const double e = exp(g * inv_eps);
+    return {e * cs, e * sn};
+}
 
 __global__ void __launch_bounds__(ADJ_BLOCK)
 k_trace_adjoint(TraceAdjArgs A)
@@ -457,6 +469,8 @@ k_trace_adjoint(TraceAdjArgs A)
     const int64_t nb = A.offsets[A.nshots];
     const int64_t cap = A.cap;
     const double inv_eps = 1.0 / A.eps;
+    const int run = A.nrec > 0 ? A.rshape[0] : 0;
+    const int run1 = A.nrec > 0 ? A.rshape[1] : 0, run2 = A.nrec > 0 ? A.rshape[2] : 0;
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
          b += (int64_t)gridDim.x * blockDim.x) {
         const int64_t idb = A.id[b];
@@ -482,30 +496,61 @@ k_trace_adjoint(TraceAdjArgs A)
                 stage<true>(A.V, s, t, acc, y, A.dt / 6.0, 0.0);
                 y = acc;
             }
-            // cotangent of the traces of record k (boxes held fixed)
-            const double *R = A.nrec > 0 ? A.gtr + ((size_t)shot * A.nrec_t + k) * A.nrec : A.gtr;
-            BeamBox bx = beam_box(y.Q1, y.Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
-            for (int r = 0; r < A.nrec; ++r) {
-                int node = A.rec[r];
-                int i1 = node % A.n1, i2 = node / A.n1;
-                if (i1 < bx.lo1 || i1 > bx.hi1 || i2 < bx.lo2 || i2 > bx.hi2) continue;
-                double r1 = (A.o1 + i1 * A.d1) - y.Q1, r2 = (A.o2 + i2 * A.d2) - y.Q2;
-                double th = (y.S + y.P1 * r1 + y.P2 * r2) * inv_eps;
-                double G = -(r1 * r1 + r2 * r2) * 0.5 * inv_eps;
-                double sn, cs;
-                sincos(th, &sn, &cs);
-                double e = exp(G);
-                Cd ew = {e * cs, e * sn};          // e^{i theta + G}
-                Cd w = cmul(y.a, ew);              // a e^{...}
-                Cd E = cmul(C, w);                 // the term whose real part is traced
-                double Rv = R[r];
-                gC = cadd(gC, cscale(cconj(w), Rv));
-                lam.a = cadd(lam.a, cscale(cconj(cmul(C, ew)), Rv));
-                lam.S += Rv * (-E.i) * inv_eps;
-                lam.P1 += Rv * (-E.i) * r1 * inv_eps;
-                lam.P2 += Rv * (-E.i) * r2 * inv_eps;
-                lam.Q1 += Rv * (E.i * y.P1 + E.r * r1) * inv_eps;
-                lam.Q2 += Rv * (E.i * y.P2 + E.r * r2) * inv_eps;
+            // cotangent of the traces of record k (boxes held fixed).  The
+            // traced term of receiver x is Re(C a e(x)), e = e^{(i (S + P.r)
+            // - |r|^2 / 2) / eps}, r = x - Q, so with F = sum R e,
+            // F_k = sum R r_k e over the receivers in the box every
+            // derivative follows from F, F_1, F_2.
+            if (A.nrec > 0) {
+                const double *R = A.gtr + ((size_t)shot * A.nrec_t + k) * A.nrec;
+                const BeamBox bx =
+                    beam_box(y.Q1, y.Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
+                Cd F0 = {0.0, 0.0}, F1 = {0.0, 0.0}, F2 = {0.0, 0.0};
+                if (run) {
+                    // one row: e at the next column is e times rho, and rho
+                    // itself steps by the real factor e^{-d1^2 / eps}
+                    const int a1 = max(bx.lo1, run1), b1 = min(bx.hi1, run1 + A.nrec - 1);
+                    if (run2 >= bx.lo2 && run2 <= bx.hi2 && a1 <= b1) {
+                        const double r2 = (A.o2 + run2 * A.d2) - y.Q2;
+                        const double r1a = (A.o1 + a1 * A.d1) - y.Q1;
+                        Cd e = gauss_phase(y.S + y.P1 * r1a + y.P2 * r2,
+                                           -0.5 * (r1a * r1a + r2 * r2), inv_eps);
+                        Cd rho = gauss_phase(y.P1 * A.d1, -(r1a + 0.5 * A.d1) * A.d1, inv_eps);
+                        const double kap = exp(-A.d1 * A.d1 * inv_eps);
+                        for (int i1 = a1; i1 <= b1; ++i1) {
+                            const double Rv = R[i1 - run1];
+                            const double r1 = (A.o1 + i1 * A.d1) - y.Q1;
+                            F0 = cadd(F0, cscale(e, Rv));
+                            F1 = cadd(F1, cscale(e, Rv * r1));
+                            e = cmul(e, rho);
+                            rho = cscale(rho, kap);
+                        }
+                        F2 = cscale(F0, r2);
+                    }
+                } else {
+                    for (int r = 0; r < A.nrec; ++r) {
+                        const int node = A.rec[r];
+                        const int i1 = node % A.n1, i2 = node / A.n1;
+                        if (i1 < bx.lo1 || i1 > bx.hi1 || i2 < bx.lo2 || i2 > bx.hi2) continue;
+                        const double r1 = (A.o1 + i1 * A.d1) - y.Q1;
+                        const double r2 = (A.o2 + i2 * A.d2) - y.Q2;
+                        const Cd e = gauss_phase(y.S + y.P1 * r1 + y.P2 * r2,
+                                                 -0.5 * (r1 * r1 + r2 * r2), inv_eps);
+                        const double Rv = R[r];
+                        F0 = cadd(F0, cscale(e, Rv));
+                        F1 = cadd(F1, cscale(e, Rv * r1));
+                        F2 = cadd(F2, cscale(e, Rv * r2));
+                    }
+                }
+                const Cd Ca = cmul(C, y.a);
+                const Cd E0 = cmul(Ca, F0), E1 = cmul(Ca, F1), E2 = cmul(Ca, F2);
+                gC = cadd(gC, cconj(cmul(y.a, F0)));
+                lam.a = cadd(lam.a, cconj(cmul(C, F0)));
+                lam.S += -E0.i * inv_eps;
+                lam.P1 += -E1.i * inv_eps;
+                lam.P2 += -E2.i * inv_eps;
+                lam.Q1 += (E0.i * y.P1 + E1.r) * inv_eps;
+                lam.Q2 += (E0.i * y.P2 + E2.r) * inv_eps;
             }
             // pull lambda back through the segment
             for (int j = A.rec_every - 1; j >= 0; --j) {
@@ -522,6 +567,17 @@ k_trace_adjoint(TraceAdjArgs A)
         }
         if (A.lam_out) store_state(A.lam_out + b, cap, lam);
     }
+}
+
+// Log slots per beam of a non-deterministic adjoint call (0: no logs).
+static int grad_log_slots(const fga_ctx *ctx, int64_t cap, int64_t steps)
+{
+    const int64_t most = 4 * steps + 1;   // a flush per stage at most, and the last
+    if (ctx->p.grad_log < 0 || cap <= 0) return 0;
+    if (ctx->p.grad_log > 0) return (int)std::min<int64_t>(ctx->p.grad_log, most);
+    const int64_t per = (int64_t)(16 * sizeof(double) + sizeof(int));
+    const int64_t fit = (FGA_GRAD_LOG_BYTES - cap * (int64_t)sizeof(int)) / (per * cap);
+    return (int)std::max<int64_t>(0, std::min<int64_t>(most, fit));
 }
 
 fga_status fga_launch_trace_adjoint(fga_ctx *ctx, const fga_beams *beams, int nshots,
@@ -567,6 +623,11 @@ fga_status fga_launch_rk4_adjoint(fga_ctx *ctx, const fga_beams *beams, int nsho
     A.gcoef = gcoef;
     A.lam0 = lam0;
     A.lam_out = lam_out;
+    A.rshape = nullptr;
+    if (nrec > 0) {
+        rc = fga_rec_shape(ctx, rec, nrec, &A.rshape);
+        if (rc != FGA_OK) return rc;
+    }
     A.n1 = ctx->g.n1;
     A.n2 = ctx->g.n2;
     A.o1 = ctx->g.o1;
@@ -578,10 +639,33 @@ fga_status fga_launch_rk4_adjoint(fga_ctx *ctx, const fga_beams *beams, int nsho
     A.Rw1 = ctx->Rw1;
     A.Rw2 = ctx->Rw2;
     const dim3 grid(ctx->num_cu * 4), block(ADJ_BLOCK);
+    const int64_t steps = (int64_t)rec_every * nrec_t;
     if (!ctx->p.deterministic) {
+        const int R = grad_log_slots(ctx, cap, steps);
+        char *base = nullptr;
+        size_t rec_bytes = 0, cell_bytes = 0;
+        if (R > 0) {
+            rec_bytes = (size_t)R * 16 * cap * sizeof(double);
+            cell_bytes = (size_t)R * cap * sizeof(int);
+            rc = fga_ensure(ctx, &ctx->det_log, &ctx->det_log_bytes,
+                            rec_bytes + cell_bytes + (size_t)cap * sizeof(int), "dJ/dc logs");
+            if (rc != FGA_OK) return rc;
+            base = (char *)ctx->det_log;
+            A.out = DcOut{dc, (double *)base, (int *)(base + rec_bytes), cap, R, ctx->g.n1,
+                          ctx->g.n2};
+            A.logcnt = (int *)(base + rec_bytes + cell_bytes);
+        }
         hipLaunchKernelGGL(k_trace_adjoint, grid, block, 0, ctx->stream, A);
         FGA_HIP(ctx, hipGetLastError());
-        return FGA_OK;
+        if (R == 0) return FGA_OK;
+        // the logged records (every log at most R long; the rest went to dc
+        // with atomics) summed by cell in a fixed order, as in the
+        // deterministic mode: on this chip it is faster than adding them
+        // with FP64 atomics, whose contention where rays cross is high
+        int64_t st[3];
+        rc = fga_det_stats(ctx, beams, nshots, R, st);
+        if (rc != FGA_OK) return rc;
+        return fga_det_reduce(ctx, cap, R, st[0], st[1], dc);
     }
     // deterministic: log, check the longest log (rerun with that length if
     // some beam ran past the slots), then reduce in a fixed order.  A rerun
@@ -594,7 +678,6 @@ fga_status fga_launch_rk4_adjoint(fga_ctx *ctx, const fga_beams *beams, int nsho
                                     hipMemcpyDeviceToDevice, ctx->stream));
         A.lam0 = (const double *)ctx->det_lam;
     }
-    const int64_t steps = (int64_t)rec_every * nrec_t;
     int R = ctx->det_R > 0 ? ctx->det_R : (int)std::min<int64_t>(4 * steps + 1, 64);
     int64_t st[3];
     for (;;) {

@@ -84,6 +84,8 @@ static fga_status check_params(fga_ctx *ctx, const fga_grid *g, const fga_params
         return fga_fail(ctx, FGA_EINVAL, "dz_scale must be positive");
     if (p->deterministic != 0 && p->deterministic != 1)
         return fga_fail(ctx, FGA_EINVAL, "deterministic must be 0 or 1");
+    if (p->grad_log < -1)
+        return fga_fail(ctx, FGA_EINVAL, "grad_log must be -1, 0 or positive");
     int R1 = fga_halfwidth(p->eps, p->tau_fbi, g->d1);
     int R2 = fga_halfwidth(p->eps, p->tau_fbi, g->d2);
     if (R1 > 8192 || R2 > 8192)
@@ -153,7 +155,7 @@ extern "C" fga_status fga_destroy(fga_ctx *ctx)
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     void *bufs[] = {ctx->c, ctx->cpad, ctx->ccoef, ctx->status, ctx->cq, ctx->maxbits, ctx->E1t, ctx->E2,
                     ctx->T, ctx->Psi, ctx->blk, ctx->partial, ctx->srec, ctx->sbox,
-                    ctx->adj_scratch, ctx->adj_psib, ctx->trace_part, ctx->bin,
+                    ctx->adj_scratch, ctx->adj_psib, ctx->rec_shape, ctx->trace_part, ctx->bin,
                     ctx->det_log, ctx->det_sort, ctx->det_cell, ctx->det_cqc, ctx->det_lam};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -292,12 +294,15 @@ extern "C" fga_status fga_trace(fga_ctx *ctx, fga_beams *beams, int32_t nshots,
     if (!rec || nrec < 1 || rec_every < 1 || nrec_t < 1 || !traces)
         return fga_fail(ctx, FGA_EINVAL, "bad receiver arguments");
     if (!ctx->have_c) return fga_fail(ctx, FGA_ESTATE, "fga_set_velocity was not called");
+    const int *shape = nullptr;
+    st = fga_rec_shape(ctx, rec, nrec, &shape);
+    if (st != FGA_OK) return st;
     for (int k = 0; k < nrec_t; ++k) {
         double *ck = ckpt ? ckpt + (size_t)k * FGA_NSTATE * beams->capacity : nullptr;
         st = fga_launch_propagate(ctx, beams, nshots, rec_every, ck);
         if (st != FGA_OK) return st;
         st = fga_launch_trace_points(ctx, beams, nshots, rec, nrec, traces + (size_t)k * nrec,
-                                     (int64_t)nrec_t * nrec);
+                                     (int64_t)nrec_t * nrec, shape);
         if (st != FGA_OK) return st;
     }
     return FGA_OK;

@@ -86,7 +86,7 @@ __global__ void k_det_bounds(const unsigned *__restrict__ keys, int64_t total, i
 __global__ void __launch_bounds__(256)
 k_det_cellsum(const int *__restrict__ begin, const int *__restrict__ end,
               const unsigned long long *__restrict__ slots, const double *__restrict__ rec,
-              int64_t cap, int ncell, double *__restrict__ tot)
+              int ncell, double *__restrict__ tot)
 {
     const int c = blockIdx.x * 4 + (threadIdx.x >> 6);   // uniform in the wavefront
     const int lane = threadIdx.x & 63;
@@ -95,11 +95,13 @@ k_det_cellsum(const int *__restrict__ begin, const int *__restrict__ end,
 #pragma unroll
     for (int m = 0; m < 16; ++m) t[m] = 0.0;
     for (int j = begin[c] + lane; j < end[c]; j += 64) {
-        const unsigned long long s = slots[j];
-        const unsigned long long k = s / (unsigned long long)cap, b = s - k * cap;
-        const double *r = rec + (size_t)k * 16 * cap + b;
+        const double2 *r = (const double2 *)(rec + (size_t)slots[j] * 16);
 #pragma unroll
-        for (int m = 0; m < 16; ++m) t[m] += r[(size_t)m * cap];
+        for (int m = 0; m < 8; ++m) {
+            const double2 v = r[m];
+            t[2 * m] += v.x;
+            t[2 * m + 1] += v.y;
+        }
     }
 #pragma unroll
     for (int m = 0; m < 16; ++m)
@@ -132,7 +134,7 @@ __global__ void k_det_gather(const double *__restrict__ tot, int n1, int n2, dou
     dc[(size_t)r * n1 + q] += acc;
 }
 
-// Layout of the log buffer for R slots per beam: records [R][16][cap] doubles,
+// Layout of the log buffer for R slots per beam: records [R][cap][16] doubles,
 // cells [R][cap] ints, lengths [cap] ints.
 static const int *det_counts(const fga_ctx *ctx, int64_t cap, int R)
 {
@@ -227,7 +229,7 @@ fga_status fga_det_reduce(fga_ctx *ctx, int64_t cap, int R, int64_t nb, int64_t 
     hipLaunchKernelGGL(k_det_zero_i32, dim3(blocks), dim3(256), 0, st, begin, (int64_t)2 * ncell);
     hipLaunchKernelGGL(k_det_bounds, dim3(blocks), dim3(256), 0, st, keys_s, total, begin, end);
     hipLaunchKernelGGL(k_det_cellsum, dim3((ncell + 3) / 4), dim3(256), 0, st, begin, end,
-                       slots_s, rec, cap, ncell, tot);
+                       slots_s, rec, ncell, tot);
     hipLaunchKernelGGL(k_det_gather, dim3((n1 + 255) / 256, n2), dim3(256), 0, st, tot, n1, n2,
                        dc);
     FGA_HIP(ctx, hipGetLastError());

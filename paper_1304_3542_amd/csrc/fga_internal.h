@@ -53,6 +53,8 @@ struct fga_ctx {
     // adjoint workspaces and the branch count of the last decomposition
     void *adj_scratch, *adj_psib;
     size_t adj_scratch_bytes, adj_psib_bytes;
+    void *rec_shape;       // [4] ints: receivers one run of a row? (first column, row)
+    size_t rec_shape_bytes;
     int last_nfj, last_nshots;
 
     // deterministic gradient: per-beam dJ/dc logs, the sort and cell
@@ -95,9 +97,13 @@ fga_status fga_launch_propagate(fga_ctx *ctx, fga_beams *beams, int nshots, int 
                                 double *ckpt);
 fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nshots,
                                   double *u);
+// Classify the receiver list on the device (no synchronisation): *shape
+// receives a device pointer to {run, first column, row, run traced per beam}
+// with run = 1 when rec[r] = rec[0] + r all lie in rec[0]'s row.
+fga_status fga_rec_shape(fga_ctx *ctx, const int32_t *rec, int nrec, const int **shape);
 fga_status fga_launch_trace_points(fga_ctx *ctx, const fga_beams *beams, int nshots,
                                    const int32_t *rec, int nrec, double *out,
-                                   int64_t out_stride_shot);
+                                   int64_t out_stride_shot, const int *shape);
 
 fga_status fga_launch_trace_adjoint(fga_ctx *ctx, const fga_beams *beams, int nshots,
                                     const int32_t *rec, int nrec, int rec_every, int nrec_t,

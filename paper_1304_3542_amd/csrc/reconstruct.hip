@@ -408,17 +408,170 @@ fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nsho
 }
 
 // ------------------------------------------------------------------ traces
-// u at receiver nodes.  Workgroup (split, shot, receiver block): one thread
-// per receiver, one slice of the shot's beams staged through LDS; the slices
-// write partial sums that a second kernel adds in slice order.
+// u at receiver nodes.  Workgroup (split, shot, receiver block), one slice of
+// the shot's beams per split; the slices write partial sums that a second
+// kernel adds in slice order.  Two forms, chosen on the device:
+//  * receivers in general position: one thread per receiver, the slice's
+//    beams staged through LDS, a direct exp and sincos per pair;
+//  * receivers one run of consecutive nodes of a row (at most TR_ROW_MAX):
+//    one lane per beam.  Along the row e(x) = e^{(i (S + P.r) - |r|^2/2)/eps}
+//    (r = x - Q) steps from one column to the next by the factor rho, and
+//    rho itself by the real e^{-d1^2 / eps}, so a beam costs one direct
+//    evaluation and a complex product per column of its box.  The lanes'
+//    terms at 16 columns at a time are summed over the wavefront by a fixed
+//    reduce-scatter (four halving exchanges leave each lane one column's
+//    sum over 16 lanes, two butterfly steps finish it), per wavefront in
+//    LDS, and the four wavefronts in order.
 #define TR_BLOCK 256
+#define TR_ROW_MAX 1024
+
+// Whether the receivers are one run of consecutive nodes of a row: shape =
+// {run, first column, row, run and nrec <= TR_ROW_MAX}.
+__global__ void k_rec_shape(const int32_t *__restrict__ rec, int nrec, int n1, int *shape)
+{
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    const int r0 = rec[0];
+    for (int r = threadIdx.x; r < nrec; r += blockDim.x)
+        if (rec[r] != r0 + r) atomicOr(&bad, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int ok = !bad && r0 >= 0 && r0 % n1 + nrec <= n1;
+        shape[0] = ok;
+        shape[1] = ok ? r0 % n1 : 0;
+        shape[2] = ok ? r0 / n1 : 0;
+        shape[3] = ok && nrec <= TR_ROW_MAX;
+    }
+}
+
+fga_status fga_rec_shape(fga_ctx *ctx, const int32_t *rec, int nrec, const int **shape)
+{
+    fga_status rc = fga_ensure(ctx, &ctx->rec_shape, &ctx->rec_shape_bytes, 4 * sizeof(int),
+                               "receiver layout");
+    if (rc != FGA_OK) return rc;
+    hipLaunchKernelGGL(k_rec_shape, dim3(1), dim3(256), 0, ctx->stream, rec, nrec, ctx->g.n1,
+                       (int *)ctx->rec_shape);
+    FGA_HIP(ctx, hipGetLastError());
+    *shape = (const int *)ctx->rec_shape;
+    return FGA_OK;
+}
+
+__device__ __forceinline__ int tr_wave_min(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int tr_wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// the row form for beams [lo, hi) of one shot: out[r] for the receiver at
+// column run1 + r of row run2; acc = [4][nrec] doubles of LDS
+__device__ void trace_row(const SplatArgs &A, double *acc, int run1, int run2, int nrec,
+                          int64_t lo, int64_t hi, double *out)
+{
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = threadIdx.x; i < 4 * nrec; i += TR_BLOCK) acc[i] = 0.0;
+    __syncthreads();
+    double *mine = acc + w * nrec;
+    const int64_t cap = A.cap;
+    const double x2 = A.o2 + run2 * A.d2;
+    const double kap = exp(-A.d1 * A.d1 * A.inv_eps);
+    for (int64_t base = lo + 64 * w; base < hi; base += 4 * 64) {
+        const int64_t b = base + lane;
+        int a1 = 1, b1 = 0;                       // empty column range
+        double er = 0.0, ei = 0.0, rr = 0.0, ri = 0.0, Wr = 0.0, Wi = 0.0;
+        if (b < hi) {
+            const double *p = A.f + b;
+            const double Q1 = p[(FGA_F_STATE + 0) * cap], Q2 = p[(FGA_F_STATE + 1) * cap];
+            const BeamBox bx = beam_box(Q1, Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
+            if (run2 >= bx.lo2 && run2 <= bx.hi2) {
+                a1 = max(bx.lo1, run1);
+                b1 = min(bx.hi1, run1 + nrec - 1);
+            }
+            if (a1 <= b1) {
+                const double P1 = p[(FGA_F_STATE + 2) * cap], P2 = p[(FGA_F_STATE + 3) * cap];
+                const double S = p[(FGA_F_STATE + 4) * cap];
+                const double ar = p[(FGA_F_STATE + 21) * cap], ai = p[(FGA_F_STATE + 22) * cap];
+                const double Cr = p[4 * cap], Ci = p[5 * cap];
+                Wr = Cr * ar - Ci * ai;
+                Wi = Cr * ai + Ci * ar;
+                const double r2 = x2 - Q2, r1 = (A.o1 + a1 * A.d1) - Q1;
+                double sn, cs;
+                sincos((S + P1 * r1 + P2 * r2) * A.inv_eps, &sn, &cs);
+                double e = exp(-(r1 * r1 + r2 * r2) * A.half_inv_eps);
+                er = e * cs;
+                ei = e * sn;
+                sincos(P1 * A.d1 * A.inv_eps, &sn, &cs);
+                e = exp(-(r1 + 0.5 * A.d1) * A.d1 * A.inv_eps);
+                rr = e * cs;
+                ri = e * sn;
+            }
+        }
+        const int u0 = tr_wave_min(a1 <= b1 ? a1 : 2147483647);
+        const int u1 = tr_wave_max(a1 <= b1 ? b1 : -2147483647 - 1);
+        // the column this lane ends up holding in each chunk of 16
+        const int jl = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
+                       ((lane >> 2) & 1);
+        for (int c0 = u0; c0 <= u1; c0 += 16) {
+            double v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                v[j] = 0.0;
+                if (c0 + j >= a1 && c0 + j <= b1) {
+                    v[j] = Wr * er - Wi * ei;
+                    const double t = er * rr - ei * ri;
+                    ei = er * ri + ei * rr;
+                    er = t;
+                    rr *= kap;
+                    ri *= kap;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int m = 32 >> s, h = 8 >> s;
+                const bool up = (lane & m) != 0;
+#pragma unroll
+                for (int j = 0; j < h; ++j) {
+                    const double send = up ? v[j] : v[j + h];
+                    const double keep = up ? v[j + h] : v[j];
+                    v[j] = keep + __shfl_xor(send, m, 64);
+                }
+            }
+            double t = v[0];
+            t += __shfl_xor(t, 2, 64);
+            t += __shfl_xor(t, 1, 64);
+            if ((lane & 3) == 0 && c0 + jl <= u1) mine[c0 + jl - run1] += t;
+        }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < nrec; r += TR_BLOCK)
+        out[r] = ((acc[r] + acc[nrec + r]) + acc[2 * nrec + r]) + acc[3 * nrec + r];
+}
 
 __global__ void __launch_bounds__(TR_BLOCK)
-k_trace_points(SplatArgs A, const int32_t *__restrict__ rec, int nrec, double *partial)
+k_trace_points(SplatArgs A, const int32_t *__restrict__ rec, int nrec,
+               const int *__restrict__ shape, double *partial)
 {
-    __shared__ double sb[7][TR_BLOCK];
-    __shared__ int4 sbox[TR_BLOCK];   // truncation box of each staged beam
+    __shared__ double lds[4 * TR_ROW_MAX];
     const int split = blockIdx.x, s = blockIdx.y;
+    const int64_t b0 = A.offsets[s], b1 = A.offsets[s + 1];
+    const int64_t nbs = b1 - b0;
+    const int64_t lo = b0 + nbs * split / A.nsplit, hi = b0 + nbs * (split + 1) / A.nsplit;
+    if (shape[3]) {
+        if (blockIdx.z == 0)
+            trace_row(A, lds, shape[1], shape[2], nrec, lo, hi,
+                      partial + ((size_t)s * A.nsplit + split) * nrec);
+        return;
+    }
+    double (*sb)[TR_BLOCK] = (double (*)[TR_BLOCK])lds;
+    int4 *sbox = (int4 *)(lds + 7 * TR_BLOCK);   // truncation box of each staged beam
     const int r = blockIdx.z * TR_BLOCK + threadIdx.x;
     int i1 = 0, i2 = 0;
     if (r < nrec) {
@@ -427,9 +580,6 @@ k_trace_points(SplatArgs A, const int32_t *__restrict__ rec, int nrec, double *p
         i2 = node / A.n1;
     }
     const double x1 = A.o1 + i1 * A.d1, x2 = A.o2 + i2 * A.d2;
-    const int64_t b0 = A.offsets[s], b1 = A.offsets[s + 1];
-    const int64_t nbs = b1 - b0;
-    const int64_t lo = b0 + nbs * split / A.nsplit, hi = b0 + nbs * (split + 1) / A.nsplit;
     const int64_t cap = A.cap;
     double acc = 0.0;
     for (int64_t base = lo; base < hi; base += TR_BLOCK) {
@@ -484,7 +634,7 @@ __global__ void k_trace_reduce(const double *__restrict__ partial, int nsplit, i
 
 fga_status fga_launch_trace_points(fga_ctx *ctx, const fga_beams *beams, int nshots,
                                    const int32_t *rec, int nrec, double *out,
-                                   int64_t stride_shot)
+                                   int64_t stride_shot, const int *shape)
 {
     const fga_grid &g = ctx->g;
     const int rblocks = (nrec + TR_BLOCK - 1) / TR_BLOCK;
@@ -511,7 +661,7 @@ fga_status fga_launch_trace_points(fga_ctx *ctx, const fga_beams *beams, int nsh
     A.Rw2 = ctx->Rw2;
     A.nsplit = nsplit;
     hipLaunchKernelGGL(k_trace_points, dim3(nsplit, nshots, rblocks), dim3(TR_BLOCK), 0,
-                       ctx->stream, A, rec, nrec, (double *)ctx->trace_part);
+                       ctx->stream, A, rec, nrec, shape, (double *)ctx->trace_part);
     hipLaunchKernelGGL(k_trace_reduce, dim3((nrec * nshots + 255) / 256), dim3(256), 0,
                        ctx->stream, (const double *)ctx->trace_part, nsplit, nrec, nshots, out,
                        stride_shot);

@@ -39,7 +39,8 @@ def _structs(grid, params):
     p = fga.fga_params(params.eps, params.qb1, params.qb2, params.qs1, params.qs2, params.nq1,
                        params.nq2, params.np1, params.np2, params.dp1, params.dp2, params.tau,
                        params.tau_fbi, params.tau_win, params.dt, params.top_n, params.amp_closed,
-                       params.dz_divided, params.dz_scale, params.deterministic)
+                       params.dz_divided, params.dz_scale, params.deterministic,
+                       params.grad_log)
     return g, p
 
 
@@ -48,7 +49,7 @@ def _structs(grid, params):
     dict(qs2=0), dict(qb1=-1), dict(nq1=1000), dict(tau=1.5), dict(tau_fbi=0.0),
     dict(tau_win=1.0), dict(dt=-1e-3), dict(dp1=0.0), dict(top_n=-1), dict(amp_closed=2),
     dict(dz_divided=2, amp_closed=1), dict(dz_divided=1),
-    dict(dz_divided=1, amp_closed=1, dz_scale=0.0), dict(deterministic=2),
+    dict(dz_divided=1, amp_closed=1, dz_scale=0.0), dict(deterministic=2), dict(grad_log=-2),
 ])
 def test_create_rejects_bad_params(bad):
     import paper_1304_3542_amd as fga

@@ -249,3 +249,30 @@ def test_propagate_adjoint_dot_product_with_oracle_tangent():
     norm = np.linalg.norm(Mv) * np.linalg.norm(w)
     assert abs(lhs) > 1e-4 * norm
     assert abs(lhs - rhs) <= 1e-12 * norm, (lhs, rhs, norm)
+
+
+@pytest.mark.parametrize("deterministic", [0, 1])
+def test_gradient_entry_points_with_no_beams(deterministic):
+    """f0 = 0 keeps no beam: every gradient entry point runs, leaves dc and
+    df0 at zero and reports no error (atomic and deterministic modes)."""
+    import torch
+    import paper_1304_3542_amd as fga
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(False)
+    ns = f0.shape[0]
+    p = p.replace(deterministic=deterministic)
+    ctx, beams = _ctx(g, p, c, ns)
+    ctx.decompose(torch.zeros((ns, g.n2, g.n1), dtype=torch.float64, device="cuda"), None, beams)
+    assert int(ctx.offsets(beams, ns)[-1]) == 0
+    ckpt = ctx.propagate_ckpt(beams, ns, 5, 3)
+    u = ctx.reconstruct(beams, ns)
+    assert float(u.abs().max()) == 0.0
+    dstate, dcoef = ctx.reconstruct_adjoint(beams, ns, torch.ones_like(u))
+    dc = torch.zeros((g.n2, g.n1), dtype=torch.float64, device="cuda")
+    ctx.propagate_adjoint(beams, ns, 5, 3, ckpt, dstate, dc)
+    rec_t = torch.from_numpy(rec).cuda()
+    ck2 = torch.empty((nrec, fga.FGA_NSTATE, beams.capacity), dtype=torch.float64, device="cuda")
+    tr = ctx.trace(beams, ns, rec_t, every, nrec, ck2)
+    gcoef = ctx.trace_adjoint(beams, ns, rec_t, every, nrec, ck2, torch.ones_like(tr), dc)
+    df0 = ctx.decompose_adjoint(beams, ns, gcoef)
+    assert ctx.status()[0] == 0
+    assert float(dc.abs().max()) == 0.0 and float(df0.abs().max()) == 0.0

@@ -124,11 +124,18 @@ def test_invalid_arguments_rejected_on_host():
     assert e.value.status == fga.FGA_ESTATE
 
 
-def test_trace_matches_oracle():
+@pytest.mark.parametrize("layout", ["scattered", "row", "part_row", "one"])
+def test_trace_matches_oracle(layout):
+    """Traces against the oracle's for receivers in general position (one
+    thread per receiver) and for runs of one row (one lane per beam, the
+    factors stepped along the row)."""
     import torch
     import paper_1304_3542_amd as fga
     g, p, c, f0, _ = small_case(seed=23, nshots=2, with_f1=False)
-    rec = np.arange(0, g.n1 * 3, 2, dtype=np.int32)        # rows 0..2, every other node
+    rec = {"scattered": np.arange(0, g.n1 * 3, 2),        # rows 0..2, every other node
+           "row": np.arange(g.n1, 2 * g.n1),              # all of row 1
+           "part_row": 7 * g.n1 + np.arange(5, 41),       # columns 5..40 of row 7
+           "one": np.array([4 * g.n1 + 9])}[layout].astype(np.int32)
     b = oracle.decompose(f0, None, c, g, p)
     tr_or = oracle.trace(b, c, g, p, rec, rec_every=5, nrec=4)
     ctx = fga.FGA(g, p, "fp64", max_shots=2)
