@@ -12,6 +12,7 @@
 // Beam record: f[53][capacity] = q(3), p(3), C(re, im), state(45) with the
 // state Q(3) P(3) S A[3][3](re, im) B[3][3](re, im) a(re, im).
 #include <limits.h>
+#include <algorithm>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -45,6 +46,8 @@ struct fga3_ctx {
     unsigned long long *maxbits;
     int64_t *blk;
     size_t blk_bytes;
+    void *part;            // splat partial sums [nshots][nsplit][n3][n2][n1]
+    size_t part_bytes;
     int64_t *status;
     char err[512];
 };
@@ -722,101 +725,166 @@ __global__ void __launch_bounds__(64) k3_rk4(const double *__restrict__ c, fga3_
 
 // ------------------------------------------------------------------ step 3
 //
-// One workgroup per 8 x 8 x 4 tile of nodes (a node per thread).  The beams
-// of the tile's shot are taken 128 at a time: their truncation boxes are
-// tested against the tile, and for the boxes that meet it the separable
-// factors g_a(x_a) = exp(i P_a r_a/eps - r_a^2/(2 eps)) at the tile's 8, 8
-// and 4 coordinates and W = C a exp(iS/eps) go to LDS; then every node adds
-// Re(W g1 g2 g3) of the beams whose box holds it, in beam order.
-#define T3X 8
-#define T3Y 8
-#define T3Z 4
-#define T3B 128
+// A workgroup takes one tile of 16 (x1) x 16 (x2) x 64 (x3) nodes and one
+// slice of a shot's beams (each shot's beams are cut into nsplit slices).
+// Thread (l1, g) owns the 4 x 16 nodes (X0 + l1, Y0 + j, Z0 + 4 g + q).  The
+// sum is separable: with r_a = x_a - Q_a,
+//   g_a(x_a) = exp(i P_a r_a / eps - r_a^2 / (2 eps)),   W = C a exp(iS/eps),
+// a beam adds Re(W g1 g2 g3) inside its truncation box and nothing outside.
+// The beams are staged 32 at a time, their factors at the tile's
+// coordinates formed as six runs of 16 (x1, x2 and four quarters of x3), one
+// thread per (beam, run), zero outside the box: a direct evaluation at the
+// run's first node inside the box, then
+//   g(x + d) = g(x) rho(x),   rho(x + d) = rho(x) exp(-d^2 / eps)
+// (exact identities of the Gaussian; the products add rounding over at most
+// 15 steps); the x1 factors carry W.  Every thread then forms
+// H_q = W g1(x1) g3(x3_q) for its four x3 once per beam and adds
+// Re(H_q g2(x2)) to its 64 nodes (two FMAs each); the 16 g2 are read by the
+// whole wavefront from the same LDS addresses.  The slices' partial sums are
+// added in slice order by k3_splat_reduce.
+#define T3E 16   // tile edge in x1 and x2, and the length of every factor run
+#define T3Z 64   // tile edge in x3
+#define T3B 32   // beams staged per round
 
-__global__ void __launch_bounds__(256) k3_splat(fga_beams B, int nshots, fga3_grid G, double eps,
-                                                int Rw1, int Rw2, int Rw3, double *u)
+__global__ void __launch_bounds__(256) k3_splat(fga_beams B, fga3_grid G, double eps, int Rw1,
+                                                int Rw2, int Rw3, int nsplit,
+                                                double *__restrict__ partial)
 {
-    __shared__ double2 sW[T3B], sg1[T3B][T3X], sg2[T3B][T3Y], sg3[T3B][T3Z];
-    __shared__ int sbox[T3B][6];
-    __shared__ int sflag[T3B];
-    const int tz = blockIdx.z % ((G.n3 + T3Z - 1) / T3Z);
-    const int s = blockIdx.z / ((G.n3 + T3Z - 1) / T3Z);
-    const int X0 = blockIdx.x * T3X, Y0 = blockIdx.y * T3Y, Z0 = tz * T3Z;
-    const int tid = threadIdx.x;
-    const int i1 = X0 + (tid % T3X), i2 = Y0 + (tid / T3X) % T3Y, i3 = Z0 + tid / (T3X * T3Y);
+    // runs: 0 = x1 (times W), 1 = x2, 2..5 = x3 quarters
+    __shared__ double2 sg[6][T3B][T3E];
+    __shared__ int smeet[6][T3B];
+    __shared__ int sflag[T3B];   // the beam's box meets the tile
+    const int nt1 = (G.n1 + T3E - 1) / T3E;
+    const int X0 = (blockIdx.x % nt1) * T3E, Z0 = (blockIdx.x / nt1) * T3Z;
+    const int Y0 = blockIdx.y * T3E;
+    const int split = blockIdx.z % nsplit, s = blockIdx.z / nsplit;
+    const int tid = threadIdx.x, l1 = tid % T3E, gq = tid / T3E;
     const int64_t cap = B.capacity;
-    const int64_t b0 = B.offsets[s], b1 = B.offsets[s + 1];
+    const int64_t b0 = B.offsets[s], b1 = B.offsets[s + 1], nbs = b1 - b0;
+    const int64_t lo = b0 + nbs * split / nsplit, hi = b0 + nbs * (split + 1) / nsplit;
     const double ieps = 1.0 / eps, hieps = 0.5 / eps;
-    double acc = 0.0;
-    for (int64_t c0 = b0; c0 < b1; c0 += T3B) {
-        const int nc = (int)min((int64_t)T3B, b1 - c0);
-        if (tid < nc) {
-            const double *f = B.f + (size_t)F3_FS * cap + c0 + tid;
-            const double Q[3] = {f[0], f[cap], f[2 * cap]};
-            const double d[3] = {G.d1, G.d2, G.d3}, o[3] = {G.o1, G.o2, G.o3};
-            const int n[3] = {G.n1, G.n2, G.n3}, Rw[3] = {Rw1, Rw2, Rw3};
-            const int t0[3] = {X0, Y0, Z0}, tl[3] = {T3X, T3Y, T3Z};
-            bool meet = true;
-            for (int a = 0; a < 3; ++a) {
-                double t = floor((Q[a] - o[a]) / d[a] + 0.5);
+    double acc[4][T3E];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int j = 0; j < T3E; ++j) acc[q][j] = 0.0;
+    for (int64_t c0 = lo; c0 < hi; c0 += T3B) {
+        const int nc = (int)min((int64_t)T3B, hi - c0);
+        if (tid < 6 * T3B) {
+            const int run = tid / T3B, bb = tid % T3B;
+            const int a = run < 2 ? run : 2;           // axis of the run
+            double2 *g = sg[run][bb];
+            int m0 = 1, m1 = 0;                        // empty range
+            double gr = 0.0, gi = 0.0, rr = 0.0, ri = 0.0, kap = 0.0;
+            if (bb < nc) {
+                const double *f = B.f + (size_t)F3_FS * cap + c0 + bb;
+                const double o = a == 0 ? G.o1 : (a == 1 ? G.o2 : G.o3);
+                const double d = a == 0 ? G.d1 : (a == 1 ? G.d2 : G.d3);
+                const int n = a == 0 ? G.n1 : (a == 1 ? G.n2 : G.n3);
+                const int Rw = a == 0 ? Rw1 : (a == 1 ? Rw2 : Rw3);
+                const int t0 = a == 0 ? X0 : (a == 1 ? Y0 : Z0 + (run - 2) * T3E);
+                const double Q = f[(size_t)a * cap], P = f[(size_t)(3 + a) * cap];
+                double t = floor((Q - o) / d + 0.5);
                 t = fmin(fmax(t, -1e8), 1e8);
                 const int cn = (int)t;
-                const int lo = max(cn - Rw[a], 0), hi = min(cn + Rw[a], n[a] - 1);
-                sbox[tid][2 * a] = lo;
-                sbox[tid][2 * a + 1] = hi;
-                meet = meet && lo <= t0[a] + tl[a] - 1 && hi >= t0[a] && lo <= hi;
+                const int blo = max(cn - Rw, 0), bhi = min(cn + Rw, n - 1);
+                m0 = max(blo - t0, 0);
+                m1 = min(bhi - t0, T3E - 1);
+                if (m0 <= m1) {
+                    const double r = (o + (t0 + m0) * d) - Q;
+                    double sn, cs;
+                    sincos(P * r * ieps, &sn, &cs);
+                    double e = exp(-r * r * hieps);
+                    gr = e * cs;
+                    gi = e * sn;
+                    if (run == 0) {
+                        const double S = f[6 * cap];
+                        const double Cr = B.f[(size_t)6 * cap + c0 + bb];
+                        const double Ci = B.f[(size_t)7 * cap + c0 + bb];
+                        const double ar = f[(size_t)43 * cap], ai = f[(size_t)44 * cap];
+                        sincos(S * ieps, &sn, &cs);
+                        const double wr0 = Cr * ar - Ci * ai, wi0 = Cr * ai + Ci * ar;
+                        const double wr = wr0 * cs - wi0 * sn, wi = wr0 * sn + wi0 * cs;
+                        const double t2 = wr * gr - wi * gi;
+                        gi = wr * gi + wi * gr;
+                        gr = t2;
+                    }
+                    sincos(P * d * ieps, &sn, &cs);
+                    e = exp(-(r + 0.5 * d) * d * ieps);
+                    rr = e * cs;
+                    ri = e * sn;
+                    kap = exp(-d * d * ieps);
+                }
             }
-            sflag[tid] = meet;
-            if (meet) {
-                const double S = f[6 * cap];
-                const double Cr = B.f[(size_t)6 * cap + c0 + tid];
-                const double Ci = B.f[(size_t)7 * cap + c0 + tid];
-                const double ar = f[(size_t)43 * cap], ai = f[(size_t)44 * cap];
-                double sn, cs;
-                sincos(S * ieps, &sn, &cs);
-                const double wr = Cr * ar - Ci * ai, wi = Cr * ai + Ci * ar;
-                sW[tid] = double2{wr * cs - wi * sn, wr * sn + wi * cs};
+            smeet[run][bb] = m0 <= m1;
+#pragma unroll
+            for (int m = 0; m < T3E; ++m) {
+                if (m < m0 || m > m1) {
+                    g[m] = double2{0.0, 0.0};
+                } else {
+                    g[m] = double2{gr, gi};
+                    const double t2 = gr * rr - gi * ri;
+                    gi = gr * ri + gi * rr;
+                    gr = t2;
+                    rr *= kap;
+                    ri *= kap;
+                }
             }
         }
         __syncthreads();
-        // the factors of the beams that meet the tile: 20 per beam
-        for (int idx = tid; idx < nc * (T3X + T3Y + T3Z); idx += 256) {
-            const int bb = idx / (T3X + T3Y + T3Z), k = idx % (T3X + T3Y + T3Z);
-            if (!sflag[bb]) continue;
-            const double *f = B.f + (size_t)F3_FS * cap + c0 + bb;
-            int a, m;
-            if (k < T3X) { a = 0; m = k; }
-            else if (k < T3X + T3Y) { a = 1; m = k - T3X; }
-            else { a = 2; m = k - T3X - T3Y; }
-            const double o = a == 0 ? G.o1 : (a == 1 ? G.o2 : G.o3);
-            const double d = a == 0 ? G.d1 : (a == 1 ? G.d2 : G.d3);
-            const int base = a == 0 ? X0 : (a == 1 ? Y0 : Z0);
-            const double r = (o + (base + m) * d) - f[(size_t)a * cap];
-            const double P = f[(size_t)(3 + a) * cap];
-            double sn, cs;
-            sincos(P * r * ieps, &sn, &cs);
-            const double e = exp(-r * r * hieps);
-            const double2 g = double2{e * cs, e * sn};
-            if (a == 0) sg1[bb][m] = g;
-            else if (a == 1) sg2[bb][m] = g;
-            else sg3[bb][m] = g;
-        }
+        if (tid < T3B)
+            sflag[tid] = smeet[0][tid] && smeet[1][tid] &&
+                         (smeet[2][tid] || smeet[3][tid] || smeet[4][tid] || smeet[5][tid]);
         __syncthreads();
-        const int l1 = tid % T3X, l2 = (tid / T3X) % T3Y, l3 = tid / (T3X * T3Y);
+        // thread gq's four x3 lie in quarter gq / 4 of the x3 run
+        const int qr = 2 + gq / 4, qm = 4 * (gq % 4);
         for (int bb = 0; bb < nc; ++bb) {
             if (!sflag[bb]) continue;
-            if (i1 < sbox[bb][0] || i1 > sbox[bb][1] || i2 < sbox[bb][2] || i2 > sbox[bb][3] ||
-                i3 < sbox[bb][4] || i3 > sbox[bb][5])
-                continue;
-            const double2 w = sW[bb], g1 = sg1[bb][l1], g2 = sg2[bb][l2], g3 = sg3[bb][l3];
-            const double p12r = g1.x * g2.x - g1.y * g2.y, p12i = g1.x * g2.y + g1.y * g2.x;
-            const double pr = p12r * g3.x - p12i * g3.y, pi = p12r * g3.y + p12i * g3.x;
-            acc += w.x * pr - w.y * pi;
+            const double2 g1 = sg[0][bb][l1];
+            double hr[4], hm[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double2 g3 = sg[qr][bb][qm + q];
+                hr[q] = g1.x * g3.x - g1.y * g3.y;
+                hm[q] = g1.x * g3.y + g1.y * g3.x;
+            }
+            const double2 *g2 = sg[1][bb];
+#pragma unroll
+            for (int j = 0; j < T3E; ++j) {
+                const double2 v = g2[j];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q][j] += hr[q] * v.x - hm[q] * v.y;
+            }
         }
         __syncthreads();
     }
-    if (i1 < G.n1 && i2 < G.n2 && i3 < G.n3)
-        u[(((size_t)s * G.n3 + i3) * G.n2 + i2) * G.n1 + i1] = acc;
+    const int i1 = X0 + l1;
+    if (i1 < G.n1) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i3 = Z0 + 4 * gq + q;
+            if (i3 >= G.n3) continue;
+            double *pp =
+                partial + ((size_t)(s * nsplit + split) * G.n3 + i3) * G.n2 * G.n1 + i1;
+#pragma unroll
+            for (int j = 0; j < T3E; ++j)
+                if (Y0 + j < G.n2) pp[(size_t)(Y0 + j) * G.n1] = acc[q][j];
+        }
+    }
+}
+
+// u[s][node] = the slices' partial sums added in slice order
+__global__ void k3_splat_reduce(const double *__restrict__ partial, int nsplit, int nshots,
+                                int64_t npts, double *__restrict__ u)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nshots * npts;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = i / npts, k = i - s * npts;
+        const double *p = partial + (size_t)s * nsplit * npts + k;
+        double v = 0.0;
+        for (int sp = 0; sp < nsplit; ++sp) v += p[(size_t)sp * npts];
+        u[i] = v;
+    }
 }
 
 // ------------------------------------------------------------------ C ABI
@@ -916,7 +984,7 @@ extern "C" fga_status fga3_destroy(fga3_ctx *ctx)
     if (!ctx) return FGA_OK;
     (void)hipStreamSynchronize(ctx->stream);
     void *bufs[] = {ctx->c, ctx->status, ctx->maxbits, ctx->E[0], ctx->E[1], ctx->E[2],
-                    ctx->T1, ctx->T2, ctx->Psi, ctx->cq, ctx->blk};
+                    ctx->T1, ctx->T2, ctx->Psi, ctx->cq, ctx->blk, ctx->part};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     free(ctx);
@@ -1018,10 +1086,21 @@ extern "C" fga_status fga3_reconstruct(fga3_ctx *ctx, const fga_beams *beams, in
     if (st != FGA_OK) return st;
     if (!u) return f3_fail(ctx, FGA_EINVAL, "u is null");
     const fga3_grid &G = ctx->g;
-    dim3 grid((G.n1 + T3X - 1) / T3X, (G.n2 + T3Y - 1) / T3Y,
-              (unsigned)(((G.n3 + T3Z - 1) / T3Z) * nshots));
-    hipLaunchKernelGGL(k3_splat, grid, dim3(256), 0, ctx->stream, *beams, nshots, G, ctx->p.eps,
-                       ctx->Rw[0], ctx->Rw[1], ctx->Rw[2], u);
+    const int nt1 = (G.n1 + T3E - 1) / T3E, nt2 = (G.n2 + T3E - 1) / T3E;
+    const int nt3 = (G.n3 + T3Z - 1) / T3Z;
+    const int64_t units = (int64_t)nt1 * nt2 * nt3 * nshots;
+    int64_t want = std::max<int64_t>(1, (4 * ctx->num_cu + units - 1) / units);
+    want = std::min<int64_t>(want, std::min<int64_t>(32, std::max(1, 65535 / nshots)));
+    const int nsplit = (int)want;
+    const int64_t npts = (int64_t)G.n1 * G.n2 * G.n3;
+    st = f3_ensure(ctx, &ctx->part, &ctx->part_bytes,
+                   (size_t)nshots * nsplit * npts * sizeof(double), "splat partial sums");
+    if (st != FGA_OK) return st;
+    dim3 grid((unsigned)(nt1 * nt3), (unsigned)nt2, (unsigned)(nsplit * nshots));
+    hipLaunchKernelGGL(k3_splat, grid, dim3(256), 0, ctx->stream, *beams, G, ctx->p.eps,
+                       ctx->Rw[0], ctx->Rw[1], ctx->Rw[2], nsplit, (double *)ctx->part);
+    hipLaunchKernelGGL(k3_splat_reduce, dim3(ctx->num_cu * 4), dim3(256), 0, ctx->stream,
+                       (const double *)ctx->part, nsplit, nshots, npts, u);
     F3_HIP(ctx, hipGetLastError());
     return FGA_OK;
 }
