@@ -24,34 +24,6 @@ struct Fac {
     R re, im;
 };
 
-// factor e^{i theta + G} times coef (complex, double) in precision R
-template <typename R>
-__device__ __forceinline__ Fac<R> factor(double theta, double G, double cr, double ci);
-
-template <>
-__device__ __forceinline__ Fac<double> factor<double>(double theta, double G, double cr, double ci)
-{
-    double s, c;
-    sincos(theta, &s, &c);
-    double e = exp(G);
-    double wr = e * c, wi = e * s;
-    return {cr * wr - ci * wi, cr * wi + ci * wr};
-}
-
-template <>
-__device__ __forceinline__ Fac<float> factor<float>(double theta, double G, double cr, double ci)
-{
-    // reduce the phase to [-pi, pi] in double before the FP32 sincos
-    const double inv2pi = 0.15915494309189535, twopi = 6.283185307179586;
-    double red = fma(-twopi, rint(theta * inv2pi), theta);
-    float s, c;
-    sincosf((float)red, &s, &c);
-    float e = expf((float)G);
-    float wr = e * c, wi = e * s;
-    float fr = (float)cr, fi = (float)ci;
-    return {fr * wr - fi * wi, fr * wi + fi * wr};
-}
-
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_splat(SplatArgs A)
@@ -107,44 +79,67 @@ k_splat(SplatArgs A)
         if (hit) lst[wb + before] = t;
         __syncthreads();
 
-        // 2. factor batches and rank-one accumulation
+        // 2. factor batches and rank-one accumulation.  Sixteen threads per
+        // beam: thread sub forms 8 consecutive factors of one axis (sub / 8:
+        // U along x1 with C a e^{iS/eps}, V along x2), zero outside the box,
+        // by one direct evaluation at the run's first node in the box and
+        // then g(x + d) = g(x) rho(x), rho(x + d) = rho(x) e^{-d^2/eps}
+        // (exact identities of the Gaussian, evaluated in FP64).
         for (int k0 = 0; k0 < nlist; k0 += SP_KC) {
             {
-                int k = t >> 4, sub = t & 15;
+                const int k = t >> 4, sub = t & 15;
+                const int ax = sub >> 3, x0 = 8 * (sub & 7);
+                Fac<R> *dst = ax == 0 ? &U[k][x0] : &Vf[k][x0];
+                int m0 = 1, m1 = 0;                        // empty run
+                double gr = 0.0, gi = 0.0, rr = 0.0, ri = 0.0, kap = 0.0;
                 if (k0 + k < nlist) {
                     int64_t bb = base + lst[k0 + k];
                     const double *p = F + bb;
-                    double Q1 = p[(FGA_F_STATE + 0) * cap], Q2 = p[(FGA_F_STATE + 1) * cap];
-                    double P1 = p[(FGA_F_STATE + 2) * cap], P2 = p[(FGA_F_STATE + 3) * cap];
-                    double S = p[(FGA_F_STATE + 4) * cap];
-                    double ar = p[(FGA_F_STATE + 21) * cap], ai = p[(FGA_F_STATE + 22) * cap];
-                    double Cr = p[4 * cap], Ci = p[5 * cap];
-                    double car = Cr * ar - Ci * ai, cai = Cr * ai + Ci * ar;
-                    BeamBox bx = beam_box(Q1, Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
-#pragma unroll
-                    for (int mm = 0; mm < 4; ++mm) {
-                        int xi = sub + 16 * mm;
-                        int i1 = X0 + xi;
-                        Fac<R> v{(R)0, (R)0};
-                        if (i1 >= bx.lo1 && i1 <= bx.hi1) {
-                            double r1 = (A.o1 + i1 * A.d1) - Q1;
-                            v = factor<R>((S + P1 * r1) * A.inv_eps, -r1 * r1 * A.half_inv_eps,
-                                          car, cai);
+                    const double Q1 = p[(FGA_F_STATE + 0) * cap], Q2 = p[(FGA_F_STATE + 1) * cap];
+                    const BeamBox bx =
+                        beam_box(Q1, Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
+                    const int start = (ax == 0 ? X0 : Z0) + x0;
+                    const int blo = ax == 0 ? bx.lo1 : bx.lo2, bhi = ax == 0 ? bx.hi1 : bx.hi2;
+                    m0 = max(blo - start, 0);
+                    m1 = min(bhi - start, 7);
+                    if (m0 <= m1) {
+                        const double o = ax == 0 ? A.o1 : A.o2, d = ax == 0 ? A.d1 : A.d2;
+                        const double Q = ax == 0 ? Q1 : Q2;
+                        const double P = p[(FGA_F_STATE + 2 + ax) * cap];
+                        const double r = (o + (start + m0) * d) - Q;
+                        double th = P * r, cr = 1.0, ci = 0.0;
+                        if (ax == 0) {
+                            const double ar = p[(FGA_F_STATE + 21) * cap];
+                            const double ai = p[(FGA_F_STATE + 22) * cap];
+                            const double Cr = p[4 * cap], Ci = p[5 * cap];
+                            cr = Cr * ar - Ci * ai;
+                            ci = Cr * ai + Ci * ar;
+                            th += p[(FGA_F_STATE + 4) * cap];
                         }
-                        U[k][xi] = v;
-                        int i2 = Z0 + xi;
-                        Fac<R> w{(R)0, (R)0};
-                        if (i2 >= bx.lo2 && i2 <= bx.hi2) {
-                            double r2 = (A.o2 + i2 * A.d2) - Q2;
-                            w = factor<R>(P2 * r2 * A.inv_eps, -r2 * r2 * A.half_inv_eps, 1.0, 0.0);
-                        }
-                        Vf[k][xi] = w;
+                        double sn, cs;
+                        sincos(th * A.inv_eps, &sn, &cs);
+                        double e = exp(-r * r * A.half_inv_eps);
+                        const double wr = e * cs, wi = e * sn;
+                        gr = cr * wr - ci * wi;
+                        gi = cr * wi + ci * wr;
+                        sincos(P * d * A.inv_eps, &sn, &cs);
+                        e = exp(-(r + 0.5 * d) * d * A.inv_eps);
+                        rr = e * cs;
+                        ri = e * sn;
+                        kap = exp(-d * d * A.inv_eps);
                     }
-                } else {
+                }
 #pragma unroll
-                    for (int mm = 0; mm < 4; ++mm) {
-                        U[k][sub + 16 * mm] = {(R)0, (R)0};
-                        Vf[k][sub + 16 * mm] = {(R)0, (R)0};
+                for (int m = 0; m < 8; ++m) {
+                    if (m < m0 || m > m1) {
+                        dst[m] = {(R)0, (R)0};
+                    } else {
+                        dst[m] = {(R)gr, (R)gi};
+                        const double t2 = gr * rr - gi * ri;
+                        gi = gr * ri + gi * rr;
+                        gr = t2;
+                        rr *= kap;
+                        ri *= kap;
                     }
                 }
             }
