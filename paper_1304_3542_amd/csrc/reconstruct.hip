@@ -19,24 +19,31 @@
 
 #include "splat.h"
 
-template <typename R>
-struct Fac {
-    R re, im;
-};
+// FP64 splat.  A workgroup takes one 128 x 128 tile and one slice of its
+// shot's beams; thread (tx, tz) owns the 8 x 8 nodes (X0 + tx + 16 i,
+// Z0 + tz + 16 j).  The slice is scanned 256 beams at a time, the beams whose
+// box meets the tile listed in order, and taken 16 at a time: their factors
+//   U(x1) = C a e^{(i (S + P1 r1) - r1^2/2) / eps},  V(x2) = e^{(i P2 r2 - r2^2/2) / eps}
+// at the tile's 128 + 128 coordinates (zero outside the box) go to LDS, and
+// every thread adds Re(U V) = Ur Vr - Ui Vi to its 64 nodes.  The factors
+// are formed in runs of 8 consecutive nodes, one direct evaluation at the
+// run's first node in the box and then g(x + d) = g(x) rho(x),
+// rho(x + d) = rho(x) e^{-d^2/eps} (exact identities of the Gaussian).
+#define SP64_T 128
+#define SP64_KC 16
 
-template <typename R>
 __global__ void __launch_bounds__(256)
-k_splat(SplatArgs A)
+k_splat64(SplatArgs A)
 {
     __shared__ int lst[SP_CHUNK];
     __shared__ int wcnt[4];
-    __shared__ Fac<R> U[SP_KC][SP_T];
-    __shared__ Fac<R> Vf[SP_KC][SP_T];
+    __shared__ double2 U[SP64_KC][SP64_T];
+    __shared__ double2 Vf[SP64_KC][SP64_T];
 
     const int t = threadIdx.x;
     const int tx = t & 15, tz = t >> 4;
     const int tile = blockIdx.x;
-    const int X0 = (tile % A.ntile1) * SP_T, Z0 = (tile / A.ntile1) * SP_T;
+    const int X0 = (tile % A.ntile1) * SP64_T, Z0 = (tile / A.ntile1) * SP64_T;
     const int split = blockIdx.y, s = blockIdx.z;
     const int64_t b0 = A.offsets[s], b1 = A.offsets[s + 1];
     const int64_t nbs = b1 - b0;
@@ -44,15 +51,11 @@ k_splat(SplatArgs A)
     const int64_t cap = A.cap;
     const double *F = A.f;
 
-    double acc[4][4];
-    R acc_r[4][4];
+    double acc[8][8];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            acc[i][j] = 0.0;
-            acc_r[i][j] = (R)0;
-        }
+        for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
 
     for (int64_t base = lo; base < hi; base += SP_CHUNK) {
         // 1. keep the beams of this chunk whose box meets the tile
@@ -61,8 +64,8 @@ k_splat(SplatArgs A)
         if (b < hi) {
             double Q1 = F[(FGA_F_STATE + 0) * cap + b], Q2 = F[(FGA_F_STATE + 1) * cap + b];
             BeamBox bx = beam_box(Q1, Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
-            hit = (bx.lo1 <= min(bx.hi1, X0 + SP_T - 1) && max(bx.lo1, X0) <= bx.hi1 &&
-                   bx.lo2 <= min(bx.hi2, Z0 + SP_T - 1) && max(bx.lo2, Z0) <= bx.hi2)
+            hit = (bx.lo1 <= min(bx.hi1, X0 + SP64_T - 1) && max(bx.lo1, X0) <= bx.hi1 &&
+                   bx.lo2 <= min(bx.hi2, Z0 + SP64_T - 1) && max(bx.lo2, Z0) <= bx.hi2)
                       ? 1
                       : 0;
         }
@@ -79,21 +82,19 @@ k_splat(SplatArgs A)
         if (hit) lst[wb + before] = t;
         __syncthreads();
 
-        // 2. factor batches and rank-one accumulation.  Sixteen threads per
-        // beam: thread sub forms 8 consecutive factors of one axis (sub / 8:
-        // U along x1 with C a e^{iS/eps}, V along x2), zero outside the box,
-        // by one direct evaluation at the run's first node in the box and
-        // then g(x + d) = g(x) rho(x), rho(x + d) = rho(x) e^{-d^2/eps}
-        // (exact identities of the Gaussian, evaluated in FP64).
-        for (int k0 = 0; k0 < nlist; k0 += SP_KC) {
-            {
-                const int k = t >> 4, sub = t & 15;
-                const int ax = sub >> 3, x0 = 8 * (sub & 7);
-                Fac<R> *dst = ax == 0 ? &U[k][x0] : &Vf[k][x0];
+        // 2. factor batches and rank-one accumulation: 32 runs of 8 per beam
+        // (16 along x1, 16 along x2), two per thread
+        for (int k0 = 0; k0 < nlist; k0 += SP64_KC) {
+            const int k = t >> 4;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int run = (t & 15) + 16 * h;
+                const int ax = run >> 4, x0 = 8 * (run & 15);
+                double2 *dst = ax == 0 ? &U[k][x0] : &Vf[k][x0];
                 int m0 = 1, m1 = 0;                        // empty run
                 double gr = 0.0, gi = 0.0, rr = 0.0, ri = 0.0, kap = 0.0;
                 if (k0 + k < nlist) {
-                    int64_t bb = base + lst[k0 + k];
+                    const int64_t bb = base + lst[k0 + k];
                     const double *p = F + bb;
                     const double Q1 = p[(FGA_F_STATE + 0) * cap], Q2 = p[(FGA_F_STATE + 1) * cap];
                     const BeamBox bx =
@@ -130,11 +131,11 @@ k_splat(SplatArgs A)
                     }
                 }
 #pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    if (m < m0 || m > m1) {
-                        dst[m] = {(R)0, (R)0};
+                for (int mm = 0; mm < 8; ++mm) {
+                    if (mm < m0 || mm > m1) {
+                        dst[mm] = double2{0.0, 0.0};
                     } else {
-                        dst[m] = {(R)gr, (R)gi};
+                        dst[mm] = double2{gr, gi};
                         const double t2 = gr * rr - gi * ri;
                         gi = gr * ri + gi * rr;
                         gr = t2;
@@ -144,38 +145,30 @@ k_splat(SplatArgs A)
                 }
             }
             __syncthreads();
-#pragma unroll 4
-            for (int k = 0; k < SP_KC; ++k) {
-                Fac<R> u[4], v[4];
+            const int kn = min(SP64_KC, nlist - k0);
+            for (int kk = 0; kk < kn; ++kk) {
+                double2 u[8], v[8];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) u[i] = U[k][tx + 16 * i];
+                for (int i = 0; i < 8; ++i) u[i] = U[kk][tx + 16 * i];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) v[j] = Vf[k][tz + 16 * j];
+                for (int j = 0; j < 8; ++j) v[j] = Vf[kk][tz + 16 * j];
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < 8; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        acc_r[i][j] = fma(u[i].re, v[j].re, fma(-u[i].im, v[j].im, acc_r[i][j]));
+                    for (int j = 0; j < 8; ++j)
+                        acc[i][j] = fma(u[i].x, v[j].x, fma(-u[i].y, v[j].y, acc[i][j]));
             }
             __syncthreads();
         }
-        // fold the working-precision sums into double once per chunk
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                acc[i][j] += (double)acc_r[i][j];
-                acc_r[i][j] = (R)0;
-            }
     }
 
     double *out = A.partial + ((size_t)s * A.nsplit + split) * A.n2 * (size_t)A.n1;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 8; ++j) {
         int i2 = Z0 + tz + 16 * j;
         if (i2 >= A.n2) continue;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 8; ++i) {
             int i1 = X0 + tx + 16 * i;
             if (i1 < A.n1) out[(size_t)i2 * A.n1 + i1] = acc[i][j];
         }
@@ -377,7 +370,13 @@ fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nsho
     // every tile scans a slice of its shot's beams: enough slices for about
     // per_cu work units per CU (mixed: one wavefront per unit, so that the
     // dispatcher evens out tiles of very different load; FP64: one workgroup
-    // of four wavefronts per unit)
+    // of four wavefronts per unit, on 128 x 128 tiles)
+    if (!mfma) {
+        nt1 = (g.n1 + SP64_T - 1) / SP64_T;
+        nt2 = (g.n2 + SP64_T - 1) / SP64_T;
+        tiles = nt1 * nt2;
+        A.ntile1 = nt1;
+    }
     int per_cu = ctx->splat_units_per_cu > 0 ? ctx->splat_units_per_cu : (mfma ? 32 : 4);
     int want_units = per_cu * ctx->num_cu;
     int want = (want_units + tiles * nshots - 1) / (tiles * nshots);
@@ -393,7 +392,7 @@ fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nsho
         hipLaunchKernelGGL(k_splat_mfma, dim3((nunits + 3) / 4), dim3(256), 0, ctx->stream, A,
                            nunits, (const SplatRec *)ctx->srec, (const short4 *)ctx->sbox);
     } else {
-        hipLaunchKernelGGL(k_splat<double>, dim3(tiles, nsplit, nshots), dim3(256), 0,
+        hipLaunchKernelGGL(k_splat64, dim3(tiles, nsplit, nshots), dim3(256), 0,
                            ctx->stream, A);
     }
     hipLaunchKernelGGL(k_splat_reduce, dim3(1024), dim3(256), 0, ctx->stream, ctx->partial, u,
