@@ -726,54 +726,61 @@ __global__ void __launch_bounds__(64) k3_rk4(const double *__restrict__ c, fga3_
 // ------------------------------------------------------------------ step 3
 //
 // A workgroup takes one tile of 16 (x1) x 16 (x2) x 64 (x3) nodes and one
-// slice of a shot's beams (each shot's beams are cut into nsplit slices).
-// Thread (l1, g) owns the 4 x 16 nodes (X0 + l1, Y0 + j, Z0 + 4 g + q).  The
-// sum is separable: with r_a = x_a - Q_a,
+// slice of a shot's beams (each shot's beams are cut into nsplit slices);
+// wavefront w owns the 16 x3 planes Z0 + 16 w + t.  The sum is separable:
+// with r_a = x_a - Q_a,
 //   g_a(x_a) = exp(i P_a r_a / eps - r_a^2 / (2 eps)),   W = C a exp(iS/eps),
 // a beam adds Re(W g1 g2 g3) inside its truncation box and nothing outside.
 // The beams are staged 32 at a time, their factors at the tile's
-// coordinates formed as six runs of 16 (x1, x2 and four quarters of x3), one
-// thread per (beam, run), zero outside the box: a direct evaluation at the
-// run's first node inside the box, then
+// coordinates formed as six runs of 16 (x1 carrying W, x2, four quarters of
+// x3), one thread per (beam, run), zero outside the box: a direct evaluation
+// at the run's first node in the box and then
 //   g(x + d) = g(x) rho(x),   rho(x + d) = rho(x) exp(-d^2 / eps)
 // (exact identities of the Gaussian; the products add rounding over at most
-// 15 steps); the x1 factors carry W.  Every thread then forms
-// H_q = W g1(x1) g3(x3_q) for its four x3 once per beam and adds
-// Re(H_q g2(x2)) to its 64 nodes (two FMAs each); the 16 g2 are read by the
-// whole wavefront from the same LDS addresses.  The slices' partial sums are
-// added in slice order by k3_splat_reduce.
+// 15 steps).  The beams whose box meets the tile are listed and taken two at
+// a time; on plane t the update is the real product
+//   u[x1][x2] += sum_k A[x1][k] B[k][x2],  k = (beam of the pair, re / im),
+//   A = [Re H, -Im H],  B = [Re g2 ; Im g2],  H = W g1(x1) g3(x3_t),
+// one v_mfma_f64_16x16x4f64 (lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; element i of its result is D[4 i + l / 16][l % 16]).
+// The slices' partial sums are added in slice order by k3_splat_reduce.
 #define T3E 16   // tile edge in x1 and x2, and the length of every factor run
 #define T3Z 64   // tile edge in x3
 #define T3B 32   // beams staged per round
 
-__global__ void __launch_bounds__(256) k3_splat(fga_beams B, fga3_grid G, double eps, int Rw1,
+typedef double d3x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256, 2) k3_splat(fga_beams B, fga3_grid G, double eps, int Rw1,
                                                 int Rw2, int Rw3, int nsplit,
                                                 double *__restrict__ partial)
 {
-    // runs: 0 = x1 (times W), 1 = x2, 2..5 = x3 quarters
-    __shared__ double2 sg[6][T3B][T3E];
+    // runs: 0 = x1 (times W), 1 = x2, 2..5 = x3 quarters, beam index fastest
+    // (the staging lanes write consecutive slots); slot T3B stays zero
+    __shared__ double2 sg[6][T3E][T3B + 1];
     __shared__ int smeet[6][T3B];
-    __shared__ int sflag[T3B];   // the beam's box meets the tile
+    __shared__ int slist[T3B];
+    __shared__ int snmeet;
     const int nt1 = (G.n1 + T3E - 1) / T3E;
     const int X0 = (blockIdx.x % nt1) * T3E, Z0 = (blockIdx.x / nt1) * T3Z;
     const int Y0 = blockIdx.y * T3E;
     const int split = blockIdx.z % nsplit, s = blockIdx.z / nsplit;
-    const int tid = threadIdx.x, l1 = tid % T3E, gq = tid / T3E;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int64_t cap = B.capacity;
     const int64_t b0 = B.offsets[s], b1 = B.offsets[s + 1], nbs = b1 - b0;
     const int64_t lo = b0 + nbs * split / nsplit, hi = b0 + nbs * (split + 1) / nsplit;
     const double ieps = 1.0 / eps, hieps = 0.5 / eps;
-    double acc[4][T3E];
+    if (tid < 6 * T3E) sg[tid / T3E][tid % T3E][T3B] = double2{0.0, 0.0};
+    // this lane's place in the products: x1 (rows of A), x2 (columns of B),
+    // which beam of the pair and which part (re / im)
+    const int mrow = lane % 16, kcol = lane / 16, pb = kcol / 2, part = kcol % 2;
+    d3x4 acc[T3E];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int j = 0; j < T3E; ++j) acc[q][j] = 0.0;
+    for (int t = 0; t < T3E; ++t) acc[t] = d3x4{0.0, 0.0, 0.0, 0.0};
     for (int64_t c0 = lo; c0 < hi; c0 += T3B) {
         const int nc = (int)min((int64_t)T3B, hi - c0);
         if (tid < 6 * T3B) {
             const int run = tid / T3B, bb = tid % T3B;
             const int a = run < 2 ? run : 2;           // axis of the run
-            double2 *g = sg[run][bb];
             int m0 = 1, m1 = 0;                        // empty range
             double gr = 0.0, gi = 0.0, rr = 0.0, ri = 0.0, kap = 0.0;
             if (bb < nc) {
@@ -820,9 +827,9 @@ __global__ void __launch_bounds__(256) k3_splat(fga_beams B, fga3_grid G, double
 #pragma unroll
             for (int m = 0; m < T3E; ++m) {
                 if (m < m0 || m > m1) {
-                    g[m] = double2{0.0, 0.0};
+                    sg[run][m][bb] = double2{0.0, 0.0};
                 } else {
-                    g[m] = double2{gr, gi};
+                    sg[run][m][bb] = double2{gr, gi};
                     const double t2 = gr * rr - gi * ri;
                     gi = gr * ri + gi * rr;
                     gr = t2;
@@ -832,43 +839,45 @@ __global__ void __launch_bounds__(256) k3_splat(fga_beams B, fga3_grid G, double
             }
         }
         __syncthreads();
-        if (tid < T3B)
-            sflag[tid] = smeet[0][tid] && smeet[1][tid] &&
-                         (smeet[2][tid] || smeet[3][tid] || smeet[4][tid] || smeet[5][tid]);
+        // list the beams whose box meets the tile, in order
+        if (w == 0) {
+            const int fl = lane < T3B && smeet[0][lane & (T3B - 1)] &&
+                           smeet[1][lane & (T3B - 1)] &&
+                           (smeet[2][lane & (T3B - 1)] || smeet[3][lane & (T3B - 1)] ||
+                            smeet[4][lane & (T3B - 1)] || smeet[5][lane & (T3B - 1)]);
+            const unsigned long long mk = __ballot(fl);
+            if (fl) slist[__popcll(mk & ((1ull << lane) - 1ull))] = lane;
+            if (lane == 0) snmeet = __popcll(mk);
+        }
         __syncthreads();
-        // thread gq's four x3 lie in quarter gq / 4 of the x3 run
-        const int qr = 2 + gq / 4, qm = 4 * (gq % 4);
-        for (int bb = 0; bb < nc; ++bb) {
-            if (!sflag[bb]) continue;
-            const double2 g1 = sg[0][bb][l1];
-            double hr[4], hm[4];
+        const int nm = snmeet;
+        for (int p = 0; p < nm; p += 2) {
+            const int bb = pb == 0 ? slist[p] : (p + 1 < nm ? slist[p + 1] : T3B);
+            const double2 g1 = sg[0][mrow][bb];
+            const double2 g2 = sg[1][mrow][bb];
+            const double bv = part == 0 ? g2.x : g2.y;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double2 g3 = sg[qr][bb][qm + q];
-                hr[q] = g1.x * g3.x - g1.y * g3.y;
-                hm[q] = g1.x * g3.y + g1.y * g3.x;
-            }
-            const double2 *g2 = sg[1][bb];
-#pragma unroll
-            for (int j = 0; j < T3E; ++j) {
-                const double2 v = g2[j];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q][j] += hr[q] * v.x - hm[q] * v.y;
+            for (int t = 0; t < T3E; ++t) {
+                const double2 h = sg[2 + w][t][bb];
+                const double av = part == 0 ? g1.x * h.x - g1.y * h.y : -(g1.x * h.y + g1.y * h.x);
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
             }
         }
         __syncthreads();
     }
-    const int i1 = X0 + l1;
-    if (i1 < G.n1) {
+    // element i of plane t: x1 = X0 + 4 i + lane / 16, x2 = Y0 + lane % 16
+    const int i2 = Y0 + lane % 16;
+    if (i2 < G.n2) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i3 = Z0 + 4 * gq + q;
+        for (int t = 0; t < T3E; ++t) {
+            const int i3 = Z0 + 16 * w + t;
             if (i3 >= G.n3) continue;
-            double *pp =
-                partial + ((size_t)(s * nsplit + split) * G.n3 + i3) * G.n2 * G.n1 + i1;
+            double *pp = partial + (((size_t)(s * nsplit + split) * G.n3 + i3) * G.n2 + i2) * G.n1;
 #pragma unroll
-            for (int j = 0; j < T3E; ++j)
-                if (Y0 + j < G.n2) pp[(size_t)(Y0 + j) * G.n1] = acc[q][j];
+            for (int i = 0; i < 4; ++i) {
+                const int i1 = X0 + 4 * i + lane / 16;
+                if (i1 < G.n1) pp[i1] = acc[t][i];
+            }
         }
     }
 }
