@@ -2,8 +2,9 @@
 three-dimensional oracle on the same seeded inputs: beam ids bit-exact,
 coefficients, states after the RK4 and the field within 1e-10, on a ragged
 case with f0 and f1 (q- and p-meshes that do not divide the grid, partial
-8 x 8 x 4 tiles) and two shots; the full-size point3d workload against the
-oracle's propagation of sampled beams."""
+16 x 16 x 64 tiles) and two shots, and on a grid two tiles deep in x3; the
+full-size point3d workload against the oracle's propagation of sampled
+beams."""
 import numpy as np
 import pytest
 
@@ -63,6 +64,26 @@ def test_d3_fp64_matches_oracle(nshots):
     assert pairwise_state_err(r["fT"][8:].T, b.state) <= 1e-10
     for s in range(nshots):
         assert rel_l2(r["u"][s], us[s]) <= 1e-10
+
+
+def test_d3_field_over_two_x3_tiles():
+    """n3 = 70 > 64: the reconstruction's tiles split x3, with packets in
+    both halves and truncation boxes that straddle the split."""
+    g = i3.Grid3(12, 10, 70, 0.0, 0.1, -0.05, 1 / 24, 1 / 24, 1 / 24)
+    eps = 1 / 48
+    c = i3.smooth_layered_velocity3(g, 41, 2.0)
+    f0 = (i3.wavepacket_source3(g, (0.22, 0.3, 0.8), 0.08, (0.6, -0.3, 0.7), eps) +
+          i3.wavepacket_source3(g, (0.25, 0.28, 2.55), 0.08, (-0.4, 0.5, -0.6), eps))[None]
+    p = i3.Params3(eps, (1, 1, 2), (3, 3, 7), (4, 3, 10), (6, 6, 6), (0.3, 0.3, 0.3), 1e-5,
+                   1e-16, 1e-16, 1e-3, 5)
+    b, us = o3.forward(f0, None, c, g, p)
+    assert 50 < b.n
+    r = _gpu(g, p, c, f0, None, b.n + 10, p.nsteps)
+    assert r["status0"][0] == 0 and r["status"][0] == 0
+    np.testing.assert_array_equal(r["id"], b.cand)
+    assert rel_l2(r["u"][0], us[0]) <= 1e-10
+    lo, hi = np.abs(us[0][:64]).max(), np.abs(us[0][64:]).max()
+    assert lo > 0 and hi > 0
 
 
 def test_d3_capacity_overflow_reports_count():
