@@ -114,6 +114,24 @@ def test_field_gradient_chain_matches_oracle(with_f1):
         assert rel_max(r["df1"], df1) <= 1e-10
 
 
+@pytest.mark.parametrize("grad_log", [-1, 3])
+def test_field_chain_same_for_every_log_setting(grad_log):
+    """fga_propagate_adjoint with dJ/dc added by atomics where made
+    (grad_log = -1) or logged in 3 slots per beam with the rest added where
+    made equals the automatic logs (every record logged, summed by cell) to
+    the rounding order."""
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(True)
+    ns = f0.shape[0]
+    b = oracle.decompose(f0, f1, c, g, p)
+    nodes = np.arange(g.n1 * g.n2, dtype=np.int32)
+    d = 0.5 * c_oracle_traces(c * 1.02, f0, f1, g, p, b.cand, nodes, p.nsteps, 1)
+    d3 = d.reshape(ns, g.n2, g.n1)
+    ra = _field_chain(g, p, c, f0, f1, d3, 5, 3)
+    r = _field_chain(g, p.replace(grad_log=grad_log), c, f0, f1, d3, 5, 3)
+    for k in ("dc", "df0", "df1", "lam0"):
+        assert rel_max(r[k], ra[k]) <= 1e-12, (k, rel_max(r[k], ra[k]))
+
+
 def test_field_chain_equals_trace_adjoint_with_every_node():
     """The same misfit through fga_trace_adjoint (every node a receiver, one
     record, one segment of 15 steps) gives the same dJ/dc and dJ/dC as the
