@@ -338,12 +338,71 @@ k_fbi_pass2_mfma(const cplx<float> *__restrict__ T, const cplx<float> *__restric
 
 // --------------------------------------------------- branches and threshold
 
+// Exact division of 32-bit unsigned integers by an invariant divisor d >= 1
+// through a multiply-high (Granlund and Montgomery, "Division by invariant
+// integers using multiplication", 1994, round-up method):
+//   l = ceil(log2 d),  m = floor(2^32 (2^l - d) / d) + 1,
+//   t = mulhi(m, n),   n / d = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0).
+struct FastDiv {
+    uint32_t d, m;
+    int s1, s2;
+};
+
+static FastDiv fast_div(uint32_t d)
+{
+    int l = 0;
+    while (l < 32 && (1ull << l) < d) ++l;
+    const unsigned __int128 num = ((unsigned __int128)1 << 32) * ((1ull << l) - d);
+    FastDiv f;
+    f.d = d;
+    f.m = (uint32_t)(num / d + 1);
+    f.s1 = l < 1 ? l : 1;
+    f.s2 = l > 1 ? l - 1 : 0;
+    return f;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f)
+{
+    const uint32_t t = __umulhi(f.m, n);
+    return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
 struct CandGeom {
     int nq1, nq2, np1, np2, nfj;
     int64_t Nq, Np;      // nq1*nq2, np1*np2
     int64_t per_shot;    // 2*Nq*Np
     double dp1, dp2, eps;
+    int small;           // Nq*Np < 2^32: candidate indices split in 32 bits
+    FastDiv fNp, fnq1, fnp1;
 };
+
+// (branch, q node, p node) of the local candidate index cl of a shot
+// (branch-major, then q flat, then p flat)
+__device__ __forceinline__ void cand_index(const CandGeom &G, int64_t cl, int &sb, int64_t &qf,
+                                           int &j1, int &j2, int &l1, int &l2)
+{
+    const int64_t NqNp = G.Nq * G.Np;
+    if (G.small) {
+        sb = cl >= NqNp ? 1 : 0;
+        const uint32_t rem = (uint32_t)(cl - sb * NqNp);
+        const uint32_t q = fdiv(rem, G.fNp), pf = rem - q * (uint32_t)G.Np;
+        const uint32_t a2 = fdiv(q, G.fnq1), b2 = fdiv(pf, G.fnp1);
+        qf = q;
+        j2 = (int)a2;
+        j1 = (int)(q - a2 * (uint32_t)G.nq1);
+        l2 = (int)b2;
+        l1 = (int)(pf - b2 * (uint32_t)G.np1);
+    } else {
+        sb = (int)(cl / NqNp);
+        const int64_t rem = cl - sb * NqNp;
+        qf = rem / G.Np;
+        const int64_t pf = rem - qf * G.Np;
+        j2 = (int)(qf / G.nq1);
+        j1 = (int)(qf - (int64_t)j2 * G.nq1);
+        l2 = (int)(pf / G.np1);
+        l1 = (int)(pf - (int64_t)l2 * G.np1);
+    }
+}
 
 // psi_{+-} = (psi0 +- i eps/(c(q)|p|) psi1)/2 for local candidate index cl
 // (branch-major, then q flat, then p flat) of shot s.
@@ -352,12 +411,9 @@ __device__ __forceinline__ void cand_psi(const cplx<R> *__restrict__ Psi,
                                          const double *__restrict__ cq, const CandGeom &G,
                                          int s, int64_t cl, R &re, R &im)
 {
-    int64_t NqNp = G.Nq * G.Np;
-    int sb = (int)(cl / NqNp);
-    int64_t rem = cl - sb * NqNp;
-    int64_t qf = rem / G.Np, pf = rem - qf * G.Np;
-    int j2 = (int)(qf / G.nq1), j1 = (int)(qf - (int64_t)j2 * G.nq1);
-    int l2 = (int)(pf / G.np1), l1 = (int)(pf - (int64_t)l2 * G.np1);
+    int sb, j1, j2, l1, l2;
+    int64_t qf;
+    cand_index(G, cl, sb, qf, j1, j2, l1, l2);
     size_t NC = (size_t)G.nq1 * G.np1;
     size_t off = ((size_t)j2 * G.np2 + l2) * NC + (size_t)j1 * G.np1 + l1;
     size_t plane = (size_t)G.nq2 * G.np2 * NC;
@@ -705,7 +761,6 @@ k_scatter(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGe
     const int s = C.s;
     const Sel S = sel[s * 2 + C.sb];
     const int64_t cap = B.capacity;
-    const int64_t NqNp = G.Nq * G.Np;
     const size_t at = (size_t)s * 2 * nblkb + blockIdx.x;
     int64_t run = blk_pos[at];
     int64_t tie_run = blk_tie[at];
@@ -726,11 +781,9 @@ k_scatter(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGe
         const int64_t pos = run + block_rank(__ballot(keep), wsum, nkeep);
         run += nkeep;
         if (keep && pos < cap) {
-            const int sb = (int)(cl / NqNp);
-            const int64_t rem = cl - sb * NqNp;
-            const int64_t qf = rem / G.Np, pf = rem - qf * G.Np;
-            const int j2 = (int)(qf / G.nq1), j1 = (int)(qf - (int64_t)j2 * G.nq1);
-            const int l2 = (int)(pf / G.np1), l1 = (int)(pf - (int64_t)l2 * G.np1);
+            int sb, j1, j2, l1, l2;
+            int64_t qf;
+            cand_index(G, cl, sb, qf, j1, j2, l1, l2);
             const double q1 = o1 + (qb1 + j1 * qs1) * d1, q2 = o2 + (qb2 + j2 * qs2) * d2;
             const double p1 = (l1 - 0.5 * (G.np1 - 1)) * G.dp1;
             const double p2 = (l2 - 0.5 * (G.np2 - 1)) * G.dp2;
@@ -796,6 +849,10 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
     G.Nq = (int64_t)p.nq1 * p.nq2;
     G.Np = (int64_t)p.np1 * p.np2;
     G.per_shot = 2 * G.Nq * G.Np;
+    G.small = G.Nq * G.Np < (int64_t)1 << 32;
+    G.fNp = fast_div((uint32_t)std::min<int64_t>(G.Np, 0xffffffffLL));
+    G.fnq1 = fast_div((uint32_t)p.nq1);
+    G.fnp1 = fast_div((uint32_t)p.np1);
     G.dp1 = p.dp1;
     G.dp2 = p.dp2;
     G.eps = p.eps;
