@@ -116,3 +116,102 @@ def test_autotune_choice_and_cache(precision, tmp_path):
     ctx2, beams2, _, u2, stream2 = run(g, p, c, f0, precision)
     with torch.cuda.stream(stream2):
         assert ctx2.autotune(beams2, f0.shape[0], u2, cache) == v
+
+
+def test_shots512_full_size():
+    """shots512 at full size (64 shots, ~2.7e6 beams, 250 steps): the mixed
+    path as the bench runs it (autotuned splat, one captured graph, replays)
+    within 1e-5 of the FP64 eager field; in FP64 the coefficients of every
+    kept beam at a seeded q node of two seeded shots against the oracle's
+    windowed DFT, and 24 seeded beams after the 250 steps against the
+    oracle's propagation of the initial states it forms from their mesh
+    nodes."""
+    import torch
+    import paper_1304_3542_amd as fga
+    from gpu_helpers import pairwise_state_err
+
+    def fit(ctx, f0t, ns):
+        beams = fga.Beams(4_000_000, ns)
+        ctx.decompose(f0t, None, beams)
+        st, need = ctx.status()
+        if st == fga.FGA_ECAPACITY:
+            del beams
+            beams = fga.Beams(need + 1024, ns)
+            ctx.decompose(f0t, None, beams)
+            st, need = ctx.status()
+        assert st == fga.FGA_OK
+        return beams
+
+    Wm = fi.workload("shots512", "mixed")
+    Wd = fi.workload("shots512", "fp64")
+    g, ns = Wm.grid, Wm.nshots
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = fga.FGA(g, Wm.params, "mixed", max_shots=ns)
+        ctx.set_velocity(torch.from_numpy(Wm.c).cuda())
+        f0t = torch.from_numpy(np.ascontiguousarray(Wm.f0)).cuda()
+        beams = fit(ctx, f0t, ns)
+        nbm = int(ctx.offsets(beams, ns)[-1])
+        u = torch.empty((ns, g.n2, g.n1), dtype=torch.float64, device="cuda")
+        ctx.propagate(beams, ns, Wm.params.nsteps)
+        ctx.autotune(beams, ns, u)
+        ctx.graph_capture(f0t, None, beams, Wm.params.nsteps, u)
+        u.fill_(0.0)
+        ctx.graph_launch()
+        ctx.graph_launch()
+        stream.synchronize()
+        assert ctx.status()[0] == fga.FGA_OK
+        um = u.cpu().numpy()
+        ctx.close()
+        del beams
+    torch.cuda.empty_cache()
+
+    p = Wd.params
+    ctx = fga.FGA(g, p, "fp64", max_shots=ns)
+    ctx.set_velocity(torch.from_numpy(Wd.c).cuda())
+    beams = fit(ctx, f0t, ns)
+    off = ctx.offsets(beams, ns)
+    nb = int(off[-1])
+    print(f"shots512: FP64 beams {nb}, mixed beams {nbm}", flush=True)
+    ids = beams.id[:nb].cpu().numpy()
+    coef = beams.f[4:6, :nb].cpu().numpy()
+    Nq, Np = p.nq1 * p.nq2, p.np1 * p.np2
+    shot, cl = ids // (2 * Nq * Np), ids % (2 * Nq * Np)
+    sb, rem = cl // (Nq * Np), cl % (Nq * Np)
+    qf, pf = rem // Np, rem % Np
+    r = fi.rng(78)
+    w = (p.qs1 * g.d1) * (p.qs2 * g.d2) * p.dp1 * p.dp2 / (2 * np.pi * p.eps) ** 3
+    for s in r.choice(ns, 2, replace=False):
+        mine = shot == s
+        q = int(r.choice(np.unique(qf[mine])))
+        j2, j1 = divmod(q, p.nq1)
+        one = p.replace(qb1=p.qb1 + p.qs1 * j1, qb2=p.qb2 + p.qs2 * j2, nq1=1, nq2=1)
+        ref = 0.5 * w * oracle.fbi(Wd.f0[s], g, one)[0, 0].ravel()
+        sel = mine & (qf == q)
+        got = coef[0, sel] + 1j * coef[1, sel]
+        assert np.abs(got - ref[pf[sel]]).max() <= 1e-10 * np.abs(ref).max(), (s, q)
+    idx = np.sort(r.choice(nb, 24, replace=False))
+    ctx.propagate(beams, ns, p.nsteps)
+    ud = ctx.reconstruct(beams, ns).cpu().numpy()
+    assert ctx.status()[0] == fga.FGA_OK
+    got = beams.f[fga.FGA_F_STATE:, idx].cpu().numpy().T
+    k1, k2 = oracle.qnodes(p)
+    pm1, pm2 = oracle.pmesh(p.np1, p.dp1), oracle.pmesh(p.np2, p.dp2)
+    st0 = np.zeros((24, oracle.NSTATE))
+    st0[:, 0] = g.o1 + g.d1 * k1[qf[idx] % p.nq1]
+    st0[:, 1] = g.o2 + g.d2 * k2[qf[idx] // p.nq1]
+    st0[:, 2] = pm1[pf[idx] % p.np1]
+    st0[:, 3] = pm2[pf[idx] // p.np1]
+    st0[:, 5] = st0[:, 11] = 1.0      # A = I
+    st0[:, 14] = st0[:, 20] = -1.0    # B = -i I
+    st0[:, 21] = 2.0                  # a = 2^{d/2}
+    sig = np.where(sb[idx] == 0, 1, -1).astype(np.int8)
+    b = oracle.Beams(shot[idx].astype(np.int32), sig, ids[idx], np.ones(24, complex),
+                     np.zeros((24, 2)), st0, np.array([0, 24], np.int64))
+    oracle.propagate(b, Wd.c, g, p.dt, p.nsteps)
+    assert pairwise_state_err(got, b.state) <= 1e-9
+    # the mixed path against FP64 (beams at the threshold may differ)
+    rel = np.linalg.norm(um - ud) / np.linalg.norm(ud)
+    print(f"shots512: mixed (graph) vs FP64 rel-L2 {rel:.3e}", flush=True)
+    assert rel <= 1e-5
+    ctx.close()
