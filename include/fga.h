@@ -125,7 +125,8 @@ typedef struct {
  *              records past a beam's slots are added with FP64 atomics where
  *              they are made.  n > 0: at most n slots per beam (no size
  *              cap).  -1: no logs, every record is added with atomics where
- *              it is made, and the call does not synchronise.  The three give
+ *              it is made, and the call does not synchronise (also what a
+ *              call does when the logs cannot be allocated).  The three give
  *              the same dc up to the rounding order.  The logged form is the
  *              faster one here: atomics from many rays into the same cells
  *              contend, and the integrating waves wait on them.

@@ -641,7 +641,7 @@ fga_status fga_launch_rk4_adjoint(fga_ctx *ctx, const fga_beams *beams, int nsho
     const dim3 grid(ctx->num_cu * 4), block(ADJ_BLOCK);
     const int64_t steps = (int64_t)rec_every * nrec_t;
     if (!ctx->p.deterministic) {
-        const int R = grad_log_slots(ctx, cap, steps);
+        int R = grad_log_slots(ctx, cap, steps);
         char *base = nullptr;
         size_t rec_bytes = 0, cell_bytes = 0;
         if (R > 0) {
@@ -649,7 +649,15 @@ fga_status fga_launch_rk4_adjoint(fga_ctx *ctx, const fga_beams *beams, int nsho
             cell_bytes = (size_t)R * cap * sizeof(int);
             rc = fga_ensure(ctx, &ctx->det_log, &ctx->det_log_bytes,
                             rec_bytes + cell_bytes + (size_t)cap * sizeof(int), "dJ/dc logs");
-            if (rc != FGA_OK) return rc;
+            if (rc == FGA_ENOMEM) {
+                // no room for the logs: every record goes to dc with atomics
+                (void)hipGetLastError();
+                R = 0;
+            } else if (rc != FGA_OK) {
+                return rc;
+            }
+        }
+        if (R > 0) {
             base = (char *)ctx->det_log;
             A.out = DcOut{dc, (double *)base, (int *)(base + rec_bytes), cap, R, ctx->g.n1,
                           ctx->g.n2};
