@@ -147,6 +147,31 @@ def test_trace_matches_oracle(layout):
     assert rel_l2(tr, tr_or) <= FP64_TOL
 
 
+def test_trace_row_longer_than_the_lane_form():
+    """A run of 1040 receivers along one row (more than the one-lane-per-beam
+    form holds in LDS) takes the per-receiver form and still matches the
+    oracle; the run's last receiver is the row's last node."""
+    import torch
+    import paper_1304_3542_amd as fga
+    g = fi.Grid(1040, 24, 0.0, 0.0, 1 / 512, 1 / 128)
+    eps = 1 / 400
+    c = fi.smooth_layered_velocity(g, seed=29, smooth_cells=4.0)
+    f0 = fi.wavepacket_source(g, (1.0, 0.09), 0.05, (0.8, 0.4), eps)[None]
+    p = fi.Params(eps, 3, 4, 16, 8, 64, 2, 12, 12, 0.25, 0.25, 1e-6, 1e-16, 1e-16, 1e-3, 20)
+    rec = (12 * g.n1 + np.arange(g.n1)).astype(np.int32)
+    b = oracle.decompose(f0, None, c, g, p)
+    assert b.n > 100
+    tr_or = oracle.trace(b, c, g, p, rec, rec_every=10, nrec=2)
+    ctx = fga.FGA(g, p, "fp64")
+    ctx.set_velocity(torch.from_numpy(c).cuda())
+    beams = fga.Beams(int(b.offsets[-1]) + 10, 1)
+    ctx.decompose(torch.from_numpy(f0).cuda(), None, beams)
+    tr = ctx.trace(beams, 1, torch.from_numpy(rec).cuda(), 10, 2).cpu().numpy()
+    assert ctx.status()[0] == 0
+    assert np.abs(tr_or).max() > 0
+    assert rel_l2(tr, tr_or) <= FP64_TOL
+
+
 def _golden(name):
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", f"{name}_fp64.npz")
