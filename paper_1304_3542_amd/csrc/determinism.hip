@@ -50,21 +50,21 @@ __global__ void k_det_zero_i32(int *p, int64_t n)
         p[i] = 0;
 }
 
-// (cell, slot) of every record, listed in beam order then log order
+// (cell, slot) of every record, listed in beam order then log order: log
+// positions k across blockIdx.y, beams across the threads, so the cell reads
+// are coalesced and no thread walks a whole log
 __global__ void k_det_list(const int *__restrict__ cnt, const int64_t *__restrict__ off,
-                           const int *__restrict__ cell, int64_t nb, int64_t cap,
+                           const int *__restrict__ cell, int64_t nb, int64_t cap, int R,
                            unsigned *__restrict__ keys, unsigned long long *__restrict__ slots)
 {
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
-         b += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t o = off[b];
-        const int n = cnt[b];
-        for (int k = 0; k < n; ++k) {
+    for (int k = blockIdx.y; k < R; k += gridDim.y)
+        for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
+             b += (int64_t)gridDim.x * blockDim.x) {
+            if (k >= cnt[b]) continue;
             const size_t s = (size_t)k * cap + b;
-            keys[o + k] = (unsigned)cell[s];
-            slots[o + k] = (unsigned long long)s;
+            keys[off[b] + k] = (unsigned)cell[s];
+            slots[off[b] + k] = (unsigned long long)s;
         }
-    }
 }
 
 // [begin, end) of every cell's run in the sorted list (cells without records
@@ -221,8 +221,9 @@ fga_status fga_det_reduce(fga_ctx *ctx, int64_t cap, int R, int64_t nb, int64_t 
     FGA_HIP(ctx, rocprim::exclusive_scan(tmp, scan_tmp, cnt, off, (int64_t)0, (size_t)nb,
                                          rocprim::plus<int64_t>(), st));
     const int blocks = ctx->num_cu * 4;
-    hipLaunchKernelGGL(k_det_list, dim3(blocks), dim3(256), 0, st, cnt, off, cell, nb, cap, keys,
-                       slots);
+    const int64_t lb = std::min<int64_t>((nb + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_det_list, dim3((unsigned)lb, (unsigned)std::min(R, 65535)), dim3(256), 0,
+                       st, cnt, off, cell, nb, cap, R, keys, slots);
     FGA_HIP(ctx, hipGetLastError());
     FGA_HIP(ctx, rocprim::radix_sort_pairs(tmp, sort_tmp, keys, keys_s, slots, slots_s,
                                            (size_t)total, 0, nbits, st));
