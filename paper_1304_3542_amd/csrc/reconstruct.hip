@@ -614,16 +614,21 @@ k_trace_points(SplatArgs A, const int32_t *__restrict__ rec, int nrec,
     if (r < nrec) partial[((size_t)s * A.nsplit + split) * nrec + r] = acc;
 }
 
+// one wavefront per trace value: lane l adds the slices l, l + 64, ... in
+// order, then a fixed butterfly over the lanes
 __global__ void k_trace_reduce(const double *__restrict__ partial, int nsplit, int nrec,
                                int nshots, double *out, int64_t stride_shot)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);   // uniform in the wavefront
+    const int lane = threadIdx.x & 63;
     if (i >= nrec * nshots) return;
-    int s = i / nrec, r = i % nrec;
+    const int s = i / nrec, r = i % nrec;
     const double *p = partial + (size_t)s * nsplit * nrec + r;
     double v = 0.0;
-    for (int k = 0; k < nsplit; ++k) v += p[(size_t)k * nrec];
-    out[(size_t)s * stride_shot + r] = v;
+    for (int k = lane; k < nsplit; k += 64) v += p[(size_t)k * nrec];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) out[(size_t)s * stride_shot + r] = v;
 }
 
 fga_status fga_launch_trace_points(fga_ctx *ctx, const fga_beams *beams, int nshots,
@@ -656,7 +661,7 @@ fga_status fga_launch_trace_points(fga_ctx *ctx, const fga_beams *beams, int nsh
     A.nsplit = nsplit;
     hipLaunchKernelGGL(k_trace_points, dim3(nsplit, nshots, rblocks), dim3(TR_BLOCK), 0,
                        ctx->stream, A, rec, nrec, shape, (double *)ctx->trace_part);
-    hipLaunchKernelGGL(k_trace_reduce, dim3((nrec * nshots + 255) / 256), dim3(256), 0,
+    hipLaunchKernelGGL(k_trace_reduce, dim3((nrec * nshots + 3) / 4), dim3(256), 0,
                        ctx->stream, (const double *)ctx->trace_part, nsplit, nrec, nshots, out,
                        stride_shot);
     FGA_HIP(ctx, hipGetLastError());
