@@ -222,8 +222,41 @@ def adjoint_iteration(steps):
     ev[1].record()
     torch.cuda.synchronize()
     st, _ = ctx.status()
-    out = {"ms_per_iter": ev[0].elapsed_time(ev[1]) / steps, "nbeams": nb, "nshots": ns,
-           "status": st, "workload": "adjoint256: 256x256 on [0,2]x[0,1], eps=1/128, 8 surface "
+    ms_seg = ev[0].elapsed_time(ev[1]) / steps
+
+    # the same iteration with the state of every step kept by the forward
+    # (the adjoint reads it instead of recomputing each 10-step segment)
+    ctx_e = fga.FGA(g, p.replace(ckpt_every_step=1), "fp64", max_shots=ns)
+    ctx_e.set_velocity(c)
+    ckpt_e = torch.empty((ctx_e.ckpt_rows(W.rec_every, nrec_t), fga.FGA_NSTATE, beams.capacity),
+                         dtype=torch.float64, device="cuda")
+
+    def it_every():
+        ctx_e.decompose(f0, None, beams)
+        tr = ctx_e.trace(beams, ns, rec, W.rec_every, nrec_t, ckpt_e)
+        dc.zero_()
+        gcoef = ctx_e.trace_adjoint(beams, ns, rec, W.rec_every, nrec_t, ckpt_e,
+                                    (tr - data).contiguous(), dc)
+        return ctx_e.decompose_adjoint(beams, ns, gcoef)
+
+    it_every()
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(steps):
+        it_every()
+    ev[1].record()
+    torch.cuda.synchronize()
+    st_e, _ = ctx_e.status()
+    ms_every = ev[0].elapsed_time(ev[1]) / steps
+    ckpt_gb = ckpt_e.numel() * 8 / 1e9
+    del ckpt_e
+    ctx_e.close()
+    out = {"ms_per_iter": ms_every, "nbeams": nb, "nshots": ns,
+           "status": st if st != 0 else st_e,
+           "checkpoints": f"every step ({ckpt_gb:.1f} GB; the adjoint reads the states)",
+           "segment_checkpoints": {"ms_per_iter": ms_seg,
+                                   "checkpoints": "every 10 steps (the adjoint recomputes)"},
+           "workload": "adjoint256: 256x256 on [0,2]x[0,1], eps=1/128, 8 surface "
            "shots, 256 receivers on the top row every 10 steps, T=0.25 s, FP64 gradient "
            "w.r.t. c and f0"}
 

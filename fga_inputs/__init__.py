@@ -87,6 +87,7 @@ class Params:
     dz_scale: float = 1.0  # their spacing in mesh steps (1: the neighbouring mesh nodes)
     deterministic: int = 0  # 1: gradients reduce dJ/dc in a fixed order (bit-identical runs)
     grad_log: int = 0  # dJ/dc logs per beam when not deterministic (0 auto, -1 none, n slots)
+    ckpt_every_step: int = 0  # 1: checkpoints of every step (adjoints read, not recompute)
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)

@@ -130,6 +130,15 @@ typedef struct {
  *              the same dc up to the rounding order.  The logged form is the
  *              faster one here: atomics from many rays into the same cells
  *              contend, and the integrating waves wait on them.
+ *   ckpt_every_step  0: fga_trace and fga_propagate_ckpt store the state
+ *              at the start of every record segment, and the adjoints
+ *              recompute each segment from it; 1: they store the state
+ *              before every RK4 step and the final state,
+ *              ckpt_dev[nsteps + 1][FGA_NSTATE][capacity] with nsteps =
+ *              nrec_t * rec_every (nseg * seg), and the adjoints read those
+ *              states instead of recomputing them (23 doubles per beam and
+ *              step of memory for about a fifth of the adjoint's
+ *              arithmetic).  Requires amp_closed = 0 and dz_divided = 0.
  *   tau_fbi    the FBI box B_eps has half-width ceil(sqrt(2 eps ln(1/tau_fbi))/d)
  *   tau_win    each Gaussian is summed over the box of half-width
  *              ceil(sqrt(2 eps ln(1/tau_win))/d) around the node nearest Q
@@ -147,6 +156,7 @@ typedef struct {
     double dz_scale;
     int32_t deterministic;
     int32_t grad_log;
+    int32_t ckpt_every_step;
 } fga_params;
 
 /* Size cap of the automatic dJ/dc logs of one context (grad_log = 0).     */
@@ -206,7 +216,8 @@ fga_status fga_reconstruct(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
  * sum at the nrec nodes rec_dev[] (flat i2*n1 + i1, int32, device).
  * traces_dev[nshots][nrec_t][nrec].  The beams end at t = nrec_t*rec_every*dt.
  * If ckpt_dev is not NULL it receives the beam states before every segment:
- * ckpt_dev[k][FGA_NSTATE][capacity], k < nrec_t.                           */
+ * ckpt_dev[k][FGA_NSTATE][capacity], k < nrec_t (with ckpt_every_step = 1:
+ * before every step and at the end, [nrec_t * rec_every + 1][...]).       */
 fga_status fga_trace(fga_ctx *ctx, fga_beams *beams, int32_t nshots,
                      const int32_t *rec_dev, int32_t nrec, int32_t rec_every,
                      int32_t nrec_t, double *traces_dev, double *ckpt_dev);
@@ -218,13 +229,14 @@ fga_status fga_trace(fga_ctx *ctx, fga_beams *beams, int32_t nshots,
  *   beams      the beams of the forward call (their coefficients C and ids
  *              are read; the states are not)
  *   rec, nrec, rec_every, nrec_t   as in the forward fga_trace call
- *   ckpt_dev   the checkpoints that fga_trace wrote ([nrec_t][23][capacity])
+ *   ckpt_dev   the checkpoints that fga_trace wrote ([nrec_t][23][capacity],
+ *              or every step's with ckpt_every_step = 1)
  *   gtr_dev    dJ/dtraces [nshots][nrec_t][nrec] (e.g. traces - data)
- *   dc_dev     [n2][n1]: dJ/dc is ADDED (caller zeroes it first); the sum
- *              uses device atomics, so its rounding order is not fixed
+ *   dc_dev     [n2][n1]: dJ/dc is ADDED (caller zeroes it first), in the
+ *              order that deterministic and grad_log describe
  *   gcoef_dev  [2][capacity]: dJ/d(Re C, Im C) per beam, overwritten
  * Scratch of rec_every * 23 doubles per beam capacity is held by the
- * context.                                                                 */
+ * context (none with ckpt_every_step = 1).                                 */
 fga_status fga_trace_adjoint(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
                              const int32_t *rec_dev, int32_t nrec, int32_t rec_every,
                              int32_t nrec_t, const double *ckpt_dev, const double *gtr_dev,
@@ -245,7 +257,9 @@ fga_status fga_reconstruct_adjoint(fga_ctx *ctx, const fga_beams *beams, int32_t
 
 /* Propagation that keeps checkpoints for fga_propagate_adjoint: nseg
  * segments of seg RK4 steps each (as nseg calls of fga_propagate), the state
- * at the start of segment k written to ckpt_dev[k][FGA_NSTATE][capacity].  */
+ * at the start of segment k written to ckpt_dev[k][FGA_NSTATE][capacity]
+ * (with ckpt_every_step = 1 every step's and the final state,
+ * [nseg * seg + 1][FGA_NSTATE][capacity]).                                 */
 fga_status fga_propagate_ckpt(fga_ctx *ctx, fga_beams *beams, int32_t nshots, int32_t seg,
                               int32_t nseg, double *ckpt_dev);
 
@@ -254,10 +268,10 @@ fga_status fga_propagate_ckpt(fga_ctx *ctx, fga_beams *beams, int32_t nshots, in
  * fga_reconstruct_adjoint) is pulled back through the RK4 of the ray,
  * dynamic ray tracing and amplitude equations to the cotangent of the state
  * before them (dstate_dev on return); dJ/dc through the velocity in every
- * step is ADDED to dc_dev [n2][n1] (device atomics: rounding order not
- * fixed).  ckpt_dev as written by the forward call.  Requires amp_closed = 0
- * (hence dz_divided = 0).  Scratch of seg * 23 doubles per beam capacity is
- * held by the context.                                                     */
+ * step is ADDED to dc_dev [n2][n1] (in the order that deterministic and
+ * grad_log describe).  ckpt_dev as written by the forward call.  Requires
+ * amp_closed = 0 (hence dz_divided = 0).  Scratch of seg * 23 doubles per
+ * beam capacity is held by the context (none with ckpt_every_step = 1).    */
 fga_status fga_propagate_adjoint(fga_ctx *ctx, const fga_beams *beams, int32_t nshots,
                                  int32_t seg, int32_t nseg, const double *ckpt_dev,
                                  double *dstate_dev, double *dc_dev);

@@ -43,7 +43,7 @@ class fga_params(ctypes.Structure):
                 ("dt", ctypes.c_double), ("top_n", ctypes.c_int32),
                 ("amp_closed", ctypes.c_int32), ("dz_divided", ctypes.c_int32),
                 ("dz_scale", ctypes.c_double), ("deterministic", ctypes.c_int32),
-                ("grad_log", ctypes.c_int32)]
+                ("grad_log", ctypes.c_int32), ("ckpt_every_step", ctypes.c_int32)]
 
 
 class fga3_grid(ctypes.Structure):
@@ -144,7 +144,8 @@ def fga_create(grid, params, precision: int = FGA_FP64, max_shots: int = 1, stre
                    params.tau_fbi, params.tau_win, params.dt, int(getattr(params, "top_n", 0)),
                    int(getattr(params, "amp_closed", 0)), int(getattr(params, "dz_divided", 0)),
                    float(getattr(params, "dz_scale", 1.0)), int(getattr(params, "deterministic", 0)),
-                   int(getattr(params, "grad_log", 0)))
+                   int(getattr(params, "grad_log", 0)),
+                   int(getattr(params, "ckpt_every_step", 0)))
     ctx = ctypes.c_void_p()
     st = load().fga_create(ctypes.byref(ctx), ctypes.byref(g), ctypes.byref(p), int(precision),
                            int(max_shots), _stream_handle(stream))
@@ -365,11 +366,16 @@ class FGA:
         fga_reconstruct_adjoint(self.ctx, beams, nshots, du, dstate, dcoef)
         return dstate, dcoef
 
+    def ckpt_rows(self, seg: int, nseg: int) -> int:
+        """Rows of the checkpoint buffer of nseg segments of seg steps:
+        nseg, or nseg * seg + 1 with ckpt_every_step."""
+        return nseg * seg + 1 if getattr(self.params, "ckpt_every_step", 0) else nseg
+
     def propagate_ckpt(self, beams: Beams, nshots: int, seg: int, nseg: int, ckpt=None):
         import torch
         if ckpt is None:
-            ckpt = torch.empty((nseg, FGA_NSTATE, beams.capacity), dtype=torch.float64,
-                               device=beams.f.device)
+            ckpt = torch.empty((self.ckpt_rows(seg, nseg), FGA_NSTATE, beams.capacity),
+                               dtype=torch.float64, device=beams.f.device)
         fga_propagate_ckpt(self.ctx, beams, nshots, seg, nseg, ckpt)
         return ckpt
 
@@ -413,8 +419,8 @@ def _trace_function():
             f1 = None if f1 is None else f1.detach().contiguous()
             fga.set_velocity(c)
             fga.decompose(f0, f1, beams)
-            ckpt = torch.empty((nrec_t, FGA_NSTATE, beams.capacity), dtype=torch.float64,
-                               device=beams.f.device)
+            ckpt = torch.empty((fga.ckpt_rows(rec_every, nrec_t), FGA_NSTATE, beams.capacity),
+                               dtype=torch.float64, device=beams.f.device)
             tr = fga.trace(beams, nshots, rec, rec_every, nrec_t, ckpt)
             actx.fga, actx.beams, actx.rec = fga, beams, rec
             actx.rec_every, actx.nrec_t, actx.nshots = rec_every, nrec_t, nshots

@@ -461,6 +461,10 @@ __device__ __forceinline__ Cd gauss_phase(double th, double g, double inv_eps)
     return {e * cs, e * sn};
 }
 
+// EVERY: the checkpoints hold the state before every step (and the final
+// one), ckpt[nrec_t * rec_every + 1][NSTATE][cap]; the segments are read,
+// not recomputed, and no scratch is used.
+template <bool EVERY>
 __global__ void __launch_bounds__(ADJ_BLOCK)
 k_trace_adjoint(TraceAdjArgs A)
 {
@@ -484,17 +488,23 @@ k_trace_adjoint(TraceAdjArgs A)
         DcAcc dacc;
         dcacc_init(dacc, b);
         for (int k = A.nrec_t - 1; k >= 0; --k) {
-            // recompute the segment from its checkpoint
             St y;
-            load_state_raw(A.ckpt + (size_t)k * FGA_NSTATE * cap, cap, b, y);
-            for (int j = 0; j < A.rec_every; ++j) {
-                store_state(A.scratch + (size_t)j * FGA_NSTATE * cap + b, cap, y);
-                St t = y, acc = y;
-                stage<false>(A.V, s, t, acc, y, A.dt / 6.0, 0.5 * A.dt);
-                stage<false>(A.V, s, t, acc, y, A.dt / 3.0, 0.5 * A.dt);
-                stage<false>(A.V, s, t, acc, y, A.dt / 3.0, A.dt);
-                stage<true>(A.V, s, t, acc, y, A.dt / 6.0, 0.0);
-                y = acc;
+            if (EVERY) {
+                // the state at the record, stored by the forward
+                load_state_raw(A.ckpt + (size_t)(k + 1) * A.rec_every * FGA_NSTATE * cap, cap, b,
+                               y);
+            } else {
+                // recompute the segment from its checkpoint
+                load_state_raw(A.ckpt + (size_t)k * FGA_NSTATE * cap, cap, b, y);
+                for (int j = 0; j < A.rec_every; ++j) {
+                    store_state(A.scratch + (size_t)j * FGA_NSTATE * cap + b, cap, y);
+                    St t = y, acc = y;
+                    stage<false>(A.V, s, t, acc, y, A.dt / 6.0, 0.5 * A.dt);
+                    stage<false>(A.V, s, t, acc, y, A.dt / 3.0, 0.5 * A.dt);
+                    stage<false>(A.V, s, t, acc, y, A.dt / 3.0, A.dt);
+                    stage<true>(A.V, s, t, acc, y, A.dt / 6.0, 0.0);
+                    y = acc;
+                }
             }
             // cotangent of the traces of record k (boxes held fixed).  The
             // traced term of receiver x is Re(C a e(x)), e = e^{(i (S + P.r)
@@ -555,7 +565,11 @@ k_trace_adjoint(TraceAdjArgs A)
             // pull lambda back through the segment
             for (int j = A.rec_every - 1; j >= 0; --j) {
                 St yj;
-                load_state_raw(A.scratch + (size_t)j * FGA_NSTATE * cap, cap, b, yj);
+                if (EVERY)
+                    load_state_raw(A.ckpt + ((size_t)k * A.rec_every + j) * FGA_NSTATE * cap, cap,
+                                   b, yj);
+                else
+                    load_state_raw(A.scratch + (size_t)j * FGA_NSTATE * cap, cap, b, yj);
                 step_vjp(A.V, s, yj, lam, A.dt, stash, dacc, A.out);
             }
         }
@@ -599,10 +613,15 @@ fga_status fga_launch_rk4_adjoint(fga_ctx *ctx, const fga_beams *beams, int nsho
                                   double *gcoef, const double *lam0, double *lam_out)
 {
     const int64_t cap = beams->capacity;
-    size_t need = (size_t)rec_every * FGA_NSTATE * cap * sizeof(double);
-    fga_status rc = fga_ensure(ctx, &ctx->adj_scratch, &ctx->adj_scratch_bytes, need,
-                               "adjoint segment scratch");
-    if (rc != FGA_OK) return rc;
+    const bool every = ctx->p.ckpt_every_step != 0;
+    fga_status rc = FGA_OK;
+    if (!every) {
+        const size_t need = (size_t)rec_every * FGA_NSTATE * cap * sizeof(double);
+        rc = fga_ensure(ctx, &ctx->adj_scratch, &ctx->adj_scratch_bytes, need,
+                        "adjoint segment scratch");
+        if (rc != FGA_OK) return rc;
+    }
+    auto kernel = every ? k_trace_adjoint<true> : k_trace_adjoint<false>;
     TraceAdjArgs A;
     A.V = fga_velgrid(ctx);
     A.f = beams->f;
@@ -663,7 +682,7 @@ fga_status fga_launch_rk4_adjoint(fga_ctx *ctx, const fga_beams *beams, int nsho
                           ctx->g.n2};
             A.logcnt = (int *)(base + rec_bytes + cell_bytes);
         }
-        hipLaunchKernelGGL(k_trace_adjoint, grid, block, 0, ctx->stream, A);
+        hipLaunchKernelGGL(kernel, grid, block, 0, ctx->stream, A);
         FGA_HIP(ctx, hipGetLastError());
         if (R == 0) return FGA_OK;
         // the logged records (every log at most R long; the rest went to dc
@@ -698,7 +717,7 @@ fga_status fga_launch_rk4_adjoint(fga_ctx *ctx, const fga_beams *beams, int nsho
         A.out = DcOut{nullptr, (double *)base, (int *)(base + rec_bytes), cap, R, ctx->g.n1,
                       ctx->g.n2};
         A.logcnt = (int *)(base + rec_bytes + cell_bytes);
-        hipLaunchKernelGGL(k_trace_adjoint, grid, block, 0, ctx->stream, A);
+        hipLaunchKernelGGL(kernel, grid, block, 0, ctx->stream, A);
         FGA_HIP(ctx, hipGetLastError());
         rc = fga_det_stats(ctx, beams, nshots, R, st);
         if (rc != FGA_OK) return rc;

@@ -86,6 +86,11 @@ static fga_status check_params(fga_ctx *ctx, const fga_grid *g, const fga_params
         return fga_fail(ctx, FGA_EINVAL, "deterministic must be 0 or 1");
     if (p->grad_log < -1)
         return fga_fail(ctx, FGA_EINVAL, "grad_log must be -1, 0 or positive");
+    if (p->ckpt_every_step != 0 && p->ckpt_every_step != 1)
+        return fga_fail(ctx, FGA_EINVAL, "ckpt_every_step must be 0 or 1");
+    if (p->ckpt_every_step && (p->amp_closed || p->dz_divided))
+        return fga_fail(ctx, FGA_EINVAL,
+                        "ckpt_every_step requires the integrated amplitude (amp_closed = 0)");
     int R1 = fga_halfwidth(p->eps, p->tau_fbi, g->d1);
     int R2 = fga_halfwidth(p->eps, p->tau_fbi, g->d2);
     if (R1 > 8192 || R2 > 8192)
@@ -298,7 +303,8 @@ extern "C" fga_status fga_trace(fga_ctx *ctx, fga_beams *beams, int32_t nshots,
     st = fga_rec_shape(ctx, rec, nrec, &shape);
     if (st != FGA_OK) return st;
     for (int k = 0; k < nrec_t; ++k) {
-        double *ck = ckpt ? ckpt + (size_t)k * FGA_NSTATE * beams->capacity : nullptr;
+        const size_t per = ctx->p.ckpt_every_step ? (size_t)rec_every : 1;
+        double *ck = ckpt ? ckpt + (size_t)k * per * FGA_NSTATE * beams->capacity : nullptr;
         st = fga_launch_propagate(ctx, beams, nshots, rec_every, ck);
         if (st != FGA_OK) return st;
         st = fga_launch_trace_points(ctx, beams, nshots, rec, nrec, traces + (size_t)k * nrec,
@@ -338,9 +344,10 @@ extern "C" fga_status fga_propagate_ckpt(fga_ctx *ctx, fga_beams *beams, int32_t
     if (seg < 1 || nseg < 1 || !ckpt)
         return fga_fail(ctx, FGA_EINVAL, "bad checkpoint arguments");
     if (!ctx->have_c) return fga_fail(ctx, FGA_ESTATE, "fga_set_velocity was not called");
+    const size_t per = ctx->p.ckpt_every_step ? (size_t)seg : 1;
     for (int k = 0; k < nseg; ++k) {
         st = fga_launch_propagate(ctx, beams, nshots, seg,
-                                  ckpt + (size_t)k * FGA_NSTATE * beams->capacity);
+                                  ckpt + (size_t)k * per * FGA_NSTATE * beams->capacity);
         if (st != FGA_OK) return st;
     }
     return FGA_OK;

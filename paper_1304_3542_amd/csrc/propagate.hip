@@ -137,7 +137,9 @@ __device__ __forceinline__ Cd det_root(const St &y, Cd prev)
 // LDS per wavefront.  CLOSED: the amplitude is not integrated; the root of
 // det Z is followed step by step (recovered at the start from the incoming
 // a = c(Q)/c(q) root, 2 at t = 0), and a = c(Q)/c(q) root at the end.
-template <bool CLOSED>
+// ckpt (if not null) receives the incoming state, or with EVERY the state
+// before every step and the final one, ckpt[nsteps + 1][NSTATE][cap].
+template <bool CLOSED, bool EVERY = false>
 __global__ void __launch_bounds__(RK_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
       const int64_t *__restrict__ offsets, int nshots, int64_t cap, int64_t NqNp, double dt,
@@ -155,7 +157,7 @@ k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
         if (b >= nb) continue;
         St y;
         load_state(f, cap, b, y);
-        if (ckpt) store_state(ckpt + b, cap, y);
+        if (ckpt && !EVERY) store_state(ckpt + b, cap, y);
         // H of branch - is -H of branch +, so every slope of the - branch is
         // exactly the negative of the + branch's: the stages run the + branch
         // with signed steps (bit-identical to signed slopes, no sign products)
@@ -173,6 +175,7 @@ k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
         vel.cur1 = vel.cur2 = INT_MIN;   // new beam: its slots hold nothing yet
         if (nsteps > 0) vel.prefetch(y.Q1, y.Q2);
         for (int it = 0; it < nsteps; ++it) {
+            if (EVERY) store_state(ckpt + (size_t)it * FGA_NSTATE * cap + b, cap, y);
             St t = y, acc = y;
             rk_stage<false, VelDma, !CLOSED>(vel, 1.0, t, acc, y, h6, h2);
             rk_stage<false, VelDma, !CLOSED>(vel, 1.0, t, acc, y, h3, h2);
@@ -181,6 +184,7 @@ k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
             y = acc;
             if (CLOSED) root = det_root(y, root);
         }
+        if (EVERY) store_state(ckpt + (size_t)nsteps * FGA_NSTATE * cap + b, cap, y);
         if (CLOSED && nsteps > 0) {
             // the last stage requested the coefficients at the final position
             double cQ, d[5];
@@ -395,6 +399,10 @@ fga_status fga_launch_propagate(fga_ctx *ctx, fga_beams *beams, int nshots, int 
         hipLaunchKernelGGL(k_rk4<true>, dim3(blocks), dim3(256), 0, ctx->stream, V, beams->f,
                            beams->id, beams->offsets, nshots, beams->capacity, NqNp, ctx->p.dt,
                            nsteps, ckpt, ctx->status);
+    else if (ckpt && ctx->p.ckpt_every_step)
+        hipLaunchKernelGGL((k_rk4<false, true>), dim3(blocks), dim3(256), 0, ctx->stream, V,
+                           beams->f, beams->id, beams->offsets, nshots, beams->capacity, NqNp,
+                           ctx->p.dt, nsteps, ckpt, ctx->status);
     else
         hipLaunchKernelGGL(k_rk4<false>, dim3(blocks), dim3(256), 0, ctx->stream, V, beams->f,
                            beams->id, beams->offsets, nshots, beams->capacity, NqNp, ctx->p.dt,

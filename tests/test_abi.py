@@ -40,7 +40,7 @@ def _structs(grid, params):
                        params.nq2, params.np1, params.np2, params.dp1, params.dp2, params.tau,
                        params.tau_fbi, params.tau_win, params.dt, params.top_n, params.amp_closed,
                        params.dz_divided, params.dz_scale, params.deterministic,
-                       params.grad_log)
+                       params.grad_log, params.ckpt_every_step)
     return g, p
 
 
@@ -50,6 +50,7 @@ def _structs(grid, params):
     dict(tau_win=1.0), dict(dt=-1e-3), dict(dp1=0.0), dict(top_n=-1), dict(amp_closed=2),
     dict(dz_divided=2, amp_closed=1), dict(dz_divided=1),
     dict(dz_divided=1, amp_closed=1, dz_scale=0.0), dict(deterministic=2), dict(grad_log=-2),
+    dict(ckpt_every_step=2), dict(ckpt_every_step=1, amp_closed=1),
 ])
 def test_create_rejects_bad_params(bad):
     import paper_1304_3542_amd as fga

@@ -22,7 +22,8 @@ def gpu_gradient(g, p, c, f0, f1, rec, every, nrec, data, precision="fp64"):
     f1t = None if f1 is None else torch.from_numpy(f1).cuda()
     ctx.decompose(torch.from_numpy(f0).cuda(), f1t, beams)
     rec_t = torch.from_numpy(rec).cuda()
-    ckpt = torch.empty((nrec, fga.FGA_NSTATE, beams.capacity), dtype=torch.float64, device="cuda")
+    ckpt = torch.empty((ctx.ckpt_rows(every, nrec), fga.FGA_NSTATE, beams.capacity),
+                       dtype=torch.float64, device="cuda")
     tr = ctx.trace(beams, ns, rec_t, every, nrec, ckpt)
     gtr = tr - torch.from_numpy(data).cuda()
     dc = torch.zeros_like(ctx_c := torch.from_numpy(c).cuda())
@@ -77,6 +78,36 @@ def test_adjoint_same_gradient_for_every_log_setting(grad_log):
         assert rel_max(r[k], ra[k]) <= 1e-12, (k, rel_max(r[k], ra[k]))
     assert rel_max(r["dc"], dc) <= 1e-10
     assert rel_max(r["df1"], df1) <= 1e-10
+
+
+@pytest.mark.parametrize("with_f1,mode", [(False, "auto"), (True, "auto"), (True, "det")])
+def test_adjoint_with_every_step_checkpoints(with_f1, mode):
+    """ckpt_every_step = 1: the forward keeps the state before every step
+    and the adjoint reads it instead of recomputing each segment.  The same
+    gradient as the default (to rounding: the forward's velocity goes
+    through the per-cell coefficients, the recompute through the B-spline
+    taps) and as the gradient oracle; in deterministic mode repeatable bit for
+    bit."""
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(with_f1)
+    if mode == "det":
+        p = p.replace(deterministic=1)
+    b = oracle.decompose(f0, f1, c, g, p)
+    data = 0.5 * c_oracle_traces(c * 1.02, f0, f1, g, p, b.cand, rec, every, nrec)
+    J, dc, df0, df1, tr = oadj.gradient(c, f0, f1, g, p, b.cand, rec, every, nrec, data)
+    ra = gpu_gradient(g, p, c, f0, f1, rec, every, nrec, data)
+    pe = p.replace(ckpt_every_step=1)
+    r = gpu_gradient(g, pe, c, f0, f1, rec, every, nrec, data)
+    assert r["status"][0] == 0
+    np.testing.assert_array_equal(r["tr"], ra["tr"])
+    keys = ("dc", "df0") + (("df1",) if with_f1 else ())
+    for k in keys:
+        assert rel_max(r[k], ra[k]) <= 1e-12, (k, rel_max(r[k], ra[k]))
+    assert rel_max(r["dc"], dc) <= 1e-10
+    assert rel_max(r["df0"], df0) <= 1e-10
+    if mode == "det":
+        r2 = gpu_gradient(g, pe, c, f0, f1, rec, every, nrec, data)
+        for k in keys:
+            np.testing.assert_array_equal(r[k], r2[k])
 
 
 def test_adjoint_mixed_within_1e5():

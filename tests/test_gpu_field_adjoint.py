@@ -132,6 +132,25 @@ def test_field_chain_same_for_every_log_setting(grad_log):
         assert rel_max(r[k], ra[k]) <= 1e-12, (k, rel_max(r[k], ra[k]))
 
 
+def test_field_chain_with_every_step_checkpoints():
+    """fga_propagate_ckpt / fga_propagate_adjoint with ckpt_every_step = 1
+    (15 steps in 3 segments, 16 stored states) give the default chain's
+    gradient to rounding and the oracle's."""
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(True)
+    ns = f0.shape[0]
+    b = oracle.decompose(f0, f1, c, g, p)
+    nodes = np.arange(g.n1 * g.n2, dtype=np.int32)
+    d = 0.5 * c_oracle_traces(c * 1.02, f0, f1, g, p, b.cand, nodes, p.nsteps, 1)
+    J, dc, df0, df1, tr = oadj.gradient(c, f0, f1, g, p, b.cand, nodes, p.nsteps, 1, d)
+    d3 = d.reshape(ns, g.n2, g.n1)
+    ra = _field_chain(g, p, c, f0, f1, d3, 5, 3)
+    r = _field_chain(g, p.replace(ckpt_every_step=1), c, f0, f1, d3, 5, 3)
+    for k in ("dc", "df0", "df1", "lam0"):
+        assert rel_max(r[k], ra[k]) <= 1e-12, (k, rel_max(r[k], ra[k]))
+    assert rel_max(r["dc"], dc) <= 1e-10
+    assert rel_max(r["df1"], df1) <= 1e-10
+
+
 def test_field_chain_equals_trace_adjoint_with_every_node():
     """The same misfit through fga_trace_adjoint (every node a receiver, one
     record, one segment of 15 steps) gives the same dJ/dc and dJ/dC as the
