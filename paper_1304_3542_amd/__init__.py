@@ -336,8 +336,18 @@ class FGA:
         fga_reconstruct(self.ctx, beams, nshots, u)
         return u
 
+    def _check_ckpt(self, ckpt, beams: Beams, seg: int, nseg: int):
+        # the library cannot see buffer sizes: a short checkpoint buffer
+        # would be written past its end
+        need = self.ckpt_rows(seg, nseg) * FGA_NSTATE * beams.capacity
+        if ckpt.numel() < need:
+            raise ValueError(f"ckpt holds {ckpt.numel()} doubles, {need} needed "
+                             f"({self.ckpt_rows(seg, nseg)} x {FGA_NSTATE} x capacity)")
+
     def trace(self, beams: Beams, nshots: int, rec, rec_every: int, nrec_t: int, ckpt=None):
         import torch
+        if ckpt is not None:
+            self._check_ckpt(ckpt, beams, rec_every, nrec_t)
         tr = torch.empty((nshots, nrec_t, rec.numel()), dtype=torch.float64,
                          device=beams.f.device)
         fga_trace(self.ctx, beams, nshots, rec, rec_every, nrec_t, tr, ckpt)
@@ -346,6 +356,7 @@ class FGA:
     def trace_adjoint(self, beams: Beams, nshots: int, rec, rec_every: int, nrec_t: int, ckpt,
                       gtr, dc):
         import torch
+        self._check_ckpt(ckpt, beams, rec_every, nrec_t)
         gcoef = torch.empty((2, beams.capacity), dtype=torch.float64, device=beams.f.device)
         fga_trace_adjoint(self.ctx, beams, nshots, rec, rec_every, nrec_t, ckpt, gtr, dc, gcoef)
         return gcoef
@@ -376,10 +387,12 @@ class FGA:
         if ckpt is None:
             ckpt = torch.empty((self.ckpt_rows(seg, nseg), FGA_NSTATE, beams.capacity),
                                dtype=torch.float64, device=beams.f.device)
+        self._check_ckpt(ckpt, beams, seg, nseg)
         fga_propagate_ckpt(self.ctx, beams, nshots, seg, nseg, ckpt)
         return ckpt
 
     def propagate_adjoint(self, beams: Beams, nshots: int, seg: int, nseg: int, ckpt, dstate, dc):
+        self._check_ckpt(ckpt, beams, seg, nseg)
         fga_propagate_adjoint(self.ctx, beams, nshots, seg, nseg, ckpt, dstate, dc)
         return dstate
 

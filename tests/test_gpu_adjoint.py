@@ -328,3 +328,28 @@ def test_trace_adjoint_directional_derivative_in_velocity():
     rich = (4 * D(h / 2) - D(h)) / 3
     assert abs(adj) > 0
     assert abs(rich - adj) <= 1e-6 * abs(adj), (rich, adj)
+
+
+def test_short_checkpoint_buffer_rejected_before_any_launch():
+    """With ckpt_every_step = 1 a checkpoint buffer of one row per record is
+    too short: the binding refuses it (nothing is launched), and accepts the
+    nrec_t * rec_every + 1 rows."""
+    import torch
+    import paper_1304_3542_amd as fga
+    g, p, c, f0, f1, rec, every, nrec = adjoint_case(False)
+    ns = f0.shape[0]
+    ctx = fga.FGA(g, p.replace(ckpt_every_step=1), "fp64", max_shots=ns)
+    ctx.set_velocity(torch.from_numpy(c).cuda())
+    beams = fga.Beams(2 * p.nq1 * p.nq2 * p.np1 * p.np2 * ns, ns)
+    ctx.decompose(torch.from_numpy(f0).cuda(), None, beams)
+    rec_t = torch.from_numpy(rec).cuda()
+    short = torch.empty((nrec, fga.FGA_NSTATE, beams.capacity), dtype=torch.float64,
+                        device="cuda")
+    with pytest.raises(ValueError):
+        ctx.trace(beams, ns, rec_t, every, nrec, short)
+    with pytest.raises(ValueError):
+        ctx.propagate_ckpt(beams, ns, every, nrec, short)
+    ckpt = torch.empty((nrec * every + 1, fga.FGA_NSTATE, beams.capacity), dtype=torch.float64,
+                       device="cuda")
+    ctx.trace(beams, ns, rec_t, every, nrec, ckpt)
+    assert ctx.status()[0] == 0
