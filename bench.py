@@ -287,7 +287,37 @@ def adjoint_iteration(steps):
     ev[1].record()
     torch.cuda.synchronize()
     st, _ = ctx.status()
-    out["field_misfit"] = {"ms_per_iter": ev[0].elapsed_time(ev[1]) / steps, "status": st,
+    ms_field_seg = ev[0].elapsed_time(ev[1]) / steps
+
+    # and with every step's state kept by the forward
+    ctx_f = fga.FGA(g, p.replace(ckpt_every_step=1), "fp64", max_shots=ns)
+    ctx_f.set_velocity(c)
+    ckpt_f = torch.empty((ctx_f.ckpt_rows(W.rec_every, nrec_t), fga.FGA_NSTATE, beams.capacity),
+                         dtype=torch.float64, device="cuda")
+
+    def it_field_every():
+        ctx_f.decompose(f0, None, beams)
+        ctx_f.propagate_ckpt(beams, ns, W.rec_every, nrec_t, ckpt_f)
+        ctx_f.reconstruct(beams, ns, u)
+        dstate, dcoef = ctx_f.reconstruct_adjoint(beams, ns, (u - u_data).contiguous())
+        dc.zero_()
+        ctx_f.propagate_adjoint(beams, ns, W.rec_every, nrec_t, ckpt_f, dstate, dc)
+        return ctx_f.decompose_adjoint(beams, ns, dcoef)
+
+    it_field_every()
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(steps):
+        it_field_every()
+    ev[1].record()
+    torch.cuda.synchronize()
+    st_f, _ = ctx_f.status()
+    del ckpt_f
+    ctx_f.close()
+    out["field_misfit"] = {"ms_per_iter": ev[0].elapsed_time(ev[1]) / steps,
+                           "status": st if st != 0 else st_f,
+                           "checkpoints": "every step",
+                           "segment_checkpoints_ms_per_iter": ms_field_seg,
                            "misfit": "1/2 |u(T) - u_data(T)|^2 over the grid"}
 
     # the receiver-misfit iteration in deterministic mode (fixed-order dJ/dc;
