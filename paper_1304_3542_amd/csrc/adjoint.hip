@@ -997,27 +997,41 @@ k_fbi_pass2_t(const double *__restrict__ psib, const cplxR<R> *__restrict__ E2, 
     out[1] = ai * d2;
 }
 
+// the pass-1 table with the window offset fastest: E1tt[l][m] = E1t[m][l]
+template <typename R>
+__global__ void k_e1_transpose(const cplxR<R> *__restrict__ E1t, cplxR<R> *__restrict__ E1tt,
+                               int W1, int np1)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < W1 * np1;
+         i += gridDim.x * blockDim.x) {
+        const int m = i / np1, l = i - m * np1;
+        E1tt[(size_t)l * W1 + m] = E1t[i];
+    }
+}
+
 // Transposed pass 1: fb[sf][i2][i1] = d1 Re sum_{j1, l1} conj(E1t[i1 - k1(j1)][l1]) Tb[sf][i2][j1 np1 + l1]
+// (the table read as E1tt[l1][m]: neighbouring lanes, neighbouring m)
 template <typename R>
 __global__ void __launch_bounds__(256)
-k_fbi_pass1_t(const double *__restrict__ Tb, const cplxR<R> *__restrict__ E1t, double *f0b,
+k_fbi_pass1_t(const double *__restrict__ Tb, const cplxR<R> *__restrict__ E1tt, double *f0b,
               double *f1b, int nfj, int n1, int n2, int R1, int qb1, int qs1, int nq1, int np1,
               double d1)
 {
     const int i1 = blockIdx.x * blockDim.x + threadIdx.x;
     const int i2 = blockIdx.y, sf = blockIdx.z;
     if (i1 >= n1) return;
-    const int NC = nq1 * np1;
+    const int NC = nq1 * np1, W1 = 2 * R1 + 1;
     const double *tb = Tb + 2 * (((size_t)sf * n2 + i2) * NC);
     double acc = 0.0;
     for (int j1 = 0; j1 < nq1; ++j1) {
         const int m = i1 - (qb1 + j1 * qs1);   // window offset of node i1 from q node j1
         if (m < -R1 || m > R1) continue;
-        const cplxR<R> *e = E1t + (size_t)(m + R1) * np1;
+        const cplxR<R> *e = E1tt + (m + R1);
         const double *t = tb + 2 * (size_t)j1 * np1;
         for (int l1 = 0; l1 < np1; ++l1) {
             // Re(conj(e) t)
-            acc += (double)e[l1].re * t[2 * l1] + (double)e[l1].im * t[2 * l1 + 1];
+            const cplxR<R> v = e[(size_t)l1 * W1];
+            acc += (double)v.re * t[2 * l1] + (double)v.im * t[2 * l1 + 1];
         }
     }
     int s = sf / nfj, fj = sf % nfj;
@@ -1061,8 +1075,14 @@ static fga_status decompose_adjoint_impl(fga_ctx *ctx, const fga_beams *beams, i
     hipLaunchKernelGGL(k_fbi_pass2_t<R>, dim3((unsigned)((NC + 255) / 256), g.n2, S), dim3(256),
                        0, st, psib, (const cplxR<R> *)ctx->E2, Tb, g.n2, ctx->R2, p.qb2, p.qs2,
                        p.nq2, p.np2, (int)NC, g.d2);
+    const int W1 = 2 * ctx->R1 + 1;
+    rc = fga_ensure(ctx, &ctx->E1tt, &ctx->E1tt_bytes, (size_t)W1 * p.np1 * sizeof(cplxR<R>),
+                    "transposed pass-1 table");
+    if (rc != FGA_OK) return rc;
+    hipLaunchKernelGGL(k_e1_transpose<R>, dim3((W1 * p.np1 + 255) / 256), dim3(256), 0, st,
+                       (const cplxR<R> *)ctx->E1t, (cplxR<R> *)ctx->E1tt, W1, p.np1);
     hipLaunchKernelGGL(k_fbi_pass1_t<R>, dim3((g.n1 + 255) / 256, g.n2, S), dim3(256), 0, st, Tb,
-                       (const cplxR<R> *)ctx->E1t, df0, df1, nfj, g.n1, g.n2, ctx->R1, p.qb1,
+                       (const cplxR<R> *)ctx->E1tt, df0, df1, nfj, g.n1, g.n2, ctx->R1, p.qb1,
                        p.qs1, p.nq1, p.np1, g.d1);
     if (nfj == 2 && dc) {
         int nq = p.nq1 * p.nq2;

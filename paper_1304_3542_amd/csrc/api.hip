@@ -160,7 +160,7 @@ extern "C" fga_status fga_destroy(fga_ctx *ctx)
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     void *bufs[] = {ctx->c, ctx->cpad, ctx->ccoef, ctx->status, ctx->cq, ctx->maxbits, ctx->E1t, ctx->E2,
                     ctx->T, ctx->Psi, ctx->blk, ctx->partial, ctx->srec, ctx->sbox,
-                    ctx->adj_scratch, ctx->adj_psib, ctx->rec_shape, ctx->trace_part, ctx->bin,
+                    ctx->adj_scratch, ctx->adj_psib, ctx->rec_shape, ctx->E1tt, ctx->trace_part, ctx->bin,
                     ctx->det_log, ctx->det_sort, ctx->det_cell, ctx->det_cqc, ctx->det_lam};
     for (void *b : bufs)
         if (b) (void)hipFree(b);

@@ -55,6 +55,8 @@ struct fga_ctx {
     size_t adj_scratch_bytes, adj_psib_bytes;
     void *rec_shape;       // [4] ints: receivers one run of a row? (first column, row)
     size_t rec_shape_bytes;
+    void *E1tt;            // [np1][W1] complex: pass-1 table, l-major (transposed pass 1)
+    size_t E1tt_bytes;
     int last_nfj, last_nshots;
 
     // deterministic gradient: per-beam dJ/dc logs, the sort and cell
