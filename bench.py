@@ -623,8 +623,8 @@ def cpu_baseline(W, nbeams, budget_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 "
+                          "(sharding over several GPUs is designed, not built)"}))
         sys.exit(2)
     import torch
     if args.calib_copy:
