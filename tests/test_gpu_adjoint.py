@@ -177,14 +177,15 @@ def test_adjoint_full_size_matches_finite_differences():
         assert abs(fd - dcn[i2, i1]) <= 1e-6 * scale, (idx, fd, dcn[i2, i1], scale)
 
 
-@pytest.mark.parametrize("with_f1", [False, True])
-def test_autograd_function_matches_oracle_gradient(with_f1):
+@pytest.mark.parametrize("with_f1,every_step", [(False, 0), (True, 0), (True, 1)])
+def test_autograd_function_matches_oracle_gradient(with_f1, every_step):
     """The adjoint behind torch.autograd: loss.backward() through
     paper_1304_3542_amd.traces gives the gradient oracle's dJ/dc, dJ/df0
-    (and dJ/df1)."""
+    (and dJ/df1), with checkpoints per record or of every step."""
     import torch
     import paper_1304_3542_amd as fga
     g, p, c, f0, f1, rec, every, nrec = adjoint_case(with_f1)
+    p = p.replace(ckpt_every_step=every_step)
     b = oracle.decompose(f0, f1, c, g, p)
     data = 0.5 * c_oracle_traces(c * 1.02, f0, f1, g, p, b.cand, rec, every, nrec)
     J, dc, df0, df1, _ = oadj.gradient(c, f0, f1, g, p, b.cand, rec, every, nrec, data)
