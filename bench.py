@@ -398,12 +398,23 @@ def topn_step(steps):
     nb = path.fit_capacity()
     ms, stage_ms, per_step = time_path(path, steps, 1)
     st, _ = path.ctx.status()
+    path.ctx.close()
+    # the few-beam end of the same mode (the paper's smallest N is 6)
+    Wf = fi.Workload("topn6", W.grid, W.params.replace(top_n=6), W.c, W.f0, None)
+    pf = Path(Wf, "mixed", 64)
+    nbf = pf.fit_capacity()
+    msf, stage_f, _ = time_path(pf, steps, 1)
+    stf, _ = pf.ctx.status()
+    pf.ctx.close()
     return {"workload": "topn512: point512 keeping the 5650 largest |psi| per wave branch "
             "(radix select), mixed", "nbeams": nb, "ms_per_step": ms,
             "ms_per_step_device_median": float(np.median(per_step)),
             "beams_per_s": nb / (ms * 1e-3),
             "stages_ms": dict(zip(("decompose", "propagate", "reconstruct"),
-                                  stage_ms.tolist())), "status": st}
+                                  stage_ms.tolist())), "status": st,
+            "n6": {"nbeams": nbf, "ms_per_step": msf,
+                   "stages_ms": dict(zip(("decompose", "propagate", "reconstruct"),
+                                         stage_f.tolist())), "status": stf}}
 
 
 def fbi_flops(W, tau_fbi):
