@@ -151,84 +151,8 @@ k_fbi_pass1(const double *f0, const double *f1, int nfj, const cplx<R> *__restri
 }
 
 // ------------------------------------------------------------------ pass 2
-// Psi[sf][j2][l2][c] = d2 * sum_m E2[l2][m] T[sf][k2(j2) + m][c]
-#define P2_BM 32
-#define P2_BN 64
-#define P2_BK 16
-
-template <typename R>
-__global__ void __launch_bounds__(256)
-k_fbi_pass2(const cplx<R> *__restrict__ T, const cplx<R> *__restrict__ E2,
-            cplx<R> *__restrict__ Psi, int n2, int R2, int qb2, int qs2, int nq2, int np2,
-            int NC, double d2)
-{
-    __shared__ cplx<R> As[P2_BK][P2_BM + 1];
-    __shared__ cplx<R> Bs[P2_BK][P2_BN];
-    int W2 = 2 * R2 + 1;
-    int sfj = blockIdx.z;
-    int sf = sfj / nq2, j2 = sfj % nq2;
-    int k2 = qb2 + j2 * qs2;
-    int mlo = max(-R2, -k2), mhi = min(R2, n2 - 1 - k2);
-    int K = mhi - mlo + 1;
-    int c0 = blockIdx.x * P2_BN, l0 = blockIdx.y * P2_BM;
-    int t = threadIdx.x;
-    int tn = t % 16, tm = t / 16;
-    const cplx<R> *Tb = T + (size_t)sf * n2 * NC;
-    R accr[2][4], acci[2][4];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) accr[i][j] = acci[i][j] = 0;
-
-    for (int kk = 0; kk < K; kk += P2_BK) {
-        // E2 tile: P2_BM x P2_BK
-        for (int e = t; e < P2_BM * P2_BK; e += 256) {
-            int mm = e / P2_BK, k = e % P2_BK;
-            int l = l0 + mm, m = mlo + kk + k;
-            cplx<R> v{0, 0};
-            if (l < np2 && kk + k < K) v = E2[(size_t)l * W2 + m + R2];
-            As[k][mm] = v;
-        }
-        // T tile: P2_BK x P2_BN
-        for (int e = t; e < P2_BK * P2_BN; e += 256) {
-            int k = e / P2_BN, n = e % P2_BN;
-            int cc = c0 + n;
-            cplx<R> v{0, 0};
-            if (cc < NC && kk + k < K) v = Tb[(size_t)(k2 + mlo + kk + k) * NC + cc];
-            Bs[k][n] = v;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int k = 0; k < P2_BK; ++k) {
-            cplx<R> a[2], b[4];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = As[k][tm + 16 * i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[k][tn + 16 * j];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    accr[i][j] += a[i].re * b[j].re - a[i].im * b[j].im;
-                    acci[i][j] += a[i].re * b[j].im + a[i].im * b[j].re;
-                }
-        }
-        __syncthreads();
-    }
-    cplx<R> *out = Psi + ((size_t)sf * nq2 + j2) * np2 * (size_t)NC;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        int l = l0 + tm + 16 * i;
-        if (l >= np2) continue;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            int cc = c0 + tn + 16 * j;
-            if (cc >= NC) continue;
-            out[(size_t)l * NC + cc].re = accr[i][j] * (R)d2;
-            out[(size_t)l * NC + cc].im = acci[i][j] * (R)d2;
-        }
-    }
-}
+// Psi[sf][j2][l2][c] = d2 * sum_m E2[l2][m] T[sf][k2(j2) + m][c], as a GEMM on the
+// matrix cores (FP32 below; FP64 in k_fbi_pass2_mfma64)
 
 // Pass 2 of the mixed path on the matrix cores.  A complex MAC over k is a
 // K = 2 real product: with v_mfma_f32_32x32x2f32 lane l holds A[l % 32][l / 32]
@@ -332,6 +256,110 @@ k_fbi_pass2_mfma(const cplx<float> *__restrict__ T, const cplx<float> *__restric
                 if (l < np2 && cc < NC) {
                     out[(size_t)l * NC + cc].re = accr[a][c][r] * s2;
                     out[(size_t)l * NC + cc].im = acci[a][c][r] * s2;
+                }
+            }
+}
+
+// FP64 pass 2 on the matrix cores (v_mfma_f64_16x16x4f64), the same complex
+// product as real ones with K doubled:
+//   Re Psi:  A = [Re E, -Im E] (rows l2, k = re/im part), B = [Re T ; Im T]
+//   Im Psi:  A = [Im E,  Re E],                            B = [Re T ; Im T]
+// one MFMA covers two window rows.  Lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] (l / 16 = 2 (window row of the pair) + part); element i
+// of its result is D[4 i + l / 16][l % 16].  A workgroup of four wavefronts
+// computes a 64 (l2) x 64 (c) tile of one (shot, j2), each wavefront a
+// 32 x 32 quarter (2 x 2 blocks of 16 x 16, Re and Im); the table and T are
+// staged through LDS, 16 window rows at a time.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+#define P2D_T 64
+#define P2D_K 16
+
+__global__ void __launch_bounds__(256)
+k_fbi_pass2_mfma64(const cplx<double> *__restrict__ T, const cplx<double> *__restrict__ E2,
+                   cplx<double> *__restrict__ Psi, int n2, int R2, int qb2, int qs2, int nq2,
+                   int np2, int NC, double d2)
+{
+    __shared__ double2 Es[P2D_K][P2D_T];   // [k][l2]
+    __shared__ double2 Ts[P2D_K][P2D_T];   // [k][c]
+    const int W2 = 2 * R2 + 1;
+    const int sfj = blockIdx.z;
+    const int sf = sfj / nq2, j2 = sfj % nq2;
+    const int k2 = qb2 + j2 * qs2;
+    const int mlo = max(-R2, -k2), mhi = min(R2, n2 - 1 - k2);
+    const int K = mhi - mlo + 1;
+    const int c0 = blockIdx.x * P2D_T, l0 = blockIdx.y * P2D_T;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    const int wr = wv >> 1, wc = wv & 1;
+    const int i = lane & 15, q = lane >> 4;          // row / column in a block; K slot
+    const int kp = q >> 1;                           // window row of the pair
+    const bool im_part = (q & 1) != 0;
+    const cplx<double> *Tb = T + (size_t)sf * n2 * NC;
+    doublex4 accr[2][2], acci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) accr[a][b][r] = acci[a][b][r] = 0.0;
+    for (int kk = 0; kk < K; kk += P2D_K) {
+        for (int e = t; e < P2D_T * P2D_K; e += 256) {
+            const int r = e / P2D_K, k = e % P2D_K;
+            const int l = l0 + r;
+            double2 v = make_double2(0.0, 0.0);
+            if (l < np2 && kk + k < K) {
+                const cplx<double> x = E2[(size_t)l * W2 + mlo + kk + k + R2];
+                v = make_double2(x.re, x.im);
+            }
+            Es[k][r] = v;
+        }
+        for (int e = t; e < P2D_K * P2D_T; e += 256) {
+            const int k = e / P2D_T, n = e % P2D_T;
+            const int cc = c0 + n;
+            double2 v = make_double2(0.0, 0.0);
+            if (cc < NC && kk + k < K) {
+                const cplx<double> x = Tb[(size_t)(k2 + mlo + kk + k) * NC + cc];
+                v = make_double2(x.re, x.im);
+            }
+            Ts[k][n] = v;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int k = 0; k < P2D_K; k += 2) {
+            double ar[2], ai[2], b[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const double2 e = Es[k + kp][wr * 32 + a * 16 + i];
+                ar[a] = im_part ? -e.y : e.x;
+                ai[a] = im_part ? e.x : e.y;
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const double2 x = Ts[k + kp][wc * 32 + c * 16 + i];
+                b[c] = im_part ? x.y : x.x;
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    accr[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], b[c], accr[a][c], 0, 0, 0);
+                    acci[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], b[c], acci[a][c], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    cplx<double> *out = Psi + ((size_t)sf * nq2 + j2) * np2 * (size_t)NC;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int l = l0 + wr * 32 + a * 16 + 4 * r + q;
+                const int cc = c0 + wc * 32 + c * 16 + i;
+                if (l < np2 && cc < NC) {
+                    out[(size_t)l * NC + cc].re = accr[a][c][r] * d2;
+                    out[(size_t)l * NC + cc].im = acci[a][c][r] * d2;
                 }
             }
 }
@@ -894,10 +922,11 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
                            (const cplx<float> *)ctx->E2, (cplx<float> *)ctx->Psi, g.n2, ctx->R2,
                            p.qb2, p.qs2, p.nq2, p.np2, (int)NC, g.d2);
     } else {
-        dim3 g2((unsigned)((NC + P2_BN - 1) / P2_BN), (p.np2 + P2_BM - 1) / P2_BM, S * p.nq2);
-        hipLaunchKernelGGL(k_fbi_pass2<R>, g2, dim3(256), 0, st, (const cplx<R> *)ctx->T,
-                           (const cplx<R> *)ctx->E2, (cplx<R> *)ctx->Psi, g.n2, ctx->R2, p.qb2,
-                           p.qs2, p.nq2, p.np2, (int)NC, g.d2);
+        dim3 g2((unsigned)((NC + P2D_T - 1) / P2D_T), (p.np2 + P2D_T - 1) / P2D_T, S * p.nq2);
+        hipLaunchKernelGGL(k_fbi_pass2_mfma64, g2, dim3(256), 0, st,
+                           (const cplx<double> *)ctx->T, (const cplx<double> *)ctx->E2,
+                           (cplx<double> *)ctx->Psi, g.n2, ctx->R2, p.qb2, p.qs2, p.nq2, p.np2,
+                           (int)NC, g.d2);
     }
     if (p.top_n > 0) {
         const int npass = (int)sizeof(R);   // eight bits of the key per pass
