@@ -1,0 +1,43 @@
+"""Host-side checks of bench.py: the one-GPU guard and the lookup of the
+committed HBM counters for the kernels its roofline names."""
+import importlib.util
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def load_bench():
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode != 0
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_profiled_names_exist_in_counter_summary():
+    b = load_bench()
+    z = json.load(open(b.PROFILE_JSON))
+    for kern in b.KERNEL_SOURCES:
+        assert b.PROFILED_NAME[kern] in z["kernels"], kern
+        assert kern in z["source_sha"], kern
+
+
+def test_traffic_follows_source_hash(tmp_path, monkeypatch):
+    b = load_bench()
+    z = json.load(open(b.PROFILE_JSON))
+    # with the stored hash replaced, the traffic must be withheld
+    z["source_sha"] = {k: "0" * 16 for k in z["source_sha"]}
+    p = tmp_path / "counters.json"
+    p.write_text(json.dumps(z))
+    monkeypatch.setattr(b, "PROFILE_JSON", str(p))
+    for kern in b.KERNEL_SOURCES:
+        assert b.profiled_traffic(kern) is None
