@@ -164,6 +164,35 @@ def time_path(path, steps, warmup):
     return wall * 1e3, st.mean(axis=0), per_step
 
 
+def graph_replays(path, steps, nb):
+    """The same step (decompose -> propagate -> reconstruct) captured once as
+    a HIP graph and replayed: device ms per replay from HIP events on the
+    context's stream, median and interquartile range."""
+    import torch
+    W = path.W
+    fga = path.fga
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    fga.fga_set_stream(path.ctx.ctx, stream)
+    with torch.cuda.stream(stream):
+        path.ctx.graph_capture(path.f0, path.f1, path.beams, W.params.nsteps, path.u)
+        path.ctx.graph_launch()
+        stream.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        evs[0].record(stream)
+        for k in range(steps):
+            path.ctx.graph_launch()
+            evs[k + 1].record(stream)
+        stream.synchronize()
+        st, _ = path.ctx.status()
+    fga.fga_set_stream(path.ctx.ctx, torch.cuda.current_stream())
+    ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(steps)])
+    med = float(np.median(ms))
+    return {"replays": steps, "ms_per_replay_median": med,
+            "iqr": float(np.percentile(ms, 75) - np.percentile(ms, 25)),
+            "beams_per_s": nb / (med * 1e-3), "status": st}
+
+
 def time_splat_kernel(path, reps=3):
     """Duration of the reconstruction on its stream (HIP events): the
     record pre-pass, the binning, the MFMA splat and the tile reduction
@@ -657,6 +686,7 @@ def main():
     ms_step, stage_ms, per_step = time_path(mixed, args.steps, args.warmup)
     u_mixed = mixed.u.cpu().numpy()
     f_host = mixed.beams.f[:, :nb].cpu().numpy()
+    graph = graph_replays(mixed, args.steps, nb) if args.steps > 0 else None
 
     fp64 = Path(Wd, "fp64", min(cand, 4_000_000))
     nb64 = fp64.fit_capacity()
@@ -734,6 +764,7 @@ def main():
         "rel_l2_vs_fp64_gpu": rel_vs_fp64,
         "rel_l2_vs_oracle_sample": rel_oracle,
         "stages_ms": stages,
+        "graph": graph,
         "grid_points_per_s": npts / (ms_step * 1e-3),
         "pairs": pairs,
         "pairs_per_s": pairs / (stage_ms[2] * 1e-3),
