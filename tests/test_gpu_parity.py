@@ -223,6 +223,47 @@ def test_full_size_mixed_against_stored_oracle_values():
     assert rel_l2(u.ravel()[z["nodes"]], z["u"]) <= MIXED_TOL
 
 
+def test_full_size_graph_replays_match_eager_and_oracle():
+    """point512 (mixed) in the timed benchmark's graph form: the whole step
+    captured once and replayed, with eager work and synchronisations between
+    the replays; every replay equals the eager step bit for bit (beams and
+    field) and the stored oracle values to the mixed tolerance."""
+    import torch
+    import paper_1304_3542_amd as fga
+    z = _golden("point512")
+    W = fi.workload("point512", "mixed")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = fga.FGA(W.grid, W.params, "mixed")
+        ctx.set_velocity(torch.from_numpy(W.c).cuda())
+        f0 = torch.from_numpy(np.ascontiguousarray(W.f0)).cuda()
+        beams = fga.Beams(int(z["nbeams"]) + 4096, 1)
+        ctx.decompose(f0, None, beams)
+        ctx.propagate(beams, 1, W.params.nsteps)
+        u_eager = ctx.reconstruct(beams, 1).clone()
+        nb = int(ctx.offsets(beams, 1)[-1])
+        f_eager = beams.f[:, :nb].clone()
+        assert ctx.status()[0] == 0
+        u = torch.full_like(u_eager, float("nan"))
+        ctx.graph_capture(f0, None, beams, W.params.nsteps, u)
+        stream.synchronize()
+        for rep in range(3):
+            u.fill_(float("nan"))
+            beams.f[:, :nb].zero_()
+            stream.synchronize()
+            ctx.graph_launch()
+            stream.synchronize()
+            print(f"graph replay {rep}", flush=True)
+            assert ctx.status()[0] == 0
+            assert int(ctx.offsets(beams, 1)[-1]) == nb
+            assert torch.equal(beams.f[:, :nb], f_eager), rep
+            assert torch.equal(u, u_eager), rep
+            # eager work on the same stream between the replays
+            ctx.reconstruct(beams, 1)
+            stream.synchronize()
+    assert rel_l2(u.cpu().numpy()[0].ravel()[z["nodes"]], z["u"]) <= MIXED_TOL
+
+
 def test_wavepacket_against_exact_solution():
     """Physics check of the whole GPU path (parity unpinned: the O(eps)
     constant of the asymptotics is not printed in the paper): the FP64 GPU
