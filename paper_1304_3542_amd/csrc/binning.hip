@@ -217,15 +217,17 @@ __device__ __forceinline__ int wave_max(int v)
 __global__ void __launch_bounds__(64)
 k_bin_fill(BinArgs B)
 {
-    extern __shared__ int run[];
+    // next list position of every shot-tile for this chunk: its list start
+    // plus the entries of the chunks before, advanced as entries are written
+    extern __shared__ int64_t pos[];
     const int lane = threadIdx.x;
     const unsigned long long below = (1ull << lane) - 1ull;
     const int64_t nb = B.offsets[B.nshots];
     const int nused = bin_nchunks(B);
     for (int chunk = blockIdx.x; chunk < nused; chunk += gridDim.x) {
-        for (int t = lane; t < B.ntiles_total; t += 64) run[t] = 0;
-        __syncthreads();
         const int32_t *woff = B.wcnt + (size_t)chunk * B.ntiles_total;
+        for (int t = lane; t < B.ntiles_total; t += 64) pos[t] = B.tile_start[t] + woff[t];
+        __syncthreads();
         for (int r = 0; r < BIN_WCH / 64; ++r) {
             const int64_t b = (int64_t)chunk * BIN_WCH + r * 64 + lane;
             int t1lo = 0, t1hi = -1, t2lo = 0, t2hi = -1, s = -1;
@@ -246,12 +248,10 @@ k_bin_fill(BinArgs B)
                         const unsigned long long m = __ballot(hit);
                         if (!m) continue;
                         const int tt = ss * B.ntiles + t2 * B.ntile1 + t1;
-                        const int base = run[tt];
-                        if (hit)
-                            B.list[B.tile_start[tt] + woff[tt] + base + __popcll(m & below)] =
-                                (int32_t)b;
+                        const int64_t base = pos[tt];
+                        if (hit) B.list[base + __popcll(m & below)] = (int32_t)b;
                         __builtin_amdgcn_wave_barrier();
-                        if (lane == 0) run[tt] = base + __popcll(m);
+                        if (lane == 0) pos[tt] = base + __popcll(m);
                         __builtin_amdgcn_wave_barrier();
                     }
             }
@@ -437,7 +437,8 @@ fga_status fga_launch_splat_binned(fga_ctx *ctx, const fga_beams *beams, int nsh
     hipLaunchKernelGGL(k_bin_scan_tiles, dim3((T + 63) / 64), dim3(64 * BIN_SCAN_GROUPS), 0,
                        ctx->stream, B);
     hipLaunchKernelGGL(k_bin_scan_items, dim3(1), dim3(1024), 0, ctx->stream, B);
-    hipLaunchKernelGGL(k_bin_fill, dim3(cgrid), dim3(64), lds, ctx->stream, B);
+    hipLaunchKernelGGL(k_bin_fill, dim3(cgrid), dim3(64), (size_t)T * sizeof(int64_t),
+                       ctx->stream, B);
     hipLaunchKernelGGL(k_splat_binned, dim3((max_items + 3) / 4), dim3(256), 0, ctx->stream, A,
                        B, (const SplatRec *)rec);
     hipLaunchKernelGGL(k_splat_reduce_binned, dim3(1024), dim3(256), 0, ctx->stream, A, B, u);
