@@ -160,6 +160,7 @@ __global__ void __launch_bounds__(1024)
 k_bin_scan_items(BinArgs B)
 {
     __shared__ int64_t sh[1024];
+    __shared__ int32_t s_item[BIN_MAX_TILES + 1];   // first item of every tile
     const int t = threadIdx.x;
     const int T = B.ntiles_total;
     const int lo = t * BIN_PER_THREAD;
@@ -185,20 +186,34 @@ k_bin_scan_items(BinArgs B)
         B.meta[2] = L;
         B.tile_start[T] = H;
         B.tile_item[T] = (int32_t)NI;
+        s_item[T] = (int32_t)NI;
     }
 #pragma unroll
     for (int k = 0; k < BIN_PER_THREAD; ++k) {
         if (lo + k >= T) break;
         B.tile_start[lo + k] = off;
         B.tile_item[lo + k] = (int32_t)ioff;
-        for (int64_t e = 0; e < cnt[k]; e += L, ++ioff) {
-            BinItem it;
-            it.start = off + e;
-            it.len = (int32_t)(cnt[k] - e < L ? cnt[k] - e : L);
-            it.tile = lo + k;
-            B.items[ioff] = it;
-        }
+        s_item[lo + k] = (int32_t)ioff;
+        ioff += (cnt[k] + L - 1) / L;
         off += cnt[k];
+    }
+    __syncthreads();
+    // the work items, all threads at once: item i belongs to the tile k with
+    // s_item[k] <= i < s_item[k + 1] (tiles without items never satisfy it)
+    for (int i = t; i < (int)NI; i += 1024) {
+        int a = 0, b = T;
+        while (b - a > 1) {
+            const int m = (a + b) >> 1;
+            if (s_item[m] <= i) a = m;
+            else b = m;
+        }
+        const int64_t e = (int64_t)(i - s_item[a]) * L;
+        const int64_t n = B.tile_start[a + 1] - B.tile_start[a];
+        BinItem it;
+        it.start = B.tile_start[a] + e;
+        it.len = (int32_t)(n - e < L ? n - e : L);
+        it.tile = a;
+        B.items[i] = it;
     }
 }
 
