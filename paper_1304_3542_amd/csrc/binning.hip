@@ -377,8 +377,18 @@ __global__ void k_splat_reduce_binned(SplatArgs A, BinArgs B, double *__restrict
         const int tt = s * B.ntiles + (i2 / SP_T) * A.ntile1 + i1 / SP_T;
         const int local = (i2 % SP_T) * SP_T + (i1 % SP_T);
         const int a = B.tile_item[tt], e = B.tile_item[tt + 1];
+        const double *p = A.partial + local;
         double v = 0.0;
-        for (int it = a; it < e; ++it) v += A.partial[(size_t)it * SP_T * SP_T + local];
+        int it = a;
+        // eight loads in flight, added in item order as one at a time would
+        for (; it + 8 <= e; it += 8) {
+            double w[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) w[q] = p[(size_t)(it + q) * SP_T * SP_T];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v += w[q];
+        }
+        for (; it < e; ++it) v += p[(size_t)it * SP_T * SP_T];
         u[i] = v;
     }
 }
