@@ -27,8 +27,15 @@
  *   - All pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
  *     tensors) owned by the caller.  The library owns the context and its
  *     workspaces only.
- *   - All work is enqueued on the context's stream and is asynchronous; no
- *     entry point synchronises except fga_sync_status and fga_copy_offsets.
+ *   - All work is enqueued on the context's stream and is asynchronous.
+ *     The calls that wait for the stream are: fga_sync_status,
+ *     fga_copy_offsets, fga_autotune and fga_graph_capture (always); the
+ *     gradient calls with logged dJ/dc (grad_log >= 0 or deterministic = 1,
+ *     once per call, to size the reduction); and any call that must grow a
+ *     workspace the context owns (it waits before freeing the smaller
+ *     buffer, which happens on the first call of a new size or mode, so a
+ *     repeated call of the same shape does not wait).  Growing a workspace
+ *     makes a captured graph stale (see fga_graph_launch).
  *   - Grid arrays are C-ordered [n2][n1] float64 on nodes x_i = o + i*d
  *     (axis 1 horizontal and fastest, axis 2 depth).
  *   - Errors in arguments return immediately with FGA_EINVAL and leave the
@@ -63,7 +70,9 @@ typedef enum {
                        FP64 ray/amplitude integration                        */
 } fga_precision;
 
-/* Node-centred grid: x1 = o1 + i1*d1 (i1 < n1), x2 = o2 + i2*d2 (i2 < n2). */
+/* Node-centred grid: x1 = o1 + i1*d1 (i1 < n1), x2 = o2 + i2*d2 (i2 < n2),
+ * 4 <= n1, n2 <= FGA_MAX_N (truncation boxes keep node indices in 16 bits). */
+#define FGA_MAX_N 32767
 typedef struct {
     int32_t n1, n2;
     double o1, o2, d1, d2;
@@ -295,7 +304,12 @@ fga_status fga_decompose_adjoint(fga_ctx *ctx, const fga_beams *beams, int32_t n
  * graph on a context-owned capture stream and instantiates it; the stream
  * must not be capturing already.  fga_graph_launch replays it on the
  * context's stream with the pointers given at capture (update the inputs in
- * place between replays).  A later capture replaces the graph.             */
+ * place between replays).  A later capture replaces the graph.  A call on
+ * this context that reallocates one of its workspaces after the capture (a
+ * larger beam capacity or shot count, fga_autotune trying a larger split,
+ * the gradient calls' buffers) frees memory the graph addresses: from then
+ * on fga_graph_launch returns FGA_ESTATE without launching, until the next
+ * fga_graph_capture.                                                       */
 fga_status fga_graph_capture(fga_ctx *ctx, int32_t nshots, const double *f0_dev,
                              const double *f1_dev, fga_beams *beams, int32_t nsteps,
                              double *u_dev);

@@ -52,6 +52,8 @@ def lib():
         I32, I64, D = ctypes.c_int, ctypes.c_int64, ctypes.c_double
         G = [P, I32, I32, D, D, D, D]
         L.or_velocity.argtypes = G + [D, D, P]
+        L.or_fbi_bound.argtypes = [P, I32, I32, D, D, D, D, I32, I32, I32, I32, I32,
+                                   I32, P]
         L.or_velocity_points.argtypes = G + [I64, P, P, P]
         L.or_fbi.argtypes = [P, I32, I32, D, D, D, D, I32, I32, I32, I32, I32,
                              I32, I32, I32, D, D, P]
@@ -117,6 +119,18 @@ def fbi(f: np.ndarray, grid, params) -> np.ndarray:
     return out[..., 0] + 1j * out[..., 1]
 
 
+def fbi_bound(f: np.ndarray, grid, params) -> np.ndarray:
+    """d1 d2 sum_m |f(k+m)| exp(-|m d|^2/(2 eps)) over the FBI box of every q
+    node, [nq2][nq1]: no |psi(q, p)| exceeds it, whatever p (the Fourier
+    factor of the psi eq. has modulus 1)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    pr = params
+    out = np.empty((pr.nq2, pr.nq1))
+    lib().or_fbi_bound(_p(f), grid.n1, grid.n2, grid.d1, grid.d2, pr.eps, pr.tau_fbi,
+                       pr.qb1, pr.qb2, pr.qs1, pr.qs2, pr.nq1, pr.nq2, _p(out))
+    return out
+
+
 @dataclasses.dataclass
 class Beams:
     """Thresholded beams in the order (shot, branch + then -, q flat, p flat)."""
@@ -167,14 +181,60 @@ def select_top_n(mags: np.ndarray, n: int) -> np.ndarray:
     return np.sort(sel[mags[sel] > 0])
 
 
+def _branch_bound(f0s, f1s, c, grid, pr) -> np.ndarray:
+    """A bound of |psi_+-(q, p)| over every p, per q node (flat): from
+    |psi_+-| <= (|psi0| + eps/(c(q)|p|) |psi1|)/2 with the fbi_bound of each
+    and |p| at least the smallest |p| of the staggered mesh."""
+    b = 0.5 * fbi_bound(f0s, grid, pr).ravel()
+    if f1s is not None:
+        k1, k2 = qnodes(pr)
+        Q1, Q2 = np.meshgrid(grid.o1 + grid.d1 * k1, grid.o2 + grid.d2 * k2)
+        cq = velocity(c, grid, Q1.ravel(), Q2.ravel())[:, 0]
+        pmin = math.hypot(0.5 * pr.dp1, 0.5 * pr.dp2)
+        b = b + 0.5 * pr.eps / (cq * pmin) * fbi_bound(f1s, grid, pr).ravel()
+    return b
+
+
+def _skipped_q_candidates(f0s, f1s, c, grid, pr):
+    """psi_+- at the q nodes that can hold a kept beam, for the relative
+    threshold: q nodes are visited in decreasing order of their bound
+    (_branch_bound) while the bound reaches tau times the largest |psi_+-|
+    found so far.  Every q node left out has |psi_+-| below tau M at every p
+    (its bound is, and M is at least the running maximum), so it keeps no
+    beam, and M itself is attained at a visited node.  Returns the visited q
+    nodes in increasing flat order and their psi_+ and psi_- [nvisited][np]."""
+    bnd = _branch_bound(f0s, f1s, c, grid, pr)
+    order = np.argsort(-bnd, kind="stable")
+    found = {}
+    run = 0.0
+    slack = 1.0 + 1e-9          # rounding of the bound and of |psi|
+    for q in order:
+        if bnd[q] * slack < pr.tau * run:
+            break
+        j2, j1 = divmod(int(q), pr.nq1)
+        one = dataclasses.replace(pr, qb1=pr.qb1 + pr.qs1 * j1, qb2=pr.qb2 + pr.qs2 * j2,
+                                  nq1=1, nq2=1)
+        psi0 = fbi(f0s, grid, one)
+        psi1 = None if f1s is None else fbi(f1s, grid, one)
+        pp, pm = branches(psi0, psi1, c, grid, one)
+        found[int(q)] = (pp.ravel(), pm.ravel())
+        run = max(run, float(np.abs(pp).max()), float(np.abs(pm).max()))
+    qs = np.array(sorted(found), dtype=np.int64)
+    pp = np.stack([found[q][0] for q in qs])
+    pm = np.stack([found[q][1] for q in qs])
+    return qs, pp, pm
+
+
 def decompose(f0: np.ndarray, f1: Optional[np.ndarray], c, grid, params,
-              psi_cache=None) -> Beams:
+              psi_cache=None, q_skip: bool = False) -> Beams:
     """Step 1 for every shot: FBI, branch split, selection, initial state.
 
     With params.top_n == 0, thresholding keeps (sigma, q, p) with
     |psi_sigma| >= tau * M, M the largest |psi| over both branches of the
     shot, and |psi| > 0; with top_n > 0 each branch keeps its top_n largest
-    |psi_sigma| (select_top_n).
+    |psi_sigma| (select_top_n).  q_skip (threshold only) evaluates the FBI
+    only at q nodes whose bound can reach tau M (_skipped_q_candidates):
+    the same beams, for sources much smaller than the q-mesh.
     """
     pr = params
     k1, k2 = qnodes(pr)
@@ -184,15 +244,22 @@ def decompose(f0: np.ndarray, f1: Optional[np.ndarray], c, grid, params,
     npp = pr.np1 * pr.np2
     w = (pr.qs1 * grid.d1) * (pr.qs2 * grid.d2) * pr.dp1 * pr.dp2
     norm = w / (2 * math.pi * pr.eps) ** 3          # (2 pi eps)^{-3d/2}, d = 2
+    if q_skip and pr.top_n > 0:
+        raise ValueError("q_skip applies to the relative threshold only")
     parts = []
     offsets = [0]
     for s in range(f0.shape[0]):
-        if psi_cache is not None and s in psi_cache:
+        qlist = None
+        if q_skip:
+            qlist, pp, pm = _skipped_q_candidates(f0[s], None if f1 is None else f1[s],
+                                                  c, grid, pr)
+        elif psi_cache is not None and s in psi_cache:
             psi0, psi1 = psi_cache[s]
+            pp, pm = branches(psi0, psi1, c, grid, pr)
         else:
             psi0 = fbi(f0[s], grid, pr)
             psi1 = None if f1 is None else fbi(f1[s], grid, pr)
-        pp, pm = branches(psi0, psi1, c, grid, pr)
+            pp, pm = branches(psi0, psi1, c, grid, pr)
         mags = np.stack([np.abs(pp).ravel(), np.abs(pm).ravel()])   # [2][nq*np]
         if pr.top_n > 0:
             keep = np.zeros(mags.shape, bool)
@@ -204,6 +271,10 @@ def decompose(f0: np.ndarray, f1: Optional[np.ndarray], c, grid, params,
         vals = np.stack([pp.ravel(), pm.ravel()])
         sidx, flat = np.nonzero(keep)           # row-major: branch +, then -
         qf, pf = flat // npp, flat % npp
+        if qlist is not None:
+            # visited q nodes (increasing) -> mesh flat index: the order stays
+            # (branch, q flat, p flat)
+            qf = qlist[qf]
         j2, j1 = qf // pr.nq1, qf % pr.nq1
         l2, l1 = pf // pr.np1, pf % pr.np1
         nb = flat.size
@@ -340,6 +411,60 @@ def trace(beams: Beams, c, grid, params, receivers, rec_every: int,
         for s in range(ns):
             out[s, k] = reconstruct_points(beams, grid, params, receivers, shot=s)
     return out
+
+
+def frozen_beams(f0, f1, c, grid, params, cand, psi_cache=None) -> Beams:
+    """The initial beams of a given candidate set (the threshold set held
+    fixed): coefficients from the FBI of f0 (and f1) at their (q, p) nodes,
+    the t = 0 state of step 1.  psi_cache {shot: (psi0, psi1)} may hold FBI
+    values already computed for these f0, f1."""
+    pr = params
+    ns = f0.shape[0]
+    nq, npp = pr.nq1 * pr.nq2, pr.np1 * pr.np2
+    k1, k2 = qnodes(pr)
+    pm1, pm2 = pmesh(pr.np1, pr.dp1), pmesh(pr.np2, pr.dp2)
+    w = (pr.qs1 * grid.d1) * (pr.qs2 * grid.d2) * pr.dp1 * pr.dp2
+    norm = w / (2 * math.pi * pr.eps) ** 3
+    coef, states, sig, shot, psis, offs = [], [], [], [], [], [0]
+    for s in range(ns):
+        if psi_cache is not None and s in psi_cache:
+            psi0, psi1 = psi_cache[s]
+        else:
+            psi0 = fbi(f0[s], grid, pr)
+            psi1 = None if f1 is None else fbi(f1[s], grid, pr)
+        pp, pm = branches(psi0, psi1, c, grid, pr)
+        vals = np.stack([pp.ravel(), pm.ravel()])
+        mine = cand[(cand // (2 * nq * npp)) == s] - s * 2 * nq * npp
+        sb, flat = mine // (nq * npp), mine % (nq * npp)
+        psi = vals[sb, flat]
+        qf, pf = flat // npp, flat % npp
+        st = np.zeros((mine.size, NSTATE))
+        st[:, 0] = grid.o1 + grid.d1 * k1[qf % pr.nq1]
+        st[:, 1] = grid.o2 + grid.d2 * k2[qf // pr.nq1]
+        st[:, 2] = pm1[pf % pr.np1]
+        st[:, 3] = pm2[pf // pr.np1]
+        st[:, 5] = st[:, 11] = 1.0
+        st[:, 14] = st[:, 20] = -1.0
+        st[:, 21] = 2.0
+        coef.append(np.stack([psi.real, psi.imag], 1) * norm)
+        states.append(st)
+        sig.append(np.where(sb == 0, 1, -1).astype(np.int8))
+        shot.append(np.full(mine.size, s, np.int32))
+        psis.append(psi)
+        offs.append(offs[-1] + mine.size)
+    return Beams(np.concatenate(shot), np.concatenate(sig), np.asarray(cand, np.int64).copy(),
+                 np.concatenate(psis), np.ascontiguousarray(np.concatenate(coef)),
+                 np.ascontiguousarray(np.concatenate(states)), np.array(offs, np.int64))
+
+
+def trace_frozen(c, f0, f1, grid, params, cand, receivers, rec_every, nrec,
+                 c_for_branches=None, psi_cache=None) -> np.ndarray:
+    """Receiver traces (trace) of the beams `cand` with the threshold set held
+    fixed, for velocity c and initial data f0, f1 (c_for_branches, if given,
+    is the velocity whose c(q) enters u_{+-,0})."""
+    cb = c if c_for_branches is None else c_for_branches
+    b = frozen_beams(f0, f1, cb, grid, params, cand, psi_cache)
+    return trace(b, c, grid, params, receivers, rec_every, nrec)
 
 
 def forward(f0, f1, c, grid, params, imag=False):

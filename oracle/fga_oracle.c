@@ -131,11 +131,27 @@ static double pmesh(int l, int np, double dp)
     return (l - 0.5 * (np - 1)) * dp;
 }
 
+/* First and last column of every row where f is nonzero (lo > hi for a row
+ * of zeros).  A term with f = 0 adds exactly zero to the sums below, so the
+ * loops may pass over those columns without changing any result. */
+static void row_support(const double *f, int n1, int n2, int *lo, int *hi)
+{
+    for (int y2 = 0; y2 < n2; ++y2) {
+        const double *row = f + (size_t)y2 * n1;
+        int a = 0, b = n1 - 1;
+        while (a < n1 && row[a] == 0.0) ++a;
+        while (b >= a && row[b] == 0.0) --b;
+        lo[y2] = a;
+        hi[y2] = b;
+    }
+}
+
 /* psi_j(q,p) = d1 d2 sum_m f(k+m) exp(-|m d|^2/(2 eps)) exp(-i p.(m d)/eps)
  * for every q node k = (qb1 + j1 qs1, qb2 + j2 qs2) and p-mesh node.
  * Output: psi[(((j2*nq1 + j1)*np2 + l2)*np1 + l1)*2 + {0: re, 1: im}].
  * The one-dimensional factors of the kernel are tabulated once; each
- * (q, p) pair is then a direct double sum over the box. */
+ * (q, p) pair is then a direct double sum over the box (terms where f
+ * vanishes are passed over: they add exactly zero). */
 void or_fbi(const double *f, int n1, int n2, double d1, double d2, double eps,
             double tau_fbi, int qb1, int qb2, int qs1, int qs2, int nq1,
             int nq2, int np1, int np2, double dp1, double dp2, double *psi)
@@ -157,6 +173,8 @@ void or_fbi(const double *f, int n1, int n2, double d1, double d2, double eps,
             E2[(size_t)l * W2 + m + R2] =
                 exp(-r * r / (2.0 * eps)) * cexp(-I * pmesh(l, np2, dp2) * r / eps);
         }
+    int *lo = malloc(sizeof(int) * (size_t)n2), *hi = malloc(sizeof(int) * (size_t)n2);
+    row_support(f, n1, n2, lo, hi);
     int64_t nq = (int64_t)nq1 * nq2, np = (int64_t)np1 * np2;
 #pragma omp parallel for collapse(2) schedule(dynamic, 4)
     for (int64_t jq = 0; jq < nq; ++jq) {
@@ -169,12 +187,14 @@ void or_fbi(const double *f, int n1, int n2, double d1, double d2, double eps,
             double complex acc = 0.0;
             for (int m2 = -R2; m2 <= R2; ++m2) {
                 int y2 = k2 + m2;
-                if (y2 < 0 || y2 >= n2) continue;
+                if (y2 < 0 || y2 >= n2 || lo[y2] > hi[y2]) continue;
                 const double *row = f + (size_t)y2 * n1;
+                int m1a = lo[y2] - k1 > -R1 ? lo[y2] - k1 : -R1;
+                int m1b = hi[y2] - k1 < R1 ? hi[y2] - k1 : R1;
+                if (m1a > m1b) continue;
                 double sr = 0.0, si = 0.0;
-                for (int m1 = -R1; m1 <= R1; ++m1) {
+                for (int m1 = m1a; m1 <= m1b; ++m1) {
                     int y1 = k1 + m1;
-                    if (y1 < 0 || y1 >= n1) continue;
                     sr += row[y1] * creal(e1[m1 + R1]);
                     si += row[y1] * cimag(e1[m1 + R1]);
                 }
@@ -187,6 +207,49 @@ void or_fbi(const double *f, int n1, int n2, double d1, double d2, double eps,
     }
     free(E1);
     free(E2);
+    free(lo);
+    free(hi);
+}
+
+/* A bound of |psi_j(q,p)| that holds for every p at each q node:
+ * bound(q) = d1 d2 sum_m |f(k+m)| exp(-|m d|^2/(2 eps)) over the same box
+ * (the modulus of a sum is at most the sum of the moduli, and the Fourier
+ * factor has modulus 1).  Output bound[j2*nq1 + j1]. */
+void or_fbi_bound(const double *f, int n1, int n2, double d1, double d2, double eps,
+                  double tau_fbi, int qb1, int qb2, int qs1, int qs2, int nq1, int nq2,
+                  double *bound)
+{
+    int R1 = window_halfwidth(eps, tau_fbi, d1);
+    int R2 = window_halfwidth(eps, tau_fbi, d2);
+    double *w1 = malloc(sizeof(double) * (size_t)(2 * R1 + 1));
+    double *w2 = malloc(sizeof(double) * (size_t)(2 * R2 + 1));
+    for (int m = -R1; m <= R1; ++m) w1[m + R1] = exp(-(m * d1) * (m * d1) / (2.0 * eps));
+    for (int m = -R2; m <= R2; ++m) w2[m + R2] = exp(-(m * d2) * (m * d2) / (2.0 * eps));
+    int *lo = malloc(sizeof(int) * (size_t)n2), *hi = malloc(sizeof(int) * (size_t)n2);
+    row_support(f, n1, n2, lo, hi);
+    int64_t nq = (int64_t)nq1 * nq2;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t jq = 0; jq < nq; ++jq) {
+        int k1 = qb1 + (int)(jq % nq1) * qs1, k2 = qb2 + (int)(jq / nq1) * qs2;
+        double acc = 0.0;
+        for (int m2 = -R2; m2 <= R2; ++m2) {
+            int y2 = k2 + m2;
+            if (y2 < 0 || y2 >= n2 || lo[y2] > hi[y2]) continue;
+            const double *row = f + (size_t)y2 * n1;
+            double s = 0.0;
+            for (int m1 = -R1; m1 <= R1; ++m1) {
+                int y1 = k1 + m1;
+                if (y1 < 0 || y1 >= n1) continue;
+                s += fabs(row[y1]) * w1[m1 + R1];
+            }
+            acc += w2[m2 + R2] * s;
+        }
+        bound[jq] = d1 * d2 * acc;
+    }
+    free(w1);
+    free(w2);
+    free(lo);
+    free(hi);
 }
 
 /* ------------------------------------------------------------------ */

@@ -38,6 +38,8 @@ fga_status fga_ensure(fga_ctx *ctx, void **buf, size_t *have, size_t need, const
         (void)hipFree(*buf);
         *buf = nullptr;
         *have = 0;
+        // a captured graph holds the freed address: refuse to replay it
+        if (ctx->graph_exec) ctx->graph_stale = true;
     }
     hipError_t e = hipMalloc(buf, need);
     if (e != hipSuccess) {
@@ -51,8 +53,11 @@ fga_status fga_ensure(fga_ctx *ctx, void **buf, size_t *have, size_t need, const
 
 static fga_status check_params(fga_ctx *ctx, const fga_grid *g, const fga_params *p)
 {
-    if (g->n1 < 4 || g->n2 < 4 || g->n1 > (1 << 15) || g->n2 > (1 << 15))
-        return fga_fail(ctx, FGA_EINVAL, "grid size %d x %d outside [4, 32768]", g->n1, g->n2);
+    // node indices of truncation boxes are stored as 16-bit integers, with
+    // n itself marking an empty box
+    if (g->n1 < 4 || g->n2 < 4 || g->n1 > FGA_MAX_N || g->n2 > FGA_MAX_N)
+        return fga_fail(ctx, FGA_EINVAL, "grid size %d x %d outside [4, %d]", g->n1, g->n2,
+                        FGA_MAX_N);
     if (!(g->d1 > 0) || !(g->d2 > 0) || !isfinite(g->o1) || !isfinite(g->o2))
         return fga_fail(ctx, FGA_EINVAL, "grid spacing must be positive and origin finite");
     if (!(p->eps > 0) || !isfinite(p->eps))
@@ -451,6 +456,7 @@ extern "C" fga_status fga_graph_capture(fga_ctx *ctx, int32_t nshots, const doub
             ctx->graph = g;
             hipError_t e3 = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
             if (e3 != hipSuccess) st = fga_hip_check(ctx, e3, "hipGraphInstantiate");
+            else ctx->graph_stale = false;
         } else if (g) {
             (void)hipGraphDestroy(g);
         }
@@ -466,6 +472,10 @@ extern "C" fga_status fga_graph_launch(fga_ctx *ctx)
 {
     if (!ctx) return FGA_EINVAL;
     if (!ctx->graph_exec) return fga_fail(ctx, FGA_ESTATE, "no captured graph");
+    if (ctx->graph_stale)
+        return fga_fail(ctx, FGA_ESTATE,
+                        "a workspace of the captured graph was reallocated by a later call; "
+                        "capture again");
     FGA_HIP(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
     return FGA_OK;
 }

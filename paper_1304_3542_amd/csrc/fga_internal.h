@@ -78,6 +78,7 @@ struct fga_ctx {
     hipStream_t cap_stream;
     hipGraph_t graph;
     hipGraphExec_t graph_exec;
+    bool graph_stale;      // a workspace the graph uses was freed since capture
 
     char err[512];
 };

@@ -79,6 +79,24 @@ def test_create_rejects_bad_grid_precision_and_shots():
     assert lib.fga_create(None, None, None, 0, 1, None) == fga.FGA_EINVAL
 
 
+def test_grid_size_limit():
+    """Truncation boxes keep node indices in 16 bits (n marks an empty box),
+    so n1, n2 <= FGA_MAX_N = 32767: 32768 is refused on the host, 32767
+    passes the argument checks (and ends at the device query without a GPU)."""
+    import paper_1304_3542_amd as fga
+    W = fi.workload("wavepacket")
+    lib = fga.load()
+    assert "#define FGA_MAX_N 32767" in open(os.path.join(ROOT, "include", "fga.h")).read()
+    for n1, n2, bad in ((32768, 128, True), (128, 32768, True), (32767, 128, False),
+                        (128, 32767, False)):
+        g, p = _structs(fi.Grid(n1, n2, 0.0, 0.0, 1 / 128, 1 / 128), W.params)
+        ctx = ctypes.c_void_p()
+        st = lib.fga_create(ctypes.byref(ctx), ctypes.byref(g), ctypes.byref(p), 1, 1, None)
+        assert (st == fga.FGA_EINVAL) == bad, (n1, n2, st)
+        if st == fga.FGA_OK:
+            lib.fga_destroy(ctx)
+
+
 def test_null_context_calls_fail_cleanly():
     import paper_1304_3542_amd as fga
     lib = fga.load()

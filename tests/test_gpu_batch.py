@@ -96,6 +96,46 @@ def test_graph_replay_is_bitwise_and_picks_up_inputs(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_refused_after_workspace_growth(precision):
+    """A call that reallocates a workspace after the capture (here the
+    reconstruction of a beam buffer of twice the capacity, whose per-beam
+    splat records no longer fit) frees memory the graph addresses:
+    fga_graph_launch then returns FGA_ESTATE and launches nothing, and a new
+    capture replays as before."""
+    import torch
+    import paper_1304_3542_amd as fga
+    g, p, c, f0 = shots_case(ns=2, seed=55)
+    if precision == "mixed":
+        p = p.replace(tau_fbi=1e-8, tau_win=1e-8)
+    ns = f0.shape[0]
+    ctx, beams, f0t, u, stream = run(g, p, c, f0, precision)
+    eager = u.clone()
+    with torch.cuda.stream(stream):
+        ctx.graph_capture(f0t, None, beams, p.nsteps, u)
+        ctx.graph_launch()
+        stream.synchronize()
+        np.testing.assert_array_equal(u.cpu().numpy(), eager.cpu().numpy())
+        big = fga.Beams(2 * beams.capacity, ns)
+        big.f[:, : beams.capacity].copy_(beams.f)
+        big.id[: beams.capacity].copy_(beams.id)
+        big.offsets.copy_(beams.offsets)
+        u_big = ctx.reconstruct(big, ns)
+        u.fill_(7.0)
+        with pytest.raises(fga.FGAError) as err:
+            ctx.graph_launch()
+        assert err.value.status == fga.FGA_ESTATE
+        stream.synchronize()
+        assert bool((u == 7.0).all())
+        np.testing.assert_array_equal(u_big.cpu().numpy(), eager.cpu().numpy())
+        ctx.graph_capture(f0t, None, beams, p.nsteps, u)
+        u.fill_(0.0)
+        ctx.graph_launch()
+        stream.synchronize()
+    np.testing.assert_array_equal(u.cpu().numpy(), eager.cpu().numpy())
+    assert ctx.status()[0] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_autotune_choice_and_cache(precision, tmp_path):
     import torch
     g, p, c, f0 = shots_case(ns=3, seed=54)

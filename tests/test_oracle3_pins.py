@@ -223,3 +223,151 @@ def test_windowed_sum_against_brute_force():
         ref += (Ca * np.exp(1j * ph + ga)).real
     bound = 1e-12 * np.abs((b.coef[:, 0] + 1j * b.coef[:, 1]) * (b.state[:, 43] + 1j * b.state[:, 44])).sum()
     assert np.abs(u - ref).max() <= bound + 1e-13 * np.abs(ref).max()
+
+
+# --------------------------------------------- decomposition with f1, frame
+
+def _small_case(seed=12):
+    g = i3.Grid3(9, 8, 7, 0.0, 0.1, -0.05, 1 / 9, 1 / 8, 1 / 7)
+    r = np.random.default_rng(seed)
+    x1, x2, x3 = g.coords()
+    env = np.exp(-((x1[None, None, :] - 0.45) ** 2 + (x2[None, :, None] - 0.55) ** 2
+                   + (x3[:, None, None] - 0.4) ** 2) / (2 * 0.15 ** 2))
+    f0 = env * r.standard_normal(g.shape)
+    f1 = 0.8 * env * r.standard_normal(g.shape)
+    c = 1.0 + 0.6 * r.uniform(size=g.shape)
+    p = i3.Params3(1 / 60, (1, 0, 1), (3, 2, 2), (3, 4, 3), (4, 6, 4), (0.3, 0.25, 0.35),
+                   0.05, 1e-16, 1e-16, 1e-3, 0)
+    return g, p, c, f0, f1
+
+
+def _brute_psi3(f, g, p):
+    """psi [Nq][Np] (axis 1 fastest) by the unwindowed sum over every node."""
+    x = g.coords()
+    qn = [g.o[a] + g.d[a] * (p.qb[a] + p.qs[a] * np.arange(p.nq[a])) for a in range(3)]
+    pm = [o3.pmesh(p.np[a], p.dp[a]) for a in range(3)]
+    out = np.zeros((p.nq[2], p.nq[1], p.nq[0], p.np[2], p.np[1], p.np[0]), complex)
+    for j3, q3 in enumerate(qn[2]):
+        for j2, q2 in enumerate(qn[1]):
+            for j1, q1 in enumerate(qn[0]):
+                r = [x[0] - q1, x[1] - q2, x[2] - q3]
+                gw = f * np.exp(-(r[0][None, None, :] ** 2 + r[1][None, :, None] ** 2
+                                  + r[2][:, None, None] ** 2) / (2 * p.eps))
+                e = [np.exp(-1j * pm[a][:, None] * r[a][None, :] / p.eps) for a in range(3)]
+                # sum_{x3,x2,x1} gw[x3,x2,x1] e3[l3,x3] e2[l2,x2] e1[l1,x1]
+                t = np.tensordot(gw, e[0], axes=([2], [1]))        # [x3][x2][l1]
+                t = np.tensordot(t, e[1], axes=([1], [1]))         # [x3][l1][l2]
+                t = np.tensordot(t, e[2], axes=([0], [1]))         # [l1][l2][l3]
+                out[j3, j2, j1] = np.prod(g.d) * t.transpose(2, 1, 0)
+    return out.reshape(int(np.prod(p.nq)), int(np.prod(p.np)))
+
+
+def test_threshold_set_brute_force_with_f1():
+    """The kept (branch, q, p), their order and psi_+- = (psi0 +- i eps/(c(q)|p|)
+    psi1)/2 (u_{+-,0} with c(q) the interpolant at the q node) against psi0,
+    psi1 from the unwindowed sum over every node and the rule written out per
+    candidate; a wrong q or p index in the f1 term, a sign or a missing
+    factor changes the kept set or the values."""
+    g, p, c, f0, f1 = _small_case()
+    b = o3.decompose(f0[None], f1[None], c, g, p)
+    psi0 = _brute_psi3(f0, g, p)
+    psi1 = _brute_psi3(f1, g, p)
+    NQ, NP = psi0.shape
+    qn = [g.o[a] + g.d[a] * (p.qb[a] + p.qs[a] * np.arange(p.nq[a])) for a in range(3)]
+    pm = [o3.pmesh(p.np[a], p.dp[a]) for a in range(3)]
+    vals, ids = [], []
+    for br, sg in ((0, 1.0), (1, -1.0)):
+        for qf in range(NQ):
+            j1, j2, j3 = qf % p.nq[0], (qf // p.nq[0]) % p.nq[1], qf // (p.nq[0] * p.nq[1])
+            cq = o3.velocity(c, g, np.array([[qn[0][j1], qn[1][j2], qn[2][j3]]]))[0, 0]
+            for pf in range(NP):
+                l1, l2, l3 = pf % p.np[0], (pf // p.np[0]) % p.np[1], pf // (p.np[0] * p.np[1])
+                pa = math.sqrt(pm[0][l1] ** 2 + pm[1][l2] ** 2 + pm[2][l3] ** 2)
+                vals.append(0.5 * (psi0[qf, pf] + sg * 1j * p.eps / (cq * pa) * psi1[qf, pf]))
+                ids.append((br * NQ + qf) * NP + pf)
+    vals = np.array(vals)
+    M = np.abs(vals).max()
+    keep = np.abs(vals) >= p.tau * M
+    assert 50 < keep.sum() < 0.7 * keep.size
+    np.testing.assert_array_equal(b.cand, np.array(ids)[keep])
+    np.testing.assert_allclose(b.psi, vals[keep], rtol=0, atol=1e-12 * M)
+    np.testing.assert_array_equal(b.sigma, np.where(np.array(ids)[keep] < NQ * NP, 1, -1))
+
+
+def test_branch_symmetry_with_f1():
+    """For real f0, f1 the FBI satisfies psi_j(q, -p) = conj psi_j(q, p), so
+    psi_+(q, -p) = conj psi_-(q, p) for every q, p (with f1 != 0: the sign of
+    the i eps/(c(q)|p|) f1 term differs between the branches)."""
+    g, p, c, f0, f1 = _small_case(seed=13)
+    p = p.replace(tau=0.0)
+    f1 = 30.0 * f1          # eps/(c|p|) ~ 0.03: make the f1 term comparable
+    b = o3.decompose(f0[None], f1[None], c, g, p)
+    NQ, NP = int(np.prod(p.nq)), int(np.prod(p.np))
+    assert b.n == 2 * NQ * NP
+    psi = b.psi.reshape(2, NQ, p.np[2], p.np[1], p.np[0])
+    plus, minus = psi[0], psi[1]
+    # -p_l = p_{n-1-l} on the staggered symmetric mesh, per axis
+    flipped = plus[:, ::-1, ::-1, ::-1]
+    np.testing.assert_allclose(flipped, np.conj(minus), rtol=0,
+                               atol=1e-13 * np.abs(psi).max())
+    assert np.abs(plus - minus).max() > 0.1 * np.abs(psi).max()      # f1 matters
+
+
+def test_one_way_data_selects_one_branch():
+    """For a packet moving in +x1 in c = 1 (f1 = -i |xi| sgn(xi1) f0 in
+    Fourier), psi_- vanishes where psi_+ carries the packet (p1 > 0) and the
+    converse for p1 < 0: a sign or scale error in i eps/(c(q)|p|) f1 breaks
+    the split."""
+    n = 32
+    g = i3.Grid3(n, n, n, 0, 0, 0, 1 / n, 1 / n, 1 / n)
+    eps = 1 / 48
+    x1, x2, x3 = g.coords()
+    r2 = ((x1[None, None, :] - 0.5) ** 2 + (x2[None, :, None] - 0.5) ** 2
+          + (x3[:, None, None] - 0.5) ** 2)
+    f0 = np.exp(-r2 / (2 * 0.12 ** 2)) * np.cos(0.9 * x1[None, None, :] / eps)
+    xi = [2 * np.pi * np.fft.fftfreq(n, d=1 / n) for _ in range(3)]
+    K1 = xi[0][None, None, :]
+    mag = np.sqrt(K1 ** 2 + xi[1][None, :, None] ** 2 + xi[2][:, None, None] ** 2)
+    f1 = np.real(np.fft.ifftn(-1j * mag * np.sign(K1) * np.fft.fftn(f0)))
+    p = i3.Params3(eps, (12, 12, 12), (4, 4, 4), (3, 3, 3), (8, 4, 4), (0.25, 0.25, 0.25),
+                   0.0, 1e-16, 1e-16, 1e-3, 0)
+    b = o3.decompose(f0[None], f1[None], np.ones(g.shape), g, p)
+    NQ, NP = int(np.prod(p.nq)), int(np.prod(p.np))
+    psi = b.psi.reshape(2, NQ, p.np[2], p.np[1], p.np[0])
+    pos = o3.pmesh(p.np[0], p.dp[0]) > 0
+    big = np.abs(psi).max()
+    assert np.abs(psi[0][..., pos]).max() > 0.4 * big
+    assert np.abs(psi[0][..., ~pos]).max() < 0.05 * big
+    assert np.abs(psi[1][..., ~pos]).max() > 0.4 * big
+    assert np.abs(psi[1][..., pos]).max() < 0.05 * big
+
+
+def test_frame_identity_exact_on_dft_bins():
+    """At t = 0 with the p-mesh on the DFT bins of at least n points per axis
+    (dp_a = 2 pi eps/(Np_a d_a), Np_a >= n_a) the sum over p is exact
+    orthogonality (no aliasing), so step 3 after step 1 returns
+    u(x) = f0(x) S(x), S(x) = prod_a sum_{q_a} (dq_a/sqrt(pi eps))
+    exp(-(x_a - q_a)^2/eps) over the q-mesh, for any f0 (here noise on the
+    whole grid, strides (2, 1, 2), unequal spacings).  This fixes the phase
+    space weight, (2 pi eps)^{3d/2}, a(0) = 2^{d/2} and the sum of the two
+    branches exactly; S differs from 1 by the Poisson ripple of the q-mesh."""
+    g = i3.Grid3(10, 9, 8, 0.0, 0.0, 0.0, 1 / 10, 1 / 9, 1 / 8)
+    eps = 3 * g.d1 ** 2
+    qs = (2, 1, 2)
+    nq = tuple((g.n[a] + qs[a] - 1) // qs[a] for a in range(3))
+    Np = (10, 10, 8)
+    dp = tuple(2 * math.pi * eps / (Np[a] * g.d[a]) for a in range(3))
+    p = i3.Params3(eps, (0, 0, 0), qs, nq, Np, dp, 0.0, 1e-16, 1e-16, 1e-3, 0)
+    f0 = np.random.default_rng(21).standard_normal(g.shape)
+    b = o3.decompose(f0[None], None, np.ones(g.shape), g, p)
+    u = o3.reconstruct(b, g, p)
+    x = g.coords()
+    S = np.ones(g.shape)
+    for a in range(3):
+        qa = g.o[a] + g.d[a] * qs[a] * np.arange(nq[a])
+        s = (qs[a] * g.d[a] / math.sqrt(math.pi * eps)
+             * np.exp(-(x[a][:, None] - qa[None, :]) ** 2 / eps).sum(1))
+        S = S * s.reshape([-1 if k == 2 - a else 1 for k in range(3)])
+    np.testing.assert_allclose(u, f0 * S, rtol=0, atol=1e-12 * np.abs(f0).max())
+    # the identity is not trivial: the stride-2 axes ripple at the Poisson level
+    assert np.abs(S[2:-2, 2:-2, 2:-2] - 1).max() > 1e-3

@@ -31,39 +31,8 @@ def adjoint_case(with_f1=False, seed=41):
 
 def c_oracle_traces(c, f0, f1, g, p, cand, rec, rec_every, nrec, c_for_branches=None):
     """C-oracle traces of the beams `cand` (frozen set) for the given c and f0."""
-    ns = f0.shape[0]
-    cb = c if c_for_branches is None else c_for_branches
-    nq, npp = p.nq1 * p.nq2, p.np1 * p.np2
-    coef, states, sig, offs = [], [], [], [0]
-    k1, k2 = oracle.qnodes(p)
-    pm1, pm2 = oracle.pmesh(p.np1, p.dp1), oracle.pmesh(p.np2, p.dp2)
-    w = (p.qs1 * g.d1) * (p.qs2 * g.d2) * p.dp1 * p.dp2
-    norm = w / (2 * math.pi * p.eps) ** 3
-    for s in range(ns):
-        psi0 = oracle.fbi(f0[s], g, p)
-        psi1 = None if f1 is None else oracle.fbi(f1[s], g, p)
-        pp, pm = oracle.branches(psi0, psi1, cb, g, p)
-        vals = np.stack([pp.ravel(), pm.ravel()])
-        mine = cand[(cand // (2 * nq * npp)) == s] - s * 2 * nq * npp
-        sb, flat = mine // (nq * npp), mine % (nq * npp)
-        psi = vals[sb, flat]
-        qf, pf = flat // npp, flat % npp
-        st = np.zeros((mine.size, oracle.NSTATE))
-        st[:, 0] = g.o1 + g.d1 * k1[qf % p.nq1]
-        st[:, 1] = g.o2 + g.d2 * k2[qf // p.nq1]
-        st[:, 2] = pm1[pf % p.np1]
-        st[:, 3] = pm2[pf // p.np1]
-        st[:, 5] = st[:, 11] = 1.0
-        st[:, 14] = st[:, 20] = -1.0
-        st[:, 21] = 2.0
-        coef.append(np.stack([psi.real, psi.imag], 1) * norm)
-        states.append(st)
-        sig.append(np.where(sb == 0, 1, -1).astype(np.int8))
-        offs.append(offs[-1] + mine.size)
-    b = oracle.Beams(np.zeros(offs[-1], np.int32), np.concatenate(sig), cand.copy(),
-                     np.zeros(offs[-1], complex), np.ascontiguousarray(np.concatenate(coef)),
-                     np.ascontiguousarray(np.concatenate(states)), np.array(offs, np.int64))
-    return oracle.trace(b, c, g, p, rec, rec_every, nrec)
+    return oracle.trace_frozen(c, f0, f1, g, p, cand, rec, rec_every, nrec,
+                               c_for_branches=c_for_branches)
 
 
 @pytest.mark.parametrize("with_f1", [False, True])

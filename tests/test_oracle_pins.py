@@ -847,3 +847,54 @@ def test_wavepacket_against_exact_solution():
     x1, _ = g.coords()
     cen = (np.abs(u) ** 2).sum(0) @ x1 / (np.abs(u) ** 2).sum()
     assert abs(cen - 0.5) < 0.01
+
+
+def test_frame_identity_exact_on_dft_bins():
+    """At t = 0 with the p-mesh on the DFT bins of at least n points per axis
+    (dp = 2 pi eps/(Np d), Np >= n) the sum over p is exact orthogonality
+    (no aliasing), so reconstruct(decompose(f0)) = f0(x) S(x) with
+    S(x) = prod_a sum_{q_a} (dq_a/sqrt(pi eps)) exp(-(x_a - q_a)^2/eps) over
+    the q-mesh, for any f0: noise on the whole grid, strides (3, 2), unequal
+    spacings.  The Poisson bounds above are the interior size of S - 1."""
+    g = fi.Grid(21, 16, 0.1, -0.2, 1 / 21, 1 / 16)
+    eps = 3 * g.d1 ** 2
+    qs = (3, 2)
+    nq = ((g.n1 + 2) // 3, g.n2 // 2)
+    Np = (22, 16)
+    p = fi.Params(eps, 0, 0, qs[0], qs[1], nq[0], nq[1], Np[0], Np[1],
+                  2 * math.pi * eps / (Np[0] * g.d1), 2 * math.pi * eps / (Np[1] * g.d2),
+                  0.0, 1e-16, 1e-16, 1e-3, 0)
+    f0 = fi.rng(23).standard_normal(g.shape)
+    b = oracle.decompose(f0[None], None, 1.0 + 0.5 * fi.rng(24).uniform(size=g.shape), g, p)
+    u, ui = oracle.reconstruct(b, g, p, shot=0, imag=True)
+    x1, x2 = g.coords()
+    k1, k2 = oracle.qnodes(p)
+    S1 = qs[0] * g.d1 / math.sqrt(math.pi * eps) * np.exp(
+        -(x1[:, None] - (g.o1 + g.d1 * k1)[None, :]) ** 2 / eps).sum(1)
+    S2 = qs[1] * g.d2 / math.sqrt(math.pi * eps) * np.exp(
+        -(x2[:, None] - (g.o2 + g.d2 * k2)[None, :]) ** 2 / eps).sum(1)
+    np.testing.assert_allclose(u, f0 * S2[:, None] * S1[None, :], rtol=0,
+                               atol=1e-12 * np.abs(f0).max())
+    assert np.abs(ui).max() < 1e-12 * np.abs(f0).max()
+    assert np.abs(S1[3:-3] - 1).max() > 1e-3
+
+
+def test_beam_nodes_are_the_initial_centres():
+    """oracle.beam_nodes (the q node read back from a beam's candidate index,
+    used by the closed-form amplitude for c(q)) equals the initial centre Q of
+    every beam formed by step 1, over several shots and both branches, and
+    the q node of the candidate enumerated by explicit loops."""
+    g, p, c, f0, f1 = _topn_case(seed=33)
+    f0s = np.stack([f0, 0.5 * f0[::-1], f0[:, ::-1]])
+    f1s = np.stack([f1, f1, -f1])
+    b = oracle.decompose(f0s, f1s, c, g, p)
+    assert b.n > 100 and np.unique(b.shot).size == 3 and np.unique(b.sigma).size == 2
+    np.testing.assert_array_equal(oracle.beam_nodes(b, g, p), b.state[:, 0:2])
+    nq, npp = p.nq1 * p.nq2, p.np1 * p.np2
+    k1, k2 = oracle.qnodes(p)
+    for idx in fi.rng(5).choice(b.n, 40, replace=False):
+        rest = int(b.cand[idx]) % (2 * nq * npp)
+        qf = (rest % (nq * npp)) // npp
+        j2, j1 = divmod(qf, p.nq1)
+        assert tuple(oracle.beam_nodes(b.subset([idx]), g, p)[0]) == (
+            g.o1 + g.d1 * k1[j1], g.o2 + g.d2 * k2[j2])
