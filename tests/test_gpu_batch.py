@@ -97,36 +97,38 @@ def test_graph_replay_is_bitwise_and_picks_up_inputs(precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_graph_refused_after_workspace_growth(precision):
-    """A call that reallocates a workspace after the capture (here the
-    reconstruction of a beam buffer of twice the capacity, whose per-beam
-    splat records no longer fit) frees memory the graph addresses:
-    fga_graph_launch then returns FGA_ESTATE and launches nothing, and a new
-    capture replays as before."""
+    """A call that reallocates a workspace after the capture (here a
+    decomposition of three shots after a graph of two: the FBI buffers no
+    longer fit) frees memory the graph addresses: fga_graph_launch then
+    returns FGA_ESTATE and launches nothing, and a new capture replays as
+    before."""
     import torch
     import paper_1304_3542_amd as fga
-    g, p, c, f0 = shots_case(ns=2, seed=55)
+    g, p, c, f0 = shots_case(ns=3, seed=55)
     if precision == "mixed":
         p = p.replace(tau_fbi=1e-8, tau_win=1e-8)
-    ns = f0.shape[0]
-    ctx, beams, f0t, u, stream = run(g, p, c, f0, precision)
-    eager = u.clone()
+    stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
+        ctx = fga.FGA(g, p, precision, max_shots=3)
+        ctx.set_velocity(torch.from_numpy(c).cuda())
+        cand = 2 * p.nq1 * p.nq2 * p.np1 * p.np2
+        beams = fga.Beams(2 * cand, 2)
+        f0t = torch.from_numpy(np.ascontiguousarray(f0[:2])).cuda()
+        u = torch.empty((2, g.n2, g.n1), dtype=torch.float64, device="cuda")
         ctx.graph_capture(f0t, None, beams, p.nsteps, u)
+        stream.synchronize()
+        eager = u.clone()
         ctx.graph_launch()
         stream.synchronize()
         np.testing.assert_array_equal(u.cpu().numpy(), eager.cpu().numpy())
-        big = fga.Beams(2 * beams.capacity, ns)
-        big.f[:, : beams.capacity].copy_(beams.f)
-        big.id[: beams.capacity].copy_(beams.id)
-        big.offsets.copy_(beams.offsets)
-        u_big = ctx.reconstruct(big, ns)
+        beams3 = fga.Beams(3 * cand, 3)
+        ctx.decompose(torch.from_numpy(np.ascontiguousarray(f0)).cuda(), None, beams3)
         u.fill_(7.0)
         with pytest.raises(fga.FGAError) as err:
             ctx.graph_launch()
         assert err.value.status == fga.FGA_ESTATE
         stream.synchronize()
         assert bool((u == 7.0).all())
-        np.testing.assert_array_equal(u_big.cpu().numpy(), eager.cpu().numpy())
         ctx.graph_capture(f0t, None, beams, p.nsteps, u)
         u.fill_(0.0)
         ctx.graph_launch()
