@@ -231,6 +231,27 @@ fga_status fga_trace(fga_ctx *ctx, fga_beams *beams, int32_t nshots,
                      const int32_t *rec_dev, int32_t nrec, int32_t rec_every,
                      int32_t nrec_t, double *traces_dev, double *ckpt_dev);
 
+/* fga_trace for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments and results, but the receiver classification and the
+ * partial receiver sums live in a static device array of
+ * FGA_NOALLOC_SCRATCH_BYTES that the library holds on each GPU until the
+ * process ends (its address is looked up once per device by fga_create), so
+ * the call allocates and frees nothing.  The partial sums need
+ * nshots * nrec * 8 bytes per work split: when the default split count does
+ * not fit, fewer splits are used (the traces then agree with fga_trace's to
+ * the rounding of the sum order); if even one split does not fit
+ * (nshots * nrec * 8 + 256 > FGA_NOALLOC_SCRATCH_BYTES) the call returns
+ * FGA_EINVAL before any launch.  All calls on one GPU share the array: two
+ * such calls that overlap in time on that GPU (other streams, other
+ * contexts, other threads) race and give wrong traces; calls ordered on one
+ * stream are safe.  FGA_ESTATE if the context has no scratch address (more
+ * than 64 devices).                                                        */
+#define FGA_NOALLOC_SCRATCH_BYTES (16LL << 20)
+fga_status fga_trace_noalloc(fga_ctx *ctx, fga_beams *beams, int32_t nshots,
+                             const int32_t *rec_dev, int32_t nrec, int32_t rec_every,
+                             int32_t nrec_t, double *traces_dev, double *ckpt_dev);
+
 /* Adjoint of fga_trace: the gradient of J = 1/2 sum (traces - data)^2
  * through the RK4 integration of the ray, dynamic ray tracing and amplitude
  * equations and the receiver sums, with the beam set and every truncation

@@ -89,6 +89,7 @@ def load(path: str = LIB_PATH):
         "fga_propagate": [C, ctypes.POINTER(fga_beams), I32, I32],
         "fga_reconstruct": [C, ctypes.POINTER(fga_beams), I32, P],
         "fga_trace": [C, ctypes.POINTER(fga_beams), I32, P, I32, I32, I32, P, P],
+        "fga_trace_noalloc": [C, ctypes.POINTER(fga_beams), I32, P, I32, I32, I32, P, P],
         "fga_trace_adjoint": [C, ctypes.POINTER(fga_beams), I32, P, I32, I32, I32, P, P, P, P],
         "fga_decompose_adjoint": [C, ctypes.POINTER(fga_beams), I32, P, P, P, P],
         "fga_reconstruct_adjoint": [C, ctypes.POINTER(fga_beams), I32, P, P, P],
@@ -188,6 +189,15 @@ def fga_trace(ctx, beams: "Beams", nshots: int, rec, rec_every: int, nrec_t: int
     _require(traces, "traces", "float64")
     _check(ctx, load().fga_trace(ctx, beams.c_struct(), int(nshots), _ptr(rec), rec.numel(),
                                  int(rec_every), int(nrec_t), _ptr(traces), _ptr(ckpt)))
+
+
+def fga_trace_noalloc(ctx, beams: "Beams", nshots: int, rec, rec_every: int, nrec_t: int,
+                      traces, ckpt=None):
+    _require(rec, "rec", "int32")
+    _require(traces, "traces", "float64")
+    _check(ctx, load().fga_trace_noalloc(ctx, beams.c_struct(), int(nshots), _ptr(rec),
+                                         rec.numel(), int(rec_every), int(nrec_t),
+                                         _ptr(traces), _ptr(ckpt)))
 
 
 def fga_trace_adjoint(ctx, beams: "Beams", nshots: int, rec, rec_every: int, nrec_t: int,

@@ -6,9 +6,40 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "fga_internal.h"
 
 static char g_create_err[512] = "";
+
+// Scratch of fga_trace_noalloc: one static array per device (each GPU the
+// library runs on holds its own copy until the process ends).  Host code never
+// uses this name as an address: fga_create looks up the device address once
+// per device and every launch takes that pointer.
+static __device__ __align__(256) unsigned char scratch[FGA_NOALLOC_SCRATCH_BYTES];
+
+#define FGA_MAX_DEVICES 64
+static void *g_scratch_ptr[FGA_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// The device address of `scratch` on the current device (dev), looked up on
+// the first context created there.
+static fga_status scratch_address(int dev, void **out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= FGA_MAX_DEVICES) return FGA_OK;   // variant unavailable there
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fga_fail(nullptr, FGA_EHIP, "hipGetSymbolAddress(scratch): %s",
+                            hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FGA_OK;
+}
 
 fga_status fga_fail(fga_ctx *ctx, fga_status st, const char *fmt, ...)
 {
@@ -151,6 +182,11 @@ extern "C" fga_status fga_create(fga_ctx **out, const fga_grid *g, const fga_par
         fga_fail(nullptr, FGA_EHIP, "fga_create: %s", hipGetErrorString(e));
         fga_destroy(ctx);
         return FGA_EHIP;
+    }
+    st = scratch_address(ctx->dev, &ctx->noalloc_scratch);
+    if (st != FGA_OK) {
+        fga_destroy(ctx);
+        return st;
     }
     *out = ctx;
     return FGA_OK;
@@ -314,6 +350,49 @@ extern "C" fga_status fga_trace(fga_ctx *ctx, fga_beams *beams, int32_t nshots,
         if (st != FGA_OK) return st;
         st = fga_launch_trace_points(ctx, beams, nshots, rec, nrec, traces + (size_t)k * nrec,
                                      (int64_t)nrec_t * nrec, shape);
+        if (st != FGA_OK) return st;
+    }
+    return FGA_OK;
+}
+
+extern "C" fga_status fga_trace_noalloc(fga_ctx *ctx, fga_beams *beams, int32_t nshots,
+                                        const int32_t *rec, int32_t nrec, int32_t rec_every,
+                                        int32_t nrec_t, double *traces, double *ckpt)
+{
+    if (!ctx) return FGA_EINVAL;
+    fga_status st = check_beams(ctx, beams);
+    if (st != FGA_OK) return st;
+    if (nshots < 1 || nshots > ctx->max_shots)
+        return fga_fail(ctx, FGA_EINVAL, "nshots %d outside [1, %d]", nshots, ctx->max_shots);
+    if (!rec || nrec < 1 || rec_every < 1 || nrec_t < 1 || !traces)
+        return fga_fail(ctx, FGA_EINVAL, "bad receiver arguments");
+    if (!ctx->have_c) return fga_fail(ctx, FGA_ESTATE, "fga_set_velocity was not called");
+    if (!ctx->noalloc_scratch)
+        return fga_fail(ctx, FGA_ESTATE, "no static scratch on device %d", ctx->dev);
+    // layout: the receiver classification (4 ints) in the first 256 bytes,
+    // then the partial sums [nshots][nsplit][nrec]; every entry is written
+    // before it is read, so nothing needs clearing
+    const size_t avail = FGA_NOALLOC_SCRATCH_BYTES - 256;
+    const size_t per_split = (size_t)nshots * nrec * sizeof(double);
+    if (per_split > avail)
+        return fga_fail(ctx, FGA_EINVAL,
+                        "fga_trace_noalloc: %d shots x %d receivers need %zu bytes of scratch, "
+                        "above its %lld bytes",
+                        nshots, nrec, per_split + 256, (long long)FGA_NOALLOC_SCRATCH_BYTES);
+    int nsplit = fga_trace_splits(ctx, nshots, nrec);
+    if ((size_t)nsplit * per_split > avail) nsplit = (int)(avail / per_split);
+    int *shape = (int *)ctx->noalloc_scratch;
+    double *part = (double *)((char *)ctx->noalloc_scratch + 256);
+    st = fga_rec_shape_into(ctx, rec, nrec, shape);
+    if (st != FGA_OK) return st;
+    for (int k = 0; k < nrec_t; ++k) {
+        const size_t per = ctx->p.ckpt_every_step ? (size_t)rec_every : 1;
+        double *ck = ckpt ? ckpt + (size_t)k * per * FGA_NSTATE * beams->capacity : nullptr;
+        st = fga_launch_propagate(ctx, beams, nshots, rec_every, ck);
+        if (st != FGA_OK) return st;
+        st = fga_launch_trace_points_into(ctx, beams, nshots, rec, nrec,
+                                          traces + (size_t)k * nrec, (int64_t)nrec_t * nrec,
+                                          shape, part, nsplit);
         if (st != FGA_OK) return st;
     }
     return FGA_OK;

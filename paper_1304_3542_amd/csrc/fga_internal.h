@@ -80,6 +80,9 @@ struct fga_ctx {
     hipGraphExec_t graph_exec;
     bool graph_stale;      // a workspace the graph uses was freed since capture
 
+    // this device's copy of the library's static scratch array (fga_trace_noalloc)
+    void *noalloc_scratch;
+
     char err[512];
 };
 
@@ -104,9 +107,18 @@ fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nsho
 // receives a device pointer to {run, first column, row, run traced per beam}
 // with run = 1 when rec[r] = rec[0] + r all lie in rec[0]'s row.
 fga_status fga_rec_shape(fga_ctx *ctx, const int32_t *rec, int nrec, const int **shape);
+// the same into a caller-given device buffer of 4 ints (no allocation)
+fga_status fga_rec_shape_into(fga_ctx *ctx, const int32_t *rec, int nrec, int *shape);
 fga_status fga_launch_trace_points(fga_ctx *ctx, const fga_beams *beams, int nshots,
                                    const int32_t *rec, int nrec, double *out,
                                    int64_t out_stride_shot, const int *shape);
+// work splits of the receiver sums (each split writes nshots * nrec partial
+// sums), and the launch into caller-given partial sums (no allocation)
+int fga_trace_splits(const fga_ctx *ctx, int nshots, int nrec);
+fga_status fga_launch_trace_points_into(fga_ctx *ctx, const fga_beams *beams, int nshots,
+                                        const int32_t *rec, int nrec, double *out,
+                                        int64_t out_stride_shot, const int *shape, double *part,
+                                        int nsplit);
 
 fga_status fga_launch_trace_adjoint(fga_ctx *ctx, const fga_beams *beams, int nshots,
                                     const int32_t *rec, int nrec, int rec_every, int nrec_t,

@@ -439,16 +439,22 @@ __global__ void k_rec_shape(const int32_t *__restrict__ rec, int nrec, int n1, i
     }
 }
 
+fga_status fga_rec_shape_into(fga_ctx *ctx, const int32_t *rec, int nrec, int *shape)
+{
+    hipLaunchKernelGGL(k_rec_shape, dim3(1), dim3(256), 0, ctx->stream, rec, nrec, ctx->g.n1,
+                       shape);
+    FGA_HIP(ctx, hipGetLastError());
+    return FGA_OK;
+}
+
 fga_status fga_rec_shape(fga_ctx *ctx, const int32_t *rec, int nrec, const int **shape)
 {
     fga_status rc = fga_ensure(ctx, &ctx->rec_shape, &ctx->rec_shape_bytes, 4 * sizeof(int),
                                "receiver layout");
     if (rc != FGA_OK) return rc;
-    hipLaunchKernelGGL(k_rec_shape, dim3(1), dim3(256), 0, ctx->stream, rec, nrec, ctx->g.n1,
-                       (int *)ctx->rec_shape);
-    FGA_HIP(ctx, hipGetLastError());
+    rc = fga_rec_shape_into(ctx, rec, nrec, (int *)ctx->rec_shape);
     *shape = (const int *)ctx->rec_shape;
-    return FGA_OK;
+    return rc;
 }
 
 __device__ __forceinline__ int tr_wave_min(int v)
@@ -631,18 +637,33 @@ __global__ void k_trace_reduce(const double *__restrict__ partial, int nsplit, i
     if (lane == 0) out[(size_t)s * stride_shot + r] = v;
 }
 
+int fga_trace_splits(const fga_ctx *ctx, int nshots, int nrec)
+{
+    const int rblocks = (nrec + TR_BLOCK - 1) / TR_BLOCK;
+    int want = (4 * ctx->num_cu + nshots * rblocks - 1) / (nshots * rblocks);
+    return want < 1 ? 1 : (want > 256 ? 256 : want);
+}
+
 fga_status fga_launch_trace_points(fga_ctx *ctx, const fga_beams *beams, int nshots,
                                    const int32_t *rec, int nrec, double *out,
                                    int64_t stride_shot, const int *shape)
 {
-    const fga_grid &g = ctx->g;
-    const int rblocks = (nrec + TR_BLOCK - 1) / TR_BLOCK;
-    int want = (4 * ctx->num_cu + nshots * rblocks - 1) / (nshots * rblocks);
-    int nsplit = want < 1 ? 1 : (want > 256 ? 256 : want);
+    const int nsplit = fga_trace_splits(ctx, nshots, nrec);
     fga_status rc = fga_ensure(ctx, &ctx->trace_part, &ctx->trace_part_bytes,
                                (size_t)nshots * nsplit * nrec * sizeof(double),
                                "trace partial sums");
     if (rc != FGA_OK) return rc;
+    return fga_launch_trace_points_into(ctx, beams, nshots, rec, nrec, out, stride_shot, shape,
+                                        (double *)ctx->trace_part, nsplit);
+}
+
+fga_status fga_launch_trace_points_into(fga_ctx *ctx, const fga_beams *beams, int nshots,
+                                        const int32_t *rec, int nrec, double *out,
+                                        int64_t stride_shot, const int *shape, double *part,
+                                        int nsplit)
+{
+    const fga_grid &g = ctx->g;
+    const int rblocks = (nrec + TR_BLOCK - 1) / TR_BLOCK;
     SplatArgs A{};
     A.f = beams->f;
     A.offsets = beams->offsets;
@@ -660,9 +681,9 @@ fga_status fga_launch_trace_points(fga_ctx *ctx, const fga_beams *beams, int nsh
     A.Rw2 = ctx->Rw2;
     A.nsplit = nsplit;
     hipLaunchKernelGGL(k_trace_points, dim3(nsplit, nshots, rblocks), dim3(TR_BLOCK), 0,
-                       ctx->stream, A, rec, nrec, shape, (double *)ctx->trace_part);
+                       ctx->stream, A, rec, nrec, shape, part);
     hipLaunchKernelGGL(k_trace_reduce, dim3((nrec * nshots + 3) / 4), dim3(256), 0,
-                       ctx->stream, (const double *)ctx->trace_part, nsplit, nrec, nshots, out,
+                       ctx->stream, (const double *)part, nsplit, nrec, nshots, out,
                        stride_shot);
     FGA_HIP(ctx, hipGetLastError());
     return FGA_OK;
