@@ -4,10 +4,12 @@
 One step = the whole hot path on one batch of synthetic input already in
 HBM: decomposition (FBI + branch split + threshold + compaction), RK4
 propagation of every beam to T = 0.25 s (250 steps) and reconstruction of
-u(T) on the grid.  Workload: 512 x 512 smooth layered model on [0,2]x[0,1],
-eps = 1/256, point source (sigma = 2 cells), q-mesh 40 x 20, p-mesh
-112 x 112, tau = 1e-6, mixed precision (FP32 FBI and splat with the phase
-reduced in FP64, FP64 rays and amplitudes).
+u(T) on the grid.  Headline workload (the largest single-GPU
+configuration): 2048 x 1024 smooth layered model on [0,2]x[0,1],
+eps = 1/1024, point source (sigma = 2 cells), q-mesh 147 x 74, p-mesh
+400 x 400, tau = 1e-6, ~5e7 beams, mixed precision (FP32 FBI and splat with
+the phase reduced in FP64, FP64 rays and amplitudes).  The 512 x 512
+configuration (point512) and the other workloads follow as secondary keys.
 
 Prints ONE JSON line: beams/s end-to-end, the per-stage times, the error of
 the mixed path against the FP64 path (and against stored oracle values at
@@ -39,7 +41,7 @@ PEAK = {"hbm": 8.0e12, "fp64": 78.6e12, "fp32": 157.3e12}
 # 1/|det Z|^2, tr(Z^-1 dZ) and the amplitude slope and updates (~37):
 # ~521 per stage, four stages less the last stage's unused input update.
 RK4_FLOP_PER_BEAM_STEP = 2030
-PROFILE_JSON = os.path.join(ROOT, "profiles", "point512_hbm_counters.json")
+PROFILE_JSON = os.path.join(ROOT, "profiles", "{workload}_hbm_counters.json")
 KERNEL_SOURCES = {
     "k_rk4": ["paper_1304_3542_amd/csrc/propagate.hip", "paper_1304_3542_amd/csrc/rk4.h",
               "paper_1304_3542_amd/csrc/fga_internal.h"],
@@ -54,13 +56,15 @@ KERNEL_SOURCES = {
 PROFILED_NAME = {"k_rk4": "k_rk4<false, false>", "k_splat_binned": "k_splat_binned"}
 
 
-def profiled_traffic(kernel):
+def profiled_traffic(kernel, workload):
     """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE counter
-    summary, or None if the kernel's sources changed since it was taken."""
+    summary of the workload, or None if the kernel's sources changed since it
+    was taken."""
     import hashlib
-    if not os.path.exists(PROFILE_JSON) or kernel not in KERNEL_SOURCES:
+    path = PROFILE_JSON.format(workload=workload)
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
         return None
-    z = json.load(open(PROFILE_JSON))
+    z = json.load(open(path))
     h = hashlib.sha256()
     for fn in KERNEL_SOURCES[kernel]:
         h.update(open(os.path.join(ROOT, fn), "rb").read())
@@ -75,7 +79,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="point512")
+    ap.add_argument("--workload", default="large2048",
+                    help="headline workload (large2048: the largest single-GPU configuration)")
+    ap.add_argument("--graph-steps", type=int, default=5,
+                    help="timed replays of the headline step captured as one HIP graph")
+    ap.add_argument("--point-steps", type=int, default=10,
+                    help="timed steps of the 512x512 configuration (point512) as a secondary "
+                         "key (0 skips it; ignored when it is the headline)")
     ap.add_argument("--fp64-steps", type=int, default=1,
                     help="timed steps of the FP64 GPU path on the same input (at least 1: "
                          "the mixed field is checked against it)")
@@ -90,8 +100,6 @@ def parse():
                     help="timed steps of point512 with divided-difference dzQ, dzP (0 skips it)")
     ap.add_argument("--d3-steps", type=int, default=2,
                     help="timed steps of the three-dimensional point3d workload (0 skips it)")
-    ap.add_argument("--large-steps", type=int, default=1,
-                    help="timed steps of the 2048x1024 configuration (0 skips it)")
     ap.add_argument("--topn-steps", type=int, default=5,
                     help="timed steps of the N-largest selection workload (0 skips it)")
     ap.add_argument("--adjoint-steps", type=int, default=3,
@@ -568,38 +576,6 @@ def d3_step(steps):
             "status": st if st0[0] == 0 else st0[0]}
 
 
-def large_step(steps):
-    """The large configuration (2048 x 1024, eps = 1/1024, ~5e7 beams): ms per
-    mixed step and its stages, the FP64 GPU step on the same input, and the
-    mixed field's error against it."""
-    import torch
-    out = {"workload": "large2048: 2048x1024 smooth layered model, eps=1/1024, point source, "
-           "q 147x74, p 400x400, tau=1e-6"}
-    res = {}
-    for prec in ("mixed", "fp64"):
-        W = fi.workload("large2048", prec)
-        path = Path(W, prec, 8_000_000)
-        nb = path.fit_capacity()
-        ms, stage_ms, _ = time_path(path, steps if prec == "mixed" else 1, 1 if prec == "mixed" else 0)
-        res[prec] = (nb, ms, stage_ms, path.u[0].cpu().numpy())
-        st, _ = path.ctx.status()
-        path.ctx.close()
-        del path
-        torch.cuda.empty_cache()
-    nb, ms, stage_ms, um = res["mixed"]
-    nb64, ms64, stage64, u64 = res["fp64"]
-    out.update({"nbeams": nb, "ms_per_step": ms, "beams_per_s": nb / (ms * 1e-3),
-                "stages_ms": dict(zip(("decompose", "propagate", "reconstruct"),
-                                      stage_ms.tolist())),
-                "fp64_gpu": {"nbeams": nb64, "ms_per_step": ms64,
-                             "stages_ms": dict(zip(("decompose", "propagate", "reconstruct"),
-                                                   stage64.tolist()))},
-                "speedup_mixed_over_fp64": ms64 / ms,
-                "rel_l2_vs_fp64_gpu": float(np.linalg.norm(um - u64) / np.linalg.norm(u64)),
-                "status": st})
-    return out
-
-
 def box_pairs(f, nb, W, tau_win):
     """Number of (beam, node) pairs the windowed sum visits."""
     g, p = W.grid, W.params
@@ -613,32 +589,48 @@ def box_pairs(f, nb, W, tau_win):
     return float((w1 * w2).sum())
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(W, nbeams, budget_s):
     """The oracle on a bounded sample of the same workload, scaled to the
-    whole job: FBI on a few q nodes, RK4 and the windowed sum for a few
-    hundred beams."""
+    whole job: the FBI at the two q nodes of largest bound, scaled to the q
+    nodes the oracle visits (decompose(q_skip=True): the others cannot keep
+    a beam), and RK4 and the windowed sum for 1024 beams, scaled to the
+    job's beam count."""
     import oracle
     g, p = W.grid, W.params
     nq = p.nq1 * p.nq2
-    # FBI on a handful of q nodes around the source
-    qs = p.replace(qb1=p.qb1 + p.qs1 * (p.nq1 // 2), qb2=p.qb2 + p.qs2 * (p.nq2 // 2),
-                   nq1=2, nq2=1)
+    bound = 0.5 * oracle.fbi_bound(W.f0[0], g, p).ravel()
+    top = np.argsort(-bound, kind="stable")[:2]
     t = time.perf_counter()
-    psi = oracle.fbi(W.f0[0], g, qs)
-    t_fbi = (time.perf_counter() - t) / 2 * nq
+    psis = []
+    for q in top:
+        j2, j1 = divmod(int(q), p.nq1)
+        one = p.replace(qb1=p.qb1 + p.qs1 * j1, qb2=p.qb2 + p.qs2 * j2, nq1=1, nq2=1)
+        psis.append((one, oracle.fbi(W.f0[0], g, one)[0, 0]))
+    t_per_q = (time.perf_counter() - t) / len(top)
+    M = max(0.5 * np.abs(ps).max() for _, ps in psis)
+    visited = int((bound * (1 + 1e-9) >= p.tau * M).sum())
+    t_fbi = t_per_q * visited
     # beams: the largest |psi| of the sampled q nodes, both branches
     nsb = 1024
+    one, psi = psis[0]
     order = np.argsort(-np.abs(psi.ravel()))[:nsb // 2]
-    j2, j1, l2, l1 = np.unravel_index(order, psi.shape)
-    k1, k2 = oracle.qnodes(qs)
+    l2, l1 = np.unravel_index(order, psi.shape)
     pm1, pm2 = oracle.pmesh(p.np1, p.dp1), oracle.pmesh(p.np2, p.dp2)
     st = np.zeros((nsb, oracle.NSTATE))
-    for h in range(2):
-        sl = slice(h * (nsb // 2), (h + 1) * (nsb // 2))
-        st[sl, 0] = g.o1 + g.d1 * k1[j1]
-        st[sl, 1] = g.o2 + g.d2 * k2[j2]
-        st[sl, 2] = pm1[l1]
-        st[sl, 3] = pm2[l2]
+    st[:, 0] = g.o1 + g.d1 * one.qb1
+    st[:, 1] = g.o2 + g.d2 * one.qb2
+    st[:, 2] = np.tile(pm1[l1], 2)
+    st[:, 3] = np.tile(pm2[l2], 2)
     st[:, 5] = st[:, 11] = 1.0
     st[:, 14] = st[:, 20] = -1.0
     st[:, 21] = 2.0
@@ -656,46 +648,59 @@ def cpu_baseline(W, nbeams, budget_s):
     total = t_fbi + t_rk4 + t_rec
     return {
         "value": nbeams / total, "unit": "beams/s", "cores": oracle.threads(),
-        "kind": "oracle",
-        "sample": (f"FP64 oracle: FBI at 2 of {nq} q nodes, RK4 ({p.nsteps} steps) and the "
-                   f"windowed sum for {nsb} beams, each scaled linearly to the {nbeams} "
-                   f"beams / {nq} q nodes of the job"),
+        "cpu": cpu_model(), "kind": "oracle",
+        "sample": (f"FP64 oracle on {W.name}: FBI at the 2 q nodes of largest bound "
+                   f"({t_per_q:.2f} s each), scaled to the {visited} of {nq} q nodes it "
+                   f"visits (the others cannot keep a beam); RK4 ({p.nsteps} steps) and the "
+                   f"windowed sum over the grid for {nsb} beams, scaled linearly to the "
+                   f"{nbeams} beams of the job"),
         "est_seconds": {"fbi": t_fbi, "rk4": t_rk4, "reconstruct": t_rec},
     }
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 "
-                          "(sharding over several GPUs is designed, not built)"}))
-        sys.exit(2)
+WORKLOAD_TEXT = {
+    "large2048": "large2048: 2048x1024 smooth layered model on [0,2]x[0,1], eps=1/1024, point "
+                 "source (sigma 2 cells), q 147x74, p 400x400, tau=1e-6, T=0.25 s, dt=1 ms, "
+                 "mixed precision",
+    "point512": "point512: 512x512 smooth layered model, eps=1/256, point source, q 40x20, "
+                "p 112x112, tau=1e-6, T=0.25 s, dt=1 ms, mixed precision",
+}
+
+
+def measure(name, steps, warmup, fp64_steps, graph_steps):
+    """The whole step of one single-shot workload in mixed precision (timed
+    steps on the host clock and per stage with HIP events, graph replays),
+    the FP64 GPU path on the same input, the mixed field's error against it
+    and against the stored oracle values, and the roofline entries of the
+    path's kernels."""
     import torch
-    if args.calib_copy:
-        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    W = fi.workload(args.workload, "mixed")
-    Wd = fi.workload(args.workload, "fp64")
+    W = fi.workload(name, "mixed")
+    Wd = fi.workload(name, "fp64")
     cand = 2 * W.params.nq1 * W.params.nq2 * W.params.np1 * W.params.np2 * W.nshots
 
     mixed = Path(W, "mixed", min(cand, 4_000_000))
     nb = mixed.fit_capacity()
-    ms_step, stage_ms, per_step = time_path(mixed, args.steps, args.warmup)
+    ms_step, stage_ms, per_step = time_path(mixed, steps, warmup)
     u_mixed = mixed.u.cpu().numpy()
     f_host = mixed.beams.f[:, :nb].cpu().numpy()
-    graph = graph_replays(mixed, args.steps, nb) if args.steps > 0 else None
+    graph = graph_replays(mixed, graph_steps, nb) if graph_steps > 0 else None
+    pairs = box_pairs(f_host, nb, W, W.params.tau_win)
+    del f_host
+    splat_ms = time_splat_kernel(mixed)
 
     fp64 = Path(Wd, "fp64", min(cand, 4_000_000))
     nb64 = fp64.fit_capacity()
-    ms64, stage64, _ = time_path(fp64, max(1, args.fp64_steps), 0)
+    ms64, stage64, _ = time_path(fp64, max(1, fp64_steps), 0)
     u64 = fp64.u.cpu().numpy()
+    fp64.ctx.close()
+    del fp64
+    mixed.ctx.close()
+    del mixed
+    torch.cuda.empty_cache()
     rel_vs_fp64 = float(np.linalg.norm(u_mixed - u64) / np.linalg.norm(u64))
 
     rel_oracle = None
-    gold = os.path.join(ROOT, "tests", "golden", f"{args.workload}_fp64.npz")
+    gold = os.path.join(ROOT, "tests", "golden", f"{name}_fp64.npz")
     if os.path.exists(gold) and W.nshots == 1:
         z = np.load(gold)
         ref = z["u"]
@@ -703,10 +708,9 @@ def main():
             "mixed": float(np.linalg.norm(u_mixed[0].ravel()[z["nodes"]] - ref) / np.linalg.norm(ref)),
             "fp64": float(np.linalg.norm(u64[0].ravel()[z["nodes"]] - ref) / np.linalg.norm(ref)),
             "nodes": int(z["nodes"].size),
+            "nbeams_oracle": int(z["nbeams"]),
         }
 
-    pairs = box_pairs(f_host, nb, W, W.params.tau_win)
-    splat_ms = time_splat_kernel(mixed)
     npts = W.grid.n1 * W.grid.n2 * W.nshots
     stages = {"decompose": stage_ms[0], "propagate": stage_ms[1], "reconstruct": stage_ms[2]}
     dom = max(stages, key=stages.get)
@@ -724,70 +728,114 @@ def main():
                              "frac": fb_ach / PEAK["fp32"], "ms": stage_ms[0],
                              "ms_covers": "decompose stage",
                              "flop_per_launch": f2_fl, "flop_pass1": f1_fl},
+        # one launch per propagate call: the stage time is the kernel's
         "k_rk4": {"bound": "alu", "achieved": rk_ach / 1e12, "peak": PEAK["fp64"] / 1e12,
                   "unit": "TFLOP/s", "frac": rk_ach / PEAK["fp64"], "ms": stage_ms[1],
-                  "flop_per_launch": rk_fl, "traffic": profiled_traffic("k_rk4")},
+                  "flop_per_launch": rk_fl, "traffic": profiled_traffic("k_rk4", name)},
         # ms is the whole reconstruction (records, binning, splat, reduction)
         "k_splat_binned": {"bound": "mfma", "achieved": sp_ach / 1e12,
                            "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
                            "frac": sp_ach / PEAK["fp32"], "ms": splat_ms,
                            "ms_covers": "reconstruct stage",
                            "flop_per_launch": sp_fl,
-                           "traffic": profiled_traffic("k_splat_binned")},
+                           "traffic": profiled_traffic("k_splat_binned", name)},
     }
     roof = dict(kernels["k_rk4" if dom != "reconstruct" else "k_splat_binned"])
     roof["kernel"] = "k_rk4" if dom != "reconstruct" else "k_splat_binned"
     for key in ("ms", "flop_per_launch", "ms_covers"):
         roof.pop(key, None)
+    return {
+        "nb": nb, "ms_step": ms_step, "per_step": per_step, "stages": stages,
+        "graph": graph, "rel_vs_fp64": rel_vs_fp64, "rel_oracle": rel_oracle,
+        "pairs": pairs, "npts": npts, "kernels": kernels, "roofline": roof,
+        "fp64_gpu": {"ms_per_step": ms64, "nbeams": nb64,
+                     "stages_ms": dict(zip(stages, stage64.tolist())),
+                     "speedup_mixed_over_fp64": ms64 / ms_step},
+        "u_mixed": u_mixed, "W": W, "Wd": Wd,
+    }
 
+
+def summary(name, r, steps, warmup):
+    """The JSON fields of one measured workload."""
+    ps = r["per_step"]
+    return {
+        "workload": WORKLOAD_TEXT.get(name, name),
+        "nbeams": r["nb"],
+        "steps": steps, "warmup": warmup,
+        "ms_per_step": r["ms_step"],
+        "beams_per_s": r["nb"] / (r["ms_step"] * 1e-3),
+        "ms_per_step_device": {"median": float(np.median(ps)),
+                               "iqr": float(np.percentile(ps, 75) - np.percentile(ps, 25)),
+                               "min": float(ps.min()), "max": float(ps.max())},
+        "valid": bool(r["rel_vs_fp64"] <= 1e-5),
+        "rel_l2_vs_fp64_gpu": r["rel_vs_fp64"],
+        "rel_l2_vs_oracle_sample": r["rel_oracle"],
+        "stages_ms": r["stages"],
+        "graph": r["graph"],
+        "grid_points_per_s": r["npts"] / (r["ms_step"] * 1e-3),
+        "pairs": r["pairs"],
+        "pairs_per_s": r["pairs"] / (r["stages"]["reconstruct"] * 1e-3),
+        "fp64_gpu": r["fp64_gpu"],
+        "roofline": r["roofline"],
+        "kernels": r["kernels"],
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 "
+                          "(sharding over several GPUs is designed, not built)"}))
+        sys.exit(2)
+    import torch
+    if args.calib_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    name = args.workload
+    r = measure(name, args.steps, args.warmup, args.fp64_steps, args.graph_steps)
+    head = summary(name, r, args.steps, args.warmup)
     out = {
         "metric": "beams/s end-to-end (FBI+trace+sum) at rel-L2<=1e-5 vs FP64; adjoint ms/iter",
-        "value": nb / (ms_step * 1e-3),
+        "value": head["beams_per_s"],
         "unit": "beams/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "ms_per_step_device": {"median": float(np.median(per_step)),
-                               "iqr": float(np.percentile(per_step, 75) -
-                                            np.percentile(per_step, 25)),
-                               "min": float(per_step.min()), "max": float(per_step.max())},
+        "ms_per_step": r["ms_step"],
+        "ms_per_step_device": head["ms_per_step_device"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: 512x512 smooth layered model, eps=1/256, "
-                               f"point source, q 40x20, p 112x112, tau=1e-6, T=0.25 s, dt=1 ms, "
-                               f"mixed precision", "nshots": W.nshots, "nbeams": nb},
-        "valid": bool(rel_vs_fp64 <= 1e-5),
-        "rel_l2_vs_fp64_gpu": rel_vs_fp64,
-        "rel_l2_vs_oracle_sample": rel_oracle,
-        "stages_ms": stages,
-        "graph": graph,
-        "grid_points_per_s": npts / (ms_step * 1e-3),
-        "pairs": pairs,
-        "pairs_per_s": pairs / (stage_ms[2] * 1e-3),
-        "fp64_gpu": {"ms_per_step": ms64, "nbeams": nb64,
-                     "stages_ms": dict(zip(stages, stage64.tolist())),
-                     "speedup_mixed_over_fp64": ms64 / ms_step},
-        "roofline": roof,
-        "kernels": kernels,
+        "config": {"workload": head["workload"], "nshots": r["W"].nshots, "nbeams": r["nb"]},
     }
+    for k in ("valid", "rel_l2_vs_fp64_gpu", "rel_l2_vs_oracle_sample", "stages_ms", "graph",
+              "grid_points_per_s", "pairs", "pairs_per_s", "fp64_gpu", "roofline", "kernels"):
+        out[k] = head[k]
+    u_point = r["u_mixed"] if name == "point512" else None
+    Wd, nb = r["Wd"], r["nb"]
+    del r
+    if name != "point512" and args.point_steps > 0:
+        rp = measure("point512", args.point_steps, 1, 1, args.point_steps)
+        out["point512"] = summary("point512", rp, args.point_steps, 1)
+        u_point = rp["u_mixed"]
+        del rp
     if args.adjoint_steps > 0:
         out["adjoint"] = adjoint_iteration(args.adjoint_steps)
     if args.batch_steps > 0:
         out["batched"] = batched_shots(args.batch_steps)
     if args.topn_steps > 0:
         out["topn"] = topn_step(args.topn_steps)
-    if args.closed_steps > 0:
-        out["closed_amplitude"] = closed_step(args.closed_steps, u_mixed)
-    if args.dd_steps > 0:
-        out["divided_differences"] = dd_step(args.dd_steps, u_mixed)
+    if args.closed_steps > 0 and u_point is not None:
+        out["closed_amplitude"] = closed_step(args.closed_steps, u_point)
+    if args.dd_steps > 0 and u_point is not None:
+        out["divided_differences"] = dd_step(args.dd_steps, u_point)
     if args.d3_steps > 0:
         out["d3"] = d3_step(args.d3_steps)
-    if args.large_steps > 0:
-        out["large"] = large_step(args.large_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Wd, nb, args.cpu_seconds)
     print(json.dumps(out), flush=True)

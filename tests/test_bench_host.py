@@ -23,21 +23,42 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
 
 
+def _summaries(b):
+    out = []
+    for w in ("point512", "large2048"):
+        path = b.PROFILE_JSON.format(workload=w)
+        if os.path.exists(path):
+            out.append((w, json.load(open(path))))
+    return out
+
+
 def test_profiled_names_exist_in_counter_summary():
     b = load_bench()
-    z = json.load(open(b.PROFILE_JSON))
-    for kern in b.KERNEL_SOURCES:
-        assert b.PROFILED_NAME[kern] in z["kernels"], kern
-        assert kern in z["source_sha"], kern
+    found = _summaries(b)
+    assert found
+    for _, z in found:
+        for kern in b.KERNEL_SOURCES:
+            assert b.PROFILED_NAME[kern] in z["kernels"], kern
+            assert kern in z["source_sha"], kern
 
 
 def test_traffic_follows_source_hash(tmp_path, monkeypatch):
     b = load_bench()
-    z = json.load(open(b.PROFILE_JSON))
-    # with the stored hash replaced, the traffic must be withheld
-    z["source_sha"] = {k: "0" * 16 for k in z["source_sha"]}
-    p = tmp_path / "counters.json"
-    p.write_text(json.dumps(z))
-    monkeypatch.setattr(b, "PROFILE_JSON", str(p))
-    for kern in b.KERNEL_SOURCES:
-        assert b.profiled_traffic(kern) is None
+    for w, z in _summaries(b):
+        # with the stored hash replaced, the traffic must be withheld
+        z["source_sha"] = {k: "0" * 16 for k in z["source_sha"]}
+        (tmp_path / f"{w}_hbm_counters.json").write_text(json.dumps(z))
+        monkeypatch.setattr(b, "PROFILE_JSON", str(tmp_path / "{workload}_hbm_counters.json"))
+        for kern in b.KERNEL_SOURCES:
+            assert b.profiled_traffic(kern, w) is None
+
+
+def test_default_headline_is_the_largest_configuration():
+    b = load_bench()
+    sys_argv = sys.argv
+    try:
+        sys.argv = ["bench.py"]
+        args = b.parse()
+    finally:
+        sys.argv = sys_argv
+    assert args.workload == "large2048" and args.steps >= 5 and args.graph_steps >= 1
