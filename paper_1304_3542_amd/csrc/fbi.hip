@@ -150,9 +150,37 @@ k_fbi_pass1(const double *f0, const double *f1, int nfj, const cplx<R> *__restri
     }
 }
 
+// |psi| in the precision of the path, with one explicit FMA so that every
+// kernel that forms it (the pass-2 epilogue's maximum, the selection, the
+// compaction) rounds it the same way
+template <typename R>
+__device__ __forceinline__ R cabs_r(R re, R im)
+{
+    return sqrt(fma(re, re, im * im));
+}
+
+// Largest |psi_+-| = |psi| / 2 of a workgroup's outputs (f1 = 0: both
+// branches are psi0 / 2) folded into the shot's maximum: a wavefront
+// butterfly, the four wavefronts through LDS, one atomicMax on the bit
+// pattern (non-negative doubles order like their bit patterns).  NaN never
+// wins here; k_count and k_scatter map it to key 0.
+template <typename R>
+__device__ __forceinline__ void fold_branch_max(R best, unsigned long long *maxbits, double *red)
+{
+    double b = (double)best;
+    for (int o = 32; o > 0; o >>= 1) b = fmax(b, __shfl_xor(b, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        atomicMax(maxbits, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
 // ------------------------------------------------------------------ pass 2
 // Psi[sf][j2][l2][c] = d2 * sum_m E2[l2][m] T[sf][k2(j2) + m][c], as a GEMM on the
-// matrix cores (FP32 below; FP64 in k_fbi_pass2_mfma64)
+// matrix cores (FP32 below; FP64 in k_fbi_pass2_mfma64).  With maxbits (f1 = 0,
+// relative threshold) the epilogue also folds the shot's largest |psi_+-|.
 
 // Pass 2 of the mixed path on the matrix cores.  A complex MAC over k is a
 // K = 2 real product: with v_mfma_f32_32x32x2f32 lane l holds A[l % 32][l / 32]
@@ -170,7 +198,7 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_fbi_pass2_mfma(const cplx<float> *__restrict__ T, const cplx<float> *__restrict__ E2,
                  cplx<float> *__restrict__ Psi, int n2, int R2, int qb2, int qs2, int nq2,
-                 int np2, int NC, double d2)
+                 int np2, int NC, double d2, unsigned long long *maxbits)
 {
     __shared__ float2 Es[P2M_K][P2M_T];   // [k][l2]
     __shared__ float2 Ts[P2M_K][P2M_T];   // [k][c]
@@ -245,6 +273,7 @@ k_fbi_pass2_mfma(const cplx<float> *__restrict__ T, const cplx<float> *__restric
     // D[i][j] of a 32 x 32 block: j = lane % 32, i = 8 (r / 4) + 4 (lane / 32) + r % 4
     cplx<float> *out = Psi + ((size_t)sf * nq2 + j2) * np2 * (size_t)NC;
     const float s2 = (float)d2;
+    float best = 0.f;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -254,10 +283,17 @@ k_fbi_pass2_mfma(const cplx<float> *__restrict__ T, const cplx<float> *__restric
                 const int l = l0 + wr * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 const int cc = c0 + wc * 64 + c * 32 + (lane & 31);
                 if (l < np2 && cc < NC) {
-                    out[(size_t)l * NC + cc].re = accr[a][c][r] * s2;
-                    out[(size_t)l * NC + cc].im = acci[a][c][r] * s2;
+                    const float vr = accr[a][c][r] * s2, vi = acci[a][c][r] * s2;
+                    out[(size_t)l * NC + cc].re = vr;
+                    out[(size_t)l * NC + cc].im = vi;
+                    const float m = cabs_r(0.5f * vr, 0.5f * vi);
+                    best = m > best ? m : best;
                 }
             }
+    if (maxbits) {
+        __shared__ double red[4];
+        fold_branch_max(best, maxbits + sf, red);
+    }
 }
 
 // FP64 pass 2 on the matrix cores (v_mfma_f64_16x16x4f64), the same complex
@@ -277,7 +313,7 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256)
 k_fbi_pass2_mfma64(const cplx<double> *__restrict__ T, const cplx<double> *__restrict__ E2,
                    cplx<double> *__restrict__ Psi, int n2, int R2, int qb2, int qs2, int nq2,
-                   int np2, int NC, double d2)
+                   int np2, int NC, double d2, unsigned long long *maxbits)
 {
     __shared__ double2 Es[P2D_K][P2D_T];   // [k][l2]
     __shared__ double2 Ts[P2D_K][P2D_T];   // [k][c]
@@ -349,6 +385,7 @@ k_fbi_pass2_mfma64(const cplx<double> *__restrict__ T, const cplx<double> *__res
         __syncthreads();
     }
     cplx<double> *out = Psi + ((size_t)sf * nq2 + j2) * np2 * (size_t)NC;
+    double best = 0.0;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -358,10 +395,17 @@ k_fbi_pass2_mfma64(const cplx<double> *__restrict__ T, const cplx<double> *__res
                 const int l = l0 + wr * 32 + a * 16 + 4 * r + q;
                 const int cc = c0 + wc * 32 + c * 16 + i;
                 if (l < np2 && cc < NC) {
-                    out[(size_t)l * NC + cc].re = accr[a][c][r] * d2;
-                    out[(size_t)l * NC + cc].im = acci[a][c][r] * d2;
+                    const double vr = accr[a][c][r] * d2, vi = acci[a][c][r] * d2;
+                    out[(size_t)l * NC + cc].re = vr;
+                    out[(size_t)l * NC + cc].im = vi;
+                    const double m = cabs_r(0.5 * vr, 0.5 * vi);
+                    best = m > best ? m : best;
                 }
             }
+    if (maxbits) {
+        __shared__ double red[4];
+        fold_branch_max(best, maxbits + sf, red);
+    }
 }
 
 // --------------------------------------------------- branches and threshold
@@ -459,11 +503,6 @@ __device__ __forceinline__ void cand_psi(const cplx<R> *__restrict__ Psi,
     im = (R)0.5 * (p0.im + sg * r * p1.re);
 }
 
-template <typename R>
-__device__ __forceinline__ R cabs_r(R re, R im)
-{
-    return sqrt(re * re + im * im);
-}
 
 template <typename R>
 __global__ void __launch_bounds__(256)
@@ -644,11 +683,14 @@ __device__ __forceinline__ CmpBlock cmp_block(const CandGeom &G, int nblkb)
     return B;
 }
 
-// per block: kept-above-key count (gt) and equal-key count (eq)
+// per block: kept-above-key count (gt) and equal-key count (eq).  With sym
+// (f1 = 0: psi_+ = psi_- = psi0 / 2, and both branches have the same
+// selection record) only the blocks of branch + run, and each writes its
+// counts for the matching block of branch - too.
 template <typename R>
 __global__ void __launch_bounds__(CMP_BLOCK)
 k_count(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGeom G,
-        const Sel *sel, int64_t *blk_gt, int64_t *blk_eq, int nblkb)
+        const Sel *sel, int64_t *blk_gt, int64_t *blk_eq, int nblkb, int sym)
 {
     __shared__ int red[2][CMP_BLOCK / 64];
     const CmpBlock B = cmp_block(G, nblkb);
@@ -681,6 +723,10 @@ k_count(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGeom
         const size_t at = (size_t)B.s * 2 * nblkb + blockIdx.x;
         blk_gt[at] = tg;
         blk_eq[at] = te;
+        if (sym) {
+            blk_gt[at + nblkb] = tg;
+            blk_eq[at + nblkb] = te;
+        }
     }
 }
 
@@ -773,16 +819,42 @@ __device__ __forceinline__ int block_rank(unsigned long long m, int *wsum, int &
     return base + __popcll(m & ((1ull << lane) - 1ull));
 }
 
+// one kept beam at position pos: mesh node, coefficient, initial state, id
+template <typename R>
+__device__ __forceinline__ void write_beam(const fga_beams &B, int64_t pos, int64_t id, double q1,
+                                           double q2, double p1, double p2, double cre,
+                                           double cim)
+{
+    const int64_t cap = B.capacity;
+    double *f = B.f;
+    f[0 * cap + pos] = q1;
+    f[1 * cap + pos] = q2;
+    f[2 * cap + pos] = p1;
+    f[3 * cap + pos] = p2;
+    f[4 * cap + pos] = cre;
+    f[5 * cap + pos] = cim;
+    const double init[FGA_NSTATE] = {q1, q2, p1, p2, 0.0,
+                                     1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0,    // A = I
+                                     0.0, -1.0, 0.0, 0.0, 0.0, 0.0, 0.0, -1.0,  // B = -i I
+                                     2.0, 0.0};                                 // a = 2
+#pragma unroll
+    for (int k = 0; k < FGA_NSTATE; ++k) f[(size_t)(FGA_F_STATE + k) * cap + pos] = init[k];
+    B.id[pos] = id;
+}
+
 // Compaction in candidate order: per round, wave ballots rank the tied and
 // the kept candidates inside each wavefront and the wavefront totals (LDS)
 // order the wavefronts, so kept beams of one round land at consecutive
-// positions and ties are taken in candidate order.
+// positions and ties are taken in candidate order.  With sym (f1 = 0) only
+// the blocks of branch + run, and every kept candidate is also written as
+// the beam of branch - at the same rank inside the matching block (same
+// coefficient, same initial state, id + Nq Np).
 template <typename R>
 __global__ void __launch_bounds__(CMP_BLOCK)
 k_scatter(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGeom G,
           const Sel *sel, const int64_t *blk_pos, const int64_t *blk_tie, int nblkb,
           fga_beams B, double o1, double o2, double d1, double d2, int qb1, int qb2,
-          int qs1, int qs2, double norm)
+          int qs1, int qs2, double norm, int sym)
 {
     __shared__ int wsum[CMP_BLOCK / 64];
     const CmpBlock C = cmp_block(G, nblkb);
@@ -791,6 +863,7 @@ k_scatter(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGe
     const int64_t cap = B.capacity;
     const size_t at = (size_t)s * 2 * nblkb + blockIdx.x;
     int64_t run = blk_pos[at];
+    int64_t run_m = sym ? blk_pos[at + nblkb] : 0;
     int64_t tie_run = blk_tie[at];
     for (int i = 0; i < CMP_ITEMS; ++i) {
         const int64_t cl = C.first + (int64_t)i * CMP_BLOCK + threadIdx.x;
@@ -806,29 +879,22 @@ k_scatter(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGe
         const bool keep = key > S.key || (tie && tie_run + tr < S.ties);
         tie_run += ntie;
         int nkeep = 0;
-        const int64_t pos = run + block_rank(__ballot(keep), wsum, nkeep);
+        const int rank = block_rank(__ballot(keep), wsum, nkeep);
+        const int64_t pos = run + rank, pos_m = run_m + rank;
         run += nkeep;
-        if (keep && pos < cap) {
+        run_m += nkeep;
+        if (keep && (pos < cap || (sym && pos_m < cap))) {
             int sb, j1, j2, l1, l2;
             int64_t qf;
             cand_index(G, cl, sb, qf, j1, j2, l1, l2);
             const double q1 = o1 + (qb1 + j1 * qs1) * d1, q2 = o2 + (qb2 + j2 * qs2) * d2;
             const double p1 = (l1 - 0.5 * (G.np1 - 1)) * G.dp1;
             const double p2 = (l2 - 0.5 * (G.np2 - 1)) * G.dp2;
-            double *f = B.f;
-            f[0 * cap + pos] = q1;
-            f[1 * cap + pos] = q2;
-            f[2 * cap + pos] = p1;
-            f[3 * cap + pos] = p2;
-            f[4 * cap + pos] = norm * (double)re;
-            f[5 * cap + pos] = norm * (double)im;
-            const double init[FGA_NSTATE] = {q1, q2, p1, p2, 0.0,
-                                             1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0,    // A = I
-                                             0.0, -1.0, 0.0, 0.0, 0.0, 0.0, 0.0, -1.0,  // B = -i I
-                                             2.0, 0.0};                                 // a = 2
-#pragma unroll
-            for (int k = 0; k < FGA_NSTATE; ++k) f[(size_t)(FGA_F_STATE + k) * cap + pos] = init[k];
-            B.id[pos] = (int64_t)s * G.per_shot + cl;
+            const double cre = norm * (double)re, cim = norm * (double)im;
+            const int64_t id = (int64_t)s * G.per_shot + cl;
+            if (pos < cap) write_beam<R>(B, pos, id, q1, q2, p1, p2, cre, cim);
+            if (sym && pos_m < cap)
+                write_beam<R>(B, pos_m, id + G.Nq * G.Np, q1, q2, p1, p2, cre, cim);
         }
     }
 }
@@ -912,6 +978,13 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
     int nq = p.nq1 * p.nq2;
     hipLaunchKernelGGL(k_cq, dim3((nq + 255) / 256), dim3(256), 0, st, fga_velgrid(ctx), g.o1,
                        g.o2, g.d1, g.d2, p.qb1, p.qb2, p.qs1, p.qs2, p.nq1, p.nq2, ctx->cq);
+    // f1 = 0: psi_+ = psi_- = psi0 / 2, so the branch maximum is folded into
+    // pass 2 (relative threshold) and the compaction reads each candidate once
+    // for both branches
+    const int sym = nfj == 1;
+    unsigned long long *fold = (sym && p.top_n == 0) ? ctx->maxbits : nullptr;
+    if (fold)
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, st, ctx->maxbits, nshots);
     dim3 g1((p.np1 + P1_BN - 1) / P1_BN, (g.n2 + P1_BM - 1) / P1_BM, S * p.nq1);
     hipLaunchKernelGGL(k_fbi_pass1<R>, g1, dim3(256), 0, st, f0, f1, nfj,
                        (const cplx<R> *)ctx->E1t, (cplx<R> *)ctx->T, g.n1, g.n2, ctx->R1, p.qb1,
@@ -920,13 +993,13 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
         dim3 g2((unsigned)((NC + P2M_T - 1) / P2M_T), (p.np2 + P2M_T - 1) / P2M_T, S * p.nq2);
         hipLaunchKernelGGL(k_fbi_pass2_mfma, g2, dim3(256), 0, st, (const cplx<float> *)ctx->T,
                            (const cplx<float> *)ctx->E2, (cplx<float> *)ctx->Psi, g.n2, ctx->R2,
-                           p.qb2, p.qs2, p.nq2, p.np2, (int)NC, g.d2);
+                           p.qb2, p.qs2, p.nq2, p.np2, (int)NC, g.d2, fold);
     } else {
         dim3 g2((unsigned)((NC + P2D_T - 1) / P2D_T), (p.np2 + P2D_T - 1) / P2D_T, S * p.nq2);
         hipLaunchKernelGGL(k_fbi_pass2_mfma64, g2, dim3(256), 0, st,
                            (const cplx<double> *)ctx->T, (const cplx<double> *)ctx->E2,
                            (cplx<double> *)ctx->Psi, g.n2, ctx->R2, p.qb2, p.qs2, p.nq2, p.np2,
-                           (int)NC, g.d2);
+                           (int)NC, g.d2, fold);
     }
     if (p.top_n > 0) {
         const int npass = (int)sizeof(R);   // eight bits of the key per pass
@@ -940,21 +1013,25 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
                                nsb, pass, npass);
         }
     } else {
-        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, st, ctx->maxbits, nshots);
-        int gmax = (int)std::min<int64_t>((G.per_shot + 255) / 256, 1024);
-        hipLaunchKernelGGL(k_branch_max<R>, dim3(gmax, nshots), dim3(256), 0, st,
-                           (const cplx<R> *)ctx->Psi, ctx->cq, G, ctx->maxbits);
+        if (!fold) {
+            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, st, ctx->maxbits, nshots);
+            int gmax = (int)std::min<int64_t>((G.per_shot + 255) / 256, 1024);
+            hipLaunchKernelGGL(k_branch_max<R>, dim3(gmax, nshots), dim3(256), 0, st,
+                               (const cplx<R> *)ctx->Psi, ctx->cq, G, ctx->maxbits);
+        }
         hipLaunchKernelGGL(k_sel_threshold<R>, dim3((nsb + 63) / 64), dim3(64), 0, st,
                            ctx->maxbits, p.tau, sel, nsb);
     }
-    hipLaunchKernelGGL(k_count<R>, dim3(nblk, nshots), dim3(CMP_BLOCK), 0, st,
-                       (const cplx<R> *)ctx->Psi, ctx->cq, G, sel, blk_kept, blk_eq, nblkb);
+    const int nblk_run = sym ? nblkb : nblk;
+    hipLaunchKernelGGL(k_count<R>, dim3(nblk_run, nshots), dim3(CMP_BLOCK), 0, st,
+                       (const cplx<R> *)ctx->Psi, ctx->cq, G, sel, blk_kept, blk_eq, nblkb, sym);
     hipLaunchKernelGGL(k_scan_ties, dim3(nsb), dim3(1024), 0, st, sel, blk_kept, blk_eq, nblkb);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, blk_kept, (int64_t)nblk_all,
                        nblk, nshots, beams->offsets, beams->capacity, ctx->status);
-    hipLaunchKernelGGL(k_scatter<R>, dim3(nblk, nshots), dim3(CMP_BLOCK), 0, st,
+    hipLaunchKernelGGL(k_scatter<R>, dim3(nblk_run, nshots), dim3(CMP_BLOCK), 0, st,
                        (const cplx<R> *)ctx->Psi, ctx->cq, G, sel, blk_kept, blk_eq, nblkb,
-                       *beams, g.o1, g.o2, g.d1, g.d2, p.qb1, p.qb2, p.qs1, p.qs2, ctx->norm);
+                       *beams, g.o1, g.o2, g.d1, g.d2, p.qb1, p.qb2, p.qs1, p.qs2, ctx->norm,
+                       sym);
     FGA_HIP(ctx, hipGetLastError());
     return FGA_OK;
 }
