@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large2048",
                     help="headline workload (large2048: the largest single-GPU configuration)")
+    ap.add_argument("--precision", default="mixed_split", choices=["mixed", "mixed_split"],
+                    help="reduced-precision path of the headline (mixed_split: the splat's "
+                         "products on the FP16 matrix cores from hi/lo splits)")
     ap.add_argument("--graph-steps", type=int, default=5,
                     help="timed replays of the headline step captured as one HIP graph")
     ap.add_argument("--point-steps", type=int, default=10,
@@ -667,7 +670,7 @@ WORKLOAD_TEXT = {
 }
 
 
-def measure(name, steps, warmup, fp64_steps, graph_steps):
+def measure(name, steps, warmup, fp64_steps, graph_steps, precision="mixed"):
     """The whole step of one single-shot workload in mixed precision (timed
     steps on the host clock and per stage with HIP events, graph replays),
     the FP64 GPU path on the same input, the mixed field's error against it
@@ -678,7 +681,7 @@ def measure(name, steps, warmup, fp64_steps, graph_steps):
     Wd = fi.workload(name, "fp64")
     cand = 2 * W.params.nq1 * W.params.nq2 * W.params.np1 * W.params.np2 * W.nshots
 
-    mixed = Path(W, "mixed", min(cand, 4_000_000))
+    mixed = Path(W, precision, min(cand, 4_000_000))
     nb = mixed.fit_capacity()
     ms_step, stage_ms, per_step = time_path(mixed, steps, warmup)
     u_mixed = mixed.u.cpu().numpy()
@@ -795,7 +798,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     name = args.workload
-    r = measure(name, args.steps, args.warmup, args.fp64_steps, args.graph_steps)
+    r = measure(name, args.steps, args.warmup, args.fp64_steps, args.graph_steps,
+                args.precision)
     head = summary(name, r, args.steps, args.warmup)
     out = {
         "metric": "beams/s end-to-end (FBI+trace+sum) at rel-L2<=1e-5 vs FP64; adjoint ms/iter",
@@ -820,7 +824,7 @@ def main():
     Wd, nb = r["Wd"], r["nb"]
     del r
     if name != "point512" and args.point_steps > 0:
-        rp = measure("point512", args.point_steps, 1, 1, args.point_steps)
+        rp = measure("point512", args.point_steps, 1, 1, args.point_steps, args.precision)
         out["point512"] = summary("point512", rp, args.point_steps, 1)
         u_point = rp["u_mixed"]
         del rp

@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libfga.so")
 
 FGA_OK, FGA_EINVAL, FGA_ENOMEM, FGA_ECAPACITY, FGA_EHIP, FGA_ENUMERIC, FGA_ESTATE = (
     0, -1, -2, -3, -4, -5, -6)
-FGA_FP64, FGA_MIXED = 0, 1
+FGA_FP64, FGA_MIXED, FGA_MIXED_SPLIT = 0, 1, 2
+PRECISIONS = {"fp64": FGA_FP64, "mixed": FGA_MIXED, "mixed_split": FGA_MIXED_SPLIT}
 FGA_NSTATE, FGA_NFIELD, FGA_F_STATE = 23, 29, 6
 
 STATUS_NAMES = {0: "FGA_OK", -1: "FGA_EINVAL", -2: "FGA_ENOMEM", -3: "FGA_ECAPACITY",
@@ -315,7 +316,7 @@ class FGA:
         self.params = params
         self.precision = precision
         self.max_shots = max_shots
-        self.ctx = fga_create(grid, params, FGA_FP64 if precision == "fp64" else FGA_MIXED,
+        self.ctx = fga_create(grid, params, PRECISIONS[precision],
                               max_shots, stream)
 
     def close(self):

@@ -140,7 +140,7 @@ extern "C" fga_status fga_create(fga_ctx **out, const fga_grid *g, const fga_par
 {
     if (!out || !g || !p) return fga_fail(nullptr, FGA_EINVAL, "null argument to fga_create");
     *out = nullptr;
-    if (precision != FGA_FP64 && precision != FGA_MIXED)
+    if (precision != FGA_FP64 && precision != FGA_MIXED && precision != FGA_MIXED_SPLIT)
         return fga_fail(nullptr, FGA_EINVAL, "unknown precision %d", precision);
     if (max_shots < 1 || max_shots > 65535)
         return fga_fail(nullptr, FGA_EINVAL, "max_shots must lie in [1, 65535]");
@@ -176,6 +176,7 @@ extern "C" fga_status fga_create(fga_ctx **out, const fga_grid *g, const fga_par
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->cq, sizeof(double) * p->nq1 * p->nq2);
     if (e == hipSuccess)
         e = hipMalloc((void **)&ctx->maxbits, sizeof(unsigned long long) * max_shots);
+    if (e == hipSuccess) e = hipMalloc((void **)&ctx->wmax, sizeof(unsigned) * max_shots);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->status, 0, 2 * sizeof(int64_t), ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
@@ -199,7 +200,7 @@ extern "C" fga_status fga_destroy(fga_ctx *ctx)
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-    void *bufs[] = {ctx->c, ctx->cpad, ctx->ccoef, ctx->status, ctx->cq, ctx->maxbits, ctx->E1t, ctx->E2,
+    void *bufs[] = {ctx->c, ctx->cpad, ctx->ccoef, ctx->status, ctx->cq, ctx->maxbits, ctx->wmax, ctx->E1t, ctx->E2,
                     ctx->T, ctx->Psi, ctx->blk, ctx->partial, ctx->srec, ctx->sbox,
                     ctx->adj_scratch, ctx->adj_psib, ctx->rec_shape, ctx->E1tt, ctx->trace_part, ctx->bin,
                     ctx->det_log, ctx->det_sort, ctx->det_cell, ctx->det_cqc, ctx->det_lam};
@@ -594,8 +595,8 @@ extern "C" fga_status fga_autotune(fga_ctx *ctx, const fga_beams *beams, int32_t
     }
     const int mixed[] = {4, 8, 16, 32, 64, 128};
     const int fp64[] = {1, 2, 4, 8, 16};
-    const int *cand = ctx->prec == FGA_MIXED ? mixed : fp64;
-    int ncand = ctx->prec == FGA_MIXED ? 6 : 5;
+    const int *cand = ctx->prec != FGA_FP64 ? mixed : fp64;
+    int ncand = ctx->prec != FGA_FP64 ? 6 : 5;
     hipEvent_t e0, e1;
     FGA_HIP(ctx, hipEventCreate(&e0));
     FGA_HIP(ctx, hipEventCreate(&e1));

@@ -365,6 +365,106 @@ k_splat_binned(SplatArgs A, BinArgs B, const SplatRec *__restrict__ rec)
     }
 }
 
+// The binned splat with FP16 hi/lo split products (FGA_MIXED_SPLIT): the
+// same work items, records and partial tiles as k_splat_binned; the beams of
+// an item are taken two at a time, the lower half of the wavefront forming
+// the factors of the first and the upper half those of the second (an odd
+// last beam leaves the upper half zero).  U is scaled by 2^ks per shot with
+// max |C a| 2^ks < 2^14, and the FP64 fold multiplies by 2^-ks (exact).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_splat_binned_split(SplatArgs A, BinArgs B, const SplatRec *__restrict__ rec)
+{
+    __shared__ SplatRec stage_rec[4][64];
+    SplatRec *st = stage_rec[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63;
+    const int h = lane >> 5, li = lane & 31;
+    const int it = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const float hl2e = (float)A.half_inv_eps * 1.4426950408889634f;
+    if (it < (int)B.meta[1]) {
+        const BinItem item = B.items[it];
+        const int shot = item.tile / B.ntiles;
+        const int t = item.tile % B.ntiles;
+        const int X0 = (t % A.ntile1) * SP_T, Z0 = (t / A.ntile1) * SP_T;
+        const int i1a = X0 + li, i2a = Z0 + li;
+        const double x1s[2] = {A.o1 + i1a * A.d1, A.o1 + (i1a + 32) * A.d1};
+        const double x2s[2] = {A.o2 + i2a * A.d2, A.o2 + (i2a + 32) * A.d2};
+        // the shot's power of two
+        const float wm = __uint_as_float(A.wmax[shot]);
+        int ks = 0;
+        if (wm > 0.f && wm <= 3.0e38f) {
+            int e;
+            (void)frexpf(wm, &e);      // wm < 2^e
+            ks = 14 - e;
+        }
+        const float wsc = ldexpf(1.f, ks);
+        const double inv = ldexp(1.0, -ks);
+        floatx16 acc00, acc01, acc10, acc11;
+        double acc64[4][16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            acc00[r] = acc01[r] = acc10[r] = acc11[r] = 0.f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc64[q][r] = 0.0;
+        }
+        const int32_t *lst = B.list + item.start;
+        int32_t b_next = lane < item.len ? lst[lane] : 0;
+        int chunks = 0;
+        for (int k0 = 0; k0 < item.len; k0 += 64) {
+            const int nk = min(64, item.len - k0);
+            const int32_t b = b_next;
+            if (k0 + 64 + lane < item.len) b_next = lst[k0 + 64 + lane];
+            if (lane < nk) {
+                const float4 *src = reinterpret_cast<const float4 *>(rec + b);
+                float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
+                float4 *dst = reinterpret_cast<float4 *>(st + lane);
+                dst[0] = q0;
+                dst[1] = q1;
+                dst[2] = q2;
+                dst[3] = q3;
+            }
+            __builtin_amdgcn_wave_barrier();
+            // beam 2 p + h of the chunk in this half
+            const int npair = (nk + 1) >> 1;
+            for (int pp = 0; pp < npair; ++pp) {
+                const int kk = 2 * pp + h;
+                const SplatRec &r = st[min(kk, nk - 1)];
+                const SplitFrags fr = beam_split(r, kk < nk, r.car * wsc, r.cai * wsc, i1a, x1s,
+                                                 i2a, x2s, hl2e);
+                tile_update_split(fr, acc00, acc01, acc10, acc11);
+            }
+            __builtin_amdgcn_wave_barrier();
+            // fold the FP32 sums (256 beams at most) into FP64
+            if (++chunks == 4) {
+                chunks = 0;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    acc64[0][k] += (double)acc00[k] * inv;
+                    acc64[1][k] += (double)acc01[k] * inv;
+                    acc64[2][k] += (double)acc10[k] * inv;
+                    acc64[3][k] += (double)acc11[k] * inv;
+                    acc00[k] = acc01[k] = acc10[k] = acc11[k] = 0.f;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            acc64[0][k] += (double)acc00[k] * inv;
+            acc64[1][k] += (double)acc01[k] * inv;
+            acc64[2][k] += (double)acc10[k] * inv;
+            acc64[3][k] += (double)acc11[k] * inv;
+        }
+        double *out = A.partial + (size_t)it * SP_T * SP_T;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int row = 32 * (q >> 1) + 8 * (k >> 2) + 4 * (lane >> 5) + (k & 3);
+                const int col = 32 * (q & 1) + (lane & 31);
+                out[row * SP_T + col] = acc64[q][k];
+            }
+    }
+}
+
 // u[s][i2][i1] = the sum of the partial tiles of its tile, in item order
 __global__ void k_splat_reduce_binned(SplatArgs A, BinArgs B, double *__restrict__ u)
 {
@@ -464,8 +564,12 @@ fga_status fga_launch_splat_binned(fga_ctx *ctx, const fga_beams *beams, int nsh
     hipLaunchKernelGGL(k_bin_scan_items, dim3(1), dim3(1024), 0, ctx->stream, B);
     hipLaunchKernelGGL(k_bin_fill, dim3(cgrid), dim3(64), (size_t)T * sizeof(int64_t),
                        ctx->stream, B);
-    hipLaunchKernelGGL(k_splat_binned, dim3((max_items + 3) / 4), dim3(256), 0, ctx->stream, A,
-                       B, (const SplatRec *)rec);
+    if (A.wmax)
+        hipLaunchKernelGGL(k_splat_binned_split, dim3((max_items + 3) / 4), dim3(256), 0,
+                           ctx->stream, A, B, (const SplatRec *)rec);
+    else
+        hipLaunchKernelGGL(k_splat_binned, dim3((max_items + 3) / 4), dim3(256), 0, ctx->stream,
+                           A, B, (const SplatRec *)rec);
     hipLaunchKernelGGL(k_splat_reduce_binned, dim3(1024), dim3(256), 0, ctx->stream, A, B, u);
     FGA_HIP(ctx, hipGetLastError());
     return FGA_OK;

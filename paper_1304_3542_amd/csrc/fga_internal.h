@@ -37,6 +37,7 @@ struct fga_ctx {
     size_t T_bytes, Psi_bytes;
     double *cq;            // c(q) [nq2][nq1]
     unsigned long long *maxbits;   // per-shot max |psi| (double bits)
+    unsigned *wmax;        // per-shot max |C a| (FP32 bits), FGA_MIXED_SPLIT splat
     int64_t *blk;          // per-block counts / offsets of the compaction
     size_t blk_elems;
 

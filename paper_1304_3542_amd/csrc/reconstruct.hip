@@ -175,37 +175,70 @@ k_splat64(SplatArgs A)
     }
 }
 
+__global__ void k_zero_u32(unsigned *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 __global__ void __launch_bounds__(256)
 k_splat_prep(SplatArgs A, int nshots, SplatRec *__restrict__ rec, short4 *__restrict__ box)
 {
     const int64_t nb = A.offsets[nshots];
     const int64_t cap = A.cap;
     const double inv2pe = A.inv_eps * 0.15915494309189535;
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
-         b += (int64_t)gridDim.x * blockDim.x) {
-        const double *p = A.f + b;
-        double Q1 = p[(FGA_F_STATE + 0) * cap], Q2 = p[(FGA_F_STATE + 1) * cap];
-        double P1 = p[(FGA_F_STATE + 2) * cap], P2 = p[(FGA_F_STATE + 3) * cap];
-        double S = p[(FGA_F_STATE + 4) * cap];
-        double ar = p[(FGA_F_STATE + 21) * cap], ai = p[(FGA_F_STATE + 22) * cap];
-        double Cr = p[4 * cap], Ci = p[5 * cap];
-        BeamBox bx = beam_box(Q1, Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
-        SplatRec r;
-        r.B1 = P1 * inv2pe;
-        r.A1 = (S - P1 * Q1) * inv2pe;
-        r.B2 = P2 * inv2pe;
-        r.A2 = -P2 * Q2 * inv2pe;
-        r.Q1 = Q1;
-        r.Q2 = Q2;
-        r.car = (float)(Cr * ar - Ci * ai);
-        r.cai = (float)(Cr * ai + Ci * ar);
-        // empty boxes stay empty after narrowing (lo > hi)
-        r.lo1 = (short)min(bx.lo1, A.n1);
-        r.hi1 = (short)max(bx.hi1, -1);
-        r.lo2 = (short)min(bx.lo2, A.n2);
-        r.hi2 = (short)max(bx.hi2, -1);
-        rec[b] = r;
-        box[b] = make_short4(r.lo1, r.hi1, r.lo2, r.hi2);
+    // the loop bound is uniform over the workgroup, so every lane takes part
+    // in the wavefront reductions below
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nb;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = base + threadIdx.x;
+        unsigned w = 0u;          // |C a| as FP32 bits (0 for lanes past the end)
+        int s = 0x7fffffff;
+        if (b < nb) {
+            const double *p = A.f + b;
+            double Q1 = p[(FGA_F_STATE + 0) * cap], Q2 = p[(FGA_F_STATE + 1) * cap];
+            double P1 = p[(FGA_F_STATE + 2) * cap], P2 = p[(FGA_F_STATE + 3) * cap];
+            double S = p[(FGA_F_STATE + 4) * cap];
+            double ar = p[(FGA_F_STATE + 21) * cap], ai = p[(FGA_F_STATE + 22) * cap];
+            double Cr = p[4 * cap], Ci = p[5 * cap];
+            BeamBox bx = beam_box(Q1, Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
+            SplatRec r;
+            r.B1 = P1 * inv2pe;
+            r.A1 = (S - P1 * Q1) * inv2pe;
+            r.B2 = P2 * inv2pe;
+            r.A2 = -P2 * Q2 * inv2pe;
+            r.Q1 = Q1;
+            r.Q2 = Q2;
+            r.car = (float)(Cr * ar - Ci * ai);
+            r.cai = (float)(Cr * ai + Ci * ar);
+            // empty boxes stay empty after narrowing (lo > hi)
+            r.lo1 = (short)min(bx.lo1, A.n1);
+            r.hi1 = (short)max(bx.hi1, -1);
+            r.lo2 = (short)min(bx.lo2, A.n2);
+            r.hi2 = (short)max(bx.hi2, -1);
+            rec[b] = r;
+            box[b] = make_short4(r.lo1, r.hi1, r.lo2, r.hi2);
+            if (A.wmax) {
+                s = (int)(A.id[b] / A.per_shot);
+                w = __float_as_uint(sqrtf(r.car * r.car + r.cai * r.cai));
+            }
+        }
+        if (A.wmax) {
+            // the shot's largest |C a| (non-negative floats order like their bit
+            // patterns): one atomic per wavefront when it holds a single shot
+            int slo = s, shi = s == 0x7fffffff ? -1 : s;
+            unsigned wm = w;
+            for (int o = 32; o > 0; o >>= 1) {
+                slo = min(slo, __shfl_xor(slo, o));
+                shi = max(shi, __shfl_xor(shi, o));
+                wm = max(wm, (unsigned)__shfl_xor((int)wm, o));
+            }
+            if (slo == shi) {
+                if ((threadIdx.x & 63) == 0) atomicMax(&A.wmax[slo], wm);
+            } else if (b < nb) {
+                atomicMax(&A.wmax[s], w);
+            }
+        }
     }
 }
 
@@ -335,7 +368,7 @@ fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nsho
     const fga_grid &g = ctx->g;
     int nt1 = (g.n1 + SP_T - 1) / SP_T, nt2 = (g.n2 + SP_T - 1) / SP_T;
     int tiles = nt1 * nt2;
-    bool mfma = ctx->prec == FGA_MIXED;
+    bool mfma = ctx->prec != FGA_FP64;
     SplatArgs A{};
     A.f = beams->f;
     A.offsets = beams->offsets;
@@ -360,12 +393,21 @@ fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nsho
         rc = fga_ensure(ctx, &ctx->sbox, &ctx->sbox_bytes,
                         (size_t)beams->capacity * sizeof(short4), "splat boxes");
         if (rc != FGA_OK) return rc;
+        // FP16 split products: the record pass also gathers each shot's
+        // largest |C a| for the binned splat's scaling
+        const bool binned = fga_splat_binned_fits(ctx, nshots);
+        if (binned && ctx->prec == FGA_MIXED_SPLIT) {
+            A.id = beams->id;
+            A.per_shot = 2LL * ctx->p.nq1 * ctx->p.nq2 * ctx->p.np1 * ctx->p.np2;
+            A.wmax = ctx->wmax;
+            hipLaunchKernelGGL(k_zero_u32, dim3((nshots + 255) / 256), dim3(256), 0, ctx->stream,
+                               ctx->wmax, nshots);
+        }
         hipLaunchKernelGGL(k_splat_prep, dim3(2 * ctx->num_cu), dim3(256), 0, ctx->stream, A,
                            nshots, (SplatRec *)ctx->srec, (short4 *)ctx->sbox);
         // beams binned per tile and split into equal work items, unless the
         // tile count exceeds the binning's LDS counters
-        if (fga_splat_binned_fits(ctx, nshots))
-            return fga_launch_splat_binned(ctx, beams, nshots, u, A, ctx->srec, ctx->sbox);
+        if (binned) return fga_launch_splat_binned(ctx, beams, nshots, u, A, ctx->srec, ctx->sbox);
     }
     // every tile scans a slice of its shot's beams: enough slices for about
     // per_cu work units per CU (mixed: one wavefront per unit, so that the

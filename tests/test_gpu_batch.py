@@ -67,11 +67,11 @@ def test_batched_matches_oracle():
         assert rel_l2(u.cpu().numpy()[s], oracle.reconstruct(b, g, p, shot=s)) <= 1e-10
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_split"])
 def test_graph_replay_is_bitwise_and_picks_up_inputs(precision):
     import torch
     g, p, c, f0 = shots_case(ns=4, seed=53)
-    if precision == "mixed":
+    if precision != "fp64":
         p = p.replace(tau_fbi=1e-8, tau_win=1e-8)
     ctx, beams, f0t, u, stream = run(g, p, c, f0, precision)
     eager = u.clone()

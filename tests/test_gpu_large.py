@@ -42,15 +42,17 @@ def test_large_mixed_matches_fp64():
     Wd = fi.workload("large2048", "fp64")
     Wm = fi.workload("large2048", "mixed")
     nb64, ids64, u64 = run(Wd, "fp64")
-    nbm, idsm, um = run(Wm, "mixed")
-    print(f"large2048: FP64 beams {nb64}, mixed beams {nbm}", flush=True)
+    print(f"large2048: FP64 beams {nb64}", flush=True)
     assert 1e7 < nb64 < 2e8
-    # beams whose |psi| sits within rounding of the threshold may differ
-    flips = len(np.setxor1d(ids64, idsm))
-    assert flips <= 1e-3 * nb64, flips
-    rel = np.linalg.norm(um - u64) / np.linalg.norm(u64)
-    print(f"large2048: mixed vs FP64 rel-L2 {rel:.3e}, threshold flips {flips}", flush=True)
-    assert rel <= 1e-5
+    for prec in ("mixed", "mixed_split"):
+        nbm, idsm, um = run(Wm, prec)
+        # beams whose |psi| sits within rounding of the threshold may differ
+        flips = len(np.setxor1d(ids64, idsm))
+        assert flips <= 1e-3 * nb64, flips
+        rel = np.linalg.norm(um - u64) / np.linalg.norm(u64)
+        print(f"large2048: {prec} beams {nbm}, vs FP64 rel-L2 {rel:.3e}, threshold flips "
+              f"{flips}", flush=True)
+        assert rel <= 1e-5
 
 
 def test_large_fp64_sampled_against_oracle():

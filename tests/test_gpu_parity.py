@@ -46,11 +46,14 @@ def test_propagate_and_reconstruct_fp64_match_oracle(small):
     assert rel_l2(r["u"][0], small["u"]) <= FP64_TOL
 
 
-def test_mixed_path_within_1e5(small):
+@pytest.mark.parametrize("precision", ["mixed", "mixed_split"])
+def test_mixed_path_within_1e5(small, precision):
     g, p = small["g"], small["p"]
-    r = gpu_run(g, mixed_params(p), small["c"], small["f0"], small["f1"], "mixed")
+    r = gpu_run(g, mixed_params(p), small["c"], small["f0"], small["f1"], precision)
     assert r["status"] == 0
-    assert rel_l2(r["u"][0], small["u"]) <= MIXED_TOL
+    err = rel_l2(r["u"][0], small["u"])
+    print(f"{precision}: rel-L2 vs oracle {err:.2e}", flush=True)
+    assert err <= MIXED_TOL
 
 
 def test_multishot_offsets_and_fields():
@@ -215,15 +218,19 @@ def test_full_size_fp64_against_stored_oracle_values(name):
     assert rel_l2(u.ravel()[z["nodes"]], z["u"]) <= FP64_TOL
 
 
-def test_full_size_mixed_against_stored_oracle_values():
+@pytest.mark.parametrize("precision", ["mixed", "mixed_split"])
+def test_full_size_mixed_against_stored_oracle_values(precision):
     z = _golden("point512")
     W = fi.workload("point512", "mixed")
-    nb, ids, coef, state, u = _full_run(W, "mixed", int(z["nbeams"]) + 4096)
+    nb, ids, coef, state, u = _full_run(W, precision, int(z["nbeams"]) + 4096)
     assert abs(nb - int(z["nbeams"])) <= 1e-3 * int(z["nbeams"])
-    assert rel_l2(u.ravel()[z["nodes"]], z["u"]) <= MIXED_TOL
+    err = rel_l2(u.ravel()[z["nodes"]], z["u"])
+    print(f"point512 {precision}: rel-L2 vs stored oracle values {err:.2e}", flush=True)
+    assert err <= MIXED_TOL
 
 
-def test_full_size_graph_replays_match_eager_and_oracle():
+@pytest.mark.parametrize("precision", ["mixed", "mixed_split"])
+def test_full_size_graph_replays_match_eager_and_oracle(precision):
     """point512 (mixed) in the timed benchmark's graph form: the whole step
     captured once and replayed, with eager work and synchronisations between
     the replays; every replay equals the eager step bit for bit (beams and
@@ -234,7 +241,7 @@ def test_full_size_graph_replays_match_eager_and_oracle():
     W = fi.workload("point512", "mixed")
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        ctx = fga.FGA(W.grid, W.params, "mixed")
+        ctx = fga.FGA(W.grid, W.params, precision)
         ctx.set_velocity(torch.from_numpy(W.c).cuda())
         f0 = torch.from_numpy(np.ascontiguousarray(W.f0)).cuda()
         beams = fga.Beams(int(z["nbeams"]) + 4096, 1)
