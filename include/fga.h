@@ -68,13 +68,15 @@ typedef enum {
     FGA_FP64 = 0,   /* every stage in double precision                       */
     FGA_MIXED = 1,  /* FP32 FBI and splat (phase reduced mod 2 pi in FP64),
                        FP64 ray/amplitude integration                        */
-    FGA_MIXED_SPLIT = 2  /* as FGA_MIXED, with the splat's FP32 products
-                       formed on the FP16 matrix cores from hi/lo splits of
-                       both factors (x = fp16(x) + fp16(x - fp16(x)), about
-                       2^-22 relative; U scaled per shot by a power of two to
-                       stay in the FP16 range) and accumulated in FP32 then
-                       FP64.  Beyond 8192 (shot, tile) pairs the splat keeps
-                       the FP32 products.                                    */
+    FGA_MIXED_SPLIT = 2  /* as FGA_MIXED, with the FP32 products of FBI
+                       pass 2 and of the splat formed on the FP16 matrix
+                       cores from hi/lo splits of both operands
+                       (x = fp16(x) + fp16(x - fp16(x)), about 2^-22
+                       relative; the pass-1 output and the splat's U scaled
+                       per shot by a power of two to stay in the FP16 range)
+                       and accumulated in FP32 (then FP64 in the splat).
+                       Beyond 8192 (shot, tile) pairs the splat keeps the
+                       FP32 products.                                        */
 } fga_precision;
 
 /* Node-centred grid: x1 = o1 + i1*d1 (i1 < n1), x2 = o2 + i2*d2 (i2 < n2),

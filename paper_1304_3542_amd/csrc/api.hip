@@ -177,6 +177,7 @@ extern "C" fga_status fga_create(fga_ctx **out, const fga_grid *g, const fga_par
     if (e == hipSuccess)
         e = hipMalloc((void **)&ctx->maxbits, sizeof(unsigned long long) * max_shots);
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->wmax, sizeof(unsigned) * max_shots);
+    if (e == hipSuccess) e = hipMalloc((void **)&ctx->tmax, sizeof(unsigned) * 2 * max_shots);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->status, 0, 2 * sizeof(int64_t), ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
@@ -200,7 +201,7 @@ extern "C" fga_status fga_destroy(fga_ctx *ctx)
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-    void *bufs[] = {ctx->c, ctx->cpad, ctx->ccoef, ctx->status, ctx->cq, ctx->maxbits, ctx->wmax, ctx->E1t, ctx->E2,
+    void *bufs[] = {ctx->c, ctx->cpad, ctx->ccoef, ctx->status, ctx->cq, ctx->maxbits, ctx->wmax, ctx->tmax, ctx->E1t, ctx->E2,
                     ctx->T, ctx->Psi, ctx->blk, ctx->partial, ctx->srec, ctx->sbox,
                     ctx->adj_scratch, ctx->adj_psib, ctx->rec_shape, ctx->E1tt, ctx->trace_part, ctx->bin,
                     ctx->det_log, ctx->det_sort, ctx->det_cell, ctx->det_cqc, ctx->det_lam};

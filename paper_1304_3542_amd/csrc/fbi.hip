@@ -79,7 +79,7 @@ template <typename R>
 __global__ void __launch_bounds__(256)
 k_fbi_pass1(const double *f0, const double *f1, int nfj, const cplx<R> *__restrict__ E1t,
             cplx<R> *__restrict__ T, int n1, int n2, int R1, int qb1, int qs1, int nq1,
-            int np1, double d1)
+            int np1, double d1, unsigned *tmax)
 {
     __shared__ R As[P1_BK][P1_BM + 1];
     __shared__ cplx<R> Bs[P1_BK][P1_BN];
@@ -135,6 +135,7 @@ k_fbi_pass1(const double *f0, const double *f1, int nfj, const cplx<R> *__restri
         __syncthreads();
     }
     const int NC = nq1 * np1;
+    float big = 0.f;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int i2 = r0 + tm + 16 * i;
@@ -144,9 +145,22 @@ k_fbi_pass1(const double *f0, const double *f1, int nfj, const cplx<R> *__restri
         for (int j = 0; j < 4; ++j) {
             const int l = l0 + tn + 16 * j;
             if (l >= np1) continue;
-            out[l].re = accr[i][j] * (R)d1;
-            out[l].im = acci[i][j] * (R)d1;
+            const R vr = accr[i][j] * (R)d1, vi = acci[i][j] * (R)d1;
+            out[l].re = vr;
+            out[l].im = vi;
+            big = fmaxf(big, fmaxf(fabsf((float)vr), fabsf((float)vi)));
         }
+    }
+    if (tmax) {
+        // largest |Re T|, |Im T| of the (shot, part): one atomic per workgroup
+        // (non-negative floats order like their bit patterns)
+        __shared__ float red[4];
+        for (int o = 32; o > 0; o >>= 1) big = fmaxf(big, __shfl_xor(big, o));
+        if ((t & 63) == 0) red[t >> 6] = big;
+        __syncthreads();
+        if (t == 0)
+            atomicMax(&tmax[sf], __float_as_uint(fmaxf(fmaxf(red[0], red[1]),
+                                                       fmaxf(red[2], red[3]))));
     }
 }
 
@@ -273,6 +287,146 @@ k_fbi_pass2_mfma(const cplx<float> *__restrict__ T, const cplx<float> *__restric
     // D[i][j] of a 32 x 32 block: j = lane % 32, i = 8 (r / 4) + 4 (lane / 32) + r % 4
     cplx<float> *out = Psi + ((size_t)sf * nq2 + j2) * np2 * (size_t)NC;
     const float s2 = (float)d2;
+    float best = 0.f;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int l = l0 + wr * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int cc = c0 + wc * 64 + c * 32 + (lane & 31);
+                if (l < np2 && cc < NC) {
+                    const float vr = accr[a][c][r] * s2, vi = acci[a][c][r] * s2;
+                    out[(size_t)l * NC + cc].re = vr;
+                    out[(size_t)l * NC + cc].im = vi;
+                    const float m = cabs_r(0.5f * vr, 0.5f * vi);
+                    best = m > best ? m : best;
+                }
+            }
+    if (maxbits) {
+        __shared__ double red[4];
+        fold_branch_max(best, maxbits + sf, red);
+    }
+}
+
+// Pass 2 of FGA_MIXED_SPLIT on the FP16 matrix cores: every FP32 operand x
+// is staged in LDS as x_hi = fp16(x), x_lo = fp16(x - x_hi) (both rounded to
+// nearest, x = x_hi + x_lo to about 2^-22 relative); T is first scaled by the
+// power of two 2^ks that puts the (shot, part)'s largest component in
+// [2^13, 2^14), so both splits stay in the FP16 range (|E| <= 1).  With
+// v_mfma_f32_32x32x16_f16 lane l supplies A[l % 32][8 (l / 32) + t] and
+// B[8 (l / 32) + t][l % 32] in slot t, so the lower half of the wavefront
+// carries window row m and the upper half row m + 1, eight k slots each as
+// four (Re, Im) pairs:
+//   Re Psi:  A = (Er, -Ei)_hi x2, (Er, -Ei)_lo x2;  B = (Tr, Ti)_hi, _lo, _hi, _lo
+//   Im Psi:  A = (Ei,  Er)_hi x2, (Ei,  Er)_lo x2;  the same B
+// whose products add up to Re(E T) and Im(E T) exactly in FP32.  (Er, -Ei)
+// flips the sign bit of the upper half; (Ei, Er) swaps the halves.  Tiles and
+// staging as in k_fbi_pass2_mfma; the epilogue multiplies by d2 2^-ks.
+__device__ __forceinline__ uint2 split_h2(float x, float y)
+{
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const h2 h = __builtin_convertvector((f2){x, y}, h2);
+    const unsigned hi = __builtin_bit_cast(unsigned, h);
+    const float hx = (float)__builtin_bit_cast(_Float16, (unsigned short)(hi & 0xffffu));
+    const float hy = (float)__builtin_bit_cast(_Float16, (unsigned short)(hi >> 16));
+    const h2 l = __builtin_convertvector((f2){x - hx, y - hy}, h2);
+    return make_uint2(hi, __builtin_bit_cast(unsigned, l));
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_fbi_pass2_split(const cplx<float> *__restrict__ T, const cplx<float> *__restrict__ E2,
+                  cplx<float> *__restrict__ Psi, int n2, int R2, int qb2, int qs2, int nq2,
+                  int np2, int NC, double d2, const unsigned *__restrict__ tmax,
+                  unsigned long long *maxbits)
+{
+    typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+    typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
+    __shared__ uint2 Es[P2M_K][P2M_T];   // [k][l2]: (Er, Ei) hi, lo
+    __shared__ uint2 Ts[P2M_K][P2M_T];   // [k][c]:  (Tr, Ti) hi, lo
+    const int W2 = 2 * R2 + 1;
+    const int sfj = blockIdx.z;
+    const int sf = sfj / nq2, j2 = sfj % nq2;
+    const int k2 = qb2 + j2 * qs2;
+    const int mlo = max(-R2, -k2), mhi = min(R2, n2 - 1 - k2);
+    const int K = mhi - mlo + 1;
+    const int c0 = blockIdx.x * P2M_T, l0 = blockIdx.y * P2M_T;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    const int wr = wv >> 1, wc = wv & 1;
+    const int i = lane & 31, h = lane >> 5;
+    // the (shot, part)'s power of two
+    const float tm = __uint_as_float(tmax[sf]);
+    int ks = 0;
+    if (tm > 0.f && tm <= 3.0e38f) {
+        int e;
+        (void)frexpf(tm, &e);   // tm < 2^e
+        ks = 14 - e;
+    }
+    const float tsc = ldexpf(1.f, ks);
+    const cplx<float> *Tb = T + (size_t)sf * n2 * NC;
+    floatx16 accr[2][2], acci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) accr[a][b][r] = acci[a][b][r] = 0.f;
+    for (int kk = 0; kk < K; kk += P2M_K) {
+        for (int e = t; e < P2M_T * P2M_K; e += 256) {
+            const int r = e / P2M_K, k = e % P2M_K;
+            const int l = l0 + r;
+            float er = 0.f, ei = 0.f;
+            if (l < np2 && kk + k < K) {
+                const cplx<float> x = E2[(size_t)l * W2 + mlo + kk + k + R2];
+                er = x.re;
+                ei = x.im;
+            }
+            Es[k][r] = split_h2(er, ei);
+        }
+        for (int e = t; e < P2M_K * P2M_T; e += 256) {
+            const int k = e / P2M_T, n = e % P2M_T;
+            const int cc = c0 + n;
+            float tr = 0.f, ti = 0.f;
+            if (cc < NC && kk + k < K) {
+                const cplx<float> x = Tb[(size_t)(k2 + mlo + kk + k) * NC + cc];
+                tr = x.re * tsc;
+                ti = x.im * tsc;
+            }
+            Ts[k][n] = split_h2(tr, ti);
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int k = 0; k < P2M_K; k += 2) {
+            halfx8 are[2], aim[2], b[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const uint2 e = Es[k + h][wr * 64 + a * 32 + i];
+                const unsigned rh = e.x ^ 0x80000000u, rl = e.y ^ 0x80000000u;
+                const unsigned ih = __builtin_amdgcn_alignbit(e.x, e.x, 16);
+                const unsigned il = __builtin_amdgcn_alignbit(e.y, e.y, 16);
+                are[a] = __builtin_bit_cast(halfx8, (uintx4){rh, rh, rl, rl});
+                aim[a] = __builtin_bit_cast(halfx8, (uintx4){ih, ih, il, il});
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const uint2 x = Ts[k + h][wc * 64 + c * 32 + i];
+                b[c] = __builtin_bit_cast(halfx8, (uintx4){x.x, x.y, x.x, x.y});
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    accr[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(are[a], b[c], accr[a][c], 0, 0, 0);
+                    acci[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aim[a], b[c], acci[a][c], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    cplx<float> *out = Psi + ((size_t)sf * nq2 + j2) * np2 * (size_t)NC;
+    const float s2 = (float)(d2 * ldexp(1.0, -ks));
     float best = 0.f;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -528,6 +682,12 @@ k_branch_max(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, Can
         // non-negative doubles order like their bit patterns
         atomicMax(&maxbits[s], (unsigned long long)__double_as_longlong(m));
     }
+}
+
+__global__ void k_zero_u32_fbi(unsigned *p, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
 }
 
 __global__ void k_zero_u64(unsigned long long *p, int n)
@@ -986,10 +1146,18 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
     if (fold)
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, st, ctx->maxbits, nshots);
     dim3 g1((p.np1 + P1_BN - 1) / P1_BN, (g.n2 + P1_BM - 1) / P1_BM, S * p.nq1);
+    const bool split = std::is_same<R, float>::value && ctx->prec == FGA_MIXED_SPLIT;
+    if (split)
+        hipLaunchKernelGGL(k_zero_u32_fbi, dim3((S + 255) / 256), dim3(256), 0, st, ctx->tmax, S);
     hipLaunchKernelGGL(k_fbi_pass1<R>, g1, dim3(256), 0, st, f0, f1, nfj,
                        (const cplx<R> *)ctx->E1t, (cplx<R> *)ctx->T, g.n1, g.n2, ctx->R1, p.qb1,
-                       p.qs1, p.nq1, p.np1, g.d1);
-    if (std::is_same<R, float>::value) {
+                       p.qs1, p.nq1, p.np1, g.d1, split ? ctx->tmax : nullptr);
+    if (split) {
+        dim3 g2((unsigned)((NC + P2M_T - 1) / P2M_T), (p.np2 + P2M_T - 1) / P2M_T, S * p.nq2);
+        hipLaunchKernelGGL(k_fbi_pass2_split, g2, dim3(256), 0, st, (const cplx<float> *)ctx->T,
+                           (const cplx<float> *)ctx->E2, (cplx<float> *)ctx->Psi, g.n2, ctx->R2,
+                           p.qb2, p.qs2, p.nq2, p.np2, (int)NC, g.d2, ctx->tmax, fold);
+    } else if (std::is_same<R, float>::value) {
         dim3 g2((unsigned)((NC + P2M_T - 1) / P2M_T), (p.np2 + P2M_T - 1) / P2M_T, S * p.nq2);
         hipLaunchKernelGGL(k_fbi_pass2_mfma, g2, dim3(256), 0, st, (const cplx<float> *)ctx->T,
                            (const cplx<float> *)ctx->E2, (cplx<float> *)ctx->Psi, g.n2, ctx->R2,

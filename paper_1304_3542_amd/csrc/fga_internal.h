@@ -38,6 +38,7 @@ struct fga_ctx {
     double *cq;            // c(q) [nq2][nq1]
     unsigned long long *maxbits;   // per-shot max |psi| (double bits)
     unsigned *wmax;        // per-shot max |C a| (FP32 bits), FGA_MIXED_SPLIT splat
+    unsigned *tmax;        // per (shot, part) max |Re T|, |Im T| (FP32 bits), split pass 2
     int64_t *blk;          // per-block counts / offsets of the compaction
     size_t blk_elems;
 

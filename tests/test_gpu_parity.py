@@ -47,6 +47,27 @@ def test_propagate_and_reconstruct_fp64_match_oracle(small):
 
 
 @pytest.mark.parametrize("precision", ["mixed", "mixed_split"])
+def test_mixed_coefficients_within_1e5(small, precision):
+    """The mixed decompositions (FP32 FBI; FP16 hi/lo split products in
+    pass 2) against the oracle's coefficients on the beams both keep, and the
+    kept sets equal up to candidates whose |psi| lies within the FBI's
+    rounding of the threshold."""
+    g, p = small["g"], small["p"]
+    b = small["b"]
+    r = gpu_run(g, mixed_params(p), small["c"], small["f0"], small["f1"], precision, nsteps=0,
+                want_u=False)
+    assert r["status"] == 0
+    ids = r["id0"]
+    common, ig, io = np.intersect1d(ids, b.cand, return_indices=True)
+    assert len(np.setxor1d(ids, b.cand)) <= 1e-3 * b.n
+    got = r["f0"][4, ig] + 1j * r["f0"][5, ig]
+    want = b.coef[io, 0] + 1j * b.coef[io, 1]
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"{precision}: coefficients max rel err {err:.2e}, kept {ids.size} vs {b.n}", flush=True)
+    assert err <= MIXED_TOL
+
+
+@pytest.mark.parametrize("precision", ["mixed", "mixed_split"])
 def test_mixed_path_within_1e5(small, precision):
     g, p = small["g"], small["p"]
     r = gpu_run(g, mixed_params(p), small["c"], small["f0"], small["f1"], precision)
