@@ -103,6 +103,8 @@ def parse():
                     help="timed steps of point512 with divided-difference dzQ, dzP (0 skips it)")
     ap.add_argument("--d3-steps", type=int, default=2,
                     help="timed steps of the three-dimensional point3d workload (0 skips it)")
+    ap.add_argument("--fwi-steps", type=int, default=3,
+                    help="timed forward+adjoint iterations of the 64-shot workload (0 skips it)")
     ap.add_argument("--topn-steps", type=int, default=5,
                     help="timed steps of the N-largest selection workload (0 skips it)")
     ap.add_argument("--adjoint-steps", type=int, default=3,
@@ -430,6 +432,89 @@ def batched_shots(steps):
             "nshots": ns, "nbeams": nb, "beams_per_shot_min": int(counts.min()),
             "beams_per_shot_max": int(counts.max()), "ms_per_replay": ms,
             "beams_per_s": nb / (ms * 1e-3), "splat_units_per_cu": chosen, "status": st}
+
+
+def fwi_iteration(steps, precision="mixed_split"):
+    """The batched forward+adjoint iteration on the 64-shot workload
+    (shots512): the reduced-precision forward of every shot's u(T) as one
+    graph replay, then the FP64 receiver misfit of the same shots (receivers
+    on the top row every 10 steps, data from the model with the +5 %
+    anomaly): traces with a checkpoint per record, the trace adjoint and the
+    decomposition adjoint (dJ/dc and dJ/df0).  ms per iteration, device
+    clock, with the parts."""
+    import torch
+    import paper_1304_3542_amd as fga
+    Wm = fi.workload("shots512", "mixed")
+    Wd = fi.workload("shots512", "fp64")
+    g, p = Wd.grid, Wd.params
+    ns = Wm.nshots
+    every = 10
+    nrec_t = p.nsteps // every
+    rec = torch.arange(g.n1, dtype=torch.int32, device="cuda")
+    c = torch.from_numpy(Wd.c).cuda()
+    c_true = torch.from_numpy(fi.gaussian_anomaly(g, Wd.c, (1.0, 0.5), 0.1, 0.05)).cuda()
+    f0 = torch.from_numpy(np.ascontiguousarray(Wm.f0)).cuda()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        cm = fga.FGA(g, Wm.params, precision, max_shots=ns)
+        cm.set_velocity(c)
+        bm = fga.Beams(4_000_000, ns)
+        cm.decompose(f0, None, bm)
+        st, need = cm.status()
+        if st == fga.FGA_ECAPACITY:
+            bm = fga.Beams(int(need * 1.05) + 1024, ns)
+        u = torch.empty((ns, g.n2, g.n1), dtype=torch.float64, device="cuda")
+        cm.graph_capture(f0, None, bm, Wm.params.nsteps, u)
+        cd = fga.FGA(g, p, "fp64", max_shots=ns)
+        bd = fga.Beams(4_000_000, ns)
+        cd.set_velocity(c_true)
+        cd.decompose(f0, None, bd)
+        st, need = cd.status()
+        if st == fga.FGA_ECAPACITY:
+            bd = fga.Beams(int(need * 1.05) + 1024, ns)
+            cd.decompose(f0, None, bd)
+        nbd = int(cd.offsets(bd, ns)[-1])
+        data = cd.trace(bd, ns, rec, every, nrec_t)
+        cd.set_velocity(c)
+        ckpt = torch.empty((nrec_t, fga.FGA_NSTATE, bd.capacity), dtype=torch.float64,
+                           device="cuda")
+        dc = torch.zeros_like(c)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+        def it(timed):
+            if timed:
+                ev[0].record(stream)
+            cm.graph_launch()
+            if timed:
+                ev[1].record(stream)
+            cd.decompose(f0, None, bd)
+            tr = cd.trace(bd, ns, rec, every, nrec_t, ckpt)
+            dc.zero_()
+            gcoef = cd.trace_adjoint(bd, ns, rec, every, nrec_t, ckpt, (tr - data).contiguous(), dc)
+            cd.decompose_adjoint(bd, ns, gcoef)
+            if timed:
+                ev[2].record(stream)
+
+        it(False)
+        stream.synchronize()
+        fw, ad = [], []
+        for _ in range(steps):
+            it(True)
+            stream.synchronize()
+            fw.append(ev[0].elapsed_time(ev[1]))
+            ad.append(ev[1].elapsed_time(ev[2]))
+        st1, _ = cm.status()
+        st2, _ = cd.status()
+    nbm = int(cm.offsets(bm, ns)[-1])
+    fw, ad = np.array(fw), np.array(ad)
+    return {"workload": "shots512 forward+adjoint: 64 surface shots on the 512x512 model; "
+            f"{precision} forward of u(T) as one graph, then the FP64 receiver misfit "
+            "(top row every 10 steps, data from a +5 % anomaly): traces with checkpoints "
+            "per record, trace adjoint, decomposition adjoint",
+            "nshots": ns, "nbeams_forward": nbm, "nbeams_adjoint": nbd,
+            "ms_per_iter": float(np.median(fw + ad)), "forward_ms": float(np.median(fw)),
+            "adjoint_ms": float(np.median(ad)), "iterations": steps,
+            "status": st1 if st1 != 0 else st2}
 
 
 def topn_step(steps):
@@ -832,6 +917,8 @@ def main():
         out["adjoint"] = adjoint_iteration(args.adjoint_steps)
     if args.batch_steps > 0:
         out["batched"] = batched_shots(args.batch_steps)
+    if args.fwi_steps > 0:
+        out["fwi_batched"] = fwi_iteration(args.fwi_steps, args.precision)
     if args.topn_steps > 0:
         out["topn"] = topn_step(args.topn_steps)
     if args.closed_steps > 0 and u_point is not None:
