@@ -251,7 +251,9 @@ def test_shots512_full_size():
     b = oracle.Beams(shot[idx].astype(np.int32), sig, ids[idx], np.ones(24, complex),
                      np.zeros((24, 2)), st0, np.array([0, 24], np.int64))
     oracle.propagate(b, Wd.c, g, p.dt, p.nsteps)
-    assert pairwise_state_err(got, b.state) <= 1e-9
+    err = pairwise_state_err(got, b.state)
+    print(f"shots512 sampled beams vs oracle: {err:.2e}", flush=True)
+    assert err <= 1e-10
     # the mixed path against FP64 (beams at the threshold may differ)
     rel = np.linalg.norm(um - ud) / np.linalg.norm(ud)
     print(f"shots512: mixed (graph) vs FP64 rel-L2 {rel:.3e}", flush=True)

@@ -141,4 +141,6 @@ def test_closed_point512_sampled_beams_match_oracle():
                      np.array([0, 96], np.int64))
     oracle.propagate(b, W.c, g, p.dt, p.nsteps, q=np.ascontiguousarray(f_init[0:2].T))
     from gpu_helpers import pairwise_state_err
-    assert pairwise_state_err(got, b.state) <= 1e-9
+    err = pairwise_state_err(got, b.state)
+    print(f"closed-form sampled beams vs oracle: {err:.2e}", flush=True)
+    assert err <= 1e-10

@@ -123,4 +123,6 @@ def test_d3_point3d_sampled_beams_match_oracle():
     b = o3.Beams3(np.zeros(32, np.int32), sig, ids, np.ones(32, complex), np.zeros((32, 2)),
                   np.ascontiguousarray(f_init[8:].T), np.array([0, 32], np.int64))
     o3.propagate(b, W.c, g, p.dt, p.nsteps)
-    assert pairwise_state_err(got, b.state) <= 1e-9
+    err = pairwise_state_err(got, b.state)
+    print(f"point3d sampled beams vs oracle: {err:.2e}", flush=True)
+    assert err <= 1e-10

@@ -213,8 +213,12 @@ def test_reconstruct_adjoint_point512_sampled_beams():
     ds, dcf = oadj.recons_vjp(f[6:].T, f[4:6].T, np.zeros(16, np.int64), g, p, 1, du)
     got = dstate[:, idx].cpu().numpy().T
     for k in (0, 1, 2, 3, 4, 21, 22):
-        assert rel_max(got[:, k], ds[:, k]) <= 1e-9, k
-    assert rel_max(dcoef[:, idx].cpu().numpy().T, dcf) <= 1e-9
+        print(f"field adjoint point512 component {k}: {rel_max(got[:, k], ds[:, k]):.2e}",
+              flush=True)
+        assert rel_max(got[:, k], ds[:, k]) <= 1e-10, k
+    print(f"field adjoint point512 dC: {rel_max(dcoef[:, idx].cpu().numpy().T, dcf):.2e}",
+          flush=True)
+    assert rel_max(dcoef[:, idx].cpu().numpy().T, dcf) <= 1e-10
 
 
 def _oracle_flow_jvp(c, g, p, y0, sigma, nsteps, v):

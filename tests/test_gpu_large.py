@@ -1,14 +1,66 @@
 """The large configuration at full size: 2048 x 1024 smooth layered model,
 eps = 1/1024, point source, q-mesh 147 x 74, p-mesh 400 x 400, tau = 1e-6
-(~5e7 beams from ~3.5e9 candidates).  The oracle cannot run at this size;
-the mixed path is compared with the FP64 GPU path (itself parity-checked
-against the oracle at smaller sizes and at sampled nodes of point512)."""
+(5.0e7 beams from 3.5e9 candidates): both paths against the oracle's values
+stored by tests/golden/make_golden.py (beam count, sampled beams, u(T) at
+sampled nodes), the mixed paths against the FP64 path on the whole field,
+and the FP64 decomposition and propagation against the oracle recomputed at
+sampled q nodes and beams."""
+import os
+
 import numpy as np
 import pytest
 
 import fga_inputs as fi
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large2048_fp64.npz")
+
+
+def test_large_against_stored_oracle_values():
+    """Against the oracle at full size (values written by make_golden.py,
+    which calls only the oracle): FP64 beam count and ids of a seeded sample
+    of 4096 beams exact, their coefficients (t = 0) and states at T within
+    1e-10, u(T) at 2048 nodes (1024 seeded, 1024 nearest seeded beams'
+    centres at T) within 1e-10; the two mixed paths' u(T) at the same nodes
+    within 1e-5."""
+    import torch
+    import paper_1304_3542_amd as fga
+    from gpu_helpers import pairwise_state_err, rel_l2
+    z = np.load(GOLDEN)
+    pick, nodes = z["pick"], z["nodes"]
+    for prec in ("fp64", "mixed", "mixed_split"):
+        W = fi.workload("large2048", "fp64" if prec == "fp64" else "mixed")
+        ctx = fga.FGA(W.grid, W.params, prec)
+        ctx.set_velocity(torch.from_numpy(W.c).cuda())
+        f0 = torch.from_numpy(np.ascontiguousarray(W.f0)).cuda()
+        beams = fga.Beams(int(z["nbeams"]) + 65536, 1)
+        ctx.decompose(f0, None, beams)
+        assert ctx.status()[0] == fga.FGA_OK
+        nb = int(ctx.offsets(beams, 1)[-1])
+        pk = torch.from_numpy(pick).cuda()
+        ids = beams.id[pk].cpu().numpy() if prec == "fp64" else None
+        coef = beams.f[4:6][:, pk].cpu().numpy().T if prec == "fp64" else None
+        ctx.propagate(beams, 1, W.params.nsteps)
+        u = ctx.reconstruct(beams, 1)[0].cpu().numpy().ravel()[nodes]
+        stT = beams.f[fga.FGA_F_STATE:][:, pk].cpu().numpy().T if prec == "fp64" else None
+        assert ctx.status()[0] == fga.FGA_OK
+        ctx.close()
+        del beams
+        torch.cuda.empty_cache()
+        err_u = rel_l2(u, z["u"])
+        if prec == "fp64":
+            assert nb == int(z["nbeams"])
+            np.testing.assert_array_equal(ids, z["ids"])
+            err_c = np.abs(coef - z["coef"]).max() / np.abs(z["coef"]).max()
+            err_s = pairwise_state_err(stT, z["stateT"])
+            print(f"large2048 fp64 vs oracle: coef {err_c:.2e}, states {err_s:.2e}, u {err_u:.2e}",
+                  flush=True)
+            assert err_c <= 1e-10 and err_s <= 1e-10 and err_u <= 1e-10
+        else:
+            print(f"large2048 {prec} vs oracle: {nb} beams, u {err_u:.2e}", flush=True)
+            assert abs(nb - int(z["nbeams"])) <= 1e-3 * int(z["nbeams"])
+            assert err_u <= 1e-5
 
 
 def run(W, precision):
@@ -120,7 +172,9 @@ def test_large_fp64_sampled_against_oracle():
     b = oracle.Beams(np.zeros(32, np.int32), sig, ids[idx], np.ones(32, complex),
                      np.zeros((32, 2)), st0, np.array([0, 32], np.int64))
     oracle.propagate(b, W.c, g, p.dt, p.nsteps)
-    assert pairwise_state_err(got, b.state) <= 1e-9
+    err = pairwise_state_err(got, b.state)
+    print(f"large2048 sampled beams vs oracle: {err:.2e}", flush=True)
+    assert err <= 1e-10
     ctx.close()
     del beams
     torch.cuda.empty_cache()
