@@ -136,7 +136,8 @@ typedef struct {
  *   grad_log   (deterministic = 0) where the gradient kernels put dJ/dc
  *              (a record = the 16 knot sums of one B-spline cell):
  *              0 (automatic): each beam logs its records in its own slots,
- *              up to min(4 steps + 1, what fits FGA_GRAD_LOG_BYTES for the
+ *              up to min(4 steps + 1, what fits the smaller of
+ *              FGA_GRAD_LOG_BYTES and half the free device memory for the
  *              beam capacity) of them; the logs are then summed by cell in a
  *              fixed order (the deterministic mode's reduction, which
  *              synchronises the stream once per call to size its sort);
@@ -177,8 +178,9 @@ typedef struct {
     int32_t ckpt_every_step;
 } fga_params;
 
-/* Size cap of the automatic dJ/dc logs of one context (grad_log = 0).     */
-#define FGA_GRAD_LOG_BYTES (8LL << 30)
+/* Size cap of the automatic dJ/dc logs of one context (grad_log = 0); a
+ * call also keeps them within half of the free device memory.             */
+#define FGA_GRAD_LOG_BYTES (96LL << 30)
 
 /* Beam storage: structure of arrays in one float64 buffer
  * f[FGA_NFIELD][capacity] (field-major), caller-allocated on the device.

@@ -590,7 +590,15 @@ static int grad_log_slots(const fga_ctx *ctx, int64_t cap, int64_t steps)
     if (ctx->p.grad_log < 0 || cap <= 0) return 0;
     if (ctx->p.grad_log > 0) return (int)std::min<int64_t>(ctx->p.grad_log, most);
     const int64_t per = (int64_t)(16 * sizeof(double) + sizeof(int));
-    const int64_t fit = (FGA_GRAD_LOG_BYTES - cap * (int64_t)sizeof(int)) / (per * cap);
+    // at most FGA_GRAD_LOG_BYTES, and at most half of the device memory that
+    // is free (counting the logs this context holds already)
+    int64_t budget = FGA_GRAD_LOG_BYTES;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+        budget = std::min<int64_t>(budget, (int64_t)(free_b / 2 + ctx->det_log_bytes));
+    else
+        (void)hipGetLastError();
+    const int64_t fit = (budget - cap * (int64_t)sizeof(int)) / (per * cap);
     return (int)std::max<int64_t>(0, std::min<int64_t>(most, fit));
 }
 
