@@ -191,6 +191,25 @@ __device__ __forceinline__ void fold_branch_max(R best, unsigned long long *maxb
     }
 }
 
+// XCD-aware order of the pass-2 tiles: workgroups reach the eight XCDs in
+// turn (workgroup P on XCD P % 8), and the tiles of every p2 block of one
+// column block read the same rows of T.  Column blocks are dealt to the XCDs
+// (column block cb on XCD cb % 8) and each XCD runs the p2 blocks of a column
+// block one after another, so the T rows a tile reads are in that XCD's L2
+// for the others.  gridDim.x = 8 nlb ceil(ncb / 8); false for the padding.
+__device__ __forceinline__ bool p2_tile(int ncb, int nlb, int &cb, int &lb)
+{
+    const int P = blockIdx.x, xcd = P & 7, slot = P >> 3;
+    lb = slot % nlb;
+    cb = (slot / nlb) * 8 + xcd;
+    return cb < ncb;
+}
+
+static inline unsigned p2_grid_x(int ncb, int nlb)
+{
+    return (unsigned)(8 * nlb * ((ncb + 7) / 8));
+}
+
 // ------------------------------------------------------------------ pass 2
 // Psi[sf][j2][l2][c] = d2 * sum_m E2[l2][m] T[sf][k2(j2) + m][c], as a GEMM on the
 // matrix cores (FP32 below; FP64 in k_fbi_pass2_mfma64).  With maxbits (f1 = 0,
@@ -214,15 +233,18 @@ k_fbi_pass2_mfma(const cplx<float> *__restrict__ T, const cplx<float> *__restric
                  cplx<float> *__restrict__ Psi, int n2, int R2, int qb2, int qs2, int nq2,
                  int np2, int NC, double d2, unsigned long long *maxbits)
 {
-    __shared__ float2 Es[P2M_K][P2M_T];   // [k][l2]
+    // [k][l2], rows padded: the staging threads write along k
+    __shared__ float2 Es[P2M_K][P2M_T + 1];
     __shared__ float2 Ts[P2M_K][P2M_T];   // [k][c]
+    int cb, lb;
+    if (!p2_tile((NC + P2M_T - 1) / P2M_T, (np2 + P2M_T - 1) / P2M_T, cb, lb)) return;
     const int W2 = 2 * R2 + 1;
     const int sfj = blockIdx.z;
     const int sf = sfj / nq2, j2 = sfj % nq2;
     const int k2 = qb2 + j2 * qs2;
     const int mlo = max(-R2, -k2), mhi = min(R2, n2 - 1 - k2);
     const int K = mhi - mlo + 1;
-    const int c0 = blockIdx.x * P2M_T, l0 = blockIdx.y * P2M_T;
+    const int c0 = cb * P2M_T, l0 = lb * P2M_T;
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
     const int wr = wv >> 1, wc = wv & 1;
@@ -344,15 +366,18 @@ k_fbi_pass2_split(const cplx<float> *__restrict__ T, const cplx<float> *__restri
 {
     typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
     typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
-    __shared__ uint2 Es[P2M_K][P2M_T];   // [k][l2]: (Er, Ei) hi, lo
+    // [k][l2]: (Er, Ei) hi, lo; rows padded: the staging threads write along k
+    __shared__ uint2 Es[P2M_K][P2M_T + 1];
     __shared__ uint2 Ts[P2M_K][P2M_T];   // [k][c]:  (Tr, Ti) hi, lo
+    int cb, lb;
+    if (!p2_tile((NC + P2M_T - 1) / P2M_T, (np2 + P2M_T - 1) / P2M_T, cb, lb)) return;
     const int W2 = 2 * R2 + 1;
     const int sfj = blockIdx.z;
     const int sf = sfj / nq2, j2 = sfj % nq2;
     const int k2 = qb2 + j2 * qs2;
     const int mlo = max(-R2, -k2), mhi = min(R2, n2 - 1 - k2);
     const int K = mhi - mlo + 1;
-    const int c0 = blockIdx.x * P2M_T, l0 = blockIdx.y * P2M_T;
+    const int c0 = cb * P2M_T, l0 = lb * P2M_T;
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
     const int wr = wv >> 1, wc = wv & 1;
@@ -374,30 +399,45 @@ k_fbi_pass2_split(const cplx<float> *__restrict__ T, const cplx<float> *__restri
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) accr[a][b][r] = acci[a][b][r] = 0.f;
-    for (int kk = 0; kk < K; kk += P2M_K) {
-        for (int e = t; e < P2M_T * P2M_K; e += 256) {
-            const int r = e / P2M_K, k = e % P2M_K;
-            const int l = l0 + r;
-            float er = 0.f, ei = 0.f;
-            if (l < np2 && kk + k < K) {
-                const cplx<float> x = E2[(size_t)l * W2 + mlo + kk + k + R2];
-                er = x.re;
-                ei = x.im;
+    // the next chunk's table and T values are loaded into registers before
+    // the current chunk's MFMAs and split into LDS after them, so the load
+    // latency hides behind the matrix work
+    constexpr int PER = P2M_T * P2M_K / 256;
+    float2 pe[PER], pt[PER];
+    auto load = [&](int kk) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q;
+            {
+                const int r = e / P2M_K, k = e % P2M_K;
+                const int l = l0 + r;
+                pe[q] = make_float2(0.f, 0.f);
+                if (l < np2 && kk + k < K) {
+                    const cplx<float> x = E2[(size_t)l * W2 + mlo + kk + k + R2];
+                    pe[q] = make_float2(x.re, x.im);
+                }
             }
-            Es[k][r] = split_h2(er, ei);
+            {
+                const int k = e / P2M_T, n = e % P2M_T;
+                const int cc = c0 + n;
+                pt[q] = make_float2(0.f, 0.f);
+                if (cc < NC && kk + k < K) {
+                    const cplx<float> x = Tb[(size_t)(k2 + mlo + kk + k) * NC + cc];
+                    pt[q] = make_float2(x.re, x.im);
+                }
+            }
         }
-        for (int e = t; e < P2M_K * P2M_T; e += 256) {
-            const int k = e / P2M_T, n = e % P2M_T;
-            const int cc = c0 + n;
-            float tr = 0.f, ti = 0.f;
-            if (cc < NC && kk + k < K) {
-                const cplx<float> x = Tb[(size_t)(k2 + mlo + kk + k) * NC + cc];
-                tr = x.re * tsc;
-                ti = x.im * tsc;
-            }
-            Ts[k][n] = split_h2(tr, ti);
+    };
+    load(0);
+    for (int kk = 0; kk < K; kk += P2M_K) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q;
+            Es[e % P2M_K][e / P2M_K] = split_h2(pe[q].x, pe[q].y);
+            Ts[e / P2M_T][e % P2M_T] = split_h2(pt[q].x * tsc, pt[q].y * tsc);
         }
         __syncthreads();
+        if (kk + P2M_K < K) load(kk + P2M_K);
 #pragma unroll 2
         for (int k = 0; k < P2M_K; k += 2) {
             halfx8 are[2], aim[2], b[2];
@@ -1153,12 +1193,14 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
                        (const cplx<R> *)ctx->E1t, (cplx<R> *)ctx->T, g.n1, g.n2, ctx->R1, p.qb1,
                        p.qs1, p.nq1, p.np1, g.d1, split ? ctx->tmax : nullptr);
     if (split) {
-        dim3 g2((unsigned)((NC + P2M_T - 1) / P2M_T), (p.np2 + P2M_T - 1) / P2M_T, S * p.nq2);
+        dim3 g2(p2_grid_x((int)((NC + P2M_T - 1) / P2M_T), (p.np2 + P2M_T - 1) / P2M_T), 1,
+                S * p.nq2);
         hipLaunchKernelGGL(k_fbi_pass2_split, g2, dim3(256), 0, st, (const cplx<float> *)ctx->T,
                            (const cplx<float> *)ctx->E2, (cplx<float> *)ctx->Psi, g.n2, ctx->R2,
                            p.qb2, p.qs2, p.nq2, p.np2, (int)NC, g.d2, ctx->tmax, fold);
     } else if (std::is_same<R, float>::value) {
-        dim3 g2((unsigned)((NC + P2M_T - 1) / P2M_T), (p.np2 + P2M_T - 1) / P2M_T, S * p.nq2);
+        dim3 g2(p2_grid_x((int)((NC + P2M_T - 1) / P2M_T), (p.np2 + P2M_T - 1) / P2M_T), 1,
+                S * p.nq2);
         hipLaunchKernelGGL(k_fbi_pass2_mfma, g2, dim3(256), 0, st, (const cplx<float> *)ctx->T,
                            (const cplx<float> *)ctx->E2, (cplx<float> *)ctx->Psi, g.n2, ctx->R2,
                            p.qb2, p.qs2, p.nq2, p.np2, (int)NC, g.d2, fold);

@@ -187,14 +187,19 @@ k_splat_prep(SplatArgs A, int nshots, SplatRec *__restrict__ rec, short4 *__rest
     const int64_t nb = A.offsets[nshots];
     const int64_t cap = A.cap;
     const double inv2pe = A.inv_eps * 0.15915494309189535;
-    // the loop bound is uniform over the workgroup, so every lane takes part
-    // in the wavefront reductions below
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nb;
-         base += (int64_t)gridDim.x * blockDim.x) {
+    // each workgroup takes one contiguous range of beams (so a wavefront
+    // meets few shots); the loop bound is uniform over the workgroup, so
+    // every lane takes part in the wavefront reductions below
+    const int64_t per = ((nb + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x *
+                        blockDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = min(nb, lo + per);
+    int hold_s = -1;              // the wavefront's running shot maximum (uniform)
+    unsigned hold_w = 0u;
+    for (int64_t base = lo; base < hi; base += blockDim.x) {
         const int64_t b = base + threadIdx.x;
         unsigned w = 0u;          // |C a| as FP32 bits (0 for lanes past the end)
         int s = 0x7fffffff;
-        if (b < nb) {
+        if (b < hi) {
             const double *p = A.f + b;
             double Q1 = p[(FGA_F_STATE + 0) * cap], Q2 = p[(FGA_F_STATE + 1) * cap];
             double P1 = p[(FGA_F_STATE + 2) * cap], P2 = p[(FGA_F_STATE + 3) * cap];
@@ -225,7 +230,8 @@ k_splat_prep(SplatArgs A, int nshots, SplatRec *__restrict__ rec, short4 *__rest
         }
         if (A.wmax) {
             // the shot's largest |C a| (non-negative floats order like their bit
-            // patterns): one atomic per wavefront when it holds a single shot
+            // patterns): held per wavefront while its lanes see one shot, one
+            // atomic when the shot changes; lanes of a mixed round add their own
             int slo = s, shi = s == 0x7fffffff ? -1 : s;
             unsigned wm = w;
             for (int o = 32; o > 0; o >>= 1) {
@@ -234,12 +240,19 @@ k_splat_prep(SplatArgs A, int nshots, SplatRec *__restrict__ rec, short4 *__rest
                 wm = max(wm, (unsigned)__shfl_xor((int)wm, o));
             }
             if (slo == shi) {
-                if ((threadIdx.x & 63) == 0) atomicMax(&A.wmax[slo], wm);
-            } else if (b < nb) {
+                if (slo != hold_s) {
+                    if (hold_s >= 0 && (threadIdx.x & 63) == 0) atomicMax(&A.wmax[hold_s], hold_w);
+                    hold_s = slo;
+                    hold_w = wm;
+                } else {
+                    hold_w = max(hold_w, wm);
+                }
+            } else if (slo <= shi && b < hi) {
                 atomicMax(&A.wmax[s], w);
             }
         }
     }
+    if (A.wmax && hold_s >= 0 && (threadIdx.x & 63) == 0) atomicMax(&A.wmax[hold_s], hold_w);
 }
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
