@@ -258,30 +258,45 @@ k_fbi_pass2_mfma(const cplx<float> *__restrict__ T, const cplx<float> *__restric
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) accr[a][b][r] = acci[a][b][r] = 0.f;
-    for (int kk = 0; kk < K; kk += P2M_K) {
-        // table: 128 rows x 16 window rows (16 consecutive complex per row)
-        for (int e = t; e < P2M_T * P2M_K; e += 256) {
-            const int r = e / P2M_K, k = e % P2M_K;
-            const int l = l0 + r;
-            float2 v = make_float2(0.f, 0.f);
-            if (l < np2 && kk + k < K) {
-                const cplx<float> x = E2[(size_t)l * W2 + mlo + kk + k + R2];
-                v = make_float2(x.re, x.im);
+    // the table (128 rows x 16 window rows) and T (16 window rows x 128
+    // columns) of the next chunk are loaded into registers before the current
+    // chunk's MFMAs and stored to LDS after them
+    constexpr int PER = P2M_T * P2M_K / 256;
+    float2 pe[PER], pt[PER];
+    auto load = [&](int kk) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q;
+            {
+                const int r = e / P2M_K, k = e % P2M_K;
+                const int l = l0 + r;
+                pe[q] = make_float2(0.f, 0.f);
+                if (l < np2 && kk + k < K) {
+                    const cplx<float> x = E2[(size_t)l * W2 + mlo + kk + k + R2];
+                    pe[q] = make_float2(x.re, x.im);
+                }
             }
-            Es[k][r] = v;
+            {
+                const int k = e / P2M_T, n = e % P2M_T;
+                const int cc = c0 + n;
+                pt[q] = make_float2(0.f, 0.f);
+                if (cc < NC && kk + k < K) {
+                    const cplx<float> x = Tb[(size_t)(k2 + mlo + kk + k) * NC + cc];
+                    pt[q] = make_float2(x.re, x.im);
+                }
+            }
         }
-        // T: 16 window rows x 128 columns
-        for (int e = t; e < P2M_K * P2M_T; e += 256) {
-            const int k = e / P2M_T, n = e % P2M_T;
-            const int cc = c0 + n;
-            float2 v = make_float2(0.f, 0.f);
-            if (cc < NC && kk + k < K) {
-                const cplx<float> x = Tb[(size_t)(k2 + mlo + kk + k) * NC + cc];
-                v = make_float2(x.re, x.im);
-            }
-            Ts[k][n] = v;
+    };
+    load(0);
+    for (int kk = 0; kk < K; kk += P2M_K) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q;
+            Es[e % P2M_K][e / P2M_K] = pe[q];
+            Ts[e / P2M_T][e % P2M_T] = pt[q];
         }
         __syncthreads();
+        if (kk + P2M_K < K) load(kk + P2M_K);
 #pragma unroll 4
         for (int k = 0; k < P2M_K; ++k) {
             float ar[2], ai[2], b[2];
