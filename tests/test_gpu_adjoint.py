@@ -176,8 +176,8 @@ def test_adjoint_full_size_matches_oracle_finite_differences():
               flush=True)
         assert err_t <= 1e-10
         assert abs(J - float(z["J"])) <= 1e-10 * abs(float(z["J"]))
-        assert err_c <= 1e-6
-        assert err_f <= 1e-6
+        assert err_c <= 1e-6          # central differences in c: O(h^2) with h = 1e-6 c
+        assert err_f <= 1e-9          # J is quadratic in f0: differences exact up to rounding
         ctx.close()
         del ckpt, beams
         torch.cuda.empty_cache()
