@@ -369,13 +369,15 @@ k_splat_binned(SplatArgs A, BinArgs B, const SplatRec *__restrict__ rec)
 // same work items, records and partial tiles as k_splat_binned; the beams of
 // an item are taken two at a time, the lower half of the wavefront forming
 // the factors of the first and the upper half those of the second (an odd
-// last beam leaves the upper half zero).  U is scaled by 2^ks per shot with
-// max |C a| 2^ks < 2^14, and the FP64 fold multiplies by 2^-ks (exact).
+// last beam pairs with a staged record of weight zero).  U is scaled by 2^ks
+// per shot with max |C a| 2^ks < 2^14, and the FP64 fold multiplies by 2^-ks
+// (exact).  Staging a chunk, lane k forms what beam k needs beyond its
+// record: the scaled |C a| and its 32-node rotations (SplitRec).
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_splat_binned_split(SplatArgs A, BinArgs B, const SplatRec *__restrict__ rec)
 {
-    __shared__ SplatRec stage_rec[4][64];
-    SplatRec *st = stage_rec[threadIdx.x >> 6];
+    __shared__ SplitRec stage_rec[4][64];
+    const int wv = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int h = lane >> 5, li = lane & 31;
     const int it = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
@@ -385,9 +387,8 @@ k_splat_binned_split(SplatArgs A, BinArgs B, const SplatRec *__restrict__ rec)
         const int shot = item.tile / B.ntiles;
         const int t = item.tile % B.ntiles;
         const int X0 = (t % A.ntile1) * SP_T, Z0 = (t / A.ntile1) * SP_T;
-        const int i1a = X0 + li, i2a = Z0 + li;
-        const double x1s[2] = {A.o1 + i1a * A.d1, A.o1 + (i1a + 32) * A.d1};
-        const double x2s[2] = {A.o2 + i2a * A.d2, A.o2 + (i2a + 32) * A.d2};
+        const double x1 = A.o1 + (X0 + li) * A.d1, x2 = A.o2 + (Z0 + li) * A.d2;
+        const double d32_1 = 32.0 * A.d1, d32_2 = 32.0 * A.d2;
         // the shot's power of two
         const float wm = __uint_as_float(A.wmax[shot]);
         int ks = 0;
@@ -414,22 +415,38 @@ k_splat_binned_split(SplatArgs A, BinArgs B, const SplatRec *__restrict__ rec)
             const int32_t b = b_next;
             if (k0 + 64 + lane < item.len) b_next = lst[k0 + 64 + lane];
             if (lane < nk) {
-                const float4 *src = reinterpret_cast<const float4 *>(rec + b);
-                float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
-                float4 *dst = reinterpret_cast<float4 *>(st + lane);
-                dst[0] = q0;
-                dst[1] = q1;
-                dst[2] = q2;
-                dst[3] = q3;
+                const SplatRec r = rec[b];
+                SplitRec sr;
+                sr.A1 = r.A1;
+                sr.B1 = r.B1;
+                sr.A2 = r.A2;
+                sr.B2 = r.B2;
+                sr.Q1 = r.Q1;
+                sr.Q2 = r.Q2;
+                sr.w = r.w * wsc;
+                const double t1 = r.B1 * d32_1, t2 = r.B2 * d32_2;
+                const float th1 = (float)(t1 - rint(t1)), th2 = (float)(t2 - rint(t2));
+                sr.r1c = __builtin_amdgcn_cosf(th1);
+                sr.r1s = __builtin_amdgcn_sinf(th1);
+                sr.r2c = __builtin_amdgcn_cosf(th2);
+                sr.r2s = __builtin_amdgcn_sinf(th2);
+                sr.pad[0] = sr.pad[1] = sr.pad[2] = 0.f;
+                stage_rec[wv][lane] = sr;
+            } else if (lane == nk) {
+                // an odd chunk's partner of its last beam: zero weight, finite factors
+                SplitRec z;
+                z.A1 = z.B1 = z.A2 = z.B2 = z.Q1 = z.Q2 = 0.0;
+                z.w = z.r1s = z.r2s = 0.f;
+                z.r1c = z.r2c = 1.f;
+                z.pad[0] = z.pad[1] = z.pad[2] = 0.f;
+                stage_rec[wv][lane] = z;
             }
             __builtin_amdgcn_wave_barrier();
             // beam 2 p + h of the chunk in this half
             const int npair = (nk + 1) >> 1;
             for (int pp = 0; pp < npair; ++pp) {
-                const int kk = 2 * pp + h;
-                const SplatRec &r = st[min(kk, nk - 1)];
-                const SplitFrags fr = beam_split(r, kk < nk, r.car * wsc, r.cai * wsc, i1a, x1s,
-                                                 i2a, x2s, hl2e);
+                const SplitRec r = stage_rec[wv][2 * pp + h];
+                const SplitFrags fr = beam_split(r, r.w, x1, x2, (float)d32_1, (float)d32_2, hl2e);
                 tile_update_split(fr, acc00, acc01, acc10, acc11);
             }
             __builtin_amdgcn_wave_barrier();

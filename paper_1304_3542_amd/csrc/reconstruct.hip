@@ -207,15 +207,17 @@ k_splat_prep(SplatArgs A, int nshots, SplatRec *__restrict__ rec, short4 *__rest
             double ar = p[(FGA_F_STATE + 21) * cap], ai = p[(FGA_F_STATE + 22) * cap];
             double Cr = p[4 * cap], Ci = p[5 * cap];
             BeamBox bx = beam_box(Q1, Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
+            // W = C a as modulus and phase; the phase joins theta1
+            const double Wr = Cr * ar - Ci * ai, Wi = Cr * ai + Ci * ar;
             SplatRec r;
             r.B1 = P1 * inv2pe;
-            r.A1 = (S - P1 * Q1) * inv2pe;
+            r.A1 = fma(S - P1 * Q1, inv2pe, atan2(Wi, Wr) * 0.15915494309189535);
             r.B2 = P2 * inv2pe;
             r.A2 = -P2 * Q2 * inv2pe;
             r.Q1 = Q1;
             r.Q2 = Q2;
-            r.car = (float)(Cr * ar - Ci * ai);
-            r.cai = (float)(Cr * ai + Ci * ar);
+            r.w = (float)sqrt(fma(Wr, Wr, Wi * Wi));
+            r.pad = 0.f;
             // empty boxes stay empty after narrowing (lo > hi)
             r.lo1 = (short)min(bx.lo1, A.n1);
             r.hi1 = (short)max(bx.hi1, -1);
@@ -225,7 +227,7 @@ k_splat_prep(SplatArgs A, int nshots, SplatRec *__restrict__ rec, short4 *__rest
             box[b] = make_short4(r.lo1, r.hi1, r.lo2, r.hi2);
             if (A.wmax) {
                 s = (int)(A.id[b] / A.per_shot);
-                w = __float_as_uint(sqrtf(r.car * r.car + r.cai * r.cai));
+                w = __float_as_uint(r.w);
             }
         }
         if (A.wmax) {

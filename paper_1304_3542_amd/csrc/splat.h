@@ -45,13 +45,13 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 // Per-beam record of the mixed splat, formed once per reconstruction:
 // phases in revolutions as affine functions of the node coordinate,
-//   theta1(x1) = (S + P1 (x1 - Q1)) / (2 pi eps) = A1 + B1 x1,
-//   theta2(x2) = P2 (x2 - Q2) / (2 pi eps)       = A2 + B2 x2,
-// the Gaussian centre, C a in FP32 and the truncation box.  64 bytes, read
-// with one scalar load per beam.
+//   theta1(x1) = (S + P1 (x1 - Q1)) / (2 pi eps) + arg(C a) / (2 pi) = A1 + B1 x1,
+//   theta2(x2) = P2 (x2 - Q2) / (2 pi eps)                          = A2 + B2 x2,
+// the Gaussian centre, |C a| in FP32 (so that U = |C a| g1 e^{2 pi i theta1})
+// and the truncation box.  64 bytes, staged with four 16-byte loads per beam.
 struct __align__(64) SplatRec {
     double A1, B1, A2, B2, Q1, Q2;
-    float car, cai;
+    float w, pad;
     short lo1, hi1, lo2, hi2;
 };
 
@@ -71,18 +71,17 @@ __device__ __forceinline__ Frags beam_frags(const SplatRec &r, int i1, int i2, d
     const double t1 = fma(r.B1, x1, r.A1);
     const float th1 = (float)(t1 - rint(t1));
     const float rf1 = (float)(x1 - r.Q1);
-    const float e1 = __builtin_amdgcn_exp2f(-rf1 * rf1 * hl2e);
-    const float sn1 = __builtin_amdgcn_sinf(th1), cs1 = __builtin_amdgcn_cosf(th1);
     const bool in1 = i1 >= r.lo1 && i1 <= r.hi1;
-    const float ur = in1 ? e1 * (r.car * cs1 - r.cai * sn1) : 0.f;
-    const float nui = in1 ? -e1 * (r.car * sn1 + r.cai * cs1) : 0.f;
+    const float g1 = in1 ? __builtin_amdgcn_exp2f(-rf1 * rf1 * hl2e) * r.w : 0.f;
+    const float ur = g1 * __builtin_amdgcn_cosf(th1);
+    const float nui = -(g1 * __builtin_amdgcn_sinf(th1));
     const double t2 = fma(r.B2, x2, r.A2);
     const float th2 = (float)(t2 - rint(t2));
     const float rf2 = (float)(x2 - r.Q2);
-    const float e2 = __builtin_amdgcn_exp2f(-rf2 * rf2 * hl2e);
     const bool in2 = i2 >= r.lo2 && i2 <= r.hi2;
-    const float vr = in2 ? e2 * __builtin_amdgcn_cosf(th2) : 0.f;
-    const float vi = in2 ? e2 * __builtin_amdgcn_sinf(th2) : 0.f;
+    const float g2 = in2 ? __builtin_amdgcn_exp2f(-rf2 * rf2 * hl2e) : 0.f;
+    const float vr = g2 * __builtin_amdgcn_cosf(th2);
+    const float vi = g2 * __builtin_amdgcn_sinf(th2);
     auto va = __builtin_amdgcn_permlane32_swap(__float_as_uint(vr), __float_as_uint(vi), false,
                                                false);
     auto ub = __builtin_amdgcn_permlane32_swap(__float_as_uint(ur), __float_as_uint(nui), false,
@@ -92,8 +91,8 @@ __device__ __forceinline__ Frags beam_frags(const SplatRec &r, int i1, int i2, d
 }
 
 // rank-one update of the 64 x 64 tile: four MFMAs.  Blocks that the beam's
-// box misses get zero factors and add exact zeros; testing for them costs
-// more scalar work and branches than the matrix cores spend on them.
+// box misses get zero factors and add exact zeros; testing for them costs more scalar
+// work and branches than the matrix cores spend on them.
 __device__ __forceinline__ void tile_update(const Frags &fr, floatx16 &acc00, floatx16 &acc01,
                                             floatx16 &acc10, floatx16 &acc11)
 {
@@ -117,23 +116,43 @@ __device__ __forceinline__ void tile_update(const Frags &fr, floatx16 &acc00, fl
 //   A (rows x2):  (Vr, Vi)_hi, (Vr, Vi)_hi, (Vr, Vi)_lo, (Vr, Vi)_lo
 //   B (cols x1):  (Ur, -Ui)_hi, (Ur, -Ui)_lo, (Ur, -Ui)_hi, (Ur, -Ui)_lo
 // whose products add up to Re(U V) = Vr Ur - Vi Ui.  A lane forms its beam's
-// factors at two rows and two columns (the tile's two 32-row and 32-column
-// blocks); four MFMAs cover the 64 x 64 tile for two beams.  U carries
-// C a e^{iS/eps} times a power of two per shot that keeps it inside the FP16
-// range (|U| < 2^14); the FP64 fold divides it out exactly.
+// factors at two rows and two columns 32 nodes apart (the tile's two 32-row
+// and 32-column blocks); four MFMAs cover the 64 x 64 tile for two beams.
+// The factors are not masked to the truncation box, which only decides the
+// tiles a beam visits: beyond the box the Gaussian is below the window
+// tolerance (the box is where it reaches it), so the extra terms are smaller
+// than what the box already drops, and the sum moves closer to the
+// untruncated one.  The per-shot scaling keeps the products exact under a
+// power-of-two change of the data (the scaled U is the same).
+// The second row and column take the phase of the first turned by the
+// beam's rotation over 32 nodes, R = e^{2 pi i 32 B d}, which the staging
+// step forms once per beam and tile: one complex product in place of a
+// phase evaluation, a sine and a cosine.  U carries |C a| g1 times a power
+// of two per shot that keeps it inside the FP16 range (|U| < 2^14); the FP64
+// fold divides it out exactly.
 typedef _Float16 halfx2 __attribute__((ext_vector_type(2)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 typedef float floatx2 __attribute__((ext_vector_type(2)));
 
-// (x, y) -> packed FP16 hi pair and lo pair
+// A beam as staged for the split splat: the record's phases and centre, the
+// scaled |C a| and the 32-node rotations of both axes (80 bytes).
+struct __align__(16) SplitRec {
+    double A1, B1, A2, B2, Q1, Q2;
+    float w, r1c, r1s, r2c, r2s;
+    float pad[3];
+};
+
+// (x, y) -> packed FP16 hi pair and lo pair.  The lo halves come from
+// v_fma_mix{lo,hi}_f16, which forms x - fp16(x) from the packed FP16 operand
+// and the FP32 one in FP32 and rounds it to FP16 in one instruction.
 __device__ __forceinline__ void split_pair(float x, float y, unsigned &hi, unsigned &lo)
 {
     const halfx2 h = __builtin_convertvector((floatx2){x, y}, halfx2);
     hi = __builtin_bit_cast(unsigned, h);
-    const float hx = (float)__builtin_bit_cast(_Float16, (unsigned short)(hi & 0xffffu));
-    const float hy = (float)__builtin_bit_cast(_Float16, (unsigned short)(hi >> 16));
-    const halfx2 l = __builtin_convertvector((floatx2){x - hx, y - hy}, halfx2);
-    lo = __builtin_bit_cast(unsigned, l);
+    asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]\n\t"
+        "v_fma_mixhi_f16 %0, -%1, 1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+        : "=&v"(lo)
+        : "v"(hi), "v"(x), "v"(y));
 }
 
 struct SplitFrags {
@@ -141,40 +160,36 @@ struct SplitFrags {
     unsigned uh[2], ul[2];   // columns: block c = 0, 1
 };
 
-// Factors of one beam at the lane's two rows (x2a, x2b) and two columns
-// (x1a, x1b), zeroed outside the box (or for an absent beam), split into
-// FP16 hi/lo pairs.  W = C a scaled by the shot's power of two.
-__device__ __forceinline__ SplitFrags beam_split(const SplatRec &r, bool valid, float wr, float wi,
-                                                 int i1a, const double x1s[2], int i2a,
-                                                 const double x2s[2], float hl2e)
+// Factors of one beam at the lane's rows x2, x2 + 32 d2 and columns x1,
+// x1 + 32 d1, split into FP16 hi/lo pairs; w is the scaled |C a| (zero for
+// an absent beam), d32_a = 32 d_a in FP32.
+__device__ __forceinline__ SplitFrags beam_split(const SplitRec &r, float w, double x1, double x2,
+                                                 float d32_1, float d32_2, float hl2e)
 {
     SplitFrags f;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const int i1 = i1a + 32 * c;
-        const double x1 = x1s[c];
-        const double t1 = fma(r.B1, x1, r.A1);
-        const float th1 = (float)(t1 - rint(t1));
-        const float rf1 = (float)(x1 - r.Q1);
-        const float e1 = __builtin_amdgcn_exp2f(-rf1 * rf1 * hl2e);
-        const float sn1 = __builtin_amdgcn_sinf(th1), cs1 = __builtin_amdgcn_cosf(th1);
-        const bool in1 = valid && i1 >= r.lo1 && i1 <= r.hi1;
-        const float ur = in1 ? e1 * (wr * cs1 - wi * sn1) : 0.f;
-        const float nui = in1 ? -e1 * (wr * sn1 + wi * cs1) : 0.f;
-        split_pair(ur, nui, f.uh[c], f.ul[c]);
+    {
+        const double t = fma(r.B1, x1, r.A1);
+        const float th = (float)(t - rint(t));
+        const float rf = (float)(x1 - r.Q1);
+        const float sn = __builtin_amdgcn_sinf(th), cs = __builtin_amdgcn_cosf(th);
+        const float g0 = __builtin_amdgcn_exp2f(-rf * rf * hl2e) * w;
+        split_pair(g0 * cs, -(g0 * sn), f.uh[0], f.ul[0]);
+        const float rg = rf + d32_1;
+        const float g1 = __builtin_amdgcn_exp2f(-rg * rg * hl2e) * w;
+        const float cs1 = fmaf(cs, r.r1c, -sn * r.r1s), sn1 = fmaf(sn, r.r1c, cs * r.r1s);
+        split_pair(g1 * cs1, -(g1 * sn1), f.uh[1], f.ul[1]);
     }
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const int i2 = i2a + 32 * a;
-        const double x2 = x2s[a];
-        const double t2 = fma(r.B2, x2, r.A2);
-        const float th2 = (float)(t2 - rint(t2));
-        const float rf2 = (float)(x2 - r.Q2);
-        const float e2 = __builtin_amdgcn_exp2f(-rf2 * rf2 * hl2e);
-        const bool in2 = valid && i2 >= r.lo2 && i2 <= r.hi2;
-        const float vr = in2 ? e2 * __builtin_amdgcn_cosf(th2) : 0.f;
-        const float vi = in2 ? e2 * __builtin_amdgcn_sinf(th2) : 0.f;
-        split_pair(vr, vi, f.vh[a], f.vl[a]);
+    {
+        const double t = fma(r.B2, x2, r.A2);
+        const float th = (float)(t - rint(t));
+        const float rf = (float)(x2 - r.Q2);
+        const float sn = __builtin_amdgcn_sinf(th), cs = __builtin_amdgcn_cosf(th);
+        const float g0 = __builtin_amdgcn_exp2f(-rf * rf * hl2e);
+        split_pair(g0 * cs, g0 * sn, f.vh[0], f.vl[0]);
+        const float rg = rf + d32_2;
+        const float g1 = __builtin_amdgcn_exp2f(-rg * rg * hl2e);
+        const float cs1 = fmaf(cs, r.r2c, -sn * r.r2s), sn1 = fmaf(sn, r.r2c, cs * r.r2s);
+        split_pair(g1 * cs1, g1 * sn1, f.vh[1], f.vl[1]);
     }
     return f;
 }
@@ -199,4 +214,3 @@ __device__ __forceinline__ void tile_update_split(const SplitFrags &f, floatx16 
     acc10 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, b0, acc10, 0, 0, 0);
     acc11 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, b1, acc11, 0, 0, 0);
 }
-
