@@ -979,41 +979,83 @@ k_scan_ties(const Sel *sel, int64_t *blk_gt, int64_t *blk_eq, int nblkb)
     }
 }
 
-// Exclusive scan of the block counts of all shots (one workgroup), shot
-// offsets, and the capacity check.
-__global__ void __launch_bounds__(1024)
-k_scan_blocks(int64_t *blk, int64_t n, int nblk, int nshots, int64_t *offsets,
-              int64_t capacity, int64_t *status)
+// Exclusive scan of the block counts of all shots, in place, in three
+// launches over SCAN_SEGS contiguous segments: the segments' sums, their
+// exclusive scan (one workgroup; also the total, the last shot offset and the
+// capacity check), then every segment scanned from its base in tiles of 1024
+// (the first blocks of the shots give the other shot offsets).
+#define SCAN_SEGS 1024
+
+// inclusive scan over the workgroup of 1024 threads; returns the inclusive
+// value of this thread, total = the workgroup's sum
+__device__ __forceinline__ int64_t block_scan1024(int64_t v, int64_t *wsum, int64_t &total)
 {
-    __shared__ int64_t part[1024];
-    int t = threadIdx.x;
-    int64_t per = (n + 1023) / 1024;
-    int64_t lo = min((int64_t)t * per, n), hi = min(lo + per, n);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t u = __shfl_up(v, o);
+        if (lane >= o) v += u;
+    }
+    if (lane == 63) wsum[wv] = v;
+    __syncthreads();
+    int64_t base = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+        base += w < wv ? wsum[w] : 0;
+        total += wsum[w];
+    }
+    __syncthreads();
+    return base + v;
+}
+
+__global__ void __launch_bounds__(1024)
+k_scan_sums(const int64_t *__restrict__ blk, int64_t n, int64_t seg, int64_t *__restrict__ part)
+{
+    __shared__ int64_t wsum[16];
+    const int64_t lo = (int64_t)blockIdx.x * seg, hi = min(lo + seg, n);
     int64_t sum = 0;
-    for (int64_t i = lo; i < hi; ++i) sum += blk[i];
-    part[t] = sum;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        int64_t v = t >= o ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int64_t run = part[t] - sum;   // exclusive prefix of this thread's segment
-    for (int64_t i = lo; i < hi; ++i) {
-        int64_t v = blk[i];
-        blk[i] = run;
-        run += v;
-    }
-    __syncthreads();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 1024) sum += blk[i];
+    int64_t total;
+    (void)block_scan1024(sum, wsum, total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(1024)
+k_scan_parts(int64_t *part, int nparts, int nshots, int64_t *offsets, int64_t capacity,
+             int64_t *status)
+{
+    __shared__ int64_t wsum[16];
+    const int t = threadIdx.x;
+    const int64_t v = t < nparts ? part[t] : 0;
+    int64_t total;
+    const int64_t incl = block_scan1024(v, wsum, total);
+    if (t < nparts) part[t] = incl - v;
     if (t == 0) {
-        int64_t total = part[1023];
-        for (int s = 0; s < nshots; ++s) offsets[s] = min(blk[(size_t)s * nblk], capacity);
         offsets[nshots] = min(total, capacity);
         if (total > capacity) {
             atomicOr((unsigned long long *)&status[0], FGA_STATUS_CAPACITY);
             atomicMax((unsigned long long *)&status[1], (unsigned long long)total);
         }
+    }
+}
+
+__global__ void __launch_bounds__(1024)
+k_scan_down(int64_t *__restrict__ blk, int64_t n, int64_t seg, const int64_t *__restrict__ part,
+            int nblk, int nshots, int64_t *offsets, int64_t capacity)
+{
+    __shared__ int64_t wsum[16];
+    const int64_t lo = (int64_t)blockIdx.x * seg, hi = min(lo + seg, n);
+    int64_t run = part[blockIdx.x];
+    for (int64_t t0 = lo; t0 < hi; t0 += 1024) {
+        const int64_t i = t0 + threadIdx.x;
+        const int64_t v = i < hi ? blk[i] : 0;
+        int64_t total;
+        const int64_t excl = run + block_scan1024(v, wsum, total) - v;
+        if (i < hi) {
+            blk[i] = excl;
+            if (i % nblk == 0 && i / nblk < nshots) offsets[i / nblk] = min(excl, capacity);
+        }
+        run += total;
     }
 }
 
@@ -1176,13 +1218,14 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
     const size_t sel_elems = (sel_bytes + hist_bytes + 7) / 8;
     size_t have_blk = ctx->blk_elems * sizeof(int64_t);
     if ((rc = fga_ensure(ctx, (void **)&ctx->blk, &have_blk,
-                         (2 * nblk_all + sel_elems) * sizeof(int64_t), "compaction counts")) !=
-        FGA_OK)
+                         (2 * nblk_all + sel_elems + SCAN_SEGS) * sizeof(int64_t),
+                         "compaction counts")) != FGA_OK)
         return rc;
     ctx->blk_elems = have_blk / sizeof(int64_t);
     int64_t *blk_kept = ctx->blk, *blk_eq = ctx->blk + nblk_all;
     Sel *sel = (Sel *)(ctx->blk + 2 * nblk_all);
     unsigned long long *hist = (unsigned long long *)((char *)sel + sel_bytes);
+    int64_t *scan_part = ctx->blk + 2 * nblk_all + sel_elems;
 
     if (fresh) {
         hipLaunchKernelGGL(k_tables<R>, dim3(512), dim3(256), 0, st, (cplx<R> *)ctx->E1t,
@@ -1250,9 +1293,23 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
     const int nblk_run = sym ? nblkb : nblk;
     hipLaunchKernelGGL(k_count<R>, dim3(nblk_run, nshots), dim3(CMP_BLOCK), 0, st,
                        (const cplx<R> *)ctx->Psi, ctx->cq, G, sel, blk_kept, blk_eq, nblkb, sym);
-    hipLaunchKernelGGL(k_scan_ties, dim3(nsb), dim3(1024), 0, st, sel, blk_kept, blk_eq, nblkb);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, blk_kept, (int64_t)nblk_all,
-                       nblk, nshots, beams->offsets, beams->capacity, ctx->status);
+    // the tie ranks matter only to the N-largest rule (the threshold takes no
+    // equal keys: Sel.ties = 0)
+    if (p.top_n > 0)
+        hipLaunchKernelGGL(k_scan_ties, dim3(nsb), dim3(1024), 0, st, sel, blk_kept, blk_eq,
+                           nblkb);
+    {
+        const int64_t n = (int64_t)nblk_all;
+        const int64_t seg = std::max<int64_t>((n + SCAN_SEGS - 1) / SCAN_SEGS, 1024);
+        const int nseg = (int)((n + seg - 1) / seg);
+        hipLaunchKernelGGL(k_scan_sums, dim3(nseg), dim3(1024), 0, st, blk_kept, n, seg,
+                           scan_part);
+        hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(1024), 0, st, scan_part, nseg, nshots,
+                           beams->offsets, beams->capacity, ctx->status);
+        hipLaunchKernelGGL(k_scan_down, dim3(nseg), dim3(1024), 0, st, blk_kept, n, seg,
+                           (const int64_t *)scan_part, nblk, nshots, beams->offsets,
+                           beams->capacity);
+    }
     hipLaunchKernelGGL(k_scatter<R>, dim3(nblk_run, nshots), dim3(CMP_BLOCK), 0, st,
                        (const cplx<R> *)ctx->Psi, ctx->cq, G, sel, blk_kept, blk_eq, nblkb,
                        *beams, g.o1, g.o2, g.d1, g.d2, p.qb1, p.qb2, p.qs1, p.qs2, ctx->norm,
