@@ -21,9 +21,9 @@ def test_large_against_stored_oracle_values():
     """Against the oracle at full size (values written by make_golden.py,
     which calls only the oracle): FP64 beam count and ids of a seeded sample
     of 4096 beams exact, their coefficients (t = 0) and states at T within
-    1e-10, u(T) at 2048 nodes (1024 seeded, 1024 nearest seeded beams'
-    centres at T) within 1e-10; the two mixed paths' u(T) at the same nodes
-    within 1e-5."""
+    1e-10, u(T) at 2007 nodes (1024 seeded and the nodes nearest 1024
+    seeded beams' centres at T, duplicates merged) within 1e-10; the two
+    mixed paths' u(T) at the same nodes within 1e-5."""
     import torch
     import paper_1304_3542_amd as fga
     from gpu_helpers import pairwise_state_err, rel_l2
