@@ -381,14 +381,17 @@ k_splat_binned_split(SplatArgs A, BinArgs B, const SplatRec *__restrict__ rec)
     const int lane = threadIdx.x & 63;
     const int h = lane >> 5, li = lane & 31;
     const int it = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-    const float hl2e = (float)A.half_inv_eps * 1.4426950408889634f;
+    // Gaussian coordinates: exp(-r^2 / (2 eps)) = exp2(-(r sqh)^2)
+    const double sqh = sqrt(A.half_inv_eps * 1.4426950408889634);
     if (it < (int)B.meta[1]) {
         const BinItem item = B.items[it];
         const int shot = item.tile / B.ntiles;
         const int t = item.tile % B.ntiles;
         const int X0 = (t % A.ntile1) * SP_T, Z0 = (t / A.ntile1) * SP_T;
         const double x1 = A.o1 + (X0 + li) * A.d1, x2 = A.o2 + (Z0 + li) * A.d2;
+        const double xs1 = x1 * sqh, xs2 = x2 * sqh;
         const double d32_1 = 32.0 * A.d1, d32_2 = 32.0 * A.d2;
+        const float d32s_1 = (float)(d32_1 * sqh), d32s_2 = (float)(d32_2 * sqh);
         // the shot's power of two
         const float wm = __uint_as_float(A.wmax[shot]);
         int ks = 0;
@@ -421,8 +424,8 @@ k_splat_binned_split(SplatArgs A, BinArgs B, const SplatRec *__restrict__ rec)
                 sr.B1 = r.B1;
                 sr.A2 = r.A2;
                 sr.B2 = r.B2;
-                sr.Q1 = r.Q1;
-                sr.Q2 = r.Q2;
+                sr.Q1s = r.Q1 * sqh;
+                sr.Q2s = r.Q2 * sqh;
                 sr.w = r.w * wsc;
                 const double t1 = r.B1 * d32_1, t2 = r.B2 * d32_2;
                 const float th1 = (float)(t1 - rint(t1)), th2 = (float)(t2 - rint(t2));
@@ -435,7 +438,7 @@ k_splat_binned_split(SplatArgs A, BinArgs B, const SplatRec *__restrict__ rec)
             } else if (lane == nk) {
                 // an odd chunk's partner of its last beam: zero weight, finite factors
                 SplitRec z;
-                z.A1 = z.B1 = z.A2 = z.B2 = z.Q1 = z.Q2 = 0.0;
+                z.A1 = z.B1 = z.A2 = z.B2 = z.Q1s = z.Q2s = 0.0;
                 z.w = z.r1s = z.r2s = 0.f;
                 z.r1c = z.r2c = 1.f;
                 z.pad[0] = z.pad[1] = z.pad[2] = 0.f;
@@ -446,7 +449,7 @@ k_splat_binned_split(SplatArgs A, BinArgs B, const SplatRec *__restrict__ rec)
             const int npair = (nk + 1) >> 1;
             for (int pp = 0; pp < npair; ++pp) {
                 const SplitRec r = stage_rec[wv][2 * pp + h];
-                const SplitFrags fr = beam_split(r, r.w, x1, x2, (float)d32_1, (float)d32_2, hl2e);
+                const SplitFrags fr = beam_split(r, r.w, x1, x2, xs1, xs2, d32s_1, d32s_2);
                 tile_update_split(fr, acc00, acc01, acc10, acc11);
             }
             __builtin_amdgcn_wave_barrier();

@@ -50,21 +50,23 @@ __global__ void k_det_zero_i32(int *p, int64_t n)
         p[i] = 0;
 }
 
-// (cell, slot) of every record, listed in beam order then log order: log
-// positions k across blockIdx.y, beams across the threads, so the cell reads
-// are coalesced and no thread walks a whole log
+// (cell, slot) of every record, listed in beam order then log order: one
+// thread per beam walks its own log, so the work follows the records (the
+// lanes of a wavefront read log position k of consecutive beams together)
 __global__ void k_det_list(const int *__restrict__ cnt, const int64_t *__restrict__ off,
-                           const int *__restrict__ cell, int64_t nb, int64_t cap, int R,
+                           const int *__restrict__ cell, int64_t nb, int64_t cap,
                            unsigned *__restrict__ keys, unsigned long long *__restrict__ slots)
 {
-    for (int k = blockIdx.y; k < R; k += gridDim.y)
-        for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
-             b += (int64_t)gridDim.x * blockDim.x) {
-            if (k >= cnt[b]) continue;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        const int n = cnt[b];
+        const int64_t o = off[b];
+        for (int k = 0; k < n; ++k) {
             const size_t s = (size_t)k * cap + b;
-            keys[off[b] + k] = (unsigned)cell[s];
-            slots[off[b] + k] = (unsigned long long)s;
+            keys[o + k] = (unsigned)cell[s];
+            slots[o + k] = (unsigned long long)s;
         }
+    }
 }
 
 // [begin, end) of every cell's run in the sorted list (cells without records
@@ -221,9 +223,9 @@ fga_status fga_det_reduce(fga_ctx *ctx, int64_t cap, int R, int64_t nb, int64_t 
     FGA_HIP(ctx, rocprim::exclusive_scan(tmp, scan_tmp, cnt, off, (int64_t)0, (size_t)nb,
                                          rocprim::plus<int64_t>(), st));
     const int blocks = ctx->num_cu * 4;
-    const int64_t lb = std::min<int64_t>((nb + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_det_list, dim3((unsigned)lb, (unsigned)std::min(R, 65535)), dim3(256), 0,
-                       st, cnt, off, cell, nb, cap, R, keys, slots);
+    const int64_t lb = std::min<int64_t>((nb + 255) / 256, (int64_t)ctx->num_cu * 8);
+    hipLaunchKernelGGL(k_det_list, dim3((unsigned)lb), dim3(256), 0, st, cnt, off, cell, nb, cap,
+                       keys, slots);
     FGA_HIP(ctx, hipGetLastError());
     FGA_HIP(ctx, rocprim::radix_sort_pairs(tmp, sort_tmp, keys, keys_s, slots, slots_s,
                                            (size_t)total, 0, nbits, st));

@@ -134,10 +134,12 @@ typedef _Float16 halfx2 __attribute__((ext_vector_type(2)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 typedef float floatx2 __attribute__((ext_vector_type(2)));
 
-// A beam as staged for the split splat: the record's phases and centre, the
-// scaled |C a| and the 32-node rotations of both axes (80 bytes).
+// A beam as staged for the split splat: the record's phases, its centre in
+// units of sqrt(2 eps / log2 e) (so that the Gaussian is exp2 of minus a
+// square), the scaled |C a| and the 32-node rotations of both axes (80
+// bytes).
 struct __align__(16) SplitRec {
-    double A1, B1, A2, B2, Q1, Q2;
+    double A1, B1, A2, B2, Q1s, Q2s;
     float w, r1c, r1s, r2c, r2s;
     float pad[3];
 };
@@ -161,33 +163,34 @@ struct SplitFrags {
 };
 
 // Factors of one beam at the lane's rows x2, x2 + 32 d2 and columns x1,
-// x1 + 32 d1, split into FP16 hi/lo pairs; w is the scaled |C a| (zero for
-// an absent beam), d32_a = 32 d_a in FP32.
+// x1 + 32 d1, split into FP16 hi/lo pairs.  w is the scaled |C a| (zero for
+// an absent beam); xs_a = x_a sqrt(log2 e / (2 eps)) and d32s_a = 32 d_a in
+// the same units, so the Gaussian is exp2(-(xs - Qs)^2).  The phase is
+// reduced to [0, 1) revolutions (v_sin_f32 and v_cos_f32 take revolutions).
 __device__ __forceinline__ SplitFrags beam_split(const SplitRec &r, float w, double x1, double x2,
-                                                 float d32_1, float d32_2, float hl2e)
+                                                 double xs1, double xs2, float d32s_1,
+                                                 float d32s_2)
 {
     SplitFrags f;
     {
-        const double t = fma(r.B1, x1, r.A1);
-        const float th = (float)(t - rint(t));
-        const float rf = (float)(x1 - r.Q1);
+        const float th = (float)__builtin_amdgcn_fract(fma(r.B1, x1, r.A1));
+        const float rf = (float)(xs1 - r.Q1s);
         const float sn = __builtin_amdgcn_sinf(th), cs = __builtin_amdgcn_cosf(th);
-        const float g0 = __builtin_amdgcn_exp2f(-rf * rf * hl2e) * w;
+        const float g0 = __builtin_amdgcn_exp2f(-rf * rf) * w;
         split_pair(g0 * cs, -(g0 * sn), f.uh[0], f.ul[0]);
-        const float rg = rf + d32_1;
-        const float g1 = __builtin_amdgcn_exp2f(-rg * rg * hl2e) * w;
+        const float rg = rf + d32s_1;
+        const float g1 = __builtin_amdgcn_exp2f(-rg * rg) * w;
         const float cs1 = fmaf(cs, r.r1c, -sn * r.r1s), sn1 = fmaf(sn, r.r1c, cs * r.r1s);
         split_pair(g1 * cs1, -(g1 * sn1), f.uh[1], f.ul[1]);
     }
     {
-        const double t = fma(r.B2, x2, r.A2);
-        const float th = (float)(t - rint(t));
-        const float rf = (float)(x2 - r.Q2);
+        const float th = (float)__builtin_amdgcn_fract(fma(r.B2, x2, r.A2));
+        const float rf = (float)(xs2 - r.Q2s);
         const float sn = __builtin_amdgcn_sinf(th), cs = __builtin_amdgcn_cosf(th);
-        const float g0 = __builtin_amdgcn_exp2f(-rf * rf * hl2e);
+        const float g0 = __builtin_amdgcn_exp2f(-rf * rf);
         split_pair(g0 * cs, g0 * sn, f.vh[0], f.vl[0]);
-        const float rg = rf + d32_2;
-        const float g1 = __builtin_amdgcn_exp2f(-rg * rg * hl2e);
+        const float rg = rf + d32s_2;
+        const float g1 = __builtin_amdgcn_exp2f(-rg * rg);
         const float cs1 = fmaf(cs, r.r2c, -sn * r.r2s), sn1 = fmaf(sn, r.r2c, cs * r.r2s);
         split_pair(g1 * cs1, g1 * sn1, f.vh[1], f.vl[1]);
     }
