@@ -1022,7 +1022,7 @@ k_scan_sums(const int64_t *__restrict__ blk, int64_t n, int64_t seg, int64_t *__
 
 __global__ void __launch_bounds__(1024)
 k_scan_parts(int64_t *part, int nparts, int nshots, int64_t *offsets, int64_t capacity,
-             int64_t *status)
+             int64_t *status, int64_t *total_out)
 {
     __shared__ int64_t wsum[16];
     const int t = threadIdx.x;
@@ -1031,6 +1031,7 @@ k_scan_parts(int64_t *part, int nparts, int nshots, int64_t *offsets, int64_t ca
     const int64_t incl = block_scan1024(v, wsum, total);
     if (t < nparts) part[t] = incl - v;
     if (t == 0) {
+        *total_out = total;
         offsets[nshots] = min(total, capacity);
         if (total > capacity) {
             atomicOr((unsigned long long *)&status[0], FGA_STATUS_CAPACITY);
@@ -1110,8 +1111,8 @@ template <typename R>
 __global__ void __launch_bounds__(CMP_BLOCK)
 k_scatter(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGeom G,
           const Sel *sel, const int64_t *blk_pos, const int64_t *blk_tie, int nblkb,
-          fga_beams B, double o1, double o2, double d1, double d2, int qb1, int qb2,
-          int qs1, int qs2, double norm, int sym)
+          size_t nblk_all, const int64_t *total, fga_beams B, double o1, double o2, double d1,
+          double d2, int qb1, int qb2, int qs1, int qs2, double norm, int sym)
 {
     __shared__ int wsum[CMP_BLOCK / 64];
     const CmpBlock C = cmp_block(G, nblkb);
@@ -1120,6 +1121,9 @@ k_scatter(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGe
     const int64_t cap = B.capacity;
     const size_t at = (size_t)s * 2 * nblkb + blockIdx.x;
     int64_t run = blk_pos[at];
+    // the block keeps what the scan gave it: most blocks keep nothing and
+    // need not read their candidates again
+    if ((at + 1 < nblk_all ? blk_pos[at + 1] : *total) == run) return;
     int64_t run_m = sym ? blk_pos[at + nblkb] : 0;
     int64_t tie_run = blk_tie[at];
     for (int i = 0; i < CMP_ITEMS; ++i) {
@@ -1131,10 +1135,13 @@ k_scatter(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGe
             key = mag_key(cabs_r(re, im));
         }
         const bool tie = key == S.key && key != 0ull;
-        int ntie = 0;
-        const int tr = block_rank(__ballot(tie), wsum, ntie);
-        const bool keep = key > S.key || (tie && tie_run + tr < S.ties);
-        tie_run += ntie;
+        bool keep = key > S.key;
+        if (S.ties > 0) {   // uniform over the workgroup
+            int ntie = 0;
+            const int tr = block_rank(__ballot(tie), wsum, ntie);
+            keep = keep || (tie && tie_run + tr < S.ties);
+            tie_run += ntie;
+        }
         int nkeep = 0;
         const int rank = block_rank(__ballot(keep), wsum, nkeep);
         const int64_t pos = run + rank, pos_m = run_m + rank;
@@ -1218,7 +1225,7 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
     const size_t sel_elems = (sel_bytes + hist_bytes + 7) / 8;
     size_t have_blk = ctx->blk_elems * sizeof(int64_t);
     if ((rc = fga_ensure(ctx, (void **)&ctx->blk, &have_blk,
-                         (2 * nblk_all + sel_elems + SCAN_SEGS) * sizeof(int64_t),
+                         (2 * nblk_all + sel_elems + SCAN_SEGS + 1) * sizeof(int64_t),
                          "compaction counts")) != FGA_OK)
         return rc;
     ctx->blk_elems = have_blk / sizeof(int64_t);
@@ -1305,15 +1312,15 @@ static fga_status decompose_impl(fga_ctx *ctx, int nshots, const double *f0, con
         hipLaunchKernelGGL(k_scan_sums, dim3(nseg), dim3(1024), 0, st, blk_kept, n, seg,
                            scan_part);
         hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(1024), 0, st, scan_part, nseg, nshots,
-                           beams->offsets, beams->capacity, ctx->status);
+                           beams->offsets, beams->capacity, ctx->status, scan_part + SCAN_SEGS);
         hipLaunchKernelGGL(k_scan_down, dim3(nseg), dim3(1024), 0, st, blk_kept, n, seg,
                            (const int64_t *)scan_part, nblk, nshots, beams->offsets,
                            beams->capacity);
     }
     hipLaunchKernelGGL(k_scatter<R>, dim3(nblk_run, nshots), dim3(CMP_BLOCK), 0, st,
                        (const cplx<R> *)ctx->Psi, ctx->cq, G, sel, blk_kept, blk_eq, nblkb,
-                       *beams, g.o1, g.o2, g.d1, g.d2, p.qb1, p.qb2, p.qs1, p.qs2, ctx->norm,
-                       sym);
+                       nblk_all, (const int64_t *)(scan_part + SCAN_SEGS), *beams, g.o1, g.o2,
+                       g.d1, g.d2, p.qb1, p.qb2, p.qs1, p.qs2, ctx->norm, sym);
     FGA_HIP(ctx, hipGetLastError());
     return FGA_OK;
 }
