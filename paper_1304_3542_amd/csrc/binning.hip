@@ -5,7 +5,8 @@
 // ascending beam order, without sorting:
 //   1. k_bin_count       one wavefront per chunk of 1024 beams counts, in LDS,
 //                        the beams of the chunk that meet every tile;
-//   2. k_bin_scan_tiles  per tile, an exclusive scan over the chunks (each
+//   2. k_bin_seg_sums, k_bin_scan_tiles
+//                        per tile, an exclusive scan over the chunks (each
 //                        chunk's offset inside the tile's list);
 //      k_bin_scan_items  a scan over the tiles (list starts) and the split of
 //                        every list into work items of equal length (the last
@@ -23,7 +24,8 @@
 #define BIN_WCH 1024             // beams per wavefront chunk
 #define BIN_ITEM_MIN 256         // hits per work item, at least
 #define BIN_MAX_TILES 8192       // (shot, tile) pairs per call (LDS counters)
-#define BIN_SCAN_GROUPS 16       // chunk groups per tile in the chunk scan
+#define BIN_SCAN_GROUPS 16       // chunk groups per workgroup in the chunk scan
+#define BIN_SEGS 32              // chunk segments (workgroups) per tile column
 
 struct BinItem {
     int64_t start;   // first entry in the list array
@@ -40,6 +42,7 @@ struct BinArgs {
     int ntile1, ntiles;   // tiles per row, tiles per shot
     int ntiles_total;
     int32_t *wcnt;        // [chunk][ntiles_total]: counts, then offsets
+    int64_t *ssum;        // [BIN_SEGS][ntiles_total]: counts per chunk segment
     int64_t *tile_start;  // [ntiles_total + 1]: counts, then list starts
     int32_t *tile_item;   // [ntiles_total + 1]: first item of each tile
     BinItem *items;       // [max_items]
@@ -65,36 +68,128 @@ __device__ __forceinline__ bool box_tiles(const short4 bx, int &t1lo, int &t1hi,
     return true;
 }
 
+// With diff (the host's choice when nshots (nt1 + 1)(nt2 + 1) counters fit)
+// a box adds +1 and -1 at the four corners of its tile rectangle in a
+// difference array, whose 2-D prefix sums per shot are the tile counts: four
+// LDS atomics per beam instead of one per tile it meets (~33 per beam at
+// eps = 1/1024).
 __global__ void __launch_bounds__(64)
-k_bin_count(BinArgs B)
+k_bin_count(BinArgs B, int diff)
 {
     extern __shared__ int cnt[];
     const int lane = threadIdx.x;
     const int64_t nb = B.offsets[B.nshots];
     const int nused = bin_nchunks(B);
+    const int w1 = B.ntile1 + 1, w2 = B.ntiles / B.ntile1 + 1, per = w1 * w2;
+    const int ncnt = diff ? B.nshots * per : B.ntiles_total;
     for (int chunk = blockIdx.x; chunk < nused; chunk += gridDim.x) {
-        for (int t = lane; t < B.ntiles_total; t += 64) cnt[t] = 0;
+        for (int t = lane; t < ncnt; t += 64) cnt[t] = 0;
         __syncthreads();
         for (int r = 0; r < BIN_WCH / 64; ++r) {
             const int64_t b = (int64_t)chunk * BIN_WCH + r * 64 + lane;
             int t1lo, t1hi, t2lo, t2hi;
             if (b < nb && box_tiles(B.box[b], t1lo, t1hi, t2lo, t2hi)) {
-                const int s = (int)(B.id[b] / B.per_shot);
-                for (int t2 = t2lo; t2 <= t2hi; ++t2)
-                    for (int t1 = t1lo; t1 <= t1hi; ++t1)
-                        atomicAdd(&cnt[s * B.ntiles + t2 * B.ntile1 + t1], 1);
+                const int s = B.nshots == 1 ? 0 : (int)(B.id[b] / B.per_shot);
+                if (diff) {
+                    int *d = cnt + s * per;
+                    atomicAdd(&d[t2lo * w1 + t1lo], 1);
+                    atomicAdd(&d[t2lo * w1 + t1hi + 1], -1);
+                    atomicAdd(&d[(t2hi + 1) * w1 + t1lo], -1);
+                    atomicAdd(&d[(t2hi + 1) * w1 + t1hi + 1], 1);
+                } else {
+                    for (int t2 = t2lo; t2 <= t2hi; ++t2)
+                        for (int t1 = t1lo; t1 <= t1hi; ++t1)
+                            atomicAdd(&cnt[s * B.ntiles + t2 * B.ntile1 + t1], 1);
+                }
             }
         }
         __syncthreads();
+        if (diff) {
+            // prefix sums along each row, then along each column
+            for (int row = lane; row < B.nshots * w2; row += 64) {
+                int acc = 0;
+                for (int t1 = 0; t1 < w1; ++t1) {
+                    acc += cnt[row * w1 + t1];
+                    cnt[row * w1 + t1] = acc;
+                }
+            }
+            __syncthreads();
+            for (int col = lane; col < B.nshots * w1; col += 64) {
+                const int s = col / w1, t1 = col - s * w1;
+                int acc = 0;
+                for (int t2 = 0; t2 < w2; ++t2) {
+                    acc += cnt[s * per + t2 * w1 + t1];
+                    cnt[s * per + t2 * w1 + t1] = acc;
+                }
+            }
+            __syncthreads();
+        }
         int32_t *out = B.wcnt + (size_t)chunk * B.ntiles_total;
-        for (int t = lane; t < B.ntiles_total; t += 64) out[t] = cnt[t];
+        for (int t = lane; t < B.ntiles_total; t += 64) {
+            if (diff) {
+                const int s = t / B.ntiles, tt = t - s * B.ntiles;
+                const int t2 = tt / B.ntile1, t1 = tt - t2 * B.ntile1;
+                out[t] = cnt[s * per + t2 * w1 + t1];
+            } else {
+                out[t] = cnt[t];
+            }
+        }
         __syncthreads();
     }
 }
 
-// Exclusive scan over the chunks for 64 tiles per workgroup: thread
-// (group g, lane l) owns tile 64 blockIdx.x + l and a contiguous range of
-// chunks; the wavefront reads 64 consecutive counts per chunk.
+// Exclusive scan over the chunks of every tile, in two launches over a grid
+// of (64 tiles) x (BIN_SEGS chunk segments): k_bin_seg_sums sums each
+// segment's counts, k_bin_scan_tiles starts each segment from the sum of the
+// segments before it.  Inside a workgroup, thread (group g, lane l) owns tile
+// 64 blockIdx.x + l and a contiguous part of the segment; the wavefront reads
+// 64 consecutive counts per chunk.
+struct SegRange {
+    int c0, c1;   // this thread's chunks
+};
+
+__device__ __forceinline__ SegRange seg_range(const BinArgs &B, int grp)
+{
+    const int nused = bin_nchunks(B);
+    const int seg = (nused + BIN_SEGS - 1) / BIN_SEGS;
+    const int s0 = min((int)blockIdx.y * seg, nused), s1 = min(s0 + seg, nused);
+    const int per = (s1 - s0 + BIN_SCAN_GROUPS - 1) / BIN_SCAN_GROUPS;
+    SegRange r;
+    r.c0 = min(s0 + grp * per, s1);
+    r.c1 = min(r.c0 + per, s1);
+    return r;
+}
+
+__device__ __forceinline__ int64_t col_sum(const int32_t *col, size_t ld, int c0, int c1)
+{
+    int64_t sum = 0;
+    for (int c = c0; c < c1; c += 8) {
+        int32_t v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = c + k < c1 ? col[(size_t)(c + k) * ld] : 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sum += v[k];
+    }
+    return sum;
+}
+
+__global__ void __launch_bounds__(64 * BIN_SCAN_GROUPS)
+k_bin_seg_sums(BinArgs B)
+{
+    __shared__ int64_t gsum[BIN_SCAN_GROUPS][64];
+    const int l = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int t = blockIdx.x * 64 + l;
+    const bool ok = t < B.ntiles_total;
+    const SegRange r = seg_range(B, grp);
+    gsum[grp][l] = ok ? col_sum(B.wcnt + t, (size_t)B.ntiles_total, r.c0, r.c1) : 0;
+    __syncthreads();
+    if (grp == 0 && ok) {
+        int64_t sum = 0;
+        for (int k = 0; k < BIN_SCAN_GROUPS; ++k) sum += gsum[k][l];
+        B.ssum[(size_t)blockIdx.y * B.ntiles_total + t] = sum;
+    }
+}
+
 __global__ void __launch_bounds__(64 * BIN_SCAN_GROUPS)
 k_bin_scan_tiles(BinArgs B)
 {
@@ -102,37 +197,27 @@ k_bin_scan_tiles(BinArgs B)
     const int l = threadIdx.x & 63, grp = threadIdx.x >> 6;
     const int t = blockIdx.x * 64 + l;
     const bool ok = t < B.ntiles_total;
-    const int nused = bin_nchunks(B);
-    const int per = (nused + BIN_SCAN_GROUPS - 1) / BIN_SCAN_GROUPS;
-    const int c0 = min(grp * per, nused), c1 = min(c0 + per, nused);
+    const SegRange r = seg_range(B, grp);
     int32_t *col = B.wcnt + t;
     const size_t ld = (size_t)B.ntiles_total;
-    int64_t sum = 0;
-    if (ok) {
-        for (int c = c0; c < c1; c += 8) {
-            int32_t v[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] = c + k < c1 ? col[(size_t)(c + k) * ld] : 0;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) sum += v[k];
-        }
-    }
-    gsum[grp][l] = sum;
+    gsum[grp][l] = ok ? col_sum(col, ld, r.c0, r.c1) : 0;
     __syncthreads();
     int64_t run = 0;
-    for (int k = 0; k < grp; ++k) run += gsum[k][l];
     if (ok) {
-        for (int c = c0; c < c1; c += 8) {
+        for (int y = 0; y < (int)blockIdx.y; ++y) run += B.ssum[(size_t)y * ld + t];
+        for (int k = 0; k < grp; ++k) run += gsum[k][l];
+        for (int c = r.c0; c < r.c1; c += 8) {
             int32_t v[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] = c + k < c1 ? col[(size_t)(c + k) * ld] : 0;
+            for (int k = 0; k < 8; ++k) v[k] = c + k < r.c1 ? col[(size_t)(c + k) * ld] : 0;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                if (c + k < c1) col[(size_t)(c + k) * ld] = (int32_t)run;
+                if (c + k < r.c1) col[(size_t)(c + k) * ld] = (int32_t)run;
                 run += v[k];
             }
         }
-        if (grp == BIN_SCAN_GROUPS - 1) B.tile_start[t] = run;   // the tile's count
+        // the tile's count, from the last segment's last group
+        if (blockIdx.y == BIN_SEGS - 1 && grp == BIN_SCAN_GROUPS - 1) B.tile_start[t] = run;
     }
 }
 
@@ -247,7 +332,7 @@ k_bin_fill(BinArgs B)
             const int64_t b = (int64_t)chunk * BIN_WCH + r * 64 + lane;
             int t1lo = 0, t1hi = -1, t2lo = 0, t2hi = -1, s = -1;
             if (b < nb && box_tiles(B.box[b], t1lo, t1hi, t2lo, t2hi))
-                s = (int)(B.id[b] / B.per_shot);
+                s = B.nshots == 1 ? 0 : (int)(B.id[b] / B.per_shot);
             const int smin = wave_min(s < 0 ? 0x7fffffff : s), smax = wave_max(s);
             for (int ss = smin; ss <= smax; ++ss) {
                 const bool mine = s == ss;
@@ -547,6 +632,7 @@ fga_status fga_launch_splat_binned(fga_ctx *ctx, const fga_beams *beams, int nsh
         return o;
     };
     const size_t o_wcnt = take((size_t)nchunks * T * sizeof(int32_t));
+    const size_t o_ssum = take((size_t)BIN_SEGS * T * sizeof(int64_t));
     const size_t o_ts = take((size_t)(T + 1) * sizeof(int64_t));
     const size_t o_ti = take((size_t)(T + 1) * sizeof(int32_t));
     const size_t o_items = take((size_t)max_items * sizeof(BinItem));
@@ -568,6 +654,7 @@ fga_status fga_launch_splat_binned(fga_ctx *ctx, const fga_beams *beams, int nsh
     B.ntiles = ntiles;
     B.ntiles_total = T;
     B.wcnt = (int32_t *)(w + o_wcnt);
+    B.ssum = (int64_t *)(w + o_ssum);
     B.tile_start = (int64_t *)(w + o_ts);
     B.tile_item = (int32_t *)(w + o_ti);
     B.items = (BinItem *)(w + o_items);
@@ -576,11 +663,15 @@ fga_status fga_launch_splat_binned(fga_ctx *ctx, const fga_beams *beams, int nsh
     B.items_target = items_target;
     A.partial = ctx->partial;
     A.ntile1 = nt1;
-    const size_t lds = (size_t)T * sizeof(int);
+    const int ndiff = nshots * (nt1 + 1) * (nt2 + 1);
+    const int diff = ndiff <= BIN_MAX_TILES;
+    const size_t lds = (size_t)(diff ? ndiff : T) * sizeof(int);
     const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>(nchunks, 16 * ctx->num_cu));
-    hipLaunchKernelGGL(k_bin_count, dim3(cgrid), dim3(64), lds, ctx->stream, B);
-    hipLaunchKernelGGL(k_bin_scan_tiles, dim3((T + 63) / 64), dim3(64 * BIN_SCAN_GROUPS), 0,
-                       ctx->stream, B);
+    hipLaunchKernelGGL(k_bin_count, dim3(cgrid), dim3(64), lds, ctx->stream, B, diff);
+    hipLaunchKernelGGL(k_bin_seg_sums, dim3((T + 63) / 64, BIN_SEGS), dim3(64 * BIN_SCAN_GROUPS),
+                       0, ctx->stream, B);
+    hipLaunchKernelGGL(k_bin_scan_tiles, dim3((T + 63) / 64, BIN_SEGS),
+                       dim3(64 * BIN_SCAN_GROUPS), 0, ctx->stream, B);
     hipLaunchKernelGGL(k_bin_scan_items, dim3(1), dim3(1024), 0, ctx->stream, B);
     hipLaunchKernelGGL(k_bin_fill, dim3(cgrid), dim3(64), (size_t)T * sizeof(int64_t),
                        ctx->stream, B);
