@@ -783,6 +783,11 @@ def measure(name, steps, warmup, fp64_steps, graph_steps, precision="mixed"):
     nb64 = fp64.fit_capacity()
     ms64, stage64, _ = time_path(fp64, max(1, fp64_steps), 0)
     u64 = fp64.u.cpu().numpy()
+    # beams on the other side of the threshold in one path: its decisions are
+    # taken in the precision of each path's FBI
+    ids_m, ids_d = mixed.beams.id[:nb], fp64.beams.id[:nb64]
+    flips = int((~torch.isin(ids_m, ids_d)).sum().item() + (~torch.isin(ids_d, ids_m)).sum().item())
+    del ids_m, ids_d
     fp64.ctx.close()
     del fp64
     mixed.ctx.close()
@@ -844,7 +849,7 @@ def measure(name, steps, warmup, fp64_steps, graph_steps, precision="mixed"):
         roof.pop(key, None)
     return {
         "nb": nb, "ms_step": ms_step, "per_step": per_step, "stages": stages,
-        "graph": graph, "rel_vs_fp64": rel_vs_fp64, "rel_oracle": rel_oracle,
+        "graph": graph, "rel_vs_fp64": rel_vs_fp64, "rel_oracle": rel_oracle, "flips": flips,
         "pairs": pairs, "npts": npts, "kernels": kernels, "roofline": roof,
         "fp64_gpu": {"ms_per_step": ms64, "nbeams": nb64,
                      "stages_ms": dict(zip(stages, stage64.tolist())),
@@ -868,6 +873,7 @@ def summary(name, r, steps, warmup):
         "valid": bool(r["rel_vs_fp64"] <= 1e-5),
         "rel_l2_vs_fp64_gpu": r["rel_vs_fp64"],
         "rel_l2_vs_oracle_sample": r["rel_oracle"],
+        "threshold_flips_vs_fp64": r["flips"],
         "stages_ms": r["stages"],
         "graph": r["graph"],
         "grid_points_per_s": r["npts"] / (r["ms_step"] * 1e-3),
@@ -908,11 +914,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        # RK4 in FP64; FBI and splat products in FP32, or as FP16 hi/lo
+        # products summed in FP32 (split)
+        "dtype": "f64+f32+f16split" if args.precision == "mixed_split" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": head["workload"], "nshots": r["W"].nshots, "nbeams": r["nb"]},
     }
-    for k in ("valid", "rel_l2_vs_fp64_gpu", "rel_l2_vs_oracle_sample", "stages_ms", "graph",
+    for k in ("valid", "rel_l2_vs_fp64_gpu", "rel_l2_vs_oracle_sample",
+              "threshold_flips_vs_fp64", "stages_ms", "graph",
               "grid_points_per_s", "pairs", "pairs_per_s", "fp64_gpu", "roofline", "kernels"):
         out[k] = head[k]
     u_point = r["u_mixed"] if name == "point512" else None

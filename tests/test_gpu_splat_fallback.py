@@ -1,9 +1,12 @@
-"""The mixed splat beyond the binning's limit of 8192 (shot, tile) pairs:
-17 shots on a 2048 x 1024 grid (512 tiles of 64 x 64 each, 8704 pairs) go
-through the unbinned MFMA splat and its ordered reduction.  Hand-built beams
-(random centres, momenta, phases, amplitudes and coefficients, a few per
-shot, some with boxes clipped by the grid edge) against the oracle's
-windowed sum and against the FP64 path on the same beams."""
+"""The mixed splats at the binning's limits.  17 shots on a 2048 x 1024 grid
+(512 tiles of 64 x 64 each, 8704 (shot, tile) pairs, past the 8192 the
+binning handles) go through the unbinned MFMA splat and its ordered
+reduction; 15 shots (7680 pairs) stay binned, but their difference-array
+counters (15 x 33 x 17) do not fit, so the tile hits are counted one by one.
+Hand-built beams (random centres, momenta, phases, amplitudes and
+coefficients, a few per shot, some with boxes clipped by the grid edge)
+against the oracle's windowed sum and against the FP64 path on the same
+beams, with FP32 and with split FP16 products."""
 import numpy as np
 import pytest
 
@@ -33,24 +36,28 @@ def _beams(g, ns, per_shot, seed):
                         np.ones(nb, complex), coef, st, offsets)
 
 
-def test_unbinned_mixed_splat_past_8192_shot_tiles():
+@pytest.mark.parametrize("ns", [17, 15])
+def test_mixed_splat_at_the_binning_limits(ns):
     import torch
     import paper_1304_3542_amd as fga
     g = fi.Grid(2048, 1024, 0.0, 0.0, 1 / 1024, 1 / 1024)
-    ns, per_shot = 17, 24
-    assert ns * (2048 // 64) * (1024 // 64) > 8192
+    per_shot = 24
+    tiles = ns * (2048 // 64) * (1024 // 64)
+    assert (tiles > 8192) == (ns == 17) and ns * 33 * 17 > 8192
     b = _beams(g, ns, per_shot, seed=17)
     nb = b.n
     fields = np.zeros((fga.FGA_NFIELD, nb))
     fields[4:6] = b.coef.T
     fields[fga.FGA_F_STATE:] = b.state.T
+    # candidate ids carry the shot: 2 x 1 q node x 4 x 4 p nodes = 32 per shot
+    ids = np.concatenate([s * 32 + np.arange(per_shot) for s in range(ns)]).astype(np.int64)
     out = {}
-    for prec, tw in (("mixed", 1e-8), ("fp64", 1e-16)):
-        p = fi.Params(1 / 1024, 0, 0, 1, 1, 1, 1, 2, 2, 0.1, 0.1, 1e-6, tw, tw, 1e-3, 0)
+    for prec, tw in (("mixed", 1e-8), ("mixed_split", 1e-8), ("fp64", 1e-16)):
+        p = fi.Params(1 / 1024, 0, 0, 1, 1, 1, 1, 4, 4, 0.1, 0.1, 1e-6, tw, tw, 1e-3, 0)
         ctx = fga.FGA(g, p, prec, max_shots=ns)
         beams = fga.Beams(nb, ns)
         beams.f.copy_(torch.from_numpy(fields))
-        beams.id.copy_(torch.arange(nb, dtype=torch.int64))
+        beams.id.copy_(torch.from_numpy(ids))
         beams.offsets.copy_(torch.from_numpy(b.offsets))
         out[prec] = ctx.reconstruct(beams, ns).cpu().numpy()
         assert ctx.status()[0] == 0
@@ -68,9 +75,11 @@ def test_unbinned_mixed_splat_past_8192_shot_tiles():
         ref = oracle.reconstruct_points(b, g, out["fp64_p"], nodes, shot=s)
         assert np.abs(ref).max() > 0
         got64 = out["fp64"][s].ravel()[nodes]
-        gotm = out["mixed"][s].ravel()[nodes]
         assert np.abs(got64 - ref).max() <= 1e-10 * np.abs(ref).max(), s
-        assert rel_l2(gotm, ref) <= 1e-5, (s, rel_l2(gotm, ref))
-    rel = rel_l2(out["mixed"], out["fp64"])
-    print(f"unbinned mixed splat, {ns} shots: rel-L2 vs FP64 {rel:.3e}", flush=True)
-    assert rel <= 1e-5
+        for prec in ("mixed", "mixed_split"):
+            gotm = out[prec][s].ravel()[nodes]
+            assert rel_l2(gotm, ref) <= 1e-5, (prec, s, rel_l2(gotm, ref))
+    for prec in ("mixed", "mixed_split"):
+        rel = rel_l2(out[prec], out["fp64"])
+        print(f"{prec} splat, {ns} shots: rel-L2 vs FP64 {rel:.3e}", flush=True)
+        assert rel <= 1e-5
