@@ -75,6 +75,9 @@ typedef enum {
                        relative; the pass-1 output and the splat's U scaled
                        per shot by a power of two to stay in the FP16 range)
                        and accumulated in FP32 (then FP64 in the splat).
+                       The splat's box decides which 64 x 64 tiles a beam
+                       visits; inside them its Gaussian is not cut at the
+                       box (the terms beyond it are below tau_win).
                        Beyond 8192 (shot, tile) pairs the splat keeps the
                        FP32 products.                                        */
 } fga_precision;
