@@ -911,14 +911,39 @@ k_count(const cplx<R> *__restrict__ Psi, const double *__restrict__ cq, CandGeom
     const CmpBlock B = cmp_block(G, nblkb);
     const unsigned long long K = sel[B.s * 2 + B.sb].key;
     int gt = 0, eq = 0;
-    for (int i = 0; i < CMP_ITEMS; ++i) {
-        const int64_t cl = B.first + (int64_t)i * CMP_BLOCK + threadIdx.x;
-        if (cl >= B.end) break;
-        R re, im;
-        cand_psi(Psi, cq, G, B.s, cl, re, im);
-        const unsigned long long key = mag_key(cabs_r(re, im));
-        gt += key > K ? 1 : 0;
-        eq += (key == K && key != 0ull) ? 1 : 0;
+    if (G.nfj == 1 && G.small) {
+        // f1 = 0 and 32-bit candidate indices (uniform): every load of the
+        // block is issued before the first key is formed
+        const size_t NC = (size_t)G.nq1 * G.np1;
+        const cplx<R> *P = Psi + (size_t)B.s * G.nq2 * G.np2 * NC;
+        cplx<R> v[CMP_ITEMS];
+#pragma unroll
+        for (int i = 0; i < CMP_ITEMS; ++i) {
+            // past the block's end the last candidate is read and not counted
+            const int64_t cl = min(B.first + (int64_t)i * CMP_BLOCK + threadIdx.x, B.end - 1);
+            int sb, j1, j2, l1, l2;
+            int64_t qf;
+            cand_index(G, cl, sb, qf, j1, j2, l1, l2);
+            v[i] = P[((size_t)j2 * G.np2 + l2) * NC + (size_t)j1 * G.np1 + l1];
+        }
+#pragma unroll
+        for (int i = 0; i < CMP_ITEMS; ++i) {
+            const bool in = B.first + (int64_t)i * CMP_BLOCK + threadIdx.x < B.end;
+            const unsigned long long key =
+                in ? mag_key(cabs_r((R)0.5 * v[i].re, (R)0.5 * v[i].im)) : 0ull;
+            gt += key > K ? 1 : 0;
+            eq += (key == K && key != 0ull) ? 1 : 0;
+        }
+    } else {
+        for (int i = 0; i < CMP_ITEMS; ++i) {
+            const int64_t cl = B.first + (int64_t)i * CMP_BLOCK + threadIdx.x;
+            if (cl >= B.end) break;
+            R re, im;
+            cand_psi(Psi, cq, G, B.s, cl, re, im);
+            const unsigned long long key = mag_key(cabs_r(re, im));
+            gt += key > K ? 1 : 0;
+            eq += (key == K && key != 0ull) ? 1 : 0;
+        }
     }
     for (int o = 32; o > 0; o >>= 1) {
         gt += __shfl_xor(gt, o);
