@@ -315,6 +315,24 @@ __device__ __forceinline__ void vel_poly(const VelGrid &V, const VelCell &k,
     c22 = d22h * (2.0 * V.inv_d2 * V.inv_d2);
 }
 
+// c, grad c and the Hessian at (x1, x2) from the knot cell's coefficient line
+// (the same polynomial, and the same rounding, as the RK4 kernel's LDS path)
+__device__ __forceinline__ void vel_eval_coef(const VelGrid &V, double x1, double x2, double &c,
+                                              double &c1, double &c2, double &c11, double &c12,
+                                              double &c22)
+{
+    const VelCell k = vel_cell(V, x1, x2);
+    const double2 *line = reinterpret_cast<const double2 *>(vel_cell_coef(V, k));
+    double C[4][4];
+#pragma unroll
+    for (int sl = 0; sl < 8; ++sl) {
+        const double2 v = line[sl];
+        C[sl >> 1][2 * (sl & 1)] = v.x;
+        C[sl >> 1][2 * (sl & 1) + 1] = v.y;
+    }
+    vel_poly(V, k, C, c, c1, c2, c11, c12, c22);
+}
+
 // Truncation box of a Gaussian centred at Q: the nodes within Rw cells of the
 // node nearest Q (floor(t + 1/2)), clipped to the grid.
 struct BeamBox {

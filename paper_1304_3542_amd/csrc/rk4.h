@@ -74,7 +74,7 @@ __device__ __forceinline__ double rsq64(double x)
 __device__ __forceinline__ void rhs(const VelGrid &V, double s, const St &y, St &k)
 {
     double c, g1, g2, K11, K12, K22;
-    vel_eval(V, y.Q1, y.Q2, c, g1, g2, K11, K12, K22);
+    vel_eval_coef(V, y.Q1, y.Q2, c, g1, g2, K11, K12, K22);
     double n2 = y.P1 * y.P1 + y.P2 * y.P2;
     double n = sqrt(n2);
     double inv_n = rcp64(n);
@@ -165,14 +165,14 @@ __device__ __forceinline__ void store_state(double *p, int64_t cap, const St &y)
     p[22 * cap] = y.a.i;
 }
 
-// Velocity source of a stage that reads the taps from the padded samples
+// Velocity source of a stage that reads the knot cell's coefficient line
 // when the stage evaluates c.
 struct VelDirect {
     VelGrid V;
     __device__ __forceinline__ void eval(double x1, double x2, double &c, double &c1, double &c2,
                                          double &c11, double &c12, double &c22) const
     {
-        vel_eval(V, x1, x2, c, c1, c2, c11, c12, c22);
+        vel_eval_coef(V, x1, x2, c, c1, c2, c11, c12, c22);
     }
     __device__ __forceinline__ void prefetch(double, double) const {}
 };
