@@ -508,8 +508,43 @@ def fwi_iteration(steps, precision="mixed_split"):
             ad.append(ev[1].elapsed_time(ev[2]))
         st1, _ = cm.status()
         st2, _ = cd.status()
+        # the same FP64 part with the state of every step kept by the forward
+        # (23 doubles per beam and step, ~130 GB here) instead of recomputed
+        cd.close()
+        del ckpt, bd
+        torch.cuda.empty_cache()
+        ce = fga.FGA(g, p.replace(ckpt_every_step=1), "fp64", max_shots=ns)
+        ce.set_velocity(c)
+        be = fga.Beams(nbd + 1024, ns)
+        ckpt_e = torch.empty((ce.ckpt_rows(every, nrec_t), fga.FGA_NSTATE, be.capacity),
+                             dtype=torch.float64, device="cuda")
+
+        def it_every():
+            ev[1].record(stream)
+            ce.decompose(f0, None, be)
+            tr = ce.trace(be, ns, rec, every, nrec_t, ckpt_e)
+            dc.zero_()
+            gcoef = ce.trace_adjoint(be, ns, rec, every, nrec_t, ckpt_e, (tr - data).contiguous(),
+                                     dc)
+            ce.decompose_adjoint(be, ns, gcoef)
+            ev[2].record(stream)
+
+        it_every()
+        stream.synchronize()
+        ad_e = []
+        for _ in range(steps):
+            it_every()
+            stream.synchronize()
+            ad_e.append(ev[1].elapsed_time(ev[2]))
+        st3, _ = ce.status()
+        ce.close()
+        del ckpt_e, be
+        torch.cuda.empty_cache()
     nbm = int(cm.offsets(bm, ns)[-1])
     fw, ad = np.array(fw), np.array(ad)
+    every_step = {"ms_per_iter": float(np.median(fw) + np.median(ad_e)),
+                  "adjoint_ms": float(np.median(ad_e)),
+                  "checkpoints": "every step (the adjoint reads the states)", "status": st3}
     return {"workload": "shots512 forward+adjoint: 64 surface shots on the 512x512 model; "
             f"{precision} forward of u(T) as one graph, then the FP64 receiver misfit "
             "(top row every 10 steps, data from a +5 % anomaly): traces with checkpoints "
@@ -517,6 +552,7 @@ def fwi_iteration(steps, precision="mixed_split"):
             "nshots": ns, "nbeams_forward": nbm, "nbeams_adjoint": nbd,
             "ms_per_iter": float(np.median(fw + ad)), "forward_ms": float(np.median(fw)),
             "adjoint_ms": float(np.median(ad)), "iterations": steps,
+            "every_step_checkpoints": every_step,
             "status": st1 if st1 != 0 else st2}
 
 
