@@ -35,6 +35,7 @@ struct fga3_ctx {
     int max_shots;
     hipStream_t stream;
     int num_cu;
+    int splat_slots;       // k3_splat workgroups resident at once (all CUs)
     int R[3], W[3], Rw[3];
     double norm;
     double *c;
@@ -725,28 +726,33 @@ __global__ void __launch_bounds__(64) k3_rk4(const double *__restrict__ c, fga3_
 
 // ------------------------------------------------------------------ step 3
 //
-// A workgroup takes one tile of 16 (x1) x 16 (x2) x 64 (x3) nodes and one
+// A workgroup takes one tile of 16 (x1) x 32 (x2) x 32 (x3) nodes and one
 // slice of a shot's beams (each shot's beams are cut into nsplit slices);
-// wavefront w owns the 16 x3 planes Z0 + 16 w + t.  The sum is separable:
+// wavefront w owns the 8 x3 planes Z0 + 8 w + t.  The sum is separable:
 // with r_a = x_a - Q_a,
 //   g_a(x_a) = exp(i P_a r_a / eps - r_a^2 / (2 eps)),   W = C a exp(iS/eps),
 // a beam adds Re(W g1 g2 g3) inside its truncation box and nothing outside.
 // The beams are staged 32 at a time, their factors at the tile's
-// coordinates formed as six runs of 16 (x1 carrying W, x2, four quarters of
-// x3), one thread per (beam, run), zero outside the box: a direct evaluation
-// at the run's first node in the box and then
+// coordinates formed as five runs of 16 (x1 carrying W, two halves of x2,
+// two halves of x3), one thread per (beam, run), zero outside the box: a
+// direct evaluation at the run's first node in the box and then
 //   g(x + d) = g(x) rho(x),   rho(x + d) = rho(x) exp(-d^2 / eps)
 // (exact identities of the Gaussian; the products add rounding over at most
 // 15 steps).  The beams whose box meets the tile are listed and taken two at
-// a time; on plane t the update is the real product
-//   u[x1][x2] += sum_k A[x1][k] B[k][x2],  k = (beam of the pair, re / im),
-//   A = [Re H, -Im H],  B = [Re g2 ; Im g2],  H = W g1(x1) g3(x3_t),
-// one v_mfma_f64_16x16x4f64 (lane l supplies A[l % 16][l / 16] and
+// a time; on plane t and x2 half h the update is the real product
+//   u[x1][x2] += sum_k A[x1][k] B_h[k][x2],  k = (beam of the pair, re / im),
+//   A = [Re H, -Im H],  B_h = [Re g2 ; Im g2] on the half,  H = W g1(x1) g3(x3_t),
+// one v_mfma_f64_16x16x4f64 each (lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; element i of its result is D[4 i + l / 16][l % 16]).
-// The slices' partial sums are added in slice order by k3_splat_reduce.
-#define T3E 16   // tile edge in x1 and x2, and the length of every factor run
-#define T3Z 64   // tile edge in x3
+// The matrix cores and the FP64 vector instructions share one pipe on this
+// chip, so the A operand (one product and one FMA per lane) is formed once
+// per plane and used by both halves.  The slices' partial sums are added in
+// slice order by k3_splat_reduce.
+#define T3E 16   // tile edge in x1, and the length of every factor run
+#define T3Y 32   // tile edge in x2 (two runs)
+#define T3Z 32   // tile edge in x3 (two runs, 8 planes per wavefront)
 #define T3B 32   // beams staged per round
+#define T3R 5    // factor runs per beam: x1, x2 halves, x3 halves
 
 typedef double d3x4 __attribute__((ext_vector_type(4)));
 
@@ -754,34 +760,37 @@ __global__ void __launch_bounds__(256, 2) k3_splat(fga_beams B, fga3_grid G, dou
                                                 int Rw2, int Rw3, int nsplit,
                                                 double *__restrict__ partial)
 {
-    // runs: 0 = x1 (times W), 1 = x2, 2..5 = x3 quarters, beam index fastest
-    // (the staging lanes write consecutive slots); slot T3B stays zero
-    __shared__ double2 sg[6][T3E][T3B + 1];
-    __shared__ int smeet[6][T3B];
+    // runs: 0 = x1 (times W), 1..2 = x2 halves, 3..4 = x3 halves, beam index
+    // fastest (the staging lanes write consecutive slots); slot T3B stays zero
+    __shared__ double2 sg[T3R][T3E][T3B + 1];
+    __shared__ int smeet[T3R][T3B];
     __shared__ int slist[T3B];
     __shared__ int snmeet;
     const int nt1 = (G.n1 + T3E - 1) / T3E;
     const int X0 = (blockIdx.x % nt1) * T3E, Z0 = (blockIdx.x / nt1) * T3Z;
-    const int Y0 = blockIdx.y * T3E;
+    const int Y0 = blockIdx.y * T3Y;
     const int split = blockIdx.z % nsplit, s = blockIdx.z / nsplit;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int64_t cap = B.capacity;
     const int64_t b0 = B.offsets[s], b1 = B.offsets[s + 1], nbs = b1 - b0;
     const int64_t lo = b0 + nbs * split / nsplit, hi = b0 + nbs * (split + 1) / nsplit;
     const double ieps = 1.0 / eps, hieps = 0.5 / eps;
-    if (tid < 6 * T3E) sg[tid / T3E][tid % T3E][T3B] = double2{0.0, 0.0};
+    if (tid < T3R * T3E) sg[tid / T3E][tid % T3E][T3B] = double2{0.0, 0.0};
     // this lane's place in the products: x1 (rows of A), x2 (columns of B),
     // which beam of the pair and which part (re / im)
     const int mrow = lane % 16, kcol = lane / 16, pb = kcol / 2, part = kcol % 2;
-    d3x4 acc[T3E];
+    // wavefront w's planes 8 w .. 8 w + 7 of the tile lie in x3 run 3 + w / 2
+    const int zrun = 3 + w / 2, zoff = 8 * (w % 2);
+    d3x4 acc[8][2];
 #pragma unroll
-    for (int t = 0; t < T3E; ++t) acc[t] = d3x4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < 8; ++t)
+        for (int h = 0; h < 2; ++h) acc[t][h] = d3x4{0.0, 0.0, 0.0, 0.0};
     for (int64_t c0 = lo; c0 < hi; c0 += T3B) {
         const int nc = (int)min((int64_t)T3B, hi - c0);
-        if (tid < 6 * T3B) {
+        if (tid < T3R * T3B) {
             const int run = tid / T3B, bb = tid % T3B;
-            const int a = run < 2 ? run : 2;           // axis of the run
-            int m0 = 1, m1 = 0;                        // empty range
+            const int a = run == 0 ? 0 : (run < 3 ? 1 : 2);   // axis of the run
+            int m0 = 1, m1 = 0;                              // empty range
             double gr = 0.0, gi = 0.0, rr = 0.0, ri = 0.0, kap = 0.0;
             if (bb < nc) {
                 const double *f = B.f + (size_t)F3_FS * cap + c0 + bb;
@@ -789,7 +798,7 @@ __global__ void __launch_bounds__(256, 2) k3_splat(fga_beams B, fga3_grid G, dou
                 const double d = a == 0 ? G.d1 : (a == 1 ? G.d2 : G.d3);
                 const int n = a == 0 ? G.n1 : (a == 1 ? G.n2 : G.n3);
                 const int Rw = a == 0 ? Rw1 : (a == 1 ? Rw2 : Rw3);
-                const int t0 = a == 0 ? X0 : (a == 1 ? Y0 : Z0 + (run - 2) * T3E);
+                const int t0 = a == 0 ? X0 : (a == 1 ? Y0 + (run - 1) * T3E : Z0 + (run - 3) * T3E);
                 const double Q = f[(size_t)a * cap], P = f[(size_t)(3 + a) * cap];
                 double t = floor((Q - o) / d + 0.5);
                 t = fmin(fmax(t, -1e8), 1e8);
@@ -841,10 +850,9 @@ __global__ void __launch_bounds__(256, 2) k3_splat(fga_beams B, fga3_grid G, dou
         __syncthreads();
         // list the beams whose box meets the tile, in order
         if (w == 0) {
-            const int fl = lane < T3B && smeet[0][lane & (T3B - 1)] &&
-                           smeet[1][lane & (T3B - 1)] &&
-                           (smeet[2][lane & (T3B - 1)] || smeet[3][lane & (T3B - 1)] ||
-                            smeet[4][lane & (T3B - 1)] || smeet[5][lane & (T3B - 1)]);
+            const int j = lane & (T3B - 1);
+            const int fl = lane < T3B && smeet[0][j] && (smeet[1][j] || smeet[2][j]) &&
+                           (smeet[3][j] || smeet[4][j]);
             const unsigned long long mk = __ballot(fl);
             if (fl) slist[__popcll(mk & ((1ull << lane) - 1ull))] = lane;
             if (lane == 0) snmeet = __popcll(mk);
@@ -854,29 +862,35 @@ __global__ void __launch_bounds__(256, 2) k3_splat(fga_beams B, fga3_grid G, dou
         for (int p = 0; p < nm; p += 2) {
             const int bb = pb == 0 ? slist[p] : (p + 1 < nm ? slist[p + 1] : T3B);
             const double2 g1 = sg[0][mrow][bb];
-            const double2 g2 = sg[1][mrow][bb];
-            const double bv = part == 0 ? g2.x : g2.y;
+            const double2 g2a = sg[1][mrow][bb], g2b = sg[2][mrow][bb];
+            const double bva = part == 0 ? g2a.x : g2a.y, bvb = part == 0 ? g2b.x : g2b.y;
+            // A = Re(g1 h) (part 0) or -Im(g1 h) (part 1), both as ca h.x + cb h.y
+            const double ca = part == 0 ? g1.x : -g1.y;
+            const double cb = part == 0 ? -g1.y : -g1.x;
 #pragma unroll
-            for (int t = 0; t < T3E; ++t) {
-                const double2 h = sg[2 + w][t][bb];
-                const double av = part == 0 ? g1.x * h.x - g1.y * h.y : -(g1.x * h.y + g1.y * h.x);
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+            for (int t = 0; t < 8; ++t) {
+                const double2 h = sg[zrun][zoff + t][bb];
+                const double av = fma(ca, h.x, cb * h.y);
+                acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bva, acc[t][0], 0, 0, 0);
+                acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bvb, acc[t][1], 0, 0, 0);
             }
         }
         __syncthreads();
     }
-    // element i of plane t: x1 = X0 + 4 i + lane / 16, x2 = Y0 + lane % 16
-    const int i2 = Y0 + lane % 16;
-    if (i2 < G.n2) {
+    // element i of plane t, half h: x1 = X0 + 4 i + lane / 16, x2 = Y0 + 16 h + lane % 16
 #pragma unroll
-        for (int t = 0; t < T3E; ++t) {
-            const int i3 = Z0 + 16 * w + t;
+    for (int h = 0; h < 2; ++h) {
+        const int i2 = Y0 + 16 * h + lane % 16;
+        if (i2 >= G.n2) continue;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int i3 = Z0 + 8 * w + t;
             if (i3 >= G.n3) continue;
             double *pp = partial + (((size_t)(s * nsplit + split) * G.n3 + i3) * G.n2 + i2) * G.n1;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int i1 = X0 + 4 * i + lane / 16;
-                if (i1 < G.n1) pp[i1] = acc[t][i];
+                if (i1 < G.n1) pp[i1] = acc[t][h][i];
             }
         }
     }
@@ -957,6 +971,13 @@ extern "C" fga_status fga3_create(fga3_ctx **out, const fga3_grid *g, const fga3
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (ctx->num_cu < 1) ctx->num_cu = 256;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k3_splat, 256, 0) != hipSuccess ||
+        occ < 1) {
+        (void)hipGetLastError();
+        occ = 2;
+    }
+    ctx->splat_slots = ctx->num_cu * occ;
     const double d[3] = {g->d1, g->d2, g->d3};
     double w = 1.0;
     for (int a = 0; a < 3; ++a) {
@@ -1095,12 +1116,23 @@ extern "C" fga_status fga3_reconstruct(fga3_ctx *ctx, const fga_beams *beams, in
     if (st != FGA_OK) return st;
     if (!u) return f3_fail(ctx, FGA_EINVAL, "u is null");
     const fga3_grid &G = ctx->g;
-    const int nt1 = (G.n1 + T3E - 1) / T3E, nt2 = (G.n2 + T3E - 1) / T3E;
+    const int nt1 = (G.n1 + T3E - 1) / T3E, nt2 = (G.n2 + T3Y - 1) / T3Y;
     const int nt3 = (G.n3 + T3Z - 1) / T3Z;
+    // slices per (shot, tile): the count whose workgroups fill the resident
+    // slots most evenly, ceil(units n / slots) / n smallest (the time of the
+    // launch in units of one whole (shot, tile)), the fewest slices on a tie
     const int64_t units = (int64_t)nt1 * nt2 * nt3 * nshots;
-    int64_t want = std::max<int64_t>(1, (4 * ctx->num_cu + units - 1) / units);
-    want = std::min<int64_t>(want, std::min<int64_t>(32, std::max(1, 65535 / nshots)));
-    const int nsplit = (int)want;
+    const int64_t slots = std::max(1, ctx->splat_slots);
+    const int nmax = (int)std::min<int64_t>(32, std::max(1, 65535 / nshots));
+    int nsplit = 1;
+    double best = 0.0;
+    for (int n = 1; n <= nmax; ++n) {
+        const double t = (double)((units * n + slots - 1) / slots) / n;
+        if (n == 1 || t < best * (1.0 - 1e-12)) {
+            best = t;
+            nsplit = n;
+        }
+    }
     const int64_t npts = (int64_t)G.n1 * G.n2 * G.n3;
     st = f3_ensure(ctx, &ctx->part, &ctx->part_bytes,
                    (size_t)nshots * nsplit * npts * sizeof(double), "splat partial sums");

@@ -2,7 +2,7 @@
 three-dimensional oracle on the same seeded inputs: beam ids bit-exact,
 coefficients, states after the RK4 and the field within 1e-10, on a ragged
 case with f0 and f1 (q- and p-meshes that do not divide the grid, partial
-16 x 16 x 64 tiles) and two shots, and on a grid two tiles deep in x3; the
+16 x 32 x 32 tiles) and two shots, and on a grid three tiles deep in x3; the
 full-size point3d workload against the oracle's propagation of sampled
 beams."""
 import numpy as np
@@ -66,9 +66,10 @@ def test_d3_fp64_matches_oracle(nshots):
         assert rel_l2(r["u"][s], us[s]) <= 1e-10
 
 
-def test_d3_field_over_two_x3_tiles():
-    """n3 = 70 > 64: the reconstruction's tiles split x3, with packets in
-    both halves and truncation boxes that straddle the split."""
+def test_d3_field_over_three_x3_tiles():
+    """n3 = 70: the reconstruction's tiles (32 deep) split x3 twice, the
+    last one ragged, with packets on both sides of the splits and truncation
+    boxes that straddle them."""
     g = i3.Grid3(12, 10, 70, 0.0, 0.1, -0.05, 1 / 24, 1 / 24, 1 / 24)
     eps = 1 / 48
     c = i3.smooth_layered_velocity3(g, 41, 2.0)
