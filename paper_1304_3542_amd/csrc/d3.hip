@@ -161,40 +161,60 @@ __device__ void vel3_eval(const double *__restrict__ c, const fga3_grid &G, cons
     }
     double c0 = 0, g1 = 0, g2 = 0, g3 = 0, k11 = 0, k12 = 0, k13 = 0, k22 = 0, k23 = 0, k33 = 0;
 #pragma unroll 1
-    for (int k3 = 0; k3 < 4; ++k3) {
-        double a0, a1, a2;
-        bw_k(fz, k3, a0, a1, a2);
-        a1 *= dz1;
-        a2 *= dz2;
-        const int r3 = min(max(i0[2] - 1 + k3, 0), n[2] - 1);
-        double s00 = 0, s10 = 0, s01 = 0, s20 = 0, s11 = 0, s02 = 0;
-        for (int k2 = 0; k2 < 4; ++k2) {
-            const int r2 = min(max(i0[1] - 1 + k2, 0), n[1] - 1);
-            const double *row = c + ((size_t)r3 * n[1] + r2) * n[0];
-            double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-            for (int k1 = 0; k1 < 4; ++k1) {
-                const double cv = row[min(max(i0[0] - 1 + k1, 0), n[0] - 1)];
-                t0 = fma(cv, w[0][0][k1], t0);
-                t1 = fma(cv, w[0][1][k1], t1);
-                t2 = fma(cv, w[0][2][k1], t2);
+    for (int kb = 0; kb < 4; kb += 2) {
+        // the 32 taps of two knot planes, every load issued before the first
+        // use (left to itself the scheduler issues them two at a time, each
+        // pair waited for: ~32 memory round trips per stage at one wavefront
+        // per SIMD instead of 2)
+        double cvs[2][4][4];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int r3 = min(max(i0[2] - 1 + kb + j, 0), n[2] - 1);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) {
+                const int r2 = min(max(i0[1] - 1 + k2, 0), n[1] - 1);
+                const double *row = c + ((size_t)r3 * n[1] + r2) * n[0];
+#pragma unroll
+                for (int k1 = 0; k1 < 4; ++k1)
+                    cvs[j][k2][k1] = row[min(max(i0[0] - 1 + k1, 0), n[0] - 1)];
             }
-            s00 = fma(t0, w[1][0][k2], s00);
-            s10 = fma(t1, w[1][0][k2], s10);
-            s01 = fma(t0, w[1][1][k2], s01);
-            s20 = fma(t2, w[1][0][k2], s20);
-            s11 = fma(t1, w[1][1][k2], s11);
-            s02 = fma(t0, w[1][2][k2], s02);
         }
-        c0 = fma(s00, a0, c0);
-        g1 = fma(s10, a0, g1);
-        g2 = fma(s01, a0, g2);
-        g3 = fma(s00, a1, g3);
-        k11 = fma(s20, a0, k11);
-        k12 = fma(s11, a0, k12);
-        k13 = fma(s10, a1, k13);
-        k22 = fma(s02, a0, k22);
-        k23 = fma(s01, a1, k23);
-        k33 = fma(s00, a2, k33);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            double a0, a1, a2;
+            bw_k(fz, kb + j, a0, a1, a2);
+            a1 *= dz1;
+            a2 *= dz2;
+            double s00 = 0, s10 = 0, s01 = 0, s20 = 0, s11 = 0, s02 = 0;
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) {
+                double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+#pragma unroll
+                for (int k1 = 0; k1 < 4; ++k1) {
+                    const double cv = cvs[j][k2][k1];
+                    t0 = fma(cv, w[0][0][k1], t0);
+                    t1 = fma(cv, w[0][1][k1], t1);
+                    t2 = fma(cv, w[0][2][k1], t2);
+                }
+                s00 = fma(t0, w[1][0][k2], s00);
+                s10 = fma(t1, w[1][0][k2], s10);
+                s01 = fma(t0, w[1][1][k2], s01);
+                s20 = fma(t2, w[1][0][k2], s20);
+                s11 = fma(t1, w[1][1][k2], s11);
+                s02 = fma(t0, w[1][2][k2], s02);
+            }
+            c0 = fma(s00, a0, c0);
+            g1 = fma(s10, a0, g1);
+            g2 = fma(s01, a0, g2);
+            g3 = fma(s00, a1, g3);
+            k11 = fma(s20, a0, k11);
+            k12 = fma(s11, a0, k12);
+            k13 = fma(s10, a1, k13);
+            k22 = fma(s02, a0, k22);
+            k23 = fma(s01, a1, k23);
+            k33 = fma(s00, a2, k33);
+        }
     }
     v.c = c0;
     v.g[0] = g1;
