@@ -752,10 +752,11 @@ __global__ void __launch_bounds__(64) k3_rk4(const double *__restrict__ c, fga3_
 // with r_a = x_a - Q_a,
 //   g_a(x_a) = exp(i P_a r_a / eps - r_a^2 / (2 eps)),   W = C a exp(iS/eps),
 // a beam adds Re(W g1 g2 g3) inside its truncation box and nothing outside.
-// The beams are staged 32 at a time, their factors at the tile's
-// coordinates formed as five runs of 16 (x1 carrying W, two halves of x2,
-// two halves of x3), one thread per (beam, run), zero outside the box: a
-// direct evaluation at the run's first node in the box and then
+// The beams are staged 48 at a time (the most that one thread per beam and
+// run fits in the workgroup), their factors at the tile's coordinates formed
+// as five runs of 16 (x1 carrying W, two halves of x2, two halves of x3),
+// zero outside the box: a direct evaluation at the run's first node in the
+// box and then
 //   g(x + d) = g(x) rho(x),   rho(x + d) = rho(x) exp(-d^2 / eps)
 // (exact identities of the Gaussian; the products add rounding over at most
 // 15 steps).  The beams whose box meets the tile are listed and taken two at
@@ -771,7 +772,7 @@ __global__ void __launch_bounds__(64) k3_rk4(const double *__restrict__ c, fga3_
 #define T3E 16   // tile edge in x1, and the length of every factor run
 #define T3Y 32   // tile edge in x2 (two runs)
 #define T3Z 32   // tile edge in x3 (two runs, 8 planes per wavefront)
-#define T3B 32   // beams staged per round
+#define T3B 48   // beams staged per round (T3R * T3B <= 256 threads)
 #define T3R 5    // factor runs per beam: x1, x2 halves, x3 halves
 
 typedef double d3x4 __attribute__((ext_vector_type(4)));
@@ -870,7 +871,7 @@ __global__ void __launch_bounds__(256, 2) k3_splat(fga_beams B, fga3_grid G, dou
         __syncthreads();
         // list the beams whose box meets the tile, in order
         if (w == 0) {
-            const int j = lane & (T3B - 1);
+            const int j = lane < T3B ? lane : 0;
             const int fl = lane < T3B && smeet[0][j] && (smeet[1][j] || smeet[2][j]) &&
                            (smeet[3][j] || smeet[4][j]);
             const unsigned long long mk = __ballot(fl);
