@@ -728,43 +728,59 @@ def cpu_model():
 
 def cpu_baseline(W, nbeams, budget_s):
     """The oracle on a bounded sample of the same workload, scaled to the
-    whole job: the FBI at the two q nodes of largest bound, scaled to the q
-    nodes the oracle visits (decompose(q_skip=True): the others cannot keep
-    a beam), and RK4 and the windowed sum for 1024 beams, scaled to the
-    job's beam count."""
+    whole job: the FBI at the NQS q nodes of largest bound (fewer if the
+    first one shows they would overrun about two thirds of budget_s seconds,
+    never fewer than NQB), scaled to the q nodes the oracle visits (decompose(q_skip=True): the others cannot keep
+    a beam), and RK4 and the windowed sum for the 2 * PER beams of largest
+    |psi| at each of the first NQB of those nodes, scaled to the job's beam
+    count."""
     import oracle
+    NQS, NQB, PER = 100, 10, 512
     g, p = W.grid, W.params
     nq = p.nq1 * p.nq2
     bound = 0.5 * oracle.fbi_bound(W.f0[0], g, p).ravel()
-    top = np.argsort(-bound, kind="stable")[:2]
+    order_q = np.argsort(-bound, kind="stable")
     t = time.perf_counter()
     psis = []
-    for q in top:
+    nqs = NQS
+    for q in order_q:
+        if len(psis) >= nqs:
+            break
         j2, j1 = divmod(int(q), p.nq1)
         one = p.replace(qb1=p.qb1 + p.qs1 * j1, qb2=p.qb2 + p.qs2 * j2, nq1=1, nq2=1)
         psis.append((one, oracle.fbi(W.f0[0], g, one)[0, 0]))
+        if len(psis) == 1:
+            # about two thirds of the budget for the FBI windows (at least NQB)
+            spent = time.perf_counter() - t
+            nqs = int(min(NQS, max(NQB, 0.65 * budget_s / max(spent, 1e-6))))
+    top = order_q[:len(psis)]
     t_per_q = (time.perf_counter() - t) / len(top)
     M = max(0.5 * np.abs(ps).max() for _, ps in psis)
     visited = int((bound * (1 + 1e-9) >= p.tau * M).sum())
     t_fbi = t_per_q * visited
-    # beams: the largest |psi| of the sampled q nodes, both branches
-    nsb = 1024
-    one, psi = psis[0]
-    order = np.argsort(-np.abs(psi.ravel()))[:nsb // 2]
-    l2, l1 = np.unravel_index(order, psi.shape)
+    # beams: at each of the first NQB sampled q nodes the PER largest |psi|,
+    # both branches
     pm1, pm2 = oracle.pmesh(p.np1, p.dp1), oracle.pmesh(p.np2, p.dp2)
-    st = np.zeros((nsb, oracle.NSTATE))
-    st[:, 0] = g.o1 + g.d1 * one.qb1
-    st[:, 1] = g.o2 + g.d2 * one.qb2
-    st[:, 2] = np.tile(pm1[l1], 2)
-    st[:, 3] = np.tile(pm2[l2], 2)
-    st[:, 5] = st[:, 11] = 1.0
-    st[:, 14] = st[:, 20] = -1.0
-    st[:, 21] = 2.0
-    sig = np.repeat(np.array([1, -1], np.int8), nsb // 2)
-    coef = np.tile(np.stack([psi.ravel()[order].real, psi.ravel()[order].imag], 1), (2, 1))
-    b = oracle.Beams(np.zeros(nsb, np.int32), sig, np.arange(nsb, dtype=np.int64),
-                     coef[:, 0] + 1j * coef[:, 1], np.ascontiguousarray(coef), st,
+    sts, coefs = [], []
+    for one, psi in psis[:NQB]:
+        order = np.argsort(-np.abs(psi.ravel()), kind="stable")[:PER]
+        l2, l1 = np.unravel_index(order, psi.shape)
+        st = np.zeros((2 * PER, oracle.NSTATE))
+        st[:, 0] = g.o1 + g.d1 * one.qb1
+        st[:, 1] = g.o2 + g.d2 * one.qb2
+        st[:, 2] = np.tile(pm1[l1], 2)
+        st[:, 3] = np.tile(pm2[l2], 2)
+        st[:, 5] = st[:, 11] = 1.0
+        st[:, 14] = st[:, 20] = -1.0
+        st[:, 21] = 2.0
+        sts.append(st)
+        coefs.append(np.tile(psi.ravel()[order], 2))
+    st = np.concatenate(sts)
+    coef = np.concatenate(coefs)
+    nsb = st.shape[0]
+    sig = np.tile(np.repeat(np.array([1, -1], np.int8), PER), NQB)
+    b = oracle.Beams(np.zeros(nsb, np.int32), sig, np.arange(nsb, dtype=np.int64), coef,
+                     np.ascontiguousarray(np.stack([coef.real, coef.imag], 1)), st,
                      np.array([0, nsb], np.int64))
     t = time.perf_counter()
     oracle.propagate(b, W.c, g, p.dt, p.nsteps)
@@ -776,10 +792,11 @@ def cpu_baseline(W, nbeams, budget_s):
     return {
         "value": nbeams / total, "unit": "beams/s", "cores": oracle.threads(),
         "cpu": cpu_model(), "kind": "oracle",
-        "sample": (f"FP64 oracle on {W.name}: FBI at the 2 q nodes of largest bound "
+        "sample": (f"FP64 oracle on {W.name}: FBI at the {len(top)} q nodes of largest bound "
                    f"({t_per_q:.2f} s each), scaled to the {visited} of {nq} q nodes it "
                    f"visits (the others cannot keep a beam); RK4 ({p.nsteps} steps) and the "
-                   f"windowed sum over the grid for {nsb} beams, scaled linearly to the "
+                   f"windowed sum over the grid for {nsb} beams (the {PER} largest |psi| at "
+                   f"each of {NQB} of those q nodes, both branches), scaled linearly to the "
                    f"{nbeams} beams of the job"),
         "est_seconds": {"fbi": t_fbi, "rk4": t_rk4, "reconstruct": t_rec},
     }
