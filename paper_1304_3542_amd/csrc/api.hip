@@ -595,9 +595,9 @@ extern "C" fga_status fga_autotune(fga_ctx *ctx, const fga_beams *beams, int32_t
         }
     }
     const int mixed[] = {4, 8, 16, 32, 64, 128};
-    const int fp64[] = {1, 2, 4, 8, 16};
+    const int fp64[] = {2, 4, 8, 16, 32, 64};
     const int *cand = ctx->prec != FGA_FP64 ? mixed : fp64;
-    int ncand = ctx->prec != FGA_FP64 ? 6 : 5;
+    const int ncand = 6;
     hipEvent_t e0, e1;
     FGA_HIP(ctx, hipEventCreate(&e0));
     FGA_HIP(ctx, hipEventCreate(&e1));

@@ -49,6 +49,7 @@ struct BinArgs {
     int64_t *meta;        // [0] hits, [1] items, [2] item length
     int32_t *list;        // beam indices
     int items_target;     // the item length is about hits / items_target
+    int tile;             // tile edge (nodes): SP_T, or SP64_T for the FP64 splat
 };
 
 __device__ __forceinline__ int bin_nchunks(const BinArgs &B)
@@ -57,14 +58,14 @@ __device__ __forceinline__ int bin_nchunks(const BinArgs &B)
     return (int)((nb + BIN_WCH - 1) / BIN_WCH);
 }
 
-__device__ __forceinline__ bool box_tiles(const short4 bx, int &t1lo, int &t1hi, int &t2lo,
-                                          int &t2hi)
+__device__ __forceinline__ bool box_tiles(const short4 bx, int T, int &t1lo, int &t1hi,
+                                          int &t2lo, int &t2hi)
 {
     if (bx.x > bx.y || bx.z > bx.w) return false;
-    t1lo = bx.x / SP_T;
-    t1hi = bx.y / SP_T;
-    t2lo = bx.z / SP_T;
-    t2hi = bx.w / SP_T;
+    t1lo = bx.x / T;
+    t1hi = bx.y / T;
+    t2lo = bx.z / T;
+    t2hi = bx.w / T;
     return true;
 }
 
@@ -88,7 +89,7 @@ k_bin_count(BinArgs B, int diff)
         for (int r = 0; r < BIN_WCH / 64; ++r) {
             const int64_t b = (int64_t)chunk * BIN_WCH + r * 64 + lane;
             int t1lo, t1hi, t2lo, t2hi;
-            if (b < nb && box_tiles(B.box[b], t1lo, t1hi, t2lo, t2hi)) {
+            if (b < nb && box_tiles(B.box[b], B.tile, t1lo, t1hi, t2lo, t2hi)) {
                 const int s = B.nshots == 1 ? 0 : (int)(B.id[b] / B.per_shot);
                 if (diff) {
                     int *d = cnt + s * per;
@@ -331,7 +332,7 @@ k_bin_fill(BinArgs B)
         for (int r = 0; r < BIN_WCH / 64; ++r) {
             const int64_t b = (int64_t)chunk * BIN_WCH + r * 64 + lane;
             int t1lo = 0, t1hi = -1, t2lo = 0, t2hi = -1, s = -1;
-            if (b < nb && box_tiles(B.box[b], t1lo, t1hi, t2lo, t2hi))
+            if (b < nb && box_tiles(B.box[b], B.tile, t1lo, t1hi, t2lo, t2hi))
                 s = B.nshots == 1 ? 0 : (int)(B.id[b] / B.per_shot);
             const int smin = wave_min(s < 0 ? 0x7fffffff : s), smax = wave_max(s);
             for (int ss = smin; ss <= smax; ++ss) {
@@ -570,6 +571,42 @@ k_splat_binned_split(SplatArgs A, BinArgs B, const SplatRec *__restrict__ rec)
     }
 }
 
+// The binned FP64 splat: one workgroup per work item (a tile of SP64_T x
+// SP64_T nodes and a run of its list), every listed beam meets the tile, so
+// the factor batches are full (16 beams) and nothing is scanned; the factor
+// runs and the rank-one updates are those of the unbinned k_splat64, and the
+// item's partial tile goes to its own slot for k_splat_reduce_binned.
+__global__ void __launch_bounds__(256)
+k_splat64_binned(SplatArgs A, BinArgs B)
+{
+    __shared__ double2 U[SP64_KC][SP64_T];
+    __shared__ double2 Vf[SP64_KC][SP64_T];
+    const int it = blockIdx.x;
+    if (it >= (int)B.meta[1]) return;            // the grid covers the most items there can be
+    const BinItem item = B.items[it];
+    const int tl = item.tile % B.ntiles;
+    const int X0 = (tl % A.ntile1) * SP64_T, Z0 = (tl / A.ntile1) * SP64_T;
+    const int t = threadIdx.x, tx = t & 15, tz = t >> 4;
+    double acc[8][8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
+    const int32_t *lst = B.list + item.start;
+    for (int k0 = 0; k0 < item.len; k0 += SP64_KC) {
+        const int k = t >> 4;
+        sp64_stage(A, k0 + k < item.len ? (int64_t)lst[k0 + k] : -1, X0, Z0, t & 15, U[k], Vf[k]);
+        __syncthreads();
+        sp64_accumulate(U, Vf, min(SP64_KC, item.len - k0), tx, tz, acc);
+        __syncthreads();
+    }
+    double *out = A.partial + (size_t)it * SP64_T * SP64_T;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) out[(tz + 16 * j) * SP64_T + tx + 16 * i] = acc[i][j];
+}
+
 // u[s][i2][i1] = the sum of the partial tiles of its tile, in item order
 __global__ void k_splat_reduce_binned(SplatArgs A, BinArgs B, double *__restrict__ u)
 {
@@ -579,8 +616,10 @@ __global__ void k_splat_reduce_binned(SplatArgs A, BinArgs B, double *__restrict
         const int s = (int)(i / npts);
         const int64_t x = i - s * npts;
         const int i2 = (int)(x / A.n1), i1 = (int)(x - (int64_t)i2 * A.n1);
-        const int tt = s * B.ntiles + (i2 / SP_T) * A.ntile1 + i1 / SP_T;
-        const int local = (i2 % SP_T) * SP_T + (i1 % SP_T);
+        const int T = B.tile;
+        const size_t T2 = (size_t)T * T;
+        const int tt = s * B.ntiles + (i2 / T) * A.ntile1 + i1 / T;
+        const int local = (i2 % T) * T + (i1 % T);
         const int a = B.tile_item[tt], e = B.tile_item[tt + 1];
         const double *p = A.partial + local;
         double v = 0.0;
@@ -589,27 +628,29 @@ __global__ void k_splat_reduce_binned(SplatArgs A, BinArgs B, double *__restrict
         for (; it + 8 <= e; it += 8) {
             double w[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) w[q] = p[(size_t)(it + q) * SP_T * SP_T];
+            for (int q = 0; q < 8; ++q) w[q] = p[(size_t)(it + q) * T2];
 #pragma unroll
             for (int q = 0; q < 8; ++q) v += w[q];
         }
-        for (; it < e; ++it) v += p[(size_t)it * SP_T * SP_T];
+        for (; it < e; ++it) v += p[(size_t)it * T2];
         u[i] = v;
     }
 }
 
-bool fga_splat_binned_fits(const fga_ctx *ctx, int nshots)
+bool fga_splat_binned_fits(const fga_ctx *ctx, int nshots, int T)
 {
-    const int64_t nt1 = (ctx->g.n1 + SP_T - 1) / SP_T, nt2 = (ctx->g.n2 + SP_T - 1) / SP_T;
+    const int64_t nt1 = (ctx->g.n1 + T - 1) / T, nt2 = (ctx->g.n2 + T - 1) / T;
     return nt1 * nt2 * nshots <= BIN_MAX_TILES;
 }
 
-// Launches the binned splat of the records and boxes k_splat_prep wrote.
+// Launches the binned splat of the boxes k_splat_prep wrote, on tiles of
+// edge `edge`: SP_T for the mixed splats (which also read its records), SP64_T
+// for the FP64 one (which reads the beams).
 fga_status fga_launch_splat_binned(fga_ctx *ctx, const fga_beams *beams, int nshots, double *u,
-                                   SplatArgs A, const void *rec, const void *box)
+                                   SplatArgs A, const void *rec, const void *box, int edge)
 {
     const fga_grid &g = ctx->g;
-    const int nt1 = (g.n1 + SP_T - 1) / SP_T, nt2 = (g.n2 + SP_T - 1) / SP_T;
+    const int nt1 = (g.n1 + edge - 1) / edge, nt2 = (g.n2 + edge - 1) / edge;
     const int ntiles = nt1 * nt2;
     const int T = ntiles * nshots;
     if (T > BIN_MAX_TILES)
@@ -617,11 +658,14 @@ fga_status fga_launch_splat_binned(fga_ctx *ctx, const fga_beams *beams, int nsh
     const int64_t cap = beams->capacity;
     const int64_t nchunks = (cap + BIN_WCH - 1) / BIN_WCH;
     // tiles one box can meet along each axis (a box is 2 Rw + 1 nodes wide)
-    const int64_t tp1 = std::min<int64_t>(nt1, 2 * ctx->Rw1 / SP_T + 2);
-    const int64_t tp2 = std::min<int64_t>(nt2, 2 * ctx->Rw2 / SP_T + 2);
-    // one wavefront per item: about units wavefronts per CU, set by the
-    // autotuner.  The sum over tiles of ceil(count / L) is at most
+    const int64_t tp1 = std::min<int64_t>(nt1, 2 * ctx->Rw1 / edge + 2);
+    const int64_t tp2 = std::min<int64_t>(nt2, 2 * ctx->Rw2 / edge + 2);
+    // one wavefront (FP64: one workgroup of four) per item: about units per
+    // CU, set by the autotuner (32 by default: at large2048 the FP64 splat
+    // takes 1.73 s with 4 and 1.36 s with 32, the last round of long items
+    // shorter).  The sum over tiles of ceil(count / L) is at most
     // hits / L + tiles, and hits / L <= items_target.
+    const bool fp64 = edge == SP64_T;
     const int units = ctx->splat_units_per_cu > 0 ? ctx->splat_units_per_cu : 32;
     const int items_target = units * ctx->num_cu;
     const int max_items = items_target + T;
@@ -641,7 +685,7 @@ fga_status fga_launch_splat_binned(fga_ctx *ctx, const fga_beams *beams, int nsh
     fga_status rc = fga_ensure(ctx, &ctx->bin, &ctx->bin_bytes, off, "binning workspace");
     if (rc != FGA_OK) return rc;
     rc = fga_ensure(ctx, (void **)&ctx->partial, &ctx->partial_bytes,
-                    (size_t)max_items * SP_T * SP_T * sizeof(double), "splat partials");
+                    (size_t)max_items * edge * edge * sizeof(double), "splat partials");
     if (rc != FGA_OK) return rc;
     char *w = (char *)ctx->bin;
     BinArgs B;
@@ -661,8 +705,10 @@ fga_status fga_launch_splat_binned(fga_ctx *ctx, const fga_beams *beams, int nsh
     B.meta = (int64_t *)(w + o_meta);
     B.list = (int32_t *)(w + o_list);
     B.items_target = items_target;
+    B.tile = edge;
     A.partial = ctx->partial;
     A.ntile1 = nt1;
+    A.tile = edge;
     const int ndiff = nshots * (nt1 + 1) * (nt2 + 1);
     const int diff = ndiff <= BIN_MAX_TILES;
     const size_t lds = (size_t)(diff ? ndiff : T) * sizeof(int);
@@ -675,7 +721,9 @@ fga_status fga_launch_splat_binned(fga_ctx *ctx, const fga_beams *beams, int nsh
     hipLaunchKernelGGL(k_bin_scan_items, dim3(1), dim3(1024), 0, ctx->stream, B);
     hipLaunchKernelGGL(k_bin_fill, dim3(cgrid), dim3(64), (size_t)T * sizeof(int64_t),
                        ctx->stream, B);
-    if (A.wmax)
+    if (fp64)
+        hipLaunchKernelGGL(k_splat64_binned, dim3(max_items), dim3(256), 0, ctx->stream, A, B);
+    else if (A.wmax)
         hipLaunchKernelGGL(k_splat_binned_split, dim3((max_items + 3) / 4), dim3(256), 0,
                            ctx->stream, A, B, (const SplatRec *)rec);
     else

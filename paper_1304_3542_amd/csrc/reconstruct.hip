@@ -29,8 +29,6 @@
 // are formed in runs of 8 consecutive nodes, one direct evaluation at the
 // run's first node in the box and then g(x + d) = g(x) rho(x),
 // rho(x + d) = rho(x) e^{-d^2/eps} (exact identities of the Gaussian).
-#define SP64_T 128
-#define SP64_KC 16
 
 __global__ void __launch_bounds__(256)
 k_splat64(SplatArgs A)
@@ -86,78 +84,9 @@ k_splat64(SplatArgs A)
         // (16 along x1, 16 along x2), two per thread
         for (int k0 = 0; k0 < nlist; k0 += SP64_KC) {
             const int k = t >> 4;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int run = (t & 15) + 16 * h;
-                const int ax = run >> 4, x0 = 8 * (run & 15);
-                double2 *dst = ax == 0 ? &U[k][x0] : &Vf[k][x0];
-                int m0 = 1, m1 = 0;                        // empty run
-                double gr = 0.0, gi = 0.0, rr = 0.0, ri = 0.0, kap = 0.0;
-                if (k0 + k < nlist) {
-                    const int64_t bb = base + lst[k0 + k];
-                    const double *p = F + bb;
-                    const double Q1 = p[(FGA_F_STATE + 0) * cap], Q2 = p[(FGA_F_STATE + 1) * cap];
-                    const BeamBox bx =
-                        beam_box(Q1, Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
-                    const int start = (ax == 0 ? X0 : Z0) + x0;
-                    const int blo = ax == 0 ? bx.lo1 : bx.lo2, bhi = ax == 0 ? bx.hi1 : bx.hi2;
-                    m0 = max(blo - start, 0);
-                    m1 = min(bhi - start, 7);
-                    if (m0 <= m1) {
-                        const double o = ax == 0 ? A.o1 : A.o2, d = ax == 0 ? A.d1 : A.d2;
-                        const double Q = ax == 0 ? Q1 : Q2;
-                        const double P = p[(FGA_F_STATE + 2 + ax) * cap];
-                        const double r = (o + (start + m0) * d) - Q;
-                        double th = P * r, cr = 1.0, ci = 0.0;
-                        if (ax == 0) {
-                            const double ar = p[(FGA_F_STATE + 21) * cap];
-                            const double ai = p[(FGA_F_STATE + 22) * cap];
-                            const double Cr = p[4 * cap], Ci = p[5 * cap];
-                            cr = Cr * ar - Ci * ai;
-                            ci = Cr * ai + Ci * ar;
-                            th += p[(FGA_F_STATE + 4) * cap];
-                        }
-                        double sn, cs;
-                        sincos(th * A.inv_eps, &sn, &cs);
-                        double e = exp(-r * r * A.half_inv_eps);
-                        const double wr = e * cs, wi = e * sn;
-                        gr = cr * wr - ci * wi;
-                        gi = cr * wi + ci * wr;
-                        sincos(P * d * A.inv_eps, &sn, &cs);
-                        e = exp(-(r + 0.5 * d) * d * A.inv_eps);
-                        rr = e * cs;
-                        ri = e * sn;
-                        kap = exp(-d * d * A.inv_eps);
-                    }
-                }
-#pragma unroll
-                for (int mm = 0; mm < 8; ++mm) {
-                    if (mm < m0 || mm > m1) {
-                        dst[mm] = double2{0.0, 0.0};
-                    } else {
-                        dst[mm] = double2{gr, gi};
-                        const double t2 = gr * rr - gi * ri;
-                        gi = gr * ri + gi * rr;
-                        gr = t2;
-                        rr *= kap;
-                        ri *= kap;
-                    }
-                }
-            }
+            sp64_stage(A, k0 + k < nlist ? base + lst[k0 + k] : -1, X0, Z0, t & 15, U[k], Vf[k]);
             __syncthreads();
-            const int kn = min(SP64_KC, nlist - k0);
-            for (int kk = 0; kk < kn; ++kk) {
-                double2 u[8], v[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) u[i] = U[kk][tx + 16 * i];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = Vf[kk][tz + 16 * j];
-#pragma unroll
-                for (int i = 0; i < 8; ++i)
-#pragma unroll
-                    for (int j = 0; j < 8; ++j)
-                        acc[i][j] = fma(u[i].x, v[j].x, fma(-u[i].y, v[j].y, acc[i][j]));
-            }
+            sp64_accumulate(U, Vf, min(SP64_KC, nlist - k0), tx, tz, acc);
             __syncthreads();
         }
     }
@@ -181,6 +110,7 @@ __global__ void k_zero_u32(unsigned *p, int n)
     if (i < n) p[i] = 0u;
 }
 
+// The splat record and the box of every beam (rec null: the boxes only)
 __global__ void __launch_bounds__(256)
 k_splat_prep(SplatArgs A, int nshots, SplatRec *__restrict__ rec, short4 *__restrict__ box)
 {
@@ -223,7 +153,7 @@ k_splat_prep(SplatArgs A, int nshots, SplatRec *__restrict__ rec, short4 *__rest
             r.hi1 = (short)max(bx.hi1, -1);
             r.lo2 = (short)min(bx.lo2, A.n2);
             r.hi2 = (short)max(bx.hi2, -1);
-            rec[b] = r;
+            if (rec) rec[b] = r;
             box[b] = make_short4(r.lo1, r.hi1, r.lo2, r.hi2);
             if (A.wmax) {
                 s = (int)(A.id[b] / A.per_shot);
@@ -374,9 +304,9 @@ __global__ void k_splat_reduce(const double *__restrict__ partial, double *__res
     }
 }
 
-bool fga_splat_binned_fits(const fga_ctx *ctx, int nshots);
+bool fga_splat_binned_fits(const fga_ctx *ctx, int nshots, int T);
 fga_status fga_launch_splat_binned(fga_ctx *ctx, const fga_beams *beams, int nshots, double *u,
-                                   SplatArgs A, const void *rec, const void *box);
+                                   SplatArgs A, const void *rec, const void *box, int T);
 
 fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nshots, double *u)
 {
@@ -410,7 +340,7 @@ fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nsho
         if (rc != FGA_OK) return rc;
         // FP16 split products: the record pass also gathers each shot's
         // largest |C a| for the binned splat's scaling
-        const bool binned = fga_splat_binned_fits(ctx, nshots);
+        const bool binned = fga_splat_binned_fits(ctx, nshots, SP_T);
         if (binned && ctx->prec == FGA_MIXED_SPLIT) {
             A.id = beams->id;
             A.per_shot = 2LL * ctx->p.nq1 * ctx->p.nq2 * ctx->p.np1 * ctx->p.np2;
@@ -422,7 +352,16 @@ fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nsho
                            nshots, (SplatRec *)ctx->srec, (short4 *)ctx->sbox);
         // beams binned per tile and split into equal work items, unless the
         // tile count exceeds the binning's LDS counters
-        if (binned) return fga_launch_splat_binned(ctx, beams, nshots, u, A, ctx->srec, ctx->sbox);
+        if (binned)
+            return fga_launch_splat_binned(ctx, beams, nshots, u, A, ctx->srec, ctx->sbox, SP_T);
+    } else if (fga_splat_binned_fits(ctx, nshots, SP64_T)) {
+        // FP64: the beams binned per 128 x 128 tile (the boxes only)
+        rc = fga_ensure(ctx, &ctx->sbox, &ctx->sbox_bytes,
+                        (size_t)beams->capacity * sizeof(short4), "splat boxes");
+        if (rc != FGA_OK) return rc;
+        hipLaunchKernelGGL(k_splat_prep, dim3(2 * ctx->num_cu), dim3(256), 0, ctx->stream, A,
+                           nshots, (SplatRec *)nullptr, (short4 *)ctx->sbox);
+        return fga_launch_splat_binned(ctx, beams, nshots, u, A, nullptr, ctx->sbox, SP64_T);
     }
     // every tile scans a slice of its shot's beams: enough slices for about
     // per_cu work units per CU (mixed: one wavefront per unit, so that the
