@@ -587,6 +587,7 @@ k_splat64_binned(SplatArgs A, BinArgs B)
     const int tl = item.tile % B.ntiles;
     const int X0 = (tl % A.ntile1) * SP64_T, Z0 = (tl / A.ntile1) * SP64_T;
     const int t = threadIdx.x, tx = t & 15, tz = t >> 4;
+    const double kap1 = exp(-A.d1 * A.d1 * A.inv_eps), kap2 = exp(-A.d2 * A.d2 * A.inv_eps);
     double acc[8][8];
 #pragma unroll
     for (int i = 0; i < 8; ++i)
@@ -595,7 +596,8 @@ k_splat64_binned(SplatArgs A, BinArgs B)
     const int32_t *lst = B.list + item.start;
     for (int k0 = 0; k0 < item.len; k0 += SP64_KC) {
         const int k = t >> 4;
-        sp64_stage(A, k0 + k < item.len ? (int64_t)lst[k0 + k] : -1, X0, Z0, t & 15, U[k], Vf[k]);
+        sp64_stage(A, k0 + k < item.len ? (int64_t)lst[k0 + k] : -1, X0, Z0, t & 15, kap1, kap2,
+                       U[k], Vf[k]);
         __syncthreads();
         sp64_accumulate(U, Vf, min(SP64_KC, item.len - k0), tx, tz, acc);
         __syncthreads();

@@ -26,7 +26,7 @@
 //   U(x1) = C a e^{(i (S + P1 r1) - r1^2/2) / eps},  V(x2) = e^{(i P2 r2 - r2^2/2) / eps}
 // at the tile's 128 + 128 coordinates (zero outside the box) go to LDS, and
 // every thread adds Re(U V) = Ur Vr - Ui Vi to its 64 nodes.  The factors
-// are formed in runs of 8 consecutive nodes, one direct evaluation at the
+// are formed in runs of 16 consecutive nodes, one direct evaluation at the
 // run's first node in the box and then g(x + d) = g(x) rho(x),
 // rho(x + d) = rho(x) e^{-d^2/eps} (exact identities of the Gaussian).
 
@@ -48,6 +48,7 @@ k_splat64(SplatArgs A)
     const int64_t lo = b0 + nbs * split / A.nsplit, hi = b0 + nbs * (split + 1) / A.nsplit;
     const int64_t cap = A.cap;
     const double *F = A.f;
+    const double kap1 = exp(-A.d1 * A.d1 * A.inv_eps), kap2 = exp(-A.d2 * A.d2 * A.inv_eps);
 
     double acc[8][8];
 #pragma unroll
@@ -80,11 +81,12 @@ k_splat64(SplatArgs A)
         if (hit) lst[wb + before] = t;
         __syncthreads();
 
-        // 2. factor batches and rank-one accumulation: 32 runs of 8 per beam
-        // (16 along x1, 16 along x2), two per thread
+        // 2. factor batches and rank-one accumulation: 16 runs of 16 per beam
+        // (8 along x1, 8 along x2), one per thread
         for (int k0 = 0; k0 < nlist; k0 += SP64_KC) {
             const int k = t >> 4;
-            sp64_stage(A, k0 + k < nlist ? base + lst[k0 + k] : -1, X0, Z0, t & 15, U[k], Vf[k]);
+            sp64_stage(A, k0 + k < nlist ? base + lst[k0 + k] : -1, X0, Z0, t & 15, kap1, kap2,
+                       U[k], Vf[k]);
             __syncthreads();
             sp64_accumulate(U, Vf, min(SP64_KC, nlist - k0), tx, tz, acc);
             __syncthreads();

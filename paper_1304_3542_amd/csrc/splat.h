@@ -35,69 +35,65 @@ struct SplatArgs {
 //
 // The factors of beam b (none if b < 0) at the tile's coordinates,
 //   U(x1) = C a e^{(i (S + P1 r1) - r1^2/2) / eps},  V(x2) = e^{(i P2 r2 - r2^2/2) / eps},
-// zero outside the beam's box, as 32 runs of 8 nodes (16 along x1 into u, 16
-// along x2 into v); thread j < 16 of the beam's 16 forms runs j and j + 16:
-// one direct evaluation at the run's first node in the box and then
+// zero outside the beam's box, as 16 runs of 16 nodes (8 along x1 into u, 8
+// along x2 into v); thread j < 16 of the beam's 16 forms run j: one direct
+// evaluation at the run's first node in the box and then
 // g(x + d) = g(x) rho(x), rho(x + d) = rho(x) e^{-d^2/eps} (exact identities
-// of the Gaussian).
+// of the Gaussian; kap1, kap2 = e^{-d^2/eps} of the two axes).
 __device__ __forceinline__ void sp64_stage(const SplatArgs &A, int64_t b, int X0, int Z0, int j,
-                                           double2 *u, double2 *v)
+                                           double kap1, double kap2, double2 *u, double2 *v)
 {
     const int64_t cap = A.cap;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int run = j + 16 * h;
-        const int ax = run >> 4, x0 = 8 * (run & 15);
-        double2 *dst = ax == 0 ? u + x0 : v + x0;
-        int m0 = 1, m1 = 0;                        // empty run
-        double gr = 0.0, gi = 0.0, rr = 0.0, ri = 0.0, kap = 0.0;
-        if (b >= 0) {
-            const double *p = A.f + b;
-            const double Q1 = p[(FGA_F_STATE + 0) * cap], Q2 = p[(FGA_F_STATE + 1) * cap];
-            const BeamBox bx = beam_box(Q1, Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
-            const int start = (ax == 0 ? X0 : Z0) + x0;
-            const int blo = ax == 0 ? bx.lo1 : bx.lo2, bhi = ax == 0 ? bx.hi1 : bx.hi2;
-            m0 = max(blo - start, 0);
-            m1 = min(bhi - start, 7);
-            if (m0 <= m1) {
-                const double o = ax == 0 ? A.o1 : A.o2, d = ax == 0 ? A.d1 : A.d2;
-                const double Q = ax == 0 ? Q1 : Q2;
-                const double P = p[(FGA_F_STATE + 2 + ax) * cap];
-                const double r = (o + (start + m0) * d) - Q;
-                double th = P * r, cr = 1.0, ci = 0.0;
-                if (ax == 0) {
-                    const double ar = p[(FGA_F_STATE + 21) * cap];
-                    const double ai = p[(FGA_F_STATE + 22) * cap];
-                    const double Cr = p[4 * cap], Ci = p[5 * cap];
-                    cr = Cr * ar - Ci * ai;
-                    ci = Cr * ai + Ci * ar;
-                    th += p[(FGA_F_STATE + 4) * cap];
-                }
-                double sn, cs;
-                sincos(th * A.inv_eps, &sn, &cs);
-                double e = exp(-r * r * A.half_inv_eps);
-                const double wr = e * cs, wi = e * sn;
-                gr = cr * wr - ci * wi;
-                gi = cr * wi + ci * wr;
-                sincos(P * d * A.inv_eps, &sn, &cs);
-                e = exp(-(r + 0.5 * d) * d * A.inv_eps);
-                rr = e * cs;
-                ri = e * sn;
-                kap = exp(-d * d * A.inv_eps);
+    const int ax = j >> 3, x0 = 16 * (j & 7);
+    double2 *dst = ax == 0 ? u + x0 : v + x0;
+    const double kap = ax == 0 ? kap1 : kap2;
+    int m0 = 1, m1 = 0;                        // empty run
+    double gr = 0.0, gi = 0.0, rr = 0.0, ri = 0.0;
+    if (b >= 0) {
+        const double *p = A.f + b;
+        const double Q1 = p[(FGA_F_STATE + 0) * cap], Q2 = p[(FGA_F_STATE + 1) * cap];
+        const BeamBox bx = beam_box(Q1, Q2, A.o1, A.o2, A.d1, A.d2, A.Rw1, A.Rw2, A.n1, A.n2);
+        const int start = (ax == 0 ? X0 : Z0) + x0;
+        const int blo = ax == 0 ? bx.lo1 : bx.lo2, bhi = ax == 0 ? bx.hi1 : bx.hi2;
+        m0 = max(blo - start, 0);
+        m1 = min(bhi - start, 15);
+        if (m0 <= m1) {
+            const double o = ax == 0 ? A.o1 : A.o2, d = ax == 0 ? A.d1 : A.d2;
+            const double Q = ax == 0 ? Q1 : Q2;
+            const double P = p[(FGA_F_STATE + 2 + ax) * cap];
+            const double r = (o + (start + m0) * d) - Q;
+            double th = P * r, cr = 1.0, ci = 0.0;
+            if (ax == 0) {
+                const double ar = p[(FGA_F_STATE + 21) * cap];
+                const double ai = p[(FGA_F_STATE + 22) * cap];
+                const double Cr = p[4 * cap], Ci = p[5 * cap];
+                cr = Cr * ar - Ci * ai;
+                ci = Cr * ai + Ci * ar;
+                th += p[(FGA_F_STATE + 4) * cap];
             }
+            double sn, cs;
+            sincos(th * A.inv_eps, &sn, &cs);
+            double e = exp(-r * r * A.half_inv_eps);
+            const double wr = e * cs, wi = e * sn;
+            gr = cr * wr - ci * wi;
+            gi = cr * wi + ci * wr;
+            sincos(P * d * A.inv_eps, &sn, &cs);
+            e = exp(-(r + 0.5 * d) * d * A.inv_eps);
+            rr = e * cs;
+            ri = e * sn;
         }
+    }
 #pragma unroll
-        for (int mm = 0; mm < 8; ++mm) {
-            if (mm < m0 || mm > m1) {
-                dst[mm] = double2{0.0, 0.0};
-            } else {
-                dst[mm] = double2{gr, gi};
-                const double t2 = gr * rr - gi * ri;
-                gi = gr * ri + gi * rr;
-                gr = t2;
-                rr *= kap;
-                ri *= kap;
-            }
+    for (int mm = 0; mm < 16; ++mm) {
+        if (mm < m0 || mm > m1) {
+            dst[mm] = double2{0.0, 0.0};
+        } else {
+            dst[mm] = double2{gr, gi};
+            const double t2 = gr * rr - gi * ri;
+            gi = gr * ri + gi * rr;
+            gr = t2;
+            rr *= kap;
+            ri *= kap;
         }
     }
 }

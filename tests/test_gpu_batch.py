@@ -149,7 +149,7 @@ def test_autotune_choice_and_cache(precision, tmp_path):
     with torch.cuda.stream(stream):
         v = ctx.autotune(beams, f0.shape[0], u, cache)
         stream.synchronize()
-    allowed = {"mixed": {4, 8, 16, 32, 64, 128}, "fp64": {1, 2, 4, 8, 16}}[precision]
+    allowed = {"mixed": {4, 8, 16, 32, 64, 128}, "fp64": {2, 4, 8, 16, 32, 64}}[precision]
     assert v in allowed
     assert os.path.exists(cache) and '"splat_units_per_cu": %d' % v in open(cache).read()
     tol = 1e-12 if precision == "fp64" else 1e-6
