@@ -572,10 +572,22 @@ k_splat_binned_split(SplatArgs A, BinArgs B, const SplatRec *__restrict__ rec)
 }
 
 // The binned FP64 splat: one workgroup per work item (a tile of SP64_T x
-// SP64_T nodes and a run of its list), every listed beam meets the tile, so
-// the factor batches are full (16 beams) and nothing is scanned; the factor
-// runs and the rank-one updates are those of the unbinned k_splat64, and the
-// item's partial tile goes to its own slot for k_splat_reduce_binned.
+// SP64_T nodes and a run of its list); every listed beam meets the tile, so
+// the factor batches are full (16 beams) and nothing is scanned.  The
+// factors are staged as in k_splat64 (V conjugated), and the sum runs on
+// the FP64 matrix cores: wavefront w owns the 64 x 64 quadrant
+// (x1 from X0 + 64 (w & 1), x2 from Z0 + 64 (w >> 1)), 4 x 4 blocks of
+// 16 x 16, and the beams are taken two at a time,
+//   u[x1][x2] += sum_k A[x1][k] B[k][x2],  k = (beam of the pair, re / im),
+//   A = [Re U, Im U],  B = [Re conj V ; Im conj V] = [Re V ; -Im V],
+// one v_mfma_f64_16x16x4f64 per block (lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; element i of its result is D[4 i + l / 16][l % 16]).
+// A and B are read from the staged factors as they are: no vector FP64
+// work in the loop (the matrix cores and the FP64 vector instructions share
+// one pipe).  An odd batch pairs its last beam with a slot staged as zero.
+// The item's partial tile goes to its own slot for k_splat_reduce_binned.
+typedef double sp64x4 __attribute__((ext_vector_type(4)));
+
 __global__ void __launch_bounds__(256)
 k_splat64_binned(SplatArgs A, BinArgs B)
 {
@@ -586,27 +598,51 @@ k_splat64_binned(SplatArgs A, BinArgs B)
     const BinItem item = B.items[it];
     const int tl = item.tile % B.ntiles;
     const int X0 = (tl % A.ntile1) * SP64_T, Z0 = (tl / A.ntile1) * SP64_T;
-    const int t = threadIdx.x, tx = t & 15, tz = t >> 4;
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int q1 = 64 * (w & 1), q2 = 64 * (w >> 1);
+    const int mrow = lane & 15, pb = lane >> 5, part = (lane >> 4) & 1;
     const double kap1 = exp(-A.d1 * A.d1 * A.inv_eps), kap2 = exp(-A.d2 * A.d2 * A.inv_eps);
-    double acc[8][8];
+    sp64x4 acc[4][4];
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
+        for (int c = 0; c < 4; ++c) acc[a][c] = sp64x4{0.0, 0.0, 0.0, 0.0};
     const int32_t *lst = B.list + item.start;
     for (int k0 = 0; k0 < item.len; k0 += SP64_KC) {
         const int k = t >> 4;
-        sp64_stage(A, k0 + k < item.len ? (int64_t)lst[k0 + k] : -1, X0, Z0, t & 15, kap1, kap2,
-                       U[k], Vf[k]);
+        sp64_stage<true>(A, k0 + k < item.len ? (int64_t)lst[k0 + k] : -1, X0, Z0, t & 15, kap1,
+                         kap2, U[k], Vf[k]);
         __syncthreads();
-        sp64_accumulate(U, Vf, min(SP64_KC, item.len - k0), tx, tz, acc);
+        const int kn = min(SP64_KC, item.len - k0);
+        for (int p = 0; p < kn; p += 2) {
+            // this lane's beam of the pair and part: slot p + pb (staged as
+            // zero past the batch), component part of the stored pair
+            const double *ua = reinterpret_cast<const double *>(&U[p + pb][q1 + mrow]) + part;
+            const double *vb = reinterpret_cast<const double *>(&Vf[p + pb][q2 + mrow]) + part;
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = ua[32 * a];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) bv[c] = vb[32 * c];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[c], acc[a][c], 0,
+                                                                     0, 0);
+        }
         __syncthreads();
     }
+    // element i of block (a, c): x1 = q1 + 16 a + 4 i + lane / 16, x2 = q2 + 16 c + lane % 16
     double *out = A.partial + (size_t)it * SP64_T * SP64_T;
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int i = 0; i < 8; ++i) out[(tz + 16 * j) * SP64_T + tx + 16 * i] = acc[i][j];
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                out[(q2 + 16 * c + mrow) * SP64_T + q1 + 16 * a + 4 * i + (lane >> 4)] =
+                    acc[a][c][i];
 }
 
 // u[s][i2][i1] = the sum of the partial tiles of its tile, in item order

@@ -35,11 +35,13 @@ struct SplatArgs {
 //
 // The factors of beam b (none if b < 0) at the tile's coordinates,
 //   U(x1) = C a e^{(i (S + P1 r1) - r1^2/2) / eps},  V(x2) = e^{(i P2 r2 - r2^2/2) / eps},
-// zero outside the beam's box, as 16 runs of 16 nodes (8 along x1 into u, 8
-// along x2 into v); thread j < 16 of the beam's 16 forms run j: one direct
+// zero outside the beam's box (CONJ_V: conj V into v), as 16 runs of 16
+// nodes (8 along x1 into u, 8 along x2 into v); thread j < 16 of the beam's
+// 16 forms run j: one direct
 // evaluation at the run's first node in the box and then
 // g(x + d) = g(x) rho(x), rho(x + d) = rho(x) e^{-d^2/eps} (exact identities
 // of the Gaussian; kap1, kap2 = e^{-d^2/eps} of the two axes).
+template <bool CONJ_V = false>
 __device__ __forceinline__ void sp64_stage(const SplatArgs &A, int64_t b, int X0, int Z0, int j,
                                            double kap1, double kap2, double2 *u, double2 *v)
 {
@@ -81,6 +83,11 @@ __device__ __forceinline__ void sp64_stage(const SplatArgs &A, int64_t b, int X0
             e = exp(-(r + 0.5 * d) * d * A.inv_eps);
             rr = e * cs;
             ri = e * sn;
+            if (CONJ_V && ax == 1) {
+                // conj V: the conjugate start and ratio give the conjugate run
+                gi = -gi;
+                ri = -ri;
+            }
         }
     }
 #pragma unroll
