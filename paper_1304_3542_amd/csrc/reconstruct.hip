@@ -412,8 +412,9 @@ fga_status fga_launch_reconstruct(fga_ctx *ctx, const fga_beams *beams, int nsho
 //    evaluation and a complex product per column of its box.  The lanes'
 //    terms at 16 columns at a time are summed over the wavefront by a fixed
 //    reduce-scatter (four halving exchanges leave each lane one column's
-//    sum over 16 lanes, two butterfly steps finish it), per wavefront in
-//    LDS, and the four wavefronts in order.
+//    sum over 16 lanes, two butterfly steps finish it; permlane swaps and
+//    DPP moves, no LDS), per wavefront in LDS, and the four wavefronts in
+//    order.
 #define TR_BLOCK 256
 #define TR_ROW_MAX 1024
 
@@ -455,19 +456,76 @@ fga_status fga_rec_shape(fga_ctx *ctx, const int32_t *rec, int nrec, const int *
     return rc;
 }
 
-__device__ __forceinline__ int tr_wave_min(int v)
+// Lane exchanges without the LDS crossbar (ds_bpermute waits on it):
+// v_permlane32_swap(x, y) exchanges the upper half of x with the lower half
+// of y, v_permlane16_swap(x, y) the odd rows of x with the even rows of y, so
+// after either the sum (min, max) of the two registers is, in every lane,
+// that of x at lane l and l ^ 32 (16) for the lanes where the bit is clear
+// and that of y for the others; DPP moves within a row of 16 (row_ror:8 is
+// lane ^ 8; lane ^ 4 is row_ror:4 where bit 2 is clear, row_ror:12 where it
+// is set) and within a quad (lane ^ 2, lane ^ 1).
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp32(unsigned x)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double x)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = dpp32<CTRL>((unsigned)u), hi = dpp32<CTRL>((unsigned)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+#define DPP_ROR(n) (0x120 + (n))
+#define DPP_QXOR1 0xb1   // quad_perm [1, 0, 3, 2]
+#define DPP_QXOR2 0x4e   // quad_perm [2, 3, 0, 1]
+
+template <bool HALF32>
+__device__ __forceinline__ void swap64(double &x, double &y)
+{
+    const unsigned long long ux = (unsigned long long)__double_as_longlong(x);
+    const unsigned long long uy = (unsigned long long)__double_as_longlong(y);
+    const unsigned xl = (unsigned)ux, xh = (unsigned)(ux >> 32);
+    const unsigned yl = (unsigned)uy, yh = (unsigned)(uy >> 32);
+    auto l = HALF32 ? __builtin_amdgcn_permlane32_swap(xl, yl, false, false)
+                    : __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+    auto h = HALF32 ? __builtin_amdgcn_permlane32_swap(xh, yh, false, false)
+                    : __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+    x = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
+    y = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+}
+
+// v at lane ^ 4 (within the row; row_ror:k reads lane (i - k) mod 16)
+__device__ __forceinline__ unsigned xor4_32(unsigned v, bool up)
+{
+    const unsigned a = dpp32<DPP_ROR(4)>(v), b = dpp32<DPP_ROR(12)>(v);
+    return up ? a : b;
+}
+
+template <bool MAX>
+__device__ __forceinline__ int tr_wave_reduce(int v)
+{
+    const int lane = threadIdx.x & 63;
+    auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+    {
+        auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+        v = op((int)r[0], (int)r[1]);
+    }
+    {
+        auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+        v = op((int)r[0], (int)r[1]);
+    }
+    v = op(v, (int)dpp32<DPP_ROR(8)>((unsigned)v));
+    v = op(v, (int)xor4_32((unsigned)v, (lane & 4) != 0));
+    v = op(v, (int)dpp32<DPP_QXOR2>((unsigned)v));
+    v = op(v, (int)dpp32<DPP_QXOR1>((unsigned)v));
     return v;
 }
 
-__device__ __forceinline__ int tr_wave_max(int v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
+__device__ __forceinline__ int tr_wave_min(int v) { return tr_wave_reduce<false>(v); }
+__device__ __forceinline__ int tr_wave_max(int v) { return tr_wave_reduce<true>(v); }
 
 // the row form for beams [lo, hi) of one shot: out[r] for the receiver at
 // column run1 + r of row run2; acc = [4][nrec] doubles of LDS
@@ -531,20 +589,37 @@ __device__ void trace_row(const SplatArgs &A, double *acc, int run1, int run2, i
                     ri *= kap;
                 }
             }
+            // lane ^ 32, lane ^ 16: after the swap the two registers hold
+            // this lane's kept column and its partner's, added as before
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int m = 32 >> s, h = 8 >> s;
-                const bool up = (lane & m) != 0;
+            for (int j = 0; j < 8; ++j) {
+                swap64<true>(v[j], v[j + 8]);
+                v[j] = v[j] + v[j + 8];
+            }
 #pragma unroll
-                for (int j = 0; j < h; ++j) {
-                    const double send = up ? v[j] : v[j + h];
-                    const double keep = up ? v[j + h] : v[j];
-                    v[j] = keep + __shfl_xor(send, m, 64);
+            for (int j = 0; j < 4; ++j) {
+                swap64<false>(v[j], v[j + 4]);
+                v[j] = v[j] + v[j + 4];
+            }
+            {
+                const bool up = (lane & 8) != 0;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const double send = up ? v[j] : v[j + 2];
+                    const double keep = up ? v[j + 2] : v[j];
+                    v[j] = keep + dpp64<DPP_ROR(8)>(send);
                 }
             }
+            {
+                const bool up = (lane & 4) != 0;
+                const double send = up ? v[0] : v[1];
+                const double keep = up ? v[1] : v[0];
+                const double a = dpp64<DPP_ROR(4)>(send), b = dpp64<DPP_ROR(12)>(send);
+                v[0] = keep + (up ? a : b);
+            }
             double t = v[0];
-            t += __shfl_xor(t, 2, 64);
-            t += __shfl_xor(t, 1, 64);
+            t += dpp64<DPP_QXOR2>(t);
+            t += dpp64<DPP_QXOR1>(t);
             if ((lane & 3) == 0 && c0 + jl <= u1) mine[c0 + jl - run1] += t;
         }
     }
