@@ -1,5 +1,6 @@
-"""Host-side checks of bench.py: the one-GPU guard and the lookup of the
-committed HBM counters for the kernels its roofline names."""
+"""Host-side checks of bench.py: the one-GPU guard, the lookup of the
+committed HBM counters for the kernels its roofline names, the default
+workload and the host baseline's sampling."""
 import importlib.util
 import json
 import os
@@ -66,3 +67,21 @@ def test_default_headline_is_the_largest_configuration():
     finally:
         sys.argv = sys_argv
     assert args.workload == "large2048" and args.steps >= 5 and args.graph_steps >= 1
+
+
+def test_cpu_baseline_on_a_small_workload():
+    """The host baseline samples the FBI windows and the beams it says it
+    does and scales them to the job: on the 128 x 128 wave-packet workload
+    (the oracle finishes the sample in seconds) the figures are positive,
+    the stage estimates add up to the job time, and the sample text names
+    the counts."""
+    import fga_inputs as fi
+    b = load_bench()
+    W = fi.workload("wavepacket", "fp64")
+    nb = 1_000_000
+    r = b.cpu_baseline(W, nb, 2.0)
+    est = r["est_seconds"]
+    assert set(est) == {"fbi", "rk4", "reconstruct"} and min(est.values()) > 0
+    assert abs(nb / sum(est.values()) - r["value"]) <= 1e-9 * r["value"]
+    assert r["kind"] == "oracle" and r["unit"] == "beams/s" and r["cores"] >= 1
+    assert "10240 beams" in r["sample"] and "of 4096 q nodes" in r["sample"]
