@@ -79,26 +79,32 @@ __device__ __forceinline__ void cell_dma(const double *a, unsigned lds, unsigned
 // at this request rate one line per request and the shorter evaluation win
 // over the 16 taps of the padded grid.)  The wavefront issues no other
 // vector-memory load inside the step loop, so waiting for every outstanding
-// one waits exactly for these.
+// one waits exactly for these.  Every evaluation is at the position of the
+// request before it, so the cell and offsets found by prefetch() are kept
+// and eval() does not locate the cell again (its position arguments are
+// that same point).
 struct VelDma {
     VelGrid V;
     double2 *buf;   // this wavefront's 8 slots of 64 entries
     int lane;
     int cur1, cur2;   // knot cell whose coefficients the slots hold (none at first)
+    double f1, f2;    // offsets in that cell of the requested position
     __device__ __forceinline__ void prefetch(double x1, double x2)
     {
         const VelCell k = vel_cell(V, x1, x2);
         const bool changed = k.i1 != cur1 || k.i2 != cur2;
         cur1 = k.i1;
         cur2 = k.i2;
+        f1 = k.f1;
+        f2 = k.f2;
         cell_dma(vel_cell_coef(V, k), (unsigned)(size_t)(lds_void *)buf, __ballot(changed));
     }
-    __device__ __forceinline__ void eval(double x1, double x2, double &c, double &c1, double &c2,
+    __device__ __forceinline__ void eval(double, double, double &c, double &c1, double &c2,
                                          double &c11, double &c12, double &c22) const
     {
         // the LDS writes of global_load_lds complete with the load counter
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        const VelCell k = vel_cell(V, x1, x2);
+        const VelCell k = {cur1, cur2, f1, f2};
         double C[4][4];
 #pragma unroll
         for (int sl = 0; sl < 8; ++sl) {
@@ -149,7 +155,7 @@ k_rk4(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
     const int tid = threadIdx.x;
     // the wavefront index is uniform: keep the LDS base in a scalar register
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    VelDma vel{V, slots[wave], tid & 63, INT_MIN, INT_MIN};
+    VelDma vel{V, slots[wave], tid & 63, INT_MIN, INT_MIN, 0.0, 0.0};
     int64_t nb = offsets[nshots];
     for (int64_t b0 = (int64_t)blockIdx.x * RK_BLOCK; b0 < nb;
          b0 += (int64_t)gridDim.x * RK_BLOCK) {
@@ -305,7 +311,7 @@ k_rk4_dd(VelGrid V, double *__restrict__ f, const int64_t *__restrict__ id,
     const double hs = role == 0 ? 0.0 : (((role - 1) & 1) ? -h[r] : h[r]);
     const int dj = r & 1;
     const bool alongp = r >= 2;
-    VelDma vel{V, slots[wave], lane, INT_MIN, INT_MIN};
+    VelDma vel{V, slots[wave], lane, INT_MIN, INT_MIN, 0.0, 0.0};
     double2 *wq = xq[wave], *wp = xp[wave];
     const int64_t nb = offsets[nshots];
     const int64_t per_block = (int64_t)(RK_BLOCK / 64) * DD_BEAMS;

@@ -14,6 +14,15 @@ __device__ __forceinline__ Cd cmul(Cd a, Cd b) { return {a.r * b.r - a.i * b.i, 
 __device__ __forceinline__ Cd cadd(Cd a, Cd b) { return {a.r + b.r, a.i + b.i}; }
 __device__ __forceinline__ Cd csub(Cd a, Cd b) { return {a.r - b.r, a.i - b.i}; }
 __device__ __forceinline__ Cd cscale(Cd a, double s) { return {a.r * s, a.i * s}; }
+// acc + a b and acc - a b as FMA chains (no separate product and add)
+__device__ __forceinline__ Cd cfma(Cd a, Cd b, Cd acc)
+{
+    return {fma(a.r, b.r, fma(-a.i, b.i, acc.r)), fma(a.r, b.i, fma(a.i, b.r, acc.i))};
+}
+__device__ __forceinline__ Cd cfms(Cd a, Cd b, Cd acc)
+{
+    return {fma(-a.r, b.r, fma(a.i, b.i, acc.r)), fma(-a.r, b.i, fma(-a.i, b.r, acc.i))};
+}
 
 // State layout (23 doubles): Q1 Q2 P1 P2 S | A11 A12 A21 A22 (re,im) |
 // B11 B12 B21 B22 (re,im) | a (re,im)
@@ -225,8 +234,8 @@ __device__ __forceinline__ void rk_stage(Vel &vel, double s, St &t, St &acc, con
                 {t.A[0][1].r - t.B[0][1].i, t.A[0][1].i + t.B[0][1].r}};
     Cd Z1[2] = {{t.A[1][0].r - t.B[1][0].i, t.A[1][0].i + t.B[1][0].r},
                 {t.A[1][1].r - t.B[1][1].i, t.A[1][1].i + t.B[1][1].r}};
-    Cd det = csub(cmul(Z0[0], Z1[1]), cmul(Z0[1], Z1[0]));
-    Cd num = {0.0, 0.0};
+    const Cd det = cfms(Z0[1], Z1[0], cmul(Z0[0], Z1[1]));
+    Cd num;
     // sign-folded coefficients of the rank-one updates
     double su1 = s * u1, su2 = s * u2, scon = s * con;
     double nK11 = -s * n * K11, nK12 = -s * n * K12, nK22 = -s * n * K22;
@@ -246,9 +255,9 @@ __device__ __forceinline__ void rk_stage(Vel &vel, double s, St &t, St &acc, con
         Cd dZ1 = {kA1.r - kB1.i, kA1.i + kB1.r};
         // adjugate trace: row 0 pairs with (Z22, -Z21), row 1 with (-Z12, Z11)
         if (j == 0)
-            num = cadd(num, csub(cmul(Z1[1], dZ0), cmul(Z1[0], dZ1)));
+            num = cfms(Z1[0], dZ1, cmul(Z1[1], dZ0));
         else
-            num = cadd(num, csub(cmul(Z0[0], dZ1), cmul(Z0[1], dZ0)));
+            num = cfms(Z0[1], dZ0, cfma(Z0[0], dZ1, num));
         acc.A[j][0] = {fma(wacc, kA0.r, acc.A[j][0].r), fma(wacc, kA0.i, acc.A[j][0].i)};
         acc.A[j][1] = {fma(wacc, kA1.r, acc.A[j][1].r), fma(wacc, kA1.i, acc.A[j][1].i)};
         acc.B[j][0] = {fma(wacc, kB0.r, acc.B[j][0].r), fma(wacc, kB0.i, acc.B[j][0].i)};
@@ -261,9 +270,10 @@ __device__ __forceinline__ void rk_stage(Vel &vel, double s, St &t, St &acc, con
         }
     }
     if (AMP) {
-        double id2 = rcp64(det.r * det.r + det.i * det.i);
-        Cd tr = cscale(cmul(num, Cd{det.r, -det.i}), id2);
-        Cd ka = cmul(t.a, Cd{ug + 0.5 * tr.r, 0.5 * tr.i});
+        // tr(Z^{-1} dZ) / 2 = num conj(det Z) / (2 |det Z|^2)
+        const double hid2 = 0.5 * rcp64(fma(det.r, det.r, det.i * det.i));
+        const Cd w = cmul(num, Cd{det.r, -det.i});
+        Cd ka = cmul(t.a, Cd{fma(w.r, hid2, ug), w.i * hid2});
         acc.a = {fma(wacc, ka.r, acc.a.r), fma(wacc, ka.i, acc.a.i)};
         if (!LAST) t.a = {fma(hnext, ka.r, y.a.r), fma(hnext, ka.i, y.a.i)};
     }
