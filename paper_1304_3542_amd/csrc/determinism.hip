@@ -8,8 +8,9 @@
 //   2. the records are listed as (cell, log slot) in beam-then-sequence order
 //      and sorted by cell with a stable radix sort, so every cell's records
 //      stay in beam-then-sequence order,
-//   3. one wavefront per cell sums its records (lane l takes every 64th from
-//      the l-th, in order; then a fixed butterfly over the lanes),
+//   3. one wavefront per cell sums its records (eight lanes per record, one
+//      16-byte part each; lane group r takes every 8th record from the r-th,
+//      in order; then a fixed butterfly over the groups),
 //   4. one thread per grid knot adds the sums of the cells that reach it (the
 //      clamped 4 x 4 knot stencil of the B-spline) in a fixed cell order.
 // Integer atomics only count; every floating-point sum has a fixed order.
@@ -82,9 +83,11 @@ __global__ void k_det_bounds(const unsigned *__restrict__ keys, int64_t total, i
     }
 }
 
-// the 16 knot sums of every cell: one wavefront per cell, lane l adding the
-// records l, l + 64, ... of the cell's run in order, then a butterfly over
-// the lanes (a fixed tree), so the result does not depend on scheduling
+// the 16 knot sums of every cell: one wavefront per cell.  Lane 8 r + h
+// holds components 2 h, 2 h + 1 and adds the records r, r + 8, ... of the
+// cell's run in order, so one load instruction reads eight whole 128-byte
+// records; then a fixed butterfly over r.  The order does not depend on
+// scheduling.
 __global__ void __launch_bounds__(256)
 k_det_cellsum(const int *__restrict__ begin, const int *__restrict__ end,
               const unsigned long long *__restrict__ slots, const double *__restrict__ rec,
@@ -92,26 +95,37 @@ k_det_cellsum(const int *__restrict__ begin, const int *__restrict__ end,
 {
     const int c = blockIdx.x * 4 + (threadIdx.x >> 6);   // uniform in the wavefront
     const int lane = threadIdx.x & 63;
+    const int r = lane >> 3, h = lane & 7;
     if (c >= ncell) return;
-    double t[16];
+    double t0 = 0.0, t1 = 0.0;
+    const int e = end[c];
+    int j = begin[c] + r;
+    // four records of this lane in flight, added in their order
+    for (; j + 24 < e; j += 32) {
+        double2 v[4];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) t[m] = 0.0;
-    for (int j = begin[c] + lane; j < end[c]; j += 64) {
-        const double2 *r = (const double2 *)(rec + (size_t)slots[j] * 16);
+        for (int q = 0; q < 4; ++q)
+            v[q] = reinterpret_cast<const double2 *>(rec + (size_t)slots[j + 8 * q] * 16)[h];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const double2 v = r[m];
-            t[2 * m] += v.x;
-            t[2 * m + 1] += v.y;
+        for (int q = 0; q < 4; ++q) {
+            t0 += v[q].x;
+            t1 += v[q].y;
         }
     }
+    for (; j < e; j += 8) {
+        const double2 v = reinterpret_cast<const double2 *>(rec + (size_t)slots[j] * 16)[h];
+        t0 += v.x;
+        t1 += v.y;
+    }
 #pragma unroll
-    for (int m = 0; m < 16; ++m)
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) t[m] += __shfl_xor(t[m], o, 64);
-    if (lane == 0)
-#pragma unroll
-        for (int m = 0; m < 16; ++m) tot[(size_t)m * ncell + c] = t[m];
+    for (int o = 8; o <= 32; o <<= 1) {
+        t0 += __shfl_xor(t0, o, 64);
+        t1 += __shfl_xor(t1, o, 64);
+    }
+    if (r == 0) {
+        tot[(size_t)(2 * h) * ncell + c] = t0;
+        tot[(size_t)(2 * h + 1) * ncell + c] = t1;
+    }
 }
 
 // dc[r][q] += the entries (kz, kx) of the cells (i2, i1) whose clamped knot
