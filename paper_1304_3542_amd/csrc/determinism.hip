@@ -51,21 +51,51 @@ __global__ void k_det_zero_i32(int *p, int64_t n)
         p[i] = 0;
 }
 
-// (cell, slot) of every record, listed in beam order then log order: one
-// thread per beam walks its own log, so the work follows the records (the
-// lanes of a wavefront read log position k of consecutive beams together)
-__global__ void k_det_list(const int *__restrict__ cnt, const int64_t *__restrict__ off,
-                           const int *__restrict__ cell, int64_t nb, int64_t cap,
-                           unsigned *__restrict__ keys, unsigned long long *__restrict__ slots)
+// (cell, slot) of every record, listed in beam order then log order.  A
+// wavefront takes 64 consecutive beams, whose output ranges are consecutive.
+// It reads a window of DL_K log positions of its beams into LDS (position k
+// of consecutive beams is contiguous, so the reads are whole lines), then
+// writes each beam's entries of the window to its range with consecutive
+// lanes, so the stores are runs instead of one partial line per lane.
+#define DL_K 32
+
+__global__ void __launch_bounds__(256)
+k_det_list(const int *__restrict__ cnt, const int64_t *__restrict__ off,
+           const int *__restrict__ cell, int64_t nb, int64_t cap, unsigned *__restrict__ keys,
+           unsigned long long *__restrict__ slots)
 {
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
-         b += (int64_t)gridDim.x * blockDim.x) {
-        const int n = cnt[b];
-        const int64_t o = off[b];
-        for (int k = 0; k < n; ++k) {
-            const size_t s = (size_t)k * cap + b;
-            keys[o + k] = (unsigned)cell[s];
-            slots[o + k] = (unsigned long long)s;
+    __shared__ int win[4][DL_K][65];   // [wave][k][beam], padded against bank conflicts
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int64_t b0 = ((int64_t)blockIdx.x * 4 + w) * 64; b0 < nb;
+         b0 += (int64_t)gridDim.x * 256) {
+        const int64_t b = b0 + lane;
+        const int n = b < nb ? cnt[b] : 0;
+        const int64_t o = b < nb ? off[b] : 0;
+        int nmax = n;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) nmax = max(nmax, __shfl_xor(nmax, m, 64));
+        for (int k0 = 0; k0 < nmax; k0 += DL_K) {
+            const int kn = min(DL_K, nmax - k0);   // uniform
+            for (int k = 0; k < kn; ++k)
+                if (k0 + k < n) win[w][k][lane] = cell[(size_t)(k0 + k) * cap + b];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int j = 0; j < 64; ++j) {
+                // beam j's count and offset (j is uniform: scalar reads of lane j)
+                const int nj = __builtin_amdgcn_readlane(n, j);
+                const int lo = __builtin_amdgcn_readlane((int)(unsigned)(o & 0xffffffff), j);
+                const int hi = __builtin_amdgcn_readlane((int)(o >> 32), j);
+                const int64_t oj = (int64_t)(((unsigned long long)(unsigned)hi << 32) |
+                                             (unsigned long long)(unsigned)lo);
+                if (lane < min(nj - k0, kn)) {
+                    const int64_t q = oj + k0 + lane;
+                    keys[q] = (unsigned)win[w][lane][j];
+                    slots[q] = (unsigned long long)((size_t)(k0 + lane) * cap + (size_t)(b0 + j));
+                }
+            }
+            // every lane's reads of this window are done before the next one is written
+            __builtin_amdgcn_wave_barrier();
         }
     }
 }
