@@ -977,32 +977,50 @@ __global__ void k_cqb_gather(const int64_t *__restrict__ id, const int64_t *__re
 }
 
 // Transposed pass 2: Tb[sf][i2][c] = d2 sum_{j2, l2} conj(E2[l2][i2 - k2(j2)]) psib[sf][j2][l2][c]
+// A thread owns column c of P2T_ROWS consecutive rows i2, so each psib entry
+// is loaded once for the rows of the block its window covers (the windows of
+// neighbouring rows overlap almost entirely); every output still sums over
+// j2, then l2, in increasing order.
+#define P2T_ROWS 8
+
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_fbi_pass2_t(const double *__restrict__ psib, const cplxR<R> *__restrict__ E2, double *Tb,
               int n2, int R2, int qb2, int qs2, int nq2, int np2, int NC, double d2)
 {
     const int W2 = 2 * R2 + 1;
-    const int i2 = blockIdx.y, sf = blockIdx.z;
+    const int i2b = blockIdx.y * P2T_ROWS, sf = blockIdx.z;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= NC) return;
-    double ar = 0.0, ai = 0.0;
+    double ar[P2T_ROWS], ai[P2T_ROWS];
+#pragma unroll
+    for (int r = 0; r < P2T_ROWS; ++r) ar[r] = ai[r] = 0.0;
     for (int j2 = 0; j2 < nq2; ++j2) {
-        const int m = i2 - (qb2 + j2 * qs2);   // window offset of node i2 from q node j2
-        if (m < -R2 || m > R2) continue;
+        const int m0 = i2b - (qb2 + j2 * qs2);   // window offset of row i2b from q node j2
+        if (m0 + P2T_ROWS - 1 < -R2 || m0 > R2) continue;
         const double *pb = psib + 2 * (((size_t)sf * nq2 + j2) * np2 * (size_t)NC + c);
         for (int l2 = 0; l2 < np2; ++l2) {
-            cplxR<R> e = E2[(size_t)l2 * W2 + m + R2];
-            double er = (double)e.re, ei = (double)e.im;
-            double br = pb[2 * (size_t)l2 * NC], bi = pb[2 * (size_t)l2 * NC + 1];
-            // conj(e) * b
-            ar += er * br + ei * bi;
-            ai += er * bi - ei * br;
+            const double br = pb[2 * (size_t)l2 * NC], bi = pb[2 * (size_t)l2 * NC + 1];
+            const cplxR<R> *el = E2 + (size_t)l2 * W2 + R2;
+#pragma unroll
+            for (int r = 0; r < P2T_ROWS; ++r) {
+                const int m = m0 + r;
+                if (m < -R2 || m > R2) continue;   // uniform in the workgroup
+                const cplxR<R> e = el[m];
+                const double er = (double)e.re, ei = (double)e.im;
+                // conj(e) * b
+                ar[r] += er * br + ei * bi;
+                ai[r] += er * bi - ei * br;
+            }
         }
     }
-    double *out = Tb + 2 * (((size_t)sf * n2 + i2) * NC + c);
-    out[0] = ar * d2;
-    out[1] = ai * d2;
+#pragma unroll
+    for (int r = 0; r < P2T_ROWS; ++r) {
+        if (i2b + r >= n2) break;
+        double *out = Tb + 2 * (((size_t)sf * n2 + i2b + r) * NC + c);
+        out[0] = ar[r] * d2;
+        out[1] = ai[r] * d2;
+    }
 }
 
 // the pass-1 table with the window offset fastest: E1tt[l][m] = E1t[m][l]
@@ -1080,7 +1098,9 @@ static fga_status decompose_adjoint_impl(fga_ctx *ctx, const fga_beams *beams, i
                        (const cplxR<R> *)ctx->Psi, ctx->cq, p.nq1, p.nq2, p.np1, p.np2, nfj,
                        p.dp1, p.dp2, p.eps, ctx->norm, psib, cqb,
                        det ? (double *)ctx->det_cqc : nullptr);
-    hipLaunchKernelGGL(k_fbi_pass2_t<R>, dim3((unsigned)((NC + 255) / 256), g.n2, S), dim3(256),
+    hipLaunchKernelGGL(k_fbi_pass2_t<R>,
+                       dim3((unsigned)((NC + 255) / 256), (g.n2 + P2T_ROWS - 1) / P2T_ROWS, S),
+                       dim3(256),
                        0, st, psib, (const cplxR<R> *)ctx->E2, Tb, g.n2, ctx->R2, p.qb2, p.qs2,
                        p.nq2, p.np2, (int)NC, g.d2);
     const int W1 = 2 * ctx->R1 + 1;
